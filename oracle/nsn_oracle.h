@@ -1,0 +1,126 @@
+/*
+ * FP64 CPU oracle of the non-smooth Newton step -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may load
+ * this library.  It shares no code with the GPU library (include/nsn.h and the
+ * package's csrc/), and neither side includes the other.
+ *
+ * The oracle steps ONE environment at a time, in double precision, following
+ * Macklin et al., "Non-Smooth Newton Methods for Deformable Multi-Body Dynamics"
+ * (TOG 2019): Algorithm 1 (simulation loop), Sec. 3 (models), Sec. 4 (NCP
+ * functions), Sec. 5 (implicit time stepping), Sec. 6 (Newton system, Schur
+ * complement), Sec. 7 (complementarity preconditioner), Sec. 8 (damping, start
+ * iterate, PCR, geometric stiffness, regularisation), Sec. 9 (generalised
+ * compliance, particles, rigid bodies) and Appendices A/B.
+ */
+#ifndef NSN_ORACLE_H
+#define NSN_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t n_rigid;
+  const double *rigid_mass;      /* [n_rigid]; 0 = static obstacle */
+  const double *rigid_inertia;   /* [n_rigid*3] principal body-frame inertia */
+  const double *rigid_x;         /* [n_rigid*3] */
+  const double *rigid_q;         /* [n_rigid*4] (w,x,y,z) */
+  const double *rigid_v;         /* [n_rigid*3] */
+  const double *rigid_w;         /* [n_rigid*3] world-frame angular velocity */
+  const int32_t *rigid_shape;    /* [n_rigid] 0 box, 1 capsule, 2 none */
+  const double *rigid_extent;    /* [n_rigid*3] box half extents / (radius, half length, 0) */
+  int32_t n_particles;
+  const double *particle_x, *particle_v, *particle_rest; /* [n_particles*3] */
+  const double *particle_mass;   /* [n_particles] extra point mass */
+  int32_t n_tets;
+  const int32_t *tet_ids;        /* [n_tets*4] */
+  const double *tet_material;    /* [n_tets*3] (E, nu, rho) */
+  int32_t n_joints;
+  const int32_t *joint_type;     /* [n_joints] 0 revolute, 1 prismatic */
+  const int32_t *joint_body;     /* [n_joints*2] (A, B), -1 = world */
+  const double *joint_anchor;    /* [n_joints*6] pA (A frame), pB (B frame) */
+  const double *joint_axis;      /* [n_joints*6] aA, aB */
+  const double *joint_ref;       /* [n_joints*6] tA, tB (perpendicular to the axis) */
+  const double *joint_drive;     /* [n_joints*6] kp, kd, amp, freq, phase, offset */
+  double mu;
+  double gravity[3];
+  int32_t ground;                /* plane z = 0 with normal +z */
+  int32_t max_contacts;
+} orc_desc;
+
+typedef struct {
+  int32_t ncp;        /* 0 Fischer-Burmeister, 1 minimum map */
+  int32_t rmode;      /* 0 identity, 1 h^2, 2 h^2 * effective mass */
+  double damping;     /* constant step fraction t */
+  double eps;         /* Schur regularisation */
+  int32_t geo_stiff;  /* diagonal geometric stiffness on particle DOFs */
+  int32_t fem_mode;   /* 0 projected full 3x3 compliance, 1 diagonal */
+  double margin;      /* contact creation distance */
+  int32_t warm;       /* 0 zero start, 1 previous-step multipliers, 2 learned */
+  int32_t pad;
+} orc_params;
+
+typedef struct {
+  int32_t newton_iters;   /* Newton updates performed */
+  int32_t cr_iters;       /* total PCR iterations */
+  int32_t n_contacts;
+  int32_t overflow;       /* contacts dropped beyond max_contacts */
+  int32_t nonfinite;
+  int32_t pad;
+  double r_ncp;           /* final max(|M^-1 g|_inf, |err|_inf) */
+  double r_contact;       /* same, contact rows only */
+  double merit;           /* final |[g; err]|_2 */
+  double r_ncp_first;     /* residual at the start iterate */
+} orc_stats;
+
+void *orc_create(const orc_desc *d, char *err, int errlen);
+void orc_destroy(void *env);
+int orc_step(void *env, const orc_params *p, double h, int newton_iters, int cr_iters,
+             double tol, orc_stats *st);
+void orc_get_state(void *env, double *rx, double *rq, double *rv, double *rw,
+                   double *px, double *pv);
+void orc_set_state(void *env, const double *rx, const double *rq, const double *rv,
+                   const double *rw, const double *px, const double *pv);
+double orc_get_time(void *env);
+void orc_set_time(void *env, double t);
+int orc_num_contacts(void *env);
+/* contacts of the last step: key, feature body, target body, n, aL, bL, d, lambda(3) */
+int orc_get_contacts(void *env, int64_t *key, int32_t *bodies, double *geom, double *lam, int cap);
+int orc_num_rows(void *env);
+void orc_get_lambda(void *env, double *lam);   /* full multiplier vector of the last step */
+void orc_set_mlp(void *env, const double *weights, int64_t n);
+/* per-iteration residual history of the last step (r_ncp per assembly) */
+int orc_get_history(void *env, double *r, int cap);
+/* per-row data of the final assembly of the last step */
+int orc_get_rows_debug(void *env, double *err, double *cdiag, double *pdiag, int cap);
+
+/* ---- primitives exposed for the pins ---- */
+void orc_ncp_fb(double C, double lam, double r, double *phi, double *alpha, double *beta);
+void orc_ncp_min(double C, double lam, double r, double *phi, double *alpha, double *beta);
+double orc_friction_w(int ncp, double vnorm, double lam_n, double lamf_norm, double mu, double r);
+void orc_svd3(const double *F, double *U, double *s, double *V);
+void orc_sym_eig3(const double *A, double *Q, double *w);
+void orc_lame(double E, double nu, double *C1, double *D1, double *alpha);
+void orc_neohookean(const double *s, double C1, double D1, double alpha, double *psi,
+                    double *grad, double *hess);
+void orc_compliance3(const double *H, double floor_, int mode, double *E);
+int orc_pcr_dense(int n, const double *A, const double *b, const double *P, int iters,
+                  double *x, double *hist);
+void orc_quat_kinematic(const double *q, double *Q /* 4x3 */);
+void orc_tangent_basis(const double *n, double *d1, double *d2);
+
+/* ---- learned warm start (FP64 MLP: 12 -> 64 -> 64 -> 64 -> 3, ReLU) ---- */
+int64_t orc_mlp_num_params(void);
+void orc_mlp_forward(const double *w, int64_t n, const double *x, double *y);
+double orc_mlp_loss_grad(const double *w, int64_t n, const double *x, const double *t,
+                         double *grad);
+/* 12 features of every contact of the current state (computed as at step start) */
+int orc_contact_features(void *env, const orc_params *p, double h, double *feat, int64_t *key,
+                         int cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,326 @@
+"""ctypes front end of the FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may import
+this module.  It never imports the GPU package and the GPU package never imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+D = C.POINTER(C.c_double)
+I32 = C.POINTER(C.c_int32)
+I64 = C.POINTER(C.c_int64)
+
+
+class _Desc(C.Structure):
+    _fields_ = [
+        ("n_rigid", C.c_int32),
+        ("rigid_mass", D), ("rigid_inertia", D), ("rigid_x", D), ("rigid_q", D),
+        ("rigid_v", D), ("rigid_w", D), ("rigid_shape", I32), ("rigid_extent", D),
+        ("n_particles", C.c_int32),
+        ("particle_x", D), ("particle_v", D), ("particle_rest", D), ("particle_mass", D),
+        ("n_tets", C.c_int32), ("tet_ids", I32), ("tet_material", D),
+        ("n_joints", C.c_int32), ("joint_type", I32), ("joint_body", I32),
+        ("joint_anchor", D), ("joint_axis", D), ("joint_ref", D), ("joint_drive", D),
+        ("mu", C.c_double), ("gravity", C.c_double * 3), ("ground", C.c_int32),
+        ("max_contacts", C.c_int32),
+    ]
+
+
+class Params(C.Structure):
+    _fields_ = [("ncp", C.c_int32), ("rmode", C.c_int32), ("damping", C.c_double),
+                ("eps", C.c_double), ("geo_stiff", C.c_int32), ("fem_mode", C.c_int32),
+                ("margin", C.c_double), ("warm", C.c_int32), ("pad", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("cr_iters", C.c_int32),
+                ("n_contacts", C.c_int32), ("overflow", C.c_int32),
+                ("nonfinite", C.c_int32), ("pad", C.c_int32),
+                ("r_ncp", C.c_double), ("r_contact", C.c_double), ("merit", C.c_double),
+                ("r_ncp_first", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = _build.LIB
+        src = _build.SRC
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+            _build.build()
+        L = C.CDLL(path)
+        L.orc_create.restype = C.c_void_p
+        L.orc_create.argtypes = [C.POINTER(_Desc), C.c_char_p, C.c_int]
+        L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_step.argtypes = [C.c_void_p, C.POINTER(Params), C.c_double, C.c_int, C.c_int,
+                               C.c_double, C.POINTER(Stats)]
+        L.orc_get_state.argtypes = [C.c_void_p] + [D] * 6
+        L.orc_set_state.argtypes = [C.c_void_p] + [D] * 6
+        L.orc_get_time.restype = C.c_double
+        L.orc_get_time.argtypes = [C.c_void_p]
+        L.orc_set_time.argtypes = [C.c_void_p, C.c_double]
+        L.orc_num_contacts.argtypes = [C.c_void_p]
+        L.orc_num_rows.argtypes = [C.c_void_p]
+        L.orc_get_contacts.argtypes = [C.c_void_p, I64, I32, D, D, C.c_int]
+        L.orc_get_lambda.argtypes = [C.c_void_p, D]
+        L.orc_set_mlp.argtypes = [C.c_void_p, D, C.c_int64]
+        L.orc_get_history.argtypes = [C.c_void_p, D, C.c_int]
+        L.orc_get_rows_debug.argtypes = [C.c_void_p, D, D, D, C.c_int]
+        L.orc_ncp_fb.argtypes = [C.c_double] * 3 + [D] * 3
+        L.orc_ncp_min.argtypes = [C.c_double] * 3 + [D] * 3
+        L.orc_friction_w.restype = C.c_double
+        L.orc_friction_w.argtypes = [C.c_int] + [C.c_double] * 5
+        L.orc_svd3.argtypes = [D] * 4
+        L.orc_sym_eig3.argtypes = [D] * 3
+        L.orc_lame.argtypes = [C.c_double, C.c_double, D, D, D]
+        L.orc_neohookean.argtypes = [D, C.c_double, C.c_double, C.c_double, D, D, D]
+        L.orc_compliance3.argtypes = [D, C.c_double, C.c_int, D]
+        L.orc_pcr_dense.argtypes = [C.c_int, D, D, D, C.c_int, D, D]
+        L.orc_quat_kinematic.argtypes = [D, D]
+        L.orc_tangent_basis.argtypes = [D, D, D]
+        L.orc_mlp_num_params.restype = C.c_int64
+        L.orc_mlp_forward.argtypes = [D, C.c_int64, D, D]
+        L.orc_mlp_loss_grad.restype = C.c_double
+        L.orc_mlp_loss_grad.argtypes = [D, C.c_int64, D, D, D]
+        L.orc_contact_features.argtypes = [C.c_void_p, C.POINTER(Params), C.c_double, D, I64, C.c_int]
+        _LIB = L
+    return _LIB
+
+
+def _d(a):
+    return a.ctypes.data_as(D)
+
+
+def _i32(a):
+    return a.ctypes.data_as(I32)
+
+
+def make_params(sp=None, **kw):
+    """Oracle parameter struct from a scene_inputs.SolverParams (or keywords)."""
+    vals = dict(ncp=0, rmode=2, damping=0.75, eps=1e-6, geo_stiff=1, fem_mode=0,
+                margin=5e-3, warm=0)
+    if sp is not None:
+        for k in vals:
+            vals[k] = getattr(sp, k)
+    vals.update(kw)
+    return Params(**vals)
+
+
+class OracleEnv:
+    """One environment stepped by the FP64 oracle."""
+
+    def __init__(self, desc):
+        self.desc = desc
+        L = lib()
+        self._keep = {}
+
+        def arr(name, dtype):
+            a = np.ascontiguousarray(getattr(desc, name), dtype=dtype).ravel()
+            if a.size == 0:
+                a = np.zeros(1, dtype=dtype)
+            self._keep[name] = a
+            return a
+
+        s = _Desc()
+        s.n_rigid = desc.n_rigid
+        for name in ["rigid_mass", "rigid_inertia", "rigid_x", "rigid_q", "rigid_v", "rigid_w",
+                     "rigid_extent", "particle_x", "particle_v", "particle_rest", "particle_mass",
+                     "tet_material", "joint_anchor", "joint_axis", "joint_ref", "joint_drive"]:
+            setattr(s, name, _d(arr(name, np.float64)))
+        for name in ["rigid_shape", "tet_ids", "joint_type", "joint_body"]:
+            setattr(s, name, _i32(arr(name, np.int32)))
+        s.n_particles = desc.n_particles
+        s.n_tets = desc.n_tets
+        s.n_joints = desc.n_joints
+        s.mu = desc.mu
+        s.gravity = (C.c_double * 3)(*desc.gravity)
+        s.ground = desc.ground
+        s.max_contacts = desc.max_contacts
+        err = C.create_string_buffer(256)
+        self.h = L.orc_create(C.byref(s), err, 256)
+        if not self.h:
+            raise ValueError(err.value.decode())
+        self.nr, self.np_ = desc.n_rigid, desc.n_particles
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_destroy(self.h)
+            self.h = None
+
+    def step(self, h, newton_iters, cr_iters, tol=0.0, params=None):
+        p = params if params is not None else make_params()
+        st = Stats()
+        lib().orc_step(self.h, C.byref(p), float(h), int(newton_iters), int(cr_iters), float(tol),
+                       C.byref(st))
+        return st.as_dict()
+
+    def get_state(self):
+        rx = np.zeros((self.nr, 3)); rq = np.zeros((self.nr, 4)); rv = np.zeros((self.nr, 3))
+        rw = np.zeros((self.nr, 3)); px = np.zeros((self.np_, 3)); pv = np.zeros((self.np_, 3))
+        lib().orc_get_state(self.h, _d(rx), _d(rq), _d(rv), _d(rw), _d(px), _d(pv))
+        return dict(rigid_x=rx, rigid_q=rq, rigid_v=rv, rigid_w=rw, particle_x=px, particle_v=pv)
+
+    def set_state(self, st):
+        g = lambda k, shape: np.ascontiguousarray(st[k], dtype=np.float64).reshape(shape)
+        rx, rq, rv, rw = (g("rigid_x", (self.nr, 3)), g("rigid_q", (self.nr, 4)),
+                          g("rigid_v", (self.nr, 3)), g("rigid_w", (self.nr, 3)))
+        px, pv = g("particle_x", (self.np_, 3)), g("particle_v", (self.np_, 3))
+        lib().orc_set_state(self.h, _d(rx), _d(rq), _d(rv), _d(rw), _d(px), _d(pv))
+
+    @property
+    def time(self):
+        return lib().orc_get_time(self.h)
+
+    @time.setter
+    def time(self, t):
+        lib().orc_set_time(self.h, float(t))
+
+    def contacts(self):
+        n = lib().orc_num_contacts(self.h)
+        key = np.zeros(max(n, 1), np.int64); bodies = np.zeros((max(n, 1), 2), np.int32)
+        geom = np.zeros((max(n, 1), 10)); lam = np.zeros((max(n, 1), 3))
+        lib().orc_get_contacts(self.h, key.ctypes.data_as(I64), _i32(bodies), _d(geom), _d(lam), n)
+        return dict(key=key[:n], bodies=bodies[:n], normal=geom[:n, 0:3], a_local=geom[:n, 3:6],
+                    b_local=geom[:n, 6:9], thickness=geom[:n, 9], lam=lam[:n])
+
+    def lambdas(self):
+        n = lib().orc_num_rows(self.h)
+        out = np.zeros(max(n, 1))
+        lib().orc_get_lambda(self.h, _d(out))
+        return out[:n]
+
+    def history(self):
+        out = np.zeros(256)
+        n = lib().orc_get_history(self.h, _d(out), 256)
+        return out[:n]
+
+    def rows_debug(self):
+        n = lib().orc_num_rows(self.h)
+        e, c, p = np.zeros(max(n, 1)), np.zeros(max(n, 1)), np.zeros(max(n, 1))
+        lib().orc_get_rows_debug(self.h, _d(e), _d(c), _d(p), n)
+        return e[:n], c[:n], p[:n]
+
+    def set_mlp(self, blob):
+        if blob is None:
+            lib().orc_set_mlp(self.h, None, 0)
+            return
+        b = np.ascontiguousarray(blob, dtype=np.float64)
+        self._keep["mlp"] = b
+        lib().orc_set_mlp(self.h, _d(b), b.size)
+
+    def contact_features(self, h, params=None):
+        p = params if params is not None else make_params()
+        cap = self.desc.max_contacts
+        feat = np.zeros((max(cap, 1), 12)); key = np.zeros(max(cap, 1), np.int64)
+        n = lib().orc_contact_features(self.h, C.byref(p), float(h), _d(feat), key.ctypes.data_as(I64), cap)
+        n = min(n, cap)
+        return feat[:n], key[:n]
+
+
+# ---------------------------------------------------------------------------
+# primitives (for pins)
+# ---------------------------------------------------------------------------
+
+def ncp_fb(Cn, lam, r):
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_ncp_fb(Cn, lam, r, C.byref(a), C.byref(b), C.byref(c))
+    return a.value, b.value, c.value
+
+
+def ncp_min(Cn, lam, r):
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_ncp_min(Cn, lam, r, C.byref(a), C.byref(b), C.byref(c))
+    return a.value, b.value, c.value
+
+
+def friction_w(ncp, vnorm, lam_n, lamf_norm, mu, r):
+    return lib().orc_friction_w(int(ncp), vnorm, lam_n, lamf_norm, mu, r)
+
+
+def svd3(F):
+    F = np.ascontiguousarray(F, np.float64).reshape(9)
+    U, s, V = np.zeros(9), np.zeros(3), np.zeros(9)
+    lib().orc_svd3(_d(F), _d(U), _d(s), _d(V))
+    return U.reshape(3, 3), s, V.reshape(3, 3)
+
+
+def sym_eig3(A):
+    A = np.ascontiguousarray(A, np.float64).reshape(9)
+    Q, w = np.zeros(9), np.zeros(3)
+    lib().orc_sym_eig3(_d(A), _d(Q), _d(w))
+    return Q.reshape(3, 3), w
+
+
+def lame(E, nu):
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_lame(E, nu, C.byref(a), C.byref(b), C.byref(c))
+    return a.value, b.value, c.value
+
+
+def neohookean(s, C1, D1, alpha):
+    s = np.ascontiguousarray(s, np.float64)
+    psi, g, H = C.c_double(), np.zeros(3), np.zeros(9)
+    lib().orc_neohookean(_d(s), C1, D1, alpha, C.byref(psi), _d(g), _d(H))
+    return psi.value, g, H.reshape(3, 3)
+
+
+def compliance3(H, floor_, mode=0):
+    H = np.ascontiguousarray(H, np.float64).reshape(9)
+    E = np.zeros(9)
+    lib().orc_compliance3(_d(H), floor_, int(mode), _d(E))
+    return E.reshape(3, 3)
+
+
+def pcr_dense(A, b, P, iters):
+    A = np.ascontiguousarray(A, np.float64)
+    n = A.shape[0]
+    b = np.ascontiguousarray(b, np.float64)
+    P = np.ascontiguousarray(P, np.float64)
+    x, hist = np.zeros(n), np.zeros(max(iters, 1))
+    done = lib().orc_pcr_dense(n, _d(A), _d(b), _d(P), int(iters), _d(x), _d(hist))
+    return x, hist[:done]
+
+
+def quat_kinematic(q):
+    q = np.ascontiguousarray(q, np.float64)
+    Q = np.zeros(12)
+    lib().orc_quat_kinematic(_d(q), _d(Q))
+    return Q.reshape(4, 3)
+
+
+def tangent_basis(n):
+    n = np.ascontiguousarray(n, np.float64)
+    d1, d2 = np.zeros(3), np.zeros(3)
+    lib().orc_tangent_basis(_d(n), _d(d1), _d(d2))
+    return d1, d2
+
+
+def mlp_num_params():
+    return int(lib().orc_mlp_num_params())
+
+
+def mlp_forward(w, x):
+    w = np.ascontiguousarray(w, np.float64)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 12)
+    y = np.zeros((x.shape[0], 3))
+    lib().orc_mlp_forward(_d(w), x.shape[0], _d(x), _d(y))
+    return y
+
+
+def mlp_loss_grad(w, x, t):
+    w = np.ascontiguousarray(w, np.float64)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 12)
+    t = np.ascontiguousarray(t, np.float64).reshape(-1, 3)
+    g = np.zeros_like(w)
+    loss = lib().orc_mlp_loss_grad(_d(w), x.shape[0], _d(x), _d(t), _d(g))
+    return loss, g
