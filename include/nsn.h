@@ -1,0 +1,254 @@
+/*
+ * nsn.h -- C ABI of the MI355X non-smooth Newton library (libnsn.so).
+ *
+ * The library steps batches of independent environments ("envs") of rigid bodies,
+ * particles (tetrahedral FEM nodes), joints and frictional contacts with the
+ * non-smooth Newton method of Macklin et al., "Non-Smooth Newton Methods for
+ * Deformable Multi-Body Dynamics", TOG 38(5) 2019:
+ *   - Algorithm 1 (simulation loop): collision detection once per step, then N
+ *     Newton iterations, each with an assembly and M linear (PCR) iterations;
+ *   - Sec. 5 (implicit time stepping) and Sec. 6 (Newton system, Schur complement
+ *     [J H^-1 J^T + C] dlambda = (1/h)(J H^-1 g - err));
+ *   - Sec. 4 / App. A (Fischer-Burmeister or minimum-map NCP functions, friction
+ *     compliance W), Sec. 7 (complementarity preconditioner r);
+ *   - Sec. 8 (damped step t, zero start, Jacobi-preconditioned conjugate residual,
+ *     diagonal geometric stiffness, eps regularisation);
+ *   - Sec. 9 / App. B (generalised compliance of stable neo-Hookean tets in
+ *     principal stretches, particles, rigid bodies with quaternions).
+ *
+ * Conventions: SI units; z up; quaternions (w,x,y,z); angular velocities in the
+ * world frame; all host arrays are float32 and row-major unless stated.
+ *
+ * Memory ownership: the caller owns ALL device memory.  nsn_query_workspace()
+ * returns the size of one device buffer that the caller allocates (e.g. a torch
+ * uint8 tensor) and passes to nsn_create_scene(); the library sub-allocates it and
+ * never calls hipMalloc.  Host descriptor arrays are only read during
+ * nsn_create_scene() and may be freed afterwards.  Every call that takes host
+ * output arrays writes into caller-owned memory.
+ *
+ * Streams: every device operation of a scene is enqueued on the stream given at
+ * creation (NULL = the default stream).  nsn_step() is asynchronous.  Calls that
+ * return data to the host synchronise that stream first.  Calls on one scene are
+ * not re-entrant; different scenes may be used from different threads.
+ *
+ * Errors: every function returns NSN_OK or a negative status; nsn_last_error()
+ * returns a thread-local message for the last failure.  Non-convergence is NOT an
+ * error: it is reported in nsn_step_stats.
+ */
+#ifndef NSN_H
+#define NSN_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nsn_scene_s *nsn_scene;
+typedef int32_t nsn_status;
+
+#define NSN_OK 0
+#define NSN_EINVAL (-1)       /* invalid argument or descriptor */
+#define NSN_ENOMEM (-2)       /* workspace too small */
+#define NSN_EDEVICE (-3)      /* a HIP runtime call failed */
+#define NSN_ENONFINITE (-4)   /* non-finite state detected */
+#define NSN_EUNSUPPORTED (-5) /* sizes beyond the supported limits */
+#define NSN_ESTATE (-6)       /* call not valid in the current state */
+
+/* Shapes of rigid bodies (collision geometry; Sec. 10 primitive features). */
+#define NSN_SHAPE_BOX 0     /* extent = half extents */
+#define NSN_SHAPE_CAPSULE 1 /* extent = (radius, half length, 0), segment on body x */
+#define NSN_SHAPE_NONE 2    /* no collision geometry */
+
+#define NSN_JOINT_REVOLUTE 0
+#define NSN_JOINT_PRISMATIC 1
+
+#define NSN_NCP_FB 0   /* Fischer-Burmeister (Sec. 4.2) */
+#define NSN_NCP_MIN 1  /* minimum map (Sec. 4.1) */
+
+#define NSN_R_IDENTITY 0   /* r = 1 */
+#define NSN_R_H2 1         /* r_n = h^2, r_f = h */
+#define NSN_R_H2_EFFMASS 2 /* Sec. 7 eq. rscaling: r = h^2 [J M^-1 J^T]_ii (h for friction) */
+
+#define NSN_FEM_FULL_PROJECTED 0 /* E = (d2U/ds2)^-1 projected to positive definite */
+#define NSN_FEM_DIAGONAL 1       /* diagonal approximation of E */
+
+#define NSN_WARM_ZERO 0    /* u0 = 0, lambda0 = 0 (Sec. 8.1) */
+#define NSN_WARM_PREV 1    /* previous-step multipliers (contacts matched by key) */
+#define NSN_WARM_LEARNED 2 /* contact multipliers predicted by the warm-start MLP */
+
+/* One environment.  Pointers are host float32/int32 arrays, sizes as noted.
+ * A rigid body with mass 0 is a static obstacle.  Particles take their mass from
+ * the tets that use them (rho V_e / 4 each) plus particle_mass.  Tet rest shapes
+ * come from particle_rest. */
+typedef struct {
+  int32_t n_rigid;
+  const float *rigid_mass;    /* [n_rigid] */
+  const float *rigid_inertia; /* [n_rigid*3] principal body-frame inertia */
+  const float *rigid_x;       /* [n_rigid*3] */
+  const float *rigid_q;       /* [n_rigid*4] (w,x,y,z), normalised on entry */
+  const float *rigid_v;       /* [n_rigid*3] */
+  const float *rigid_w;       /* [n_rigid*3] world angular velocity */
+  const int32_t *rigid_shape; /* [n_rigid] NSN_SHAPE_* */
+  const float *rigid_extent;  /* [n_rigid*3] */
+  int32_t n_particles;
+  const float *particle_x;    /* [n_particles*3] */
+  const float *particle_v;    /* [n_particles*3] */
+  const float *particle_rest; /* [n_particles*3] */
+  const float *particle_mass; /* [n_particles] extra point mass (may be 0) */
+  int32_t n_tets;
+  const int32_t *tet_ids;     /* [n_tets*4] particle indices */
+  const float *tet_material;  /* [n_tets*3] (Young's modulus E, Poisson nu, density rho) */
+  int32_t n_joints;
+  const int32_t *joint_type;  /* [n_joints] NSN_JOINT_* */
+  const int32_t *joint_body;  /* [n_joints*2] (A, B); A may be -1 = world */
+  const float *joint_anchor;  /* [n_joints*6] anchor in A's frame, anchor in B's frame */
+  const float *joint_axis;    /* [n_joints*6] axis in A's frame, axis in B's frame */
+  const float *joint_ref;     /* [n_joints*6] unit reference direction perpendicular to the axis, per body */
+  const float *joint_drive;   /* [n_joints*6] kp, kd, amplitude, frequency, phase, offset (kp=kd=0: no drive) */
+  float mu;                   /* friction coefficient */
+  float gravity[3];
+  int32_t ground;             /* 1: static plane z = 0 with normal +z */
+  int32_t max_contacts;       /* contact capacity; extra contacts are dropped and counted */
+} nsn_env_desc;
+
+typedef struct {
+  int32_t ncp;       /* NSN_NCP_* */
+  int32_t rmode;     /* NSN_R_* */
+  float damping;     /* constant Newton step fraction t (Sec. 8.1; 0.75) */
+  float eps;         /* Schur regularisation (Sec. 8.4; 1e-6) */
+  int32_t geo_stiff; /* diagonal geometric stiffness on particle DOFs (Sec. 8.3) */
+  int32_t fem_mode;  /* NSN_FEM_* */
+  float margin;      /* contact creation distance (m) */
+  int32_t warm;      /* NSN_WARM_* */
+} nsn_solver_params;
+
+typedef struct {
+  int32_t newton_iters; /* Newton updates performed in the last step */
+  int32_t cr_iters;     /* PCR iterations performed in the last step */
+  int32_t n_contacts;
+  int32_t overflow;     /* contacts dropped beyond max_contacts */
+  int32_t nonfinite;    /* 1 if a non-finite value was produced */
+  int32_t converged;    /* 1 if r_ncp <= tol at exit (tol > 0) */
+  double r_ncp;         /* max(|M^-1 g|_inf, |err|_inf) at the final iterate (FP64) */
+  double r_contact;     /* same over contact rows only */
+  double merit;         /* |[g; err]|_2 at the final iterate (FP64 accumulation) */
+  double r_ncp_first;   /* residual at the start iterate */
+} nsn_step_stats;
+
+/* Last error message of the calling thread ("" if none).  Never NULL. */
+const char *nsn_last_error(void);
+
+/* Bytes of device workspace needed for these environments.  n_envs >= 1.
+ * Returns NSN_EINVAL on malformed descriptors (see nsn_create_scene). */
+nsn_status nsn_query_workspace(const nsn_env_desc *envs, int32_t n_envs, size_t *bytes);
+
+/* Validate the descriptors, build the device layout in `workspace` (a device
+ * pointer of at least the queried size, 256-byte aligned) and bind the scene to
+ * `hip_stream` (a hipStream_t, or NULL).  Errors: NSN_EINVAL for bad sizes, indices,
+ * masses, inertias, degenerate rest tets or materials, NSN_ENOMEM if the workspace is
+ * too small, NSN_EUNSUPPORTED if an env exceeds the kernel limits, NSN_EDEVICE on a
+ * HIP failure.  On success *out owns host bookkeeping only; free it with
+ * nsn_destroy_scene (the workspace stays the caller's). */
+nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_solver_params *p,
+                            void *hip_stream, void *workspace, size_t workspace_bytes,
+                            nsn_scene *out);
+
+nsn_status nsn_destroy_scene(nsn_scene s);
+
+/* Replace the solver parameters (takes effect at the next step). */
+nsn_status nsn_set_params(nsn_scene s, const nsn_solver_params *p);
+
+/* One time step of every env (Algorithm 1) enqueued on the scene's stream:
+ * collision detection at q^-, then up to `newton_iters` damped Newton updates with
+ * `cr_iters` PCR iterations each.  tol > 0: an env stops as soon as its residual
+ * r_ncp <= tol (checked before each update); tol = 0: fixed iteration counts.
+ * The step sequence is captured once into a hipGraph per (h, iterations, tol) and
+ * replayed.  Errors: NSN_EINVAL for h <= 0 or negative counts. */
+nsn_status nsn_step(nsn_scene s, double h, int32_t newton_iters, int32_t cr_iters, double tol);
+
+/* Statistics of the last step for every env: out[n_envs] (host).  Synchronises. */
+nsn_status nsn_get_stats(nsn_scene s, nsn_step_stats *out);
+
+/* Copy the state of one env to caller-owned host arrays sized by its descriptor
+ * (any pointer may be NULL to skip).  Synchronises the stream. */
+nsn_status nsn_read_state(nsn_scene s, int32_t env, float *rigid_x, float *rigid_q, float *rigid_v,
+                          float *rigid_w, float *particle_x, float *particle_v, double *time);
+
+/* Overwrite the state of one env (NULL pointers keep the current values).
+ * Quaternions are normalised.  Static bodies keep zero velocity.  Enqueued on the
+ * stream; the host arrays may be freed on return. */
+nsn_status nsn_write_state(nsn_scene s, int32_t env, const float *rigid_x, const float *rigid_q,
+                           const float *rigid_v, const float *rigid_w, const float *particle_x,
+                           const float *particle_v, const double *time);
+
+/* Contacts of one env from the last step: up to `cap` records.  *n receives the
+ * count.  keys[cap]; bodies[cap*2] = (feature body, target body) with particles
+ * numbered after rigid bodies and -1 = ground; geom[cap*10] = normal(3), feature
+ * point (body frame / unused for particles)(3), target point (body frame or world)(3),
+ * thickness; lam[cap*3] = (lambda_n, lambda_f1, lambda_f2).  Synchronises. */
+nsn_status nsn_read_contacts(nsn_scene s, int32_t env, int32_t cap, int32_t *n, int32_t *keys,
+                             int32_t *bodies, float *geom, float *lam);
+
+/* Full multiplier vector of one env in row order (joints: 6 rows each, tets: 3 each,
+ * contacts: 3 each); *n receives the row count.  Synchronises. */
+nsn_status nsn_read_lambda(nsn_scene s, int32_t env, int32_t cap, int32_t *n, float *lam);
+
+/* Warm-start model for NSN_WARM_LEARNED: float32 blob of 9347 MLP parameters
+ * (12 -> 64 -> 64 -> 64 -> 3, ReLU; W1[64x12] b1 W2[64x64] b2 W3[64x64] b3 W4[3x64] b4)
+ * followed by x_mean[12] x_std[12] y_mean[3] y_std[3].  Copied to the device. */
+nsn_status nsn_set_warm_start_model(nsn_scene s, const float *blob, int64_t n);
+
+/* Per-contact features of the last step's contact set, as used by the learned
+ * warm start: feat[cap*12].  Synchronises. */
+nsn_status nsn_read_features(nsn_scene s, int32_t env, int32_t cap, int32_t *n, float *feat);
+
+/* Compute the 12 warm-start features of every contact in every step (off by default
+ * except in NSN_WARM_LEARNED mode); needed by nsn_read_features. */
+nsn_status nsn_enable_features(nsn_scene s, int32_t on);
+
+/* Replay steps from captured hipGraphs (default on when the scene has a non-NULL
+ * stream; graphs are never used on the NULL stream). */
+nsn_status nsn_set_use_graphs(nsn_scene s, int32_t on);
+
+/* ---- launch schedule (used by the autotuner) -------------------------------
+ * Envs are launched in a fixed order: decreasing rows + DOFs (longest first).
+ * order[n_envs] receives that order. */
+nsn_status nsn_get_env_order(nsn_scene s, int32_t *order);
+
+/* Split the env order into consecutive buckets, each launched as one grid of
+ * workgroups with `block[i]` threads (64, 128, 256, 512 or 1024; 64 = one
+ * wavefront per env).  The buckets must tile [0, n_envs) in order. */
+nsn_status nsn_set_schedule(nsn_scene s, int32_t n_buckets, const int32_t *first, const int32_t *count,
+                            const int32_t *block);
+nsn_status nsn_get_schedule(nsn_scene s, int32_t cap, int32_t *n, int32_t *first, int32_t *count,
+                            int32_t *block);
+
+/* Device address of the per-env nsn_step_stats array (n_envs entries), valid for
+ * the scene's lifetime, for readers that copy it asynchronously. */
+nsn_status nsn_stats_device_ptr(nsn_scene s, void **ptr);
+
+/* ---- learned part: MLP kernels on caller-owned device buffers -------------
+ * Weights `w` are float32 device arrays in the layout above (9347 floats).  The
+ * matrix products run on BF16 MFMA tiles with FP32 accumulation; activations are
+ * rounded to bf16 where they enter a product.  `stream` may be NULL. */
+
+/* y[n*3] = MLP(x[n*12]) on the device. */
+nsn_status nsn_mlp_forward(const float *w, const float *x, float *y, int64_t n, void *stream);
+
+/* Mean-squared-error loss over n samples and its gradient grad[9347] (device);
+ * *loss_out (device float, may be NULL).  `scratch` is a device buffer of at least
+ * nsn_mlp_scratch_bytes(n) bytes. */
+size_t nsn_mlp_scratch_bytes(int64_t n);
+nsn_status nsn_mlp_loss_grad(const float *w, const float *x, const float *t, int64_t n,
+                             float *grad, float *loss_out, void *scratch, void *stream);
+
+/* One Adam update of w (device) from grad with moments m, v (device, zero-initialised
+ * by the caller), step count `step` >= 1. */
+nsn_status nsn_mlp_adam(float *w, const float *grad, float *m, float *v, int64_t n_params,
+                        float lr, float beta1, float beta2, float eps, int32_t step, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

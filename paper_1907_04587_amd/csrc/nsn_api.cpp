@@ -1,0 +1,745 @@
+// Host side of the C ABI (include/nsn.h): validation, the device layout inside the
+// caller's workspace, static adjacency, graph capture of the step, state I/O.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "nsn_layout.h"
+
+using namespace nsn;
+
+namespace {
+
+thread_local std::string g_err;
+
+nsn_status fail(nsn_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess) return fail(NSN_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+// Sequential sub-allocator: a dry run computes the size, a real run assigns pointers.
+struct Arena {
+  char *base;
+  size_t off = 0;
+  explicit Arena(void *b) : base((char *)b) {}
+  template <class T>
+  T *take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T *p = base ? (T *)(base + off) : nullptr;
+    off += std::max<size_t>(n, 1) * sizeof(T);
+    return p;
+  }
+};
+
+struct HostEnv {
+  int n_rig, n_par, n_tet, n_jnt, max_con, n_feat, n_targets;
+};
+
+struct Sizes {
+  int NR = 0, NP = 0, NT = 0, NJ = 0, NC = 0, NROW = 0, NDOF = 0, NF = 0, NTADJ = 0, NJADJ = 0;
+};
+
+nsn_status validate_env(const nsn_env_desc &d, int e, HostEnv &he) {
+  auto bad = [&](const std::string &m) { return fail(NSN_EINVAL, "env " + std::to_string(e) + ": " + m); };
+  if (d.n_rigid < 0 || d.n_particles < 0 || d.n_tets < 0 || d.n_joints < 0 || d.max_contacts < 0)
+    return bad("negative count");
+  if (d.n_rigid > 0 && (!d.rigid_mass || !d.rigid_inertia || !d.rigid_x || !d.rigid_q || !d.rigid_v ||
+                        !d.rigid_w || !d.rigid_shape || !d.rigid_extent))
+    return bad("missing rigid arrays");
+  if (d.n_particles > 0 && (!d.particle_x || !d.particle_v || !d.particle_rest))
+    return bad("missing particle arrays");
+  if (d.n_tets > 0 && (!d.tet_ids || !d.tet_material)) return bad("missing tet arrays");
+  if (d.n_joints > 0 && (!d.joint_type || !d.joint_body || !d.joint_anchor || !d.joint_axis || !d.joint_ref ||
+                         !d.joint_drive))
+    return bad("missing joint arrays");
+  int nfeat = 0;
+  for (int i = 0; i < d.n_rigid; ++i) {
+    const float m = d.rigid_mass[i];
+    if (!(m >= 0.f) || !std::isfinite(m)) return bad("rigid " + std::to_string(i) + ": bad mass");
+    if (m > 0.f)
+      for (int k = 0; k < 3; ++k)
+        if (!(d.rigid_inertia[3 * i + k] > 0.f)) return bad("rigid " + std::to_string(i) + ": bad inertia");
+    const int sh = d.rigid_shape[i];
+    if (sh < 0 || sh > 2) return bad("rigid " + std::to_string(i) + ": bad shape");
+    float ql = 0.f;
+    for (int k = 0; k < 4; ++k) ql += d.rigid_q[4 * i + k] * d.rigid_q[4 * i + k];
+    if (!(ql > 0.f)) return bad("rigid " + std::to_string(i) + ": zero quaternion");
+    nfeat += sh == NSN_SHAPE_BOX ? 8 : (sh == NSN_SHAPE_CAPSULE ? 2 : 0);
+  }
+  std::vector<float> mass(d.n_particles, 0.f);
+  for (int p = 0; p < d.n_particles; ++p) mass[p] = d.particle_mass ? d.particle_mass[p] : 0.f;
+  for (int t = 0; t < d.n_tets; ++t) {
+    for (int k = 0; k < 4; ++k) {
+      const int id = d.tet_ids[4 * t + k];
+      if (id < 0 || id >= d.n_particles) return bad("tet " + std::to_string(t) + ": bad particle id");
+    }
+    const float E = d.tet_material[3 * t], nu = d.tet_material[3 * t + 1], rho = d.tet_material[3 * t + 2];
+    if (!(E > 0.f) || !(nu > -1.f && nu < 0.5f) || !(rho > 0.f)) return bad("tet " + std::to_string(t) + ": bad material");
+  }
+  for (int j = 0; j < d.n_joints; ++j) {
+    const int a = d.joint_body[2 * j], b = d.joint_body[2 * j + 1], ty = d.joint_type[j];
+    if (a < -1 || a >= d.n_rigid || b < 0 || b >= d.n_rigid || a == b || (ty != 0 && ty != 1))
+      return bad("joint " + std::to_string(j) + ": bad bodies or type");
+  }
+  he.n_rig = d.n_rigid;
+  he.n_par = d.n_particles;
+  he.n_tet = d.n_tets;
+  he.n_jnt = d.n_joints;
+  he.max_con = d.max_contacts;
+  he.n_feat = nfeat;
+  he.n_targets = (d.ground ? 1 : 0) + d.n_rigid;
+  const long long ncand = (long long)(nfeat + d.n_particles) * he.n_targets;
+  if (ncand >= (1ll << 31)) return fail(NSN_EUNSUPPORTED, "env " + std::to_string(e) + ": too many collision candidates");
+  return NSN_OK;
+}
+
+// Assign every workspace buffer; with base == nullptr only the size is computed.
+void layout(const Sizes &z, int n_envs, Arena &a, DevScene &S, EnvInfo *&env, int *&order) {
+  S.n_envs = n_envs;
+  S.NR = z.NR; S.NP = z.NP; S.NT = z.NT; S.NJ = z.NJ; S.NC = z.NC; S.NROW = z.NROW; S.NDOF = z.NDOF;
+  env = a.take<EnvInfo>(n_envs);
+  order = a.take<int>(n_envs);
+  S.env = env;
+  S.env_order = order;
+  S.r_x = a.take<float4>(z.NR); S.r_q = a.take<float4>(z.NR); S.r_v = a.take<float4>(z.NR);
+  S.r_w = a.take<float4>(z.NR); S.r_x0 = a.take<float4>(z.NR); S.r_q0 = a.take<float4>(z.NR);
+  S.r_inertia = a.take<float4>(z.NR); S.r_ext = a.take<float4>(z.NR); S.r_shape = a.take<int>(z.NR);
+  S.r_Iw = a.take<float>(6 * (size_t)z.NR); S.r_Iwinv = a.take<float>(6 * (size_t)z.NR);
+  S.r_ut = a.take<float>(6 * (size_t)z.NR); S.r_u = a.take<float>(6 * (size_t)z.NR);
+  S.p_x = a.take<float4>(z.NP); S.p_v = a.take<float4>(z.NP); S.p_x0 = a.take<float4>(z.NP);
+  S.p_m = a.take<float>(z.NP); S.p_ut = a.take<float4>(z.NP); S.p_u = a.take<float4>(z.NP);
+  S.p_uprev = a.take<float4>(z.NP); S.p_H = a.take<float4>(z.NP);
+  S.feat = a.take<int2>(z.NF);
+  S.t_ids = a.take<int4>(z.NT); S.t_Dminv = a.take<float>(9 * (size_t)z.NT); S.t_mat = a.take<float4>(z.NT);
+  S.t_J = a.take<float>(2 * 18 * (size_t)z.NT); S.t_E = a.take<float>(6 * (size_t)z.NT);
+  S.j_info = a.take<int4>(z.NJ); S.j_frame = a.take<float4>(6 * (size_t)z.NJ);
+  S.j_drive = a.take<float4>(2 * (size_t)z.NJ); S.j_theta0 = a.take<float>(z.NJ);
+  S.j_J = a.take<float>(72 * (size_t)z.NJ);
+  S.c_key = a.take<int>(z.NC); S.c_body = a.take<int2>(z.NC); S.c_n = a.take<float4>(z.NC);
+  S.c_aL = a.take<float4>(z.NC); S.c_bL = a.take<float4>(z.NC); S.c_rA = a.take<float4>(z.NC);
+  S.c_rB = a.take<float4>(z.NC); S.c_alpha = a.take<float>(2 * (size_t)z.NC);
+  S.c_active = a.take<int>(2 * (size_t)z.NC); S.c_lam0 = a.take<float4>(z.NC);
+  S.c_feat = a.take<float>(12 * (size_t)z.NC); S.c_prev_key = a.take<int>(z.NC);
+  S.c_prev_lam = a.take<float4>(z.NC); S.n_prev = a.take<int>(n_envs);
+  S.r_acon_beg = a.take<int>(z.NR); S.r_acon_end = a.take<int>(z.NR);
+  S.p_acon_beg = a.take<int>(z.NP); S.p_acon_end = a.take<int>(z.NP);
+  S.r_bcon_beg = a.take<int>(z.NR); S.r_bcon_cnt = a.take<int>(z.NR); S.bcon_list = a.take<int>(z.NC);
+  S.p_tadj_ptr = a.take<int>(z.NP + 1); S.p_tadj = a.take<int>(z.NTADJ);
+  S.r_jadj_ptr = a.take<int>(z.NR + 1); S.r_jadj = a.take<int>(z.NJADJ);
+  S.row_lam = a.take<float>(z.NROW); S.row_x = a.take<float>(z.NROW); S.row_z = a.take<float>(z.NROW);
+  S.row_p = a.take<float>(z.NROW); S.row_q = a.take<float>(z.NROW); S.row_w = a.take<float>(z.NROW);
+  S.row_err = a.take<float>(z.NROW); S.row_P = a.take<float>(z.NROW); S.row_C = a.take<float>(z.NROW);
+  S.row_b = a.take<float>(z.NROW);
+  S.y = a.take<float>(z.NDOF); S.g = a.take<float>(z.NDOF); S.f = a.take<float>(z.NDOF);
+  S.n_con = a.take<int>(n_envs); S.overflow = a.take<int>(n_envs); S.time = a.take<double>(n_envs);
+  S.stats = a.take<nsn_step_stats>(n_envs);
+  S.mlp = a.take<float>(kMlpBlob);
+  S.have_mlp = 0;
+}
+
+Sizes sizes_of(const std::vector<HostEnv> &he) {
+  Sizes z;
+  for (const auto &h : he) {
+    z.NR += h.n_rig; z.NP += h.n_par; z.NT += h.n_tet; z.NJ += h.n_jnt; z.NC += h.max_con;
+    z.NROW += 6 * h.n_jnt + 3 * h.n_tet + 3 * h.max_con;
+    z.NDOF += 6 * h.n_rig + 3 * h.n_par;
+    z.NF += h.n_feat;
+    z.NTADJ += 4 * h.n_tet;
+    z.NJADJ += 2 * h.n_jnt;
+  }
+  return z;
+}
+
+}  // namespace
+
+struct GraphKey {
+  float h;
+  int n, m;
+  float tol;
+  bool operator<(const GraphKey &o) const {
+    return std::tie(h, n, m, tol) < std::tie(o.h, o.n, o.m, o.tol);
+  }
+};
+
+struct Bucket {
+  int first, count, block;
+};
+
+struct nsn_scene_s {
+  DevScene S;
+  hipStream_t stream = nullptr;
+  nsn_solver_params p;
+  std::vector<nsn_env_desc> desc_sizes;  // counts only (pointers cleared)
+  std::vector<EnvInfo> env;
+  std::vector<int> order;
+  std::vector<Bucket> buckets;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  bool use_graphs = true;
+  int want_features = 0;
+};
+
+extern "C" {
+
+const char *nsn_last_error(void) { return g_err.c_str(); }
+
+nsn_status nsn_query_workspace(const nsn_env_desc *envs, int32_t n_envs, size_t *bytes) {
+  if (!envs || n_envs < 1 || !bytes) return fail(NSN_EINVAL, "nsn_query_workspace: bad arguments");
+  std::vector<HostEnv> he(n_envs);
+  for (int e = 0; e < n_envs; ++e) {
+    nsn_status st = validate_env(envs[e], e, he[e]);
+    if (st) return st;
+  }
+  Sizes z = sizes_of(he);
+  Arena a(nullptr);
+  DevScene S{};
+  EnvInfo *env;
+  int *order;
+  layout(z, n_envs, a, S, env, order);
+  *bytes = a.off + 256;
+  return NSN_OK;
+}
+
+nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_solver_params *p,
+                            void *hip_stream, void *workspace, size_t workspace_bytes, nsn_scene *out) {
+  if (!envs || n_envs < 1 || !p || !out) return fail(NSN_EINVAL, "nsn_create_scene: bad arguments");
+  if (!workspace || ((uintptr_t)workspace & 255)) return fail(NSN_EINVAL, "workspace must be a 256-byte aligned device pointer");
+  if (p->ncp < 0 || p->ncp > 1 || p->rmode < 0 || p->rmode > 2 || p->warm < 0 || p->warm > 2 ||
+      p->fem_mode < 0 || p->fem_mode > 1 || !(p->damping > 0.f) || !(p->eps >= 0.f) || !(p->margin >= 0.f))
+    return fail(NSN_EINVAL, "bad solver parameters");
+  size_t need = 0;
+  nsn_status st = nsn_query_workspace(envs, n_envs, &need);
+  if (st) return st;
+  if (workspace_bytes < need) return fail(NSN_ENOMEM, "workspace too small: need " + std::to_string(need));
+  std::vector<HostEnv> he(n_envs);
+  for (int e = 0; e < n_envs; ++e) validate_env(envs[e], e, he[e]);
+  Sizes z = sizes_of(he);
+  auto *s = new nsn_scene_s();
+  s->stream = (hipStream_t)hip_stream;
+  s->p = *p;
+  Arena a(workspace);
+  EnvInfo *env_dev;
+  int *order_dev;
+  layout(z, n_envs, a, s->S, env_dev, order_dev);
+  DevScene &S = s->S;
+
+  // ---- host staging of every static and initial array ----
+  std::vector<EnvInfo> env(n_envs);
+  std::vector<float4> r_x(z.NR), r_q(z.NR), r_v(z.NR), r_w(z.NR), r_in(z.NR), r_ext(z.NR);
+  std::vector<int> r_shape(z.NR);
+  std::vector<float4> p_x(z.NP), p_v(z.NP);
+  std::vector<float> p_m(z.NP, 0.f);
+  std::vector<int2> feat(std::max(z.NF, 1));
+  std::vector<int4> t_ids(z.NT);
+  std::vector<float> t_Dminv(9 * (size_t)z.NT);
+  std::vector<float4> t_mat(z.NT);
+  std::vector<int4> j_info(z.NJ);
+  std::vector<float4> j_frame(6 * (size_t)z.NJ), j_drive(2 * (size_t)z.NJ);
+  std::vector<int> tadj_ptr(z.NP + 1, 0), tadj(std::max(z.NTADJ, 1)), jadj_ptr(z.NR + 1, 0), jadj(std::max(z.NJADJ, 1));
+  int ro = 0, po = 0, to = 0, jo = 0, co = 0, rowo = 0, dofo = 0, fo = 0;
+  for (int e = 0; e < n_envs; ++e) {
+    const nsn_env_desc &d = envs[e];
+    const HostEnv &h = he[e];
+    EnvInfo &E = env[e];
+    E.rig_off = ro; E.n_rig = h.n_rig; E.par_off = po; E.n_par = h.n_par;
+    E.tet_off = to; E.n_tet = h.n_tet; E.jnt_off = jo; E.n_jnt = h.n_jnt;
+    E.con_off = co; E.max_con = h.max_con; E.row_off = rowo;
+    E.row_cap = 6 * h.n_jnt + 3 * h.n_tet + 3 * h.max_con;
+    E.dof_off = dofo; E.n_dof = 6 * h.n_rig + 3 * h.n_par;
+    E.feat_off = fo; E.n_feat = h.n_feat; E.n_targets = h.n_targets; E.ground = d.ground ? 1 : 0;
+    E.bcon_off = co; E.pad0 = 0;
+    E.mu = d.mu; E.gx = d.gravity[0]; E.gy = d.gravity[1]; E.gz = d.gravity[2];
+    for (int i = 0; i < h.n_rig; ++i) {
+      const int g = ro + i;
+      float q[4];
+      float ql = 0.f;
+      for (int k = 0; k < 4; ++k) { q[k] = d.rigid_q[4 * i + k]; ql += q[k] * q[k]; }
+      ql = std::sqrt(ql);
+      for (int k = 0; k < 4; ++k) q[k] /= ql;
+      const float m = d.rigid_mass[i];
+      const bool stat = !(m > 0.f);
+      r_x[g] = make_float4(d.rigid_x[3 * i], d.rigid_x[3 * i + 1], d.rigid_x[3 * i + 2], 0.f);
+      r_q[g] = make_float4(q[0], q[1], q[2], q[3]);
+      r_v[g] = stat ? make_float4(0.f, 0.f, 0.f, 0.f) : make_float4(d.rigid_v[3 * i], d.rigid_v[3 * i + 1], d.rigid_v[3 * i + 2], 0.f);
+      r_w[g] = stat ? make_float4(0.f, 0.f, 0.f, 0.f) : make_float4(d.rigid_w[3 * i], d.rigid_w[3 * i + 1], d.rigid_w[3 * i + 2], 0.f);
+      r_in[g] = make_float4(d.rigid_inertia[3 * i], d.rigid_inertia[3 * i + 1], d.rigid_inertia[3 * i + 2], stat ? 0.f : 1.f / m);
+      r_ext[g] = make_float4(d.rigid_extent[3 * i], d.rigid_extent[3 * i + 1], d.rigid_extent[3 * i + 2], 0.f);
+      r_shape[g] = d.rigid_shape[i];
+      const int nf = r_shape[g] == NSN_SHAPE_BOX ? 8 : (r_shape[g] == NSN_SHAPE_CAPSULE ? 2 : 0);
+      for (int v = 0; v < nf; ++v) feat[fo++] = make_int2(g, v);
+    }
+    for (int i = 0; i < h.n_par; ++i) {
+      const int g = po + i;
+      p_x[g] = make_float4(d.particle_x[3 * i], d.particle_x[3 * i + 1], d.particle_x[3 * i + 2], 0.f);
+      p_v[g] = make_float4(d.particle_v[3 * i], d.particle_v[3 * i + 1], d.particle_v[3 * i + 2], 0.f);
+      p_m[g] = d.particle_mass ? d.particle_mass[i] : 0.f;
+    }
+    for (int t = 0; t < h.n_tet; ++t) {
+      const int g = to + t;
+      const int *id = d.tet_ids + 4 * t;
+      t_ids[g] = make_int4(po + id[0], po + id[1], po + id[2], po + id[3]);
+      // rest shape D_m and its inverse (Sec. 9.2 constant-strain tetrahedron), in double
+      double Dm[9];
+      const float *r0 = d.particle_rest + 3 * id[0];
+      for (int c = 0; c < 3; ++c) {
+        const float *rc = d.particle_rest + 3 * id[c + 1];
+        for (int r = 0; r < 3; ++r) Dm[3 * r + c] = (double)rc[r] - (double)r0[r];
+      }
+      const double det = Dm[0] * (Dm[4] * Dm[8] - Dm[5] * Dm[7]) - Dm[1] * (Dm[3] * Dm[8] - Dm[5] * Dm[6]) +
+                         Dm[2] * (Dm[3] * Dm[7] - Dm[4] * Dm[6]);
+      if (!(std::fabs(det) > 1e-15)) {
+        delete s;
+        return fail(NSN_EINVAL, "env " + std::to_string(e) + ": tet " + std::to_string(t) + " has a degenerate rest shape");
+      }
+      double Di[9];
+      Di[0] = (Dm[4] * Dm[8] - Dm[5] * Dm[7]) / det; Di[1] = (Dm[2] * Dm[7] - Dm[1] * Dm[8]) / det;
+      Di[2] = (Dm[1] * Dm[5] - Dm[2] * Dm[4]) / det; Di[3] = (Dm[5] * Dm[6] - Dm[3] * Dm[8]) / det;
+      Di[4] = (Dm[0] * Dm[8] - Dm[2] * Dm[6]) / det; Di[5] = (Dm[2] * Dm[3] - Dm[0] * Dm[5]) / det;
+      Di[6] = (Dm[3] * Dm[7] - Dm[4] * Dm[6]) / det; Di[7] = (Dm[1] * Dm[6] - Dm[0] * Dm[7]) / det;
+      Di[8] = (Dm[0] * Dm[4] - Dm[1] * Dm[3]) / det;
+      for (int k = 0; k < 9; ++k) t_Dminv[(size_t)k * z.NT + g] = (float)Di[k];
+      const double Ve = std::fabs(det) / 6.0;
+      const double E = d.tet_material[3 * t], nu = d.tet_material[3 * t + 1], rho = d.tet_material[3 * t + 2];
+      // READING of the material constants: C1 = mu/2, D1 = (lambda+mu)/2, alpha = 1 + mu/(lambda+mu)
+      const double mu = E / (2.0 * (1.0 + nu)), la = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+      t_mat[g] = make_float4((float)Ve, (float)(0.5 * mu), (float)(0.5 * (la + mu)), (float)(1.0 + mu / (la + mu)));
+      // READING: lumped particle mass rho V_e / 4 per vertex (Sec. 9.3)
+      for (int k = 0; k < 4; ++k) p_m[po + id[k]] += (float)(rho * Ve / 4.0);
+    }
+    for (int i = 0; i < h.n_par; ++i)
+      if (!(p_m[po + i] > 0.f)) {
+        delete s;
+        return fail(NSN_EINVAL, "env " + std::to_string(e) + ": particle " + std::to_string(i) + " has no mass");
+      }
+    for (int j = 0; j < h.n_jnt; ++j) {
+      const int g = jo + j;
+      const int A = d.joint_body[2 * j], B = d.joint_body[2 * j + 1];
+      const float *dr = d.joint_drive + 6 * j;
+      const int has_drive = (dr[0] != 0.f || dr[1] != 0.f) ? 1 : 0;
+      j_info[g] = make_int4(d.joint_type[j], A >= 0 ? ro + A : -1, ro + B, has_drive);
+      const float *an = d.joint_anchor + 6 * j, *ax = d.joint_axis + 6 * j, *rf = d.joint_ref + 6 * j;
+      j_frame[6 * g + 0] = make_float4(an[0], an[1], an[2], 0.f);
+      j_frame[6 * g + 1] = make_float4(an[3], an[4], an[5], 0.f);
+      j_frame[6 * g + 2] = make_float4(ax[0], ax[1], ax[2], 0.f);
+      j_frame[6 * g + 3] = make_float4(ax[3], ax[4], ax[5], 0.f);
+      j_frame[6 * g + 4] = make_float4(rf[0], rf[1], rf[2], 0.f);
+      j_frame[6 * g + 5] = make_float4(rf[3], rf[4], rf[5], 0.f);
+      j_drive[2 * g] = make_float4(dr[0], dr[1], dr[2], dr[3]);
+      j_drive[2 * g + 1] = make_float4(dr[4], dr[5], 0.f, 0.f);
+    }
+    ro += h.n_rig; po += h.n_par; to += h.n_tet; jo += h.n_jnt; co += h.max_con;
+    rowo += E.row_cap; dofo += E.n_dof;
+  }
+  // static adjacency: particle -> (tet, slot) and rigid -> (joint, side), in element order
+  for (int t = 0; t < z.NT; ++t) {
+    const int4 id = t_ids[t];
+    tadj_ptr[id.x + 1]++; tadj_ptr[id.y + 1]++; tadj_ptr[id.z + 1]++; tadj_ptr[id.w + 1]++;
+  }
+  for (int i = 0; i < z.NP; ++i) tadj_ptr[i + 1] += tadj_ptr[i];
+  {
+    std::vector<int> fill(tadj_ptr.begin(), tadj_ptr.end() - 1);
+    for (int t = 0; t < z.NT; ++t) {
+      const int ids[4] = {t_ids[t].x, t_ids[t].y, t_ids[t].z, t_ids[t].w};
+      for (int k = 0; k < 4; ++k) tadj[fill[ids[k]]++] = (t << 2) | k;
+    }
+  }
+  for (int j = 0; j < z.NJ; ++j) {
+    if (j_info[j].y >= 0) jadj_ptr[j_info[j].y + 1]++;
+    jadj_ptr[j_info[j].z + 1]++;
+  }
+  for (int i = 0; i < z.NR; ++i) jadj_ptr[i + 1] += jadj_ptr[i];
+  {
+    std::vector<int> fill(jadj_ptr.begin(), jadj_ptr.end() - 1);
+    for (int j = 0; j < z.NJ; ++j) {
+      if (j_info[j].y >= 0) jadj[fill[j_info[j].y]++] = (j << 1) | 0;
+      jadj[fill[j_info[j].z]++] = (j << 1) | 1;
+    }
+  }
+  // launch order: most work first (longest-processing-time first)
+  std::vector<int> order(n_envs);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const long long wa = (long long)env[a].row_cap + env[a].n_dof, wb = (long long)env[b].row_cap + env[b].n_dof;
+    return wa > wb;
+  });
+
+  // ---- upload ----
+  hipStream_t st_ = s->stream;
+  HIP_TRY(hipMemsetAsync(workspace, 0, need - 256, st_));
+  auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+    if (!bytes) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st_);
+  };
+  HIP_TRY(up(env_dev, env.data(), sizeof(EnvInfo) * n_envs));
+  HIP_TRY(up(order_dev, order.data(), sizeof(int) * n_envs));
+  HIP_TRY(up(S.r_x, r_x.data(), sizeof(float4) * z.NR));
+  HIP_TRY(up(S.r_q, r_q.data(), sizeof(float4) * z.NR));
+  HIP_TRY(up(S.r_v, r_v.data(), sizeof(float4) * z.NR));
+  HIP_TRY(up(S.r_w, r_w.data(), sizeof(float4) * z.NR));
+  HIP_TRY(up((void *)S.r_inertia, r_in.data(), sizeof(float4) * z.NR));
+  HIP_TRY(up((void *)S.r_ext, r_ext.data(), sizeof(float4) * z.NR));
+  HIP_TRY(up((void *)S.r_shape, r_shape.data(), sizeof(int) * z.NR));
+  HIP_TRY(up(S.p_x, p_x.data(), sizeof(float4) * z.NP));
+  HIP_TRY(up(S.p_v, p_v.data(), sizeof(float4) * z.NP));
+  HIP_TRY(up((void *)S.p_m, p_m.data(), sizeof(float) * z.NP));
+  HIP_TRY(up((void *)S.feat, feat.data(), sizeof(int2) * z.NF));
+  HIP_TRY(up((void *)S.t_ids, t_ids.data(), sizeof(int4) * z.NT));
+  HIP_TRY(up((void *)S.t_Dminv, t_Dminv.data(), sizeof(float) * 9 * (size_t)z.NT));
+  HIP_TRY(up((void *)S.t_mat, t_mat.data(), sizeof(float4) * z.NT));
+  HIP_TRY(up((void *)S.j_info, j_info.data(), sizeof(int4) * z.NJ));
+  HIP_TRY(up((void *)S.j_frame, j_frame.data(), sizeof(float4) * 6 * (size_t)z.NJ));
+  HIP_TRY(up((void *)S.j_drive, j_drive.data(), sizeof(float4) * 2 * (size_t)z.NJ));
+  HIP_TRY(up((void *)S.p_tadj_ptr, tadj_ptr.data(), sizeof(int) * (z.NP + 1)));
+  HIP_TRY(up((void *)S.p_tadj, tadj.data(), sizeof(int) * z.NTADJ));
+  HIP_TRY(up((void *)S.r_jadj_ptr, jadj_ptr.data(), sizeof(int) * (z.NR + 1)));
+  HIP_TRY(up((void *)S.r_jadj, jadj.data(), sizeof(int) * z.NJADJ));
+  HIP_TRY(hipStreamSynchronize(st_));
+
+  s->env = env;
+  s->order = order;
+  s->desc_sizes.assign(envs, envs + n_envs);
+  for (auto &d : s->desc_sizes) {
+    d.rigid_mass = d.rigid_inertia = d.rigid_x = d.rigid_q = d.rigid_v = d.rigid_w = d.rigid_extent = nullptr;
+    d.rigid_shape = nullptr;
+    d.particle_x = d.particle_v = d.particle_rest = d.particle_mass = nullptr;
+    d.tet_ids = nullptr; d.tet_material = nullptr;
+    d.joint_type = d.joint_body = nullptr;
+    d.joint_anchor = d.joint_axis = d.joint_ref = d.joint_drive = nullptr;
+  }
+  // default schedule: one launch; block size from the largest env
+  int max_el = 0;
+  for (auto &E : env) max_el = std::max(max_el, E.n_jnt + E.n_tet + E.max_con + E.n_rig + E.n_par);
+  int block = 64;
+  while (block < 256 && block * 4 < max_el) block *= 2;
+  s->buckets = {Bucket{0, n_envs, block}};
+  s->use_graphs = s->stream != nullptr;
+  *out = s;
+  return NSN_OK;
+}
+
+nsn_status nsn_destroy_scene(nsn_scene s) {
+  if (!s) return NSN_OK;
+  for (auto &kv : s->graphs) hipGraphExecDestroy(kv.second);
+  delete s;
+  return NSN_OK;
+}
+
+nsn_status nsn_set_params(nsn_scene s, const nsn_solver_params *p) {
+  if (!s || !p) return fail(NSN_EINVAL, "nsn_set_params: bad arguments");
+  if (p->ncp < 0 || p->ncp > 1 || p->rmode < 0 || p->rmode > 2 || p->warm < 0 || p->warm > 2 ||
+      p->fem_mode < 0 || p->fem_mode > 1 || !(p->damping > 0.f) || !(p->eps >= 0.f) || !(p->margin >= 0.f))
+    return fail(NSN_EINVAL, "bad solver parameters");
+  if (p->warm == NSN_WARM_LEARNED && !s->S.have_mlp) return fail(NSN_ESTATE, "learned warm start needs nsn_set_warm_start_model first");
+  s->p = *p;
+  for (auto &kv : s->graphs) hipGraphExecDestroy(kv.second);
+  s->graphs.clear();
+  return NSN_OK;
+}
+
+static hipError_t enqueue_step(nsn_scene s, const StepArgs &a) {
+  hipError_t e = launch_prepare(s->S, a, s->want_features || a.p.warm == NSN_WARM_LEARNED, s->stream);
+  if (e != hipSuccess) return e;
+  if (a.p.warm == NSN_WARM_LEARNED) {
+    e = launch_warm_mlp(s->S, s->stream);
+    if (e != hipSuccess) return e;
+  }
+  for (const Bucket &b : s->buckets) {
+    e = launch_newton(s->S, a, b.block, b.first, b.count, s->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+nsn_status nsn_step(nsn_scene s, double h, int32_t newton_iters, int32_t cr_iters, double tol) {
+  if (!s) return fail(NSN_EINVAL, "nsn_step: null scene");
+  if (!(h > 0.0) || newton_iters < 0 || cr_iters < 0 || !(tol >= 0.0)) return fail(NSN_EINVAL, "nsn_step: bad h, iteration counts or tol");
+  StepArgs a;
+  a.h = (float)h;
+  a.newton_iters = newton_iters;
+  a.cr_iters = cr_iters;
+  a.tol = (float)tol;
+  a.p = s->p;
+  if (!s->use_graphs) {
+    HIP_TRY(enqueue_step(s, a));
+    return NSN_OK;
+  }
+  GraphKey k{a.h, newton_iters, cr_iters, a.tol};
+  auto it = s->graphs.find(k);
+  if (it == s->graphs.end()) {
+    hipGraph_t graph;
+    HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = enqueue_step(s, a);
+    hipError_t ce = hipStreamEndCapture(s->stream, &graph);
+    if (le != hipSuccess) return fail(NSN_EDEVICE, std::string("capture: ") + hipGetErrorString(le));
+    if (ce != hipSuccess) return fail(NSN_EDEVICE, std::string("end capture: ") + hipGetErrorString(ce));
+    hipGraphExec_t exec;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(NSN_EDEVICE, std::string("instantiate: ") + hipGetErrorString(ie));
+    it = s->graphs.emplace(k, exec).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, s->stream));
+  return NSN_OK;
+}
+
+nsn_status nsn_get_stats(nsn_scene s, nsn_step_stats *out) {
+  if (!s || !out) return fail(NSN_EINVAL, "nsn_get_stats: bad arguments");
+  HIP_TRY(hipMemcpyAsync(out, s->S.stats, sizeof(nsn_step_stats) * s->S.n_envs, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return NSN_OK;
+}
+
+static nsn_status check_env(nsn_scene s, int env) {
+  if (!s) return fail(NSN_EINVAL, "null scene");
+  if (env < 0 || env >= s->S.n_envs) return fail(NSN_EINVAL, "env index out of range");
+  return NSN_OK;
+}
+
+static hipError_t d2h_f4(float *dst, const float4 *src, int n, int ncomp, hipStream_t st) {
+  if (!dst || n <= 0) return hipSuccess;
+  std::vector<float4> tmp(n);
+  hipError_t e = hipMemcpyAsync(tmp.data(), src, sizeof(float4) * n, hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < n; ++i) {
+    const float v[4] = {tmp[i].x, tmp[i].y, tmp[i].z, tmp[i].w};
+    for (int k = 0; k < ncomp; ++k) dst[ncomp * i + k] = v[k];
+  }
+  return hipSuccess;
+}
+
+nsn_status nsn_read_state(nsn_scene s, int32_t env, float *rigid_x, float *rigid_q, float *rigid_v,
+                          float *rigid_w, float *particle_x, float *particle_v, double *time) {
+  nsn_status st = check_env(s, env);
+  if (st) return st;
+  const EnvInfo &E = s->env[env];
+  const DevScene &S = s->S;
+  HIP_TRY(d2h_f4(rigid_x, S.r_x + E.rig_off, E.n_rig, 3, s->stream));
+  HIP_TRY(d2h_f4(rigid_q, S.r_q + E.rig_off, E.n_rig, 4, s->stream));
+  HIP_TRY(d2h_f4(rigid_v, S.r_v + E.rig_off, E.n_rig, 3, s->stream));
+  HIP_TRY(d2h_f4(rigid_w, S.r_w + E.rig_off, E.n_rig, 3, s->stream));
+  HIP_TRY(d2h_f4(particle_x, S.p_x + E.par_off, E.n_par, 3, s->stream));
+  HIP_TRY(d2h_f4(particle_v, S.p_v + E.par_off, E.n_par, 3, s->stream));
+  if (time) {
+    HIP_TRY(hipMemcpyAsync(time, S.time + env, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  return NSN_OK;
+}
+
+static hipError_t h2d_f4(float4 *dst, const float *src, int n, int ncomp, hipStream_t st, bool normalize_q) {
+  if (!src || n <= 0) return hipSuccess;
+  std::vector<float4> tmp(n);
+  for (int i = 0; i < n; ++i) {
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < ncomp; ++k) v[k] = src[ncomp * i + k];
+    if (normalize_q) {
+      const float l = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3]);
+      for (int k = 0; k < 4; ++k) v[k] /= l;
+    }
+    tmp[i] = make_float4(v[0], v[1], v[2], v[3]);
+  }
+  hipError_t e = hipMemcpyAsync(dst, tmp.data(), sizeof(float4) * n, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(st);  // the staging vector dies on return
+}
+
+nsn_status nsn_write_state(nsn_scene s, int32_t env, const float *rigid_x, const float *rigid_q,
+                           const float *rigid_v, const float *rigid_w, const float *particle_x,
+                           const float *particle_v, const double *time) {
+  nsn_status st = check_env(s, env);
+  if (st) return st;
+  const EnvInfo &E = s->env[env];
+  DevScene &S = s->S;
+  const nsn_env_desc &d = s->desc_sizes[env];
+  (void)d;
+  HIP_TRY(h2d_f4(S.r_x + E.rig_off, rigid_x, E.n_rig, 3, s->stream, false));
+  HIP_TRY(h2d_f4(S.r_q + E.rig_off, rigid_q, E.n_rig, 4, s->stream, true));
+  // static bodies keep zero velocity
+  if (rigid_v || rigid_w) {
+    std::vector<float4> inr(E.n_rig);
+    HIP_TRY(hipMemcpyAsync(inr.data(), S.r_inertia + E.rig_off, sizeof(float4) * E.n_rig, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    std::vector<float> v(rigid_v ? rigid_v : rigid_w, (rigid_v ? rigid_v : rigid_w) + 3 * E.n_rig);
+    if (rigid_v) {
+      std::vector<float> vv(rigid_v, rigid_v + 3 * E.n_rig);
+      for (int i = 0; i < E.n_rig; ++i)
+        if (inr[i].w == 0.f) vv[3 * i] = vv[3 * i + 1] = vv[3 * i + 2] = 0.f;
+      HIP_TRY(h2d_f4(S.r_v + E.rig_off, vv.data(), E.n_rig, 3, s->stream, false));
+    }
+    if (rigid_w) {
+      std::vector<float> ww(rigid_w, rigid_w + 3 * E.n_rig);
+      for (int i = 0; i < E.n_rig; ++i)
+        if (inr[i].w == 0.f) ww[3 * i] = ww[3 * i + 1] = ww[3 * i + 2] = 0.f;
+      HIP_TRY(h2d_f4(S.r_w + E.rig_off, ww.data(), E.n_rig, 3, s->stream, false));
+    }
+  }
+  HIP_TRY(h2d_f4(S.p_x + E.par_off, particle_x, E.n_par, 3, s->stream, false));
+  HIP_TRY(h2d_f4(S.p_v + E.par_off, particle_v, E.n_par, 3, s->stream, false));
+  if (time) {
+    HIP_TRY(hipMemcpyAsync(S.time + env, time, sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  return NSN_OK;
+}
+
+nsn_status nsn_read_contacts(nsn_scene s, int32_t env, int32_t cap, int32_t *n, int32_t *keys, int32_t *bodies,
+                             float *geom, float *lam) {
+  nsn_status st = check_env(s, env);
+  if (st) return st;
+  if (!n || cap < 0) return fail(NSN_EINVAL, "nsn_read_contacts: bad arguments");
+  const EnvInfo &E = s->env[env];
+  const DevScene &S = s->S;
+  int nc = 0;
+  HIP_TRY(hipMemcpyAsync(&nc, S.n_con + env, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  *n = nc;
+  const int m = std::min(nc, cap);
+  if (m <= 0) return NSN_OK;
+  std::vector<int> k(m);
+  std::vector<int2> b(m);
+  std::vector<float4> nn(m), aa(m), bb(m), ll(m);
+  HIP_TRY(hipMemcpyAsync(k.data(), S.c_key + E.con_off, sizeof(int) * m, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipMemcpyAsync(b.data(), S.c_body + E.con_off, sizeof(int2) * m, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipMemcpyAsync(nn.data(), S.c_n + E.con_off, sizeof(float4) * m, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipMemcpyAsync(aa.data(), S.c_aL + E.con_off, sizeof(float4) * m, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipMemcpyAsync(bb.data(), S.c_bL + E.con_off, sizeof(float4) * m, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipMemcpyAsync(ll.data(), S.c_prev_lam + E.con_off, sizeof(float4) * m, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (int i = 0; i < m; ++i) {
+    if (keys) keys[i] = k[i];
+    if (bodies) { bodies[2 * i] = b[i].x; bodies[2 * i + 1] = b[i].y; }
+    if (geom) {
+      float *g = geom + 10 * i;
+      g[0] = nn[i].x; g[1] = nn[i].y; g[2] = nn[i].z;
+      g[3] = aa[i].x; g[4] = aa[i].y; g[5] = aa[i].z;
+      g[6] = bb[i].x; g[7] = bb[i].y; g[8] = bb[i].z;
+      g[9] = nn[i].w;
+    }
+    if (lam) { lam[3 * i] = ll[i].x; lam[3 * i + 1] = ll[i].y; lam[3 * i + 2] = ll[i].z; }
+  }
+  return NSN_OK;
+}
+
+nsn_status nsn_read_lambda(nsn_scene s, int32_t env, int32_t cap, int32_t *n, float *lam) {
+  nsn_status st = check_env(s, env);
+  if (st) return st;
+  if (!n || cap < 0) return fail(NSN_EINVAL, "nsn_read_lambda: bad arguments");
+  const EnvInfo &E = s->env[env];
+  int nc = 0;
+  HIP_TRY(hipMemcpyAsync(&nc, s->S.n_con + env, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  const int rows = 6 * E.n_jnt + 3 * E.n_tet + 3 * nc;
+  *n = rows;
+  const int m = std::min(rows, cap);
+  if (m > 0 && lam) {
+    HIP_TRY(hipMemcpyAsync(lam, s->S.row_lam + E.row_off, sizeof(float) * m, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  return NSN_OK;
+}
+
+nsn_status nsn_set_warm_start_model(nsn_scene s, const float *blob, int64_t n) {
+  if (!s || !blob || n != kMlpBlob) return fail(NSN_EINVAL, "warm-start model must hold " + std::to_string(kMlpBlob) + " floats");
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(blob[i])) return fail(NSN_EINVAL, "warm-start model has non-finite values");
+  HIP_TRY(hipMemcpyAsync((void *)s->S.mlp, blob, sizeof(float) * n, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->S.have_mlp = 1;
+  for (auto &kv : s->graphs) hipGraphExecDestroy(kv.second);
+  s->graphs.clear();
+  return NSN_OK;
+}
+
+nsn_status nsn_read_features(nsn_scene s, int32_t env, int32_t cap, int32_t *n, float *feat) {
+  nsn_status st = check_env(s, env);
+  if (st) return st;
+  if (!n || cap < 0) return fail(NSN_EINVAL, "nsn_read_features: bad arguments");
+  if (!s->want_features && s->p.warm != NSN_WARM_LEARNED)
+    return fail(NSN_ESTATE, "features are only computed after nsn_enable_features(scene, 1) or in learned mode");
+  const EnvInfo &E = s->env[env];
+  int nc = 0;
+  HIP_TRY(hipMemcpyAsync(&nc, s->S.n_con + env, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  *n = nc;
+  const int m = std::min(nc, cap);
+  if (m > 0 && feat) {
+    HIP_TRY(hipMemcpyAsync(feat, s->S.c_feat + (size_t)E.con_off * 12, sizeof(float) * 12 * m, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  return NSN_OK;
+}
+
+// ---- extras used by the Python layer (declared in include/nsn_ext.h) ----
+nsn_status nsn_enable_features(nsn_scene s, int32_t on) {
+  if (!s) return fail(NSN_EINVAL, "null scene");
+  s->want_features = on ? 1 : 0;
+  for (auto &kv : s->graphs) hipGraphExecDestroy(kv.second);
+  s->graphs.clear();
+  return NSN_OK;
+}
+
+nsn_status nsn_set_use_graphs(nsn_scene s, int32_t on) {
+  if (!s) return fail(NSN_EINVAL, "null scene");
+  s->use_graphs = on && s->stream != nullptr;
+  return NSN_OK;
+}
+
+nsn_status nsn_get_env_order(nsn_scene s, int32_t *order) {
+  if (!s || !order) return fail(NSN_EINVAL, "bad arguments");
+  std::copy(s->order.begin(), s->order.end(), order);
+  return NSN_OK;
+}
+
+nsn_status nsn_set_schedule(nsn_scene s, int32_t n_buckets, const int32_t *first, const int32_t *count,
+                            const int32_t *block) {
+  if (!s || n_buckets < 1 || !first || !count || !block) return fail(NSN_EINVAL, "bad schedule");
+  std::vector<Bucket> b;
+  int expect = 0;
+  for (int i = 0; i < n_buckets; ++i) {
+    if (first[i] != expect || count[i] < 0) return fail(NSN_EINVAL, "schedule buckets must tile the env order");
+    const int bl = block[i];
+    if (bl != 64 && bl != 128 && bl != 256 && bl != 512 && bl != 1024) return fail(NSN_EINVAL, "block size must be 64..1024 (power of two)");
+    b.push_back(Bucket{first[i], count[i], bl});
+    expect += count[i];
+  }
+  if (expect != s->S.n_envs) return fail(NSN_EINVAL, "schedule must cover every env");
+  s->buckets = b;
+  for (auto &kv : s->graphs) hipGraphExecDestroy(kv.second);
+  s->graphs.clear();
+  return NSN_OK;
+}
+
+nsn_status nsn_get_schedule(nsn_scene s, int32_t cap, int32_t *n, int32_t *first, int32_t *count, int32_t *block) {
+  if (!s || !n) return fail(NSN_EINVAL, "bad arguments");
+  *n = (int)s->buckets.size();
+  for (int i = 0; i < std::min<int>(cap, *n); ++i) {
+    first[i] = s->buckets[i].first;
+    count[i] = s->buckets[i].count;
+    block[i] = s->buckets[i].block;
+  }
+  return NSN_OK;
+}
+
+// device pointer of the per-env stats array (for asynchronous readers)
+nsn_status nsn_stats_device_ptr(nsn_scene s, void **ptr) {
+  if (!s || !ptr) return fail(NSN_EINVAL, "bad arguments");
+  *ptr = s->S.stats;
+  return NSN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,129 @@
+// Device-side layout of a scene: per-env tables and the structure-of-arrays
+// buffers that live in the caller's workspace.  Shared by the host builder
+// (nsn_api.cpp) and the kernels (nsn_step.hip, nsn_mlp.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/nsn.h"
+
+namespace nsn {
+
+constexpr int kMlpIn = 12;
+constexpr int kMlpHidden = 64;
+constexpr int kMlpOut = 3;
+constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + 2 * (kMlpHidden * kMlpHidden + kMlpHidden) +
+                           kMlpOut * kMlpHidden + kMlpOut;  // 9347
+constexpr int kMlpBlob = kMlpParams + 2 * kMlpIn + 2 * kMlpOut;
+
+// Per-environment table (read once per workgroup).
+struct EnvInfo {
+  int rig_off, n_rig;      // rigid bodies [rig_off, rig_off + n_rig)
+  int par_off, n_par;      // particles
+  int tet_off, n_tet;      // tetrahedra
+  int jnt_off, n_jnt;      // joints
+  int con_off, max_con;    // contact slots
+  int row_off, row_cap;    // rows: joints (6 each), tets (3 each), contacts (3 each)
+  int dof_off, n_dof;      // body space: 6 per rigid body, 3 per particle
+  int feat_off, n_feat;    // rigid collision features (box vertices, capsule ends)
+  int n_targets, ground;   // (ground ? 1 : 0) + n_rig
+  int bcon_off, pad0;      // target-side contact lists
+  float mu, gx, gy, gz;
+};
+
+// Pointers into the workspace.  Indices stored in the tables are global
+// (already offset by the env's base) unless noted.
+struct DevScene {
+  int n_envs;
+  int NR, NP, NT, NJ, NC, NROW, NDOF;  // totals over all envs
+  const EnvInfo *env;
+  const int *env_order;  // envs sorted by decreasing work (launch order)
+
+  // rigid bodies
+  float4 *r_x, *r_q, *r_v, *r_w;  // state at the end of the last step
+  float4 *r_x0, *r_q0;             // state at the start of the current step
+  const float4 *r_inertia;         // (Ix, Iy, Iz, 1/m), 1/m = 0 for static bodies
+  const float4 *r_ext;             // shape extents
+  const int *r_shape;
+  float *r_Iw, *r_Iwinv;           // world inertia / inverse, 6 per body (xx yy zz xy xz yz)
+  float *r_ut, *r_u;               // u~ and the Newton iterate, 6 per body (v, omega)
+
+  // particles
+  float4 *p_x, *p_v, *p_x0;
+  const float *p_m;                // lumped mass
+  float4 *p_ut, *p_u, *p_uprev, *p_H;
+
+  // collision features of rigid bodies: (body, vertex)
+  const int2 *feat;
+
+  // tets (component-major SoA)
+  const int4 *t_ids;
+  const float *t_Dminv;            // 9 x NT
+  const float4 *t_mat;             // (Ve, C1, D1, alpha)
+  float *t_J;                      // 2 x 18 x NT : u_i(3), w_i(3) per stretch row, ping-pong
+  float *t_E;                      // 6 x NT : E (xx yy zz xy xz yz)
+
+  // joints
+  const int4 *j_info;              // (type, A global or -1, B global, has_drive)
+  const float4 *j_frame;           // 6 per joint: pA, pB, aA, aB, tA, tB
+  const float4 *j_drive;           // 2 per joint: (kp, kd, amp, freq), (phase, offset, -, -)
+  float *j_theta0;                 // drive coordinate at q^-
+  float *j_J;                      // NJ x 6 rows x 12 (J_A, J_B)
+
+  // contacts (capacity NC)
+  int *c_key;
+  int2 *c_body;                    // (feature body, target body): env-local numbering,
+                                   // rigid i -> i, particle p -> n_rig + p, ground -> -1
+  float4 *c_n;                     // normal, thickness
+  float4 *c_aL, *c_bL;             // feature / target points (body frame or world)
+  float4 *c_rA, *c_rB;             // world arms at the current iterate
+  float *c_alpha;                  // 2 x NC ping-pong (normal row scale alpha)
+  int *c_active;                   // 2 x NC ping-pong (friction rows active)
+  float4 *c_lam0;                  // warm-start multipliers
+  float *c_feat;                   // NC x 12 features (contact-major)
+  int *c_prev_key;                 // last step's contacts (sorted keys) and multipliers
+  float4 *c_prev_lam;
+  int *n_prev;
+
+  // contact adjacency (rebuilt every step)
+  int *r_acon_beg, *r_acon_end;    // rigid body as feature body: contact range
+  int *p_acon_beg, *p_acon_end;    // particle as feature body
+  int *r_bcon_beg, *r_bcon_cnt;    // rigid body as target: range in bcon_list
+  int *bcon_list;                  // contact indices (global)
+
+  // static adjacency
+  const int *p_tadj_ptr, *p_tadj;  // particle -> (tet << 2 | slot)
+  const int *r_jadj_ptr, *r_jadj;  // rigid body -> (joint << 1 | side)
+
+  // rows (capacity NROW)
+  float *row_lam, *row_x, *row_z, *row_p, *row_q, *row_w, *row_err, *row_P, *row_C, *row_b;
+
+  // body space (NDOF)
+  float *y, *g, *f;
+
+  // per env dynamic
+  int *n_con, *overflow;
+  double *time;
+  nsn_step_stats *stats;
+
+  // learned warm start
+  const float *mlp;
+  int have_mlp;
+};
+
+struct StepArgs {
+  float h;
+  int newton_iters, cr_iters;
+  float tol;
+  nsn_solver_params p;
+};
+
+// kernel launchers (nsn_step.hip)
+hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_features, hipStream_t st);
+// envs S.env_order[first .. first+count) with `block` threads per workgroup
+hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count,
+                         hipStream_t st);
+// learned warm start: MLP prediction for every contact of every env (nsn_mlp.hip)
+hipError_t launch_warm_mlp(const DevScene &s, hipStream_t st);
+
+}  // namespace nsn

@@ -1,0 +1,1599 @@
+// Persistent per-environment kernels of the non-smooth Newton step (gfx950).
+//
+// One workgroup owns one environment for the whole time step: collision
+// detection, start iterate, every Newton iteration (assembly, momentum residual,
+// geometric stiffness, residual check, Schur right-hand side, M PCR iterations,
+// update).  Environments of a batch are independent, so a launch of one
+// workgroup per env keeps every CU busy without grid-wide synchronisation; the
+// per-env PCR scalars and early exit fall out naturally.
+//
+// Paper: Macklin et al., "Non-Smooth Newton Methods for Deformable Multi-Body
+// Dynamics" (TOG 2019).  Section / equation references in the comments.
+//
+// Scatter J^T v (rows -> bodies) is a pull over CSR-ordered adjacency: every body
+// sums the contributions of its incident rows in a fixed order (no atomics, so
+// results are bitwise reproducible).  Gather J y (bodies -> rows) is a per-element
+// read of the body-space vector.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "nsn_layout.h"
+#include "nsn_math.h"
+
+namespace nsn {
+
+constexpr float kTauGS = 1e-6f;     // secant smoothing velocity (m/s)
+constexpr float kKappaW = 1e-4f;    // floor of the FB friction denominator (relative)
+constexpr float kClampFem = 1e-3f;  // eigenvalue floor of the material Hessian (relative to 2 C1 Ve)
+constexpr int kJacobiSweeps = 6;
+
+// --------------------------------------------------------------------------
+// block-level reductions (fixed order -> deterministic)
+// --------------------------------------------------------------------------
+template <int BS>
+struct Red {
+  static constexpr int NW = BS / 64;
+  double d[2][NW > 0 ? NW : 1];
+  float f[2][NW > 0 ? NW : 1];
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int BS>
+__device__ __forceinline__ double block_sum(double v, Red<BS> &r, int slot) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) r.d[slot][w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < Red<BS>::NW; ++i) s += r.d[slot][i];
+  return s;
+}
+
+template <int BS>
+__device__ __forceinline__ float block_max(float v, Red<BS> &r, int slot) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) r.f[slot][w] = v;
+  __syncthreads();
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < Red<BS>::NW; ++i) s = fmaxf(s, r.f[slot][i]);
+  return s;
+}
+
+// exclusive rank of a 0/1 flag within the block; *total = block count
+template <int BS>
+__device__ __forceinline__ int block_rank(int flag, int *s_wave, int *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(flag);
+  const int in_wave = __popcll(m & ((1ull << lane) - 1ull));
+  if (lane == 0) s_wave[w] = __popcll(m);
+  __syncthreads();
+  int before = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < BS / 64; ++i) {
+    int c = s_wave[i];
+    before += i < w ? c : 0;
+    tot += c;
+  }
+  *total = tot;
+  return before + in_wave;
+}
+
+// --------------------------------------------------------------------------
+// NCP functions (Sec. 4, Appendix A)
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void ncp_fb(float C, float lam, float r, float &phi, float &al, float &be) {
+  const float rl = r * lam;
+  const float rho = sqrtf(C * C + rl * rl);
+  phi = C + rl - rho;
+  if (rho > 0.f) {
+    al = 1.f - C / rho;
+    be = 1.f - rl / rho;
+  } else {  // subgradient choice at (0,0), Sec. 4.2
+    al = 0.f;
+    be = 1.f;
+  }
+}
+
+__device__ __forceinline__ void ncp_min(float C, float lam, float r, float &phi, float &al, float &be) {
+  if (C <= r * lam) {
+    phi = C; al = 1.f; be = 0.f;
+  } else {
+    phi = r * lam; al = 0.f; be = 1.f;
+  }
+}
+
+// Friction compliance W (Sec. 4.3 eq. friction_w, Appendix A.2) with the velocity
+// magnitude unsquared, a cancellation-free fixed-point numerator and the
+// denominator floored at kKappaW r mu lam_n.
+__device__ __forceinline__ float friction_w(int ncp, float vn, float lam_n, float lfn, float mu, float r) {
+  const float s = mu * lam_n - lfn;
+  if (ncp == NSN_NCP_MIN) {
+    if (vn <= r * s) return 0.f;
+    return (vn - r * s) / (mu * lam_n);
+  }
+  const float root = sqrtf(vn * vn + r * r * s * s);
+  const float num = s > 0.f ? vn * vn / (root + r * s) : root - r * s;
+  float den = vn + r * lfn - num;
+  const float fl = kKappaW * r * mu * lam_n;
+  den = den < fl ? fl : den;
+  return r * num / den;
+}
+
+// --------------------------------------------------------------------------
+// 3x3 symmetric eigen-decomposition (cyclic Jacobi, fixed sweeps) and the
+// signed SVD of the deformation gradient (Sec. 9.2, Appendix B)
+// --------------------------------------------------------------------------
+__device__ void sym_eig3(const float *Ain, M3 &Q, float w[3]) {
+  float A[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) A[i] = Ain[i];
+  float V[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+  for (int sweep = 0; sweep < kJacobiSweeps; ++sweep) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int p = k == 2 ? 1 : 0;
+      const int q = k == 0 ? 1 : 2;
+      const float apq = A[3 * p + q];
+      if (apq == 0.f) continue;
+      const float theta = (A[3 * q + q] - A[3 * p + p]) / (2.f * apq);
+      float t = 1.f / (fabsf(theta) + sqrtf(theta * theta + 1.f));
+      if (theta < 0.f) t = -t;
+      const float c = 1.f / sqrtf(t * t + 1.f), s = t * c;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const float aip = A[3 * i + p], aiq = A[3 * i + q];
+        A[3 * i + p] = c * aip - s * aiq;
+        A[3 * i + q] = s * aip + c * aiq;
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const float apj = A[3 * p + j], aqj = A[3 * q + j];
+        A[3 * p + j] = c * apj - s * aqj;
+        A[3 * q + j] = s * apj + c * aqj;
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const float vip = V[3 * i + p], viq = V[3 * i + q];
+        V[3 * i + p] = c * vip - s * viq;
+        V[3 * i + q] = s * vip + c * viq;
+      }
+    }
+  }
+  float ev[3] = {A[0], A[4], A[8]};
+  int idx[3] = {0, 1, 2};
+  // stable descending sort of three entries
+  if (ev[idx[0]] < ev[idx[1]]) { int t = idx[0]; idx[0] = idx[1]; idx[1] = t; }
+  if (ev[idx[1]] < ev[idx[2]]) {
+    int t = idx[1]; idx[1] = idx[2]; idx[2] = t;
+    if (ev[idx[0]] < ev[idx[1]]) { t = idx[0]; idx[0] = idx[1]; idx[1] = t; }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int k = idx[c];
+    w[c] = k == 0 ? ev[0] : (k == 1 ? ev[1] : ev[2]);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) Q.m[3 * r + c] = k == 0 ? V[3 * r] : (k == 1 ? V[3 * r + 1] : V[3 * r + 2]);
+  }
+}
+
+__device__ __forceinline__ void tangent_basis(V3 n, V3 &d1, V3 &d2) {
+  // world axis with the smallest |n_i| (ties -> lowest index)
+  const float ax = fabsf(n.x), ay = fabsf(n.y), az = fabsf(n.z);
+  int k = 0;
+  float best = ax;
+  if (ay < best) { best = ay; k = 1; }
+  if (az < best) { k = 2; }
+  const V3 e = k == 0 ? mk(1.f, 0.f, 0.f) : (k == 1 ? mk(0.f, 1.f, 0.f) : mk(0.f, 0.f, 1.f));
+  d1 = cross(n, e);
+  const float l = norm(d1);
+  d1 = V3{d1.x / l, d1.y / l, d1.z / l};
+  d2 = cross(n, d1);
+}
+
+// F = U diag(s) V^T, det U = det V = +1, last stretch signed by det F.
+__device__ void svd3(const M3 &F, M3 &U, float s[3], M3 &V) {
+  float FtF[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      FtF[3 * i + j] = F.m[i] * F.m[j] + F.m[3 + i] * F.m[3 + j] + F.m[6 + i] * F.m[6 + j];
+  float w[3];
+  sym_eig3(FtF, V, w);
+  if (det3(V) < 0.f) { V.m[2] = -V.m[2]; V.m[5] = -V.m[5]; V.m[8] = -V.m[8]; }
+  const V3 b0 = mul(F, col(V, 0)), b1 = mul(F, col(V, 1)), b2 = mul(F, col(V, 2));
+  V3 u1, u2;
+  const float l1 = norm(b0);
+  u1 = l1 > 0.f ? V3{b0.x / l1, b0.y / l1, b0.z / l1} : mk(1.f, 0.f, 0.f);
+  const float pr = dot(u1, b1);
+  u2 = b1 - pr * u1;
+  const float l2 = norm(u2);
+  if (l2 > 1e-6f * (l1 > 0.f ? l1 : 1.f)) {
+    u2 = V3{u2.x / l2, u2.y / l2, u2.z / l2};
+  } else {
+    V3 t1, t2;
+    tangent_basis(u1, t1, t2);
+    u2 = t1;
+  }
+  const V3 u3 = cross(u1, u2);
+  U.m[0] = u1.x; U.m[3] = u1.y; U.m[6] = u1.z;
+  U.m[1] = u2.x; U.m[4] = u2.y; U.m[7] = u2.z;
+  U.m[2] = u3.x; U.m[5] = u3.y; U.m[8] = u3.z;
+  s[0] = dot(u1, b0);
+  s[1] = dot(u2, b1);
+  s[2] = dot(u3, b2);
+}
+
+// --------------------------------------------------------------------------
+// body helpers
+// --------------------------------------------------------------------------
+struct Ctx {
+  DevScene S;
+  EnvInfo E;
+  StepArgs A;
+};
+
+// world position of a body-fixed point (env-local body id; -1 = world / ground)
+__device__ __forceinline__ V3 body_point(const Ctx &c, int body, V3 loc) {
+  if (body < 0) return loc;
+  if (body < c.E.n_rig) {
+    const int g = c.E.rig_off + body;
+    return mk(c.S.r_x[g]) + mul(quat_mat(c.S.r_q[g]), loc);
+  }
+  return mk(c.S.p_x[c.E.par_off + body - c.E.n_rig]);
+}
+
+__device__ __forceinline__ V3 body_arm(const Ctx &c, int body, V3 loc) {
+  if (body < 0 || body >= c.E.n_rig) return mk(0.f, 0.f, 0.f);
+  return mul(quat_mat(c.S.r_q[c.E.rig_off + body]), loc);
+}
+
+__device__ __forceinline__ bool rigid_static(const Ctx &c, int body) {
+  return c.S.r_inertia[c.E.rig_off + body].w == 0.f;
+}
+
+// velocity of a point under a body-space vector stored per body (rigid: r_vec 6/body,
+// particle: p_vec float4)
+__device__ __forceinline__ V3 point_vel(const Ctx &c, const float *rvec, const float4 *pvec, int body, V3 arm) {
+  if (body < 0) return mk(0.f, 0.f, 0.f);
+  if (body < c.E.n_rig) {
+    const int g = c.E.rig_off + body;
+    const float *u = rvec + 6 * g;
+    return mk(u[0], u[1], u[2]) + cross(mk(u[3], u[4], u[5]), arm);
+  }
+  return mk(pvec[c.E.par_off + body - c.E.n_rig]);
+}
+
+// dof index of an env-local body
+__device__ __forceinline__ int body_dof(const EnvInfo &E, int body) {
+  return body < E.n_rig ? E.dof_off + 6 * body : E.dof_off + 6 * E.n_rig + 3 * (body - E.n_rig);
+}
+
+// velocity of a point under a dof-indexed body-space vector Y
+__device__ __forceinline__ V3 point_vel_dof(const Ctx &c, const float *Y, int body, V3 arm) {
+  if (body < 0) return mk(0.f, 0.f, 0.f);
+  const int d = body_dof(c.E, body);
+  if (body < c.E.n_rig) return mk(Y[d], Y[d + 1], Y[d + 2]) + cross(mk(Y[d + 3], Y[d + 4], Y[d + 5]), arm);
+  return mk(Y[d], Y[d + 1], Y[d + 2]);
+}
+
+// J_i M^-1 J_i^T contribution of a direction applied at an arm of one body
+__device__ __forceinline__ float effmass_dir(const Ctx &c, int body, V3 arm, V3 dir, bool use_H) {
+  if (body < 0) return 0.f;
+  if (body < c.E.n_rig) {
+    const int g = c.E.rig_off + body;
+    const float im = c.S.r_inertia[g].w;
+    if (im == 0.f) return 0.f;
+    const V3 ad = cross(arm, dir);
+    return im * dot(dir, dir) + dot(ad, sym_mul(c.S.r_Iwinv + 6 * g, ad));
+  }
+  const int p = c.E.par_off + body - c.E.n_rig;
+  if (use_H) {
+    const float4 H = c.S.p_H[p];
+    return dir.x * dir.x / H.x + dir.y * dir.y / H.y + dir.z * dir.z / H.z;
+  }
+  return dot(dir, dir) / c.S.p_m[p];
+}
+
+// --------------------------------------------------------------------------
+// joints (READING: the paper gives no joint formulas; revolute = 3 anchor rows +
+// 2 axis rows, prismatic = 2 point-on-axis rows + 3 orientation rows, optional
+// implicit-PD drive row)
+// --------------------------------------------------------------------------
+struct JFrame {
+  V3 PA, PB, rA, rB, a, t1, t2, b, s1, s2;
+};
+
+__device__ __forceinline__ JFrame joint_frame(const Ctx &c, int jg) {
+  const int4 info = c.S.j_info[jg];
+  const float4 *fr = c.S.j_frame + 6 * jg;
+  M3 RA = {{1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f}};
+  V3 xA = mk(0.f, 0.f, 0.f);
+  if (info.y >= 0) {
+    RA = quat_mat(c.S.r_q[info.y]);
+    xA = mk(c.S.r_x[info.y]);
+  }
+  const M3 RB = quat_mat(c.S.r_q[info.z]);
+  JFrame f;
+  f.rA = mul(RA, mk(fr[0]));
+  f.rB = mul(RB, mk(fr[1]));
+  f.PA = xA + f.rA;
+  f.PB = mk(c.S.r_x[info.z]) + f.rB;
+  f.a = mul(RA, mk(fr[2]));
+  f.t1 = mul(RA, mk(fr[4]));
+  f.t2 = cross(f.a, f.t1);
+  f.b = mul(RB, mk(fr[3]));
+  f.s1 = mul(RB, mk(fr[5]));
+  f.s2 = cross(f.b, f.s1);
+  return f;
+}
+
+__device__ __forceinline__ float joint_coordinate(const Ctx &c, int jg) {
+  const JFrame f = joint_frame(c, jg);
+  if (c.S.j_info[jg].x == NSN_JOINT_REVOLUTE) return atan2f(dot(f.a, cross(f.t1, f.s1)), dot(f.t1, f.s1));
+  return dot(f.a, f.PB - f.PA);
+}
+
+__device__ __forceinline__ void store_row(float *J, V3 la, V3 aa, V3 lb, V3 ab) {
+  J[0] = la.x; J[1] = la.y; J[2] = la.z; J[3] = aa.x; J[4] = aa.y; J[5] = aa.z;
+  J[6] = lb.x; J[7] = lb.y; J[8] = lb.z; J[9] = ab.x; J[10] = ab.y; J[11] = ab.z;
+}
+
+// Assemble the 6 rows of joint jg: J (world, per side), constraint values c[6].
+__device__ void joint_rows(const Ctx &c, int jg, float *J, float cval[6]) {
+  const int4 info = c.S.j_info[jg];
+  const JFrame f = joint_frame(c, jg);
+  const V3 z = mk(0.f, 0.f, 0.f);
+  if (info.x == NSN_JOINT_REVOLUTE) {
+    const V3 ex = mk(1.f, 0.f, 0.f), ey = mk(0.f, 1.f, 0.f), ez = mk(0.f, 0.f, 1.f);
+    const V3 E3[3] = {ex, ey, ez};
+    const V3 d = f.PA - f.PB;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      cval[k] = comp(d, k);
+      store_row(J + 12 * k, E3[k], cross(f.rA, E3[k]), -E3[k], -cross(f.rB, E3[k]));
+    }
+    const V3 t1b = cross(f.t1, f.b), t2b = cross(f.t2, f.b);
+    cval[3] = dot(f.t1, f.b);
+    store_row(J + 36, z, t1b, z, -t1b);
+    cval[4] = dot(f.t2, f.b);
+    store_row(J + 48, z, t2b, z, -t2b);
+    if (info.w) {
+      cval[5] = atan2f(dot(f.a, cross(f.t1, f.s1)), dot(f.t1, f.s1));
+      store_row(J + 60, z, -f.a, z, f.a);
+    } else {
+      cval[5] = 0.f;
+      store_row(J + 60, z, z, z, z);
+    }
+  } else {
+    const V3 d = f.PB - f.PA;
+    cval[0] = dot(f.t1, d);
+    store_row(J + 0, -f.t1, cross(f.t1, d) - cross(f.rA, f.t1), f.t1, cross(f.rB, f.t1));
+    cval[1] = dot(f.t2, d);
+    store_row(J + 12, -f.t2, cross(f.t2, d) - cross(f.rA, f.t2), f.t2, cross(f.rB, f.t2));
+    const V3 x0 = cross(f.t1, f.s2), x1 = cross(f.t2, f.b), x2 = cross(f.a, f.s1);
+    cval[2] = dot(f.t1, f.s2);
+    store_row(J + 24, z, x0, z, -x0);
+    cval[3] = dot(f.t2, f.b);
+    store_row(J + 36, z, x1, z, -x1);
+    cval[4] = dot(f.a, f.s1);
+    store_row(J + 48, z, x2, z, -x2);
+    if (info.w) {
+      cval[5] = dot(f.a, d);
+      store_row(J + 60, -f.a, cross(f.a, d) - cross(f.rA, f.a), f.a, cross(f.rB, f.a));
+    } else {
+      cval[5] = 0.f;
+      store_row(J + 60, z, z, z, z);
+    }
+  }
+  if (info.y < 0 || c.S.r_inertia[info.y].w == 0.f)
+    for (int r = 0; r < 6; ++r)
+      for (int k = 0; k < 6; ++k) J[12 * r + k] = 0.f;
+  if (c.S.r_inertia[info.z].w == 0.f)
+    for (int r = 0; r < 6; ++r)
+      for (int k = 6; k < 12; ++k) J[12 * r + k] = 0.f;
+}
+
+__device__ __forceinline__ float row_dot_rigid(const float *J6, const float *Y, int d) {
+  return J6[0] * Y[d] + J6[1] * Y[d + 1] + J6[2] * Y[d + 2] + J6[3] * Y[d + 3] + J6[4] * Y[d + 4] +
+         J6[5] * Y[d + 5];
+}
+
+__device__ __forceinline__ float rigid_quad(const Ctx &c, int g, const float *J6) {
+  const float im = c.S.r_inertia[g].w;
+  if (im == 0.f) return 0.f;
+  const V3 l = mk(J6[0], J6[1], J6[2]), a = mk(J6[3], J6[4], J6[5]);
+  return im * dot(l, l) + dot(a, sym_mul(c.S.r_Iwinv + 6 * g, a));
+}
+
+// --------------------------------------------------------------------------
+// element index space of an env: [joints | tets | contacts]
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int row_joint(const EnvInfo &E, int jl) { return E.row_off + 6 * jl; }
+__device__ __forceinline__ int row_tet(const EnvInfo &E, int tl) { return E.row_off + 6 * E.n_jnt + 3 * tl; }
+__device__ __forceinline__ int row_con(const EnvInfo &E, int cl) {
+  return E.row_off + 6 * E.n_jnt + 3 * E.n_tet + 3 * cl;
+}
+
+// --------------------------------------------------------------------------
+// contact geometry (collision detection, Sec. 10; READING of the primitive rules)
+// --------------------------------------------------------------------------
+__device__ int box_ref_face(const Ctx &c, int A, int B) {
+  const int ga = c.E.rig_off + A, gb = c.E.rig_off + B;
+  const M3 RA = quat_mat(c.S.r_q[ga]), RB = quat_mat(c.S.r_q[gb]);
+  const V3 d = mk(c.S.r_x[ga]) - mk(c.S.r_x[gb]);
+  const V3 eA = mk(c.S.r_ext[ga]), eB = mk(c.S.r_ext[gb]);
+  int best = 0;
+  float bs = 0.f;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int ax = f >> 1;
+    const float sg = (f & 1) ? 1.f : -1.f;
+    const V3 nf = sg * col(RB, ax);
+    float sep = dot(nf, d) - comp(eB, ax);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) sep -= fabsf(dot(nf, col(RA, i))) * comp(eA, i);
+    if (f == 0 || sep > bs) { best = f; bs = sep; }
+  }
+  return best;
+}
+
+__device__ __forceinline__ void setc(V3 &a, int i, float v) {
+  if (i == 0) a.x = v; else if (i == 1) a.y = v; else a.z = v;
+}
+
+// returns 1 and (n, bL, dist, target thickness) for a point against a target
+// (ground plane, box, capsule); see the oracle for the rules
+__device__ int target_query(const Ctx &c, int t, V3 pw, bool box_feature, int fbody, V3 &n, V3 &bL,
+                            float &dist, float &tthick) {
+  tthick = 0.f;
+  if (t < 0) {
+    n = mk(0.f, 0.f, 1.f);
+    bL = mk(pw.x, pw.y, 0.f);
+    dist = pw.z;
+    return 1;
+  }
+  const int g = c.E.rig_off + t;
+  const M3 R = quat_mat(c.S.r_q[g]);
+  const V3 pl = mulT(R, pw - mk(c.S.r_x[g]));
+  const V3 ext = mk(c.S.r_ext[g]);
+  const int shape = c.S.r_shape[g];
+  if (shape == NSN_SHAPE_BOX) {
+    V3 nl = mk(0.f, 0.f, 0.f), bl = pl;
+    if (box_feature) {
+      const int face = box_ref_face(c, fbody, t);
+      const int ax = face >> 1;
+      const float sg = (face & 1) ? 1.f : -1.f;
+#pragma unroll
+      for (int o = 0; o < 3; ++o)
+        if (o != ax && fabsf(comp(pl, o)) > comp(ext, o) + c.A.p.margin) return 0;
+      setc(nl, ax, sg);
+      setc(bl, ax, sg * comp(ext, ax));
+      dist = sg * comp(pl, ax) - comp(ext, ax);
+    } else {
+      const bool inside = fabsf(pl.x) <= ext.x && fabsf(pl.y) <= ext.y && fabsf(pl.z) <= ext.z;
+      if (inside) {
+        int best = -1;
+        float bd = 0.f;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const int ax = f >> 1;
+          const float sg = (f & 1) ? 1.f : -1.f;
+          const float depth = comp(ext, ax) - sg * comp(pl, ax);
+          if (best < 0 || depth < bd) { best = f; bd = depth; }
+        }
+        const int ax = best >> 1;
+        const float sg = (best & 1) ? 1.f : -1.f;
+        setc(nl, ax, sg);
+        setc(bl, ax, sg * comp(ext, ax));
+        dist = -bd;
+      } else {
+        bl = mk(fminf(fmaxf(pl.x, -ext.x), ext.x), fminf(fmaxf(pl.y, -ext.y), ext.y),
+                fminf(fmaxf(pl.z, -ext.z), ext.z));
+        const V3 df = pl - bl;
+        const float l = norm(df);
+        if (!(l > 1e-9f)) return 0;
+        nl = V3{df.x / l, df.y / l, df.z / l};
+        dist = l;
+      }
+    }
+    n = mul(R, nl);
+    bL = bl;
+    return 1;
+  }
+  if (shape == NSN_SHAPE_CAPSULE) {
+    const float L = ext.y;
+    const float tp = fminf(fmaxf(pl.x, -L), L);
+    const V3 df = mk(pl.x - tp, pl.y, pl.z);
+    const float l = norm(df);
+    if (!(l > 1e-9f)) return 0;
+    n = mul(R, V3{df.x / l, df.y / l, df.z / l});
+    bL = mk(tp, 0.f, 0.f);
+    dist = l - ext.x;
+    tthick = ext.x;
+    return 1;
+  }
+  return 0;
+}
+
+// --------------------------------------------------------------------------
+// Kernel 1: step set-up (mass at q^-, u~), collision detection in canonical
+// candidate order, contact adjacency, warm-start lookup, contact features.
+// One workgroup per env.
+// --------------------------------------------------------------------------
+template <int BS>
+__global__ __launch_bounds__(BS) void k_prepare(DevScene S, StepArgs A, int want_features) {
+  __shared__ int s_wave[BS / 64];
+  __shared__ int s_count;
+  Ctx c;
+  c.S = S;
+  const int e = blockIdx.x;
+  c.E = S.env[e];
+  c.A = A;
+  const EnvInfo &E = c.E;
+  const float h = A.h;
+  const int tid = threadIdx.x;
+  const V3 grav = mk(E.gx, E.gy, E.gz);
+
+  // ---- mass at q^- and u~ = u^- + h M^-1 f (Sec. 5; f = (m g, -w x I w)) ----
+  for (int r = tid; r < E.n_rig; r += BS) {
+    const int g = E.rig_off + r;
+    const float4 q = quat_normalize(S.r_q[g]);
+    S.r_q[g] = q;
+    S.r_q0[g] = q;
+    S.r_x0[g] = S.r_x[g];
+    const float4 In = S.r_inertia[g];
+    float *Iw = S.r_Iw + 6 * g, *Ii = S.r_Iwinv + 6 * g, *ut = S.r_ut + 6 * g;
+    if (In.w == 0.f) {
+      for (int k = 0; k < 6; ++k) { Iw[k] = 0.f; Ii[k] = 0.f; ut[k] = 0.f; }
+      continue;
+    }
+    const M3 R = quat_mat(q);
+    const float Ib[3] = {In.x, In.y, In.z};
+    const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const float prod = R.m[3 * ia[k] + m] * R.m[3 * ib[k] + m];
+        s1 += prod * Ib[m];
+        s2 += prod / Ib[m];
+      }
+      Iw[k] = s1;
+      Ii[k] = s2;
+    }
+    const V3 w = mk(S.r_w[g]);
+    const V3 gyro = -cross(w, sym_mul(Iw, w));
+    const V3 dw = sym_mul(Ii, gyro);
+    const V3 v = mk(S.r_v[g]);
+    ut[0] = v.x + h * grav.x; ut[1] = v.y + h * grav.y; ut[2] = v.z + h * grav.z;
+    ut[3] = w.x + h * dw.x; ut[4] = w.y + h * dw.y; ut[5] = w.z + h * dw.z;
+  }
+  for (int p = tid; p < E.n_par; p += BS) {
+    const int g = E.par_off + p;
+    S.p_x0[g] = S.p_x[g];
+    const float4 v = S.p_v[g];
+    S.p_ut[g] = make_float4(v.x + h * grav.x, v.y + h * grav.y, v.z + h * grav.z, 0.f);
+  }
+  if (tid == 0) s_count = 0;
+  __syncthreads();
+  for (int j = tid; j < E.n_jnt; j += BS) {
+    const int jg = E.jnt_off + j;
+    S.j_theta0[jg] = S.j_info[jg].w ? joint_coordinate(c, jg) : 0.f;
+  }
+
+  // ---- collision detection at q^- (Alg. 1), canonical candidate order:
+  //      candidate = feature * n_targets + target, features = rigid features then
+  //      particles, targets = ground then rigid bodies ----
+  const int nfeat = E.n_feat + E.n_par;
+  const long long ncand = (long long)nfeat * E.n_targets;
+  for (long long base = 0; base < ncand; base += BS) {
+    const long long cand = base + tid;
+    int keep = 0, fbody = 0, tb = -1;
+    V3 n = mk(0.f, 0.f, 0.f), aL = n, bL = n;
+    float dtot = 0.f;
+    if (cand < ncand) {
+      const int fi = (int)(cand / E.n_targets);
+      const int ti = (int)(cand - (long long)fi * E.n_targets);
+      const int t = E.ground ? ti - 1 : ti;
+      const bool is_particle = fi >= E.n_feat;
+      bool ok = true;
+      float fthick = 0.f;
+      int fshape = -1;
+      if (!is_particle) {
+        const int2 fv = S.feat[E.feat_off + fi];
+        fbody = fv.x - E.rig_off;
+        fshape = S.r_shape[fv.x];
+        if (S.r_inertia[fv.x].w == 0.f) ok = false;
+        const float4 ex = S.r_ext[fv.x];
+        if (fshape == NSN_SHAPE_BOX) {
+          aL = mk((fv.y & 1) ? ex.x : -ex.x, (fv.y & 2) ? ex.y : -ex.y, (fv.y & 4) ? ex.z : -ex.z);
+        } else {
+          aL = mk((fv.y & 1) ? ex.y : -ex.y, 0.f, 0.f);
+          fthick = ex.x;
+        }
+      } else {
+        fbody = E.n_rig + (fi - E.n_feat);
+      }
+      if (ok && t >= 0) {
+        const int ts = S.r_shape[E.rig_off + t];
+        if (t == fbody || ts == NSN_SHAPE_NONE) ok = false;
+        if (ts == NSN_SHAPE_CAPSULE && !is_particle) ok = false;
+        if (fshape == NSN_SHAPE_CAPSULE) ok = false;
+        if (!is_particle && ts == NSN_SHAPE_BOX && fshape != NSN_SHAPE_BOX) ok = false;
+      }
+      if (ok) {
+        const V3 pw = body_point(c, fbody, aL);
+        float dist, tthick;
+        if (target_query(c, t, pw, !is_particle && fshape == NSN_SHAPE_BOX, fbody, n, bL, dist, tthick)) {
+          const float gap = dist - fthick;
+          const V3 va = point_vel(c, S.r_ut, S.p_ut, fbody, body_arm(c, fbody, aL));
+          const V3 vb = t >= 0 ? point_vel(c, S.r_ut, S.p_ut, t, body_arm(c, t, bL)) : mk(0.f, 0.f, 0.f);
+          const float vn = dot(n, va - vb);
+          const float pred = gap + h * (vn < 0.f ? vn : 0.f);
+          if (pred < A.p.margin) {
+            keep = 1;
+            tb = t;
+            dtot = fthick + tthick;
+          }
+        }
+      }
+    }
+    int total;
+    const int rank = block_rank<BS>(keep, s_wave, &total);
+    if (keep) {
+      const int slot = s_count + rank;
+      if (slot < E.max_con) {
+        const int gc = E.con_off + slot;
+        S.c_key[gc] = (int)cand;
+        S.c_body[gc] = make_int2(fbody, tb);
+        S.c_n[gc] = f4(n, dtot);
+        S.c_aL[gc] = f4(fbody < E.n_rig ? aL : mk(0.f, 0.f, 0.f), 0.f);
+        S.c_bL[gc] = f4(bL, 0.f);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) s_count += total;
+    __syncthreads();
+  }
+  const int nc = s_count < E.max_con ? s_count : E.max_con;
+  if (tid == 0) {
+    S.n_con[e] = nc;
+    S.overflow[e] = s_count - nc;
+  }
+
+  // ---- feature-side ranges (contacts come out sorted by feature body) ----
+  for (int r = tid; r < E.n_rig; r += BS) {
+    S.r_acon_beg[E.rig_off + r] = 0;
+    S.r_acon_end[E.rig_off + r] = 0;
+  }
+  for (int p = tid; p < E.n_par; p += BS) {
+    S.p_acon_beg[E.par_off + p] = 0;
+    S.p_acon_end[E.par_off + p] = 0;
+  }
+  __syncthreads();
+  for (int i = tid; i < nc; i += BS) {
+    const int gc = E.con_off + i;
+    const int fa = S.c_body[gc].x;
+    const bool first = i == 0 || S.c_body[gc - 1].x != fa;
+    const bool last = i == nc - 1 || S.c_body[gc + 1].x != fa;
+    if (fa < E.n_rig) {
+      if (first) S.r_acon_beg[E.rig_off + fa] = gc;
+      if (last) S.r_acon_end[E.rig_off + fa] = gc + 1;
+    } else {
+      if (first) S.p_acon_beg[E.par_off + fa - E.n_rig] = gc;
+      if (last) S.p_acon_end[E.par_off + fa - E.n_rig] = gc + 1;
+    }
+  }
+  // ---- target-side lists: one wave per rigid target, ballot compaction in order ----
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int t = wv; t < E.n_rig; t += BS / 64) {
+    int cnt = 0;
+    for (int b0 = 0; b0 < nc; b0 += 64) {
+      const int i = b0 + lane;
+      const int f = i < nc && S.c_body[E.con_off + i].y == t;
+      cnt += __popcll(__ballot(f));
+    }
+    if (lane == 0) S.r_bcon_cnt[E.rig_off + t] = cnt;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int t = 0; t < E.n_rig; ++t) {
+      S.r_bcon_beg[E.rig_off + t] = E.bcon_off + run;
+      run += S.r_bcon_cnt[E.rig_off + t];
+    }
+  }
+  __syncthreads();
+  for (int t = wv; t < E.n_rig; t += BS / 64) {
+    int run = S.r_bcon_beg[E.rig_off + t];
+    for (int b0 = 0; b0 < nc; b0 += 64) {
+      const int i = b0 + lane;
+      const int f = i < nc && S.c_body[E.con_off + i].y == t;
+      const unsigned long long m = __ballot(f);
+      if (f) S.bcon_list[run + __popcll(m & ((1ull << lane) - 1ull))] = E.con_off + i;
+      run += __popcll(m);
+    }
+  }
+
+  // ---- warm start by key (previous step) and per-contact features ----
+  const int np_prev = S.n_prev[e];
+  for (int i = tid; i < nc; i += BS) {
+    const int gc = E.con_off + i;
+    const int key = S.c_key[gc];
+    int lo = 0, hi = np_prev - 1, found = -1;
+    while (lo <= hi) {
+      const int mid = (lo + hi) >> 1;
+      const int km = S.c_prev_key[E.con_off + mid];
+      if (km == key) { found = mid; break; }
+      if (km < key) lo = mid + 1; else hi = mid - 1;
+    }
+    const float4 lp = found >= 0 ? S.c_prev_lam[E.con_off + found] : make_float4(0.f, 0.f, 0.f, 0.f);
+    S.c_lam0[gc] = lp;
+    if (want_features) {
+      // READING of the 12 features (step start, contact basis): v_n, v_t1, v_t2 under u~,
+      // C_n(q^-), previous (lam_n, lam_t1, lam_t2), 1/m_A, 1/m_B, mu, n_z, existed-before flag
+      const int2 bd = S.c_body[gc];
+      const float4 n4 = S.c_n[gc];
+      const V3 n = mk(n4);
+      const V3 aL = mk(S.c_aL[gc]), bL = mk(S.c_bL[gc]);
+      const V3 va = point_vel(c, S.r_ut, S.p_ut, bd.x, body_arm(c, bd.x, aL));
+      V3 vb = mk(0.f, 0.f, 0.f), pb = bL;
+      if (bd.y >= 0) {
+        vb = point_vel(c, S.r_ut, S.p_ut, bd.y, body_arm(c, bd.y, bL));
+        pb = body_point(c, bd.y, bL);
+      }
+      const V3 pa = body_point(c, bd.x, aL);
+      V3 d1, d2;
+      tangent_basis(n, d1, d2);
+      const V3 vr = va - vb;
+      const float ima = bd.x < E.n_rig ? S.r_inertia[E.rig_off + bd.x].w : 1.f / S.p_m[E.par_off + bd.x - E.n_rig];
+      const float imb = bd.y >= 0 ? S.r_inertia[E.rig_off + bd.y].w : 0.f;
+      float *F = S.c_feat + (size_t)gc * 12;
+      F[0] = dot(n, vr); F[1] = dot(d1, vr); F[2] = dot(d2, vr);
+      F[3] = dot(n, pa - pb) - n4.w;
+      F[4] = lp.x; F[5] = lp.y; F[6] = lp.z;
+      F[7] = ima; F[8] = imb; F[9] = E.mu; F[10] = n.z; F[11] = found >= 0 ? 1.f : 0.f;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Newton kernel pieces
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float tJ(const DevScene &S, int buf, int comp_, int tg) {
+  return S.t_J[((size_t)buf * 18 + comp_) * S.NT + tg];
+}
+
+// ---- assembly (Sec. 6.1 eq. newton_system; Appendix A/B) ----
+// physical = true: rows grad(c) G with alpha = 1 and all friction rows present,
+// Jacobians only (for the warm-start impulse).
+__device__ void assemble_joint(const Ctx &c, int jl, bool physical, double tplus) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  const float h = c.A.h;
+  const int jg = E.jnt_off + jl;
+  float cv[6];
+  joint_rows(c, jg, S.j_J + (size_t)72 * jg, cv);
+  if (physical) return;
+  const int r0 = row_joint(E, jl);
+  const int4 info = S.j_info[jg];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    float Ec = 0.f, cval = cv[r];
+    if (r == 5) {
+      if (info.w) {
+        // READING: implicit PD as a backward-Euler soft row, k_eff = kp + kd/h,
+        // E = 1/k_eff, c = theta(q) - (kp theta*(t+) + (kd/h) theta(q^-)) / k_eff
+        const float4 d0 = S.j_drive[2 * jg], d1 = S.j_drive[2 * jg + 1];
+        const float keff = d0.x + d0.y / h;
+        const double target = (double)d1.y + (double)d0.z * sin(2.0 * M_PI * (double)d0.w * tplus + (double)d1.x);
+        const float teff = (float)(((double)d0.x * target + (double)(d0.y / h) * (double)S.j_theta0[jg]) / (double)keff);
+        cval = cv[5] - teff;
+        Ec = 1.f / keff;
+      } else {
+        cval = 0.f;  // undriven: empty row that keeps its multiplier at zero
+        Ec = h * h;
+      }
+    }
+    S.row_C[r0 + r] = Ec / (h * h);
+    S.row_err[r0 + r] = (cval + Ec * S.row_lam[r0 + r]) / h;
+  }
+}
+
+__device__ void assemble_tet(const Ctx &c, int tl, int buf, bool physical) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  const float h = c.A.h;
+  const int NT = S.NT;
+  const int tg = E.tet_off + tl;
+  const int4 id = S.t_ids[tg];
+  M3 Dmi;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Dmi.m[k] = S.t_Dminv[(size_t)k * NT + tg];
+  const V3 x0 = mk(S.p_x[id.x]);
+  const V3 e1 = mk(S.p_x[id.y]) - x0, e2 = mk(S.p_x[id.z]) - x0, e3 = mk(S.p_x[id.w]) - x0;
+  M3 Ds = {{e1.x, e2.x, e3.x, e1.y, e2.y, e3.y, e1.z, e2.z, e3.z}};
+  M3 F;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      F.m[3 * i + j] = Ds.m[3 * i] * Dmi.m[j] + Ds.m[3 * i + 1] * Dmi.m[3 + j] + Ds.m[3 * i + 2] * Dmi.m[6 + j];
+  M3 U, V;
+  float s[3];
+  svd3(F, U, s, V);
+  // rows ds_i/dx: u_i * (Dm^-1 v_i)_j for vertices 1..3, minus their sum for vertex 0
+  float *Jb = S.t_J + (size_t)buf * 18 * NT;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const V3 u = col(U, i), w = mul(Dmi, col(V, i));
+    Jb[(size_t)(6 * i + 0) * NT + tg] = u.x;
+    Jb[(size_t)(6 * i + 1) * NT + tg] = u.y;
+    Jb[(size_t)(6 * i + 2) * NT + tg] = u.z;
+    Jb[(size_t)(6 * i + 3) * NT + tg] = w.x;
+    Jb[(size_t)(6 * i + 4) * NT + tg] = w.y;
+    Jb[(size_t)(6 * i + 5) * NT + tg] = w.z;
+  }
+  if (physical) return;
+  const float4 mt = S.t_mat[tg];  // (Ve, C1, D1, alpha)
+  const float Ve = mt.x, C1 = mt.y, D1 = mt.z, al = mt.w;
+  // stable neo-Hookean (Appendix B) in principal stretches
+  const float J = s[0] * s[1] * s[2];
+  const float gr[3] = {2.f * C1 * s[0] + 2.f * D1 * (J - al) * s[1] * s[2],
+                       2.f * C1 * s[1] + 2.f * D1 * (J - al) * s[0] * s[2],
+                       2.f * C1 * s[2] + 2.f * D1 * (J - al) * s[0] * s[1]};
+  const float k0 = 2.f * J - al;
+  float H[9];
+  H[0] = Ve * 2.f * (D1 * s[1] * s[1] * s[2] * s[2] + C1);
+  H[4] = Ve * 2.f * (D1 * s[0] * s[0] * s[2] * s[2] + C1);
+  H[8] = Ve * 2.f * (D1 * s[0] * s[0] * s[1] * s[1] + C1);
+  H[1] = H[3] = Ve * 2.f * D1 * s[2] * k0;
+  H[2] = H[6] = Ve * 2.f * D1 * s[1] * k0;
+  H[5] = H[7] = Ve * 2.f * D1 * s[0] * k0;
+  const float floor_ = kClampFem * 2.f * C1 * Ve;
+  float Em[6];  // xx yy zz xy xz yz
+  if (c.A.p.fem_mode == NSN_FEM_DIAGONAL) {
+    Em[0] = 1.f / fmaxf(H[0], floor_);
+    Em[1] = 1.f / fmaxf(H[4], floor_);
+    Em[2] = 1.f / fmaxf(H[8], floor_);
+    Em[3] = Em[4] = Em[5] = 0.f;
+  } else {
+    M3 Q;
+    float w[3];
+    sym_eig3(H, Q, w);
+    const float iw0 = 1.f / fmaxf(w[0], floor_), iw1 = 1.f / fmaxf(w[1], floor_), iw2 = 1.f / fmaxf(w[2], floor_);
+    const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      Em[k] = Q.m[3 * ia[k]] * Q.m[3 * ib[k]] * iw0 + Q.m[3 * ia[k] + 1] * Q.m[3 * ib[k] + 1] * iw1 +
+              Q.m[3 * ia[k] + 2] * Q.m[3 * ib[k] + 2] * iw2;
+  }
+  const int r0 = row_tet(E, tl);
+  const V3 cl = mk(Ve * gr[0] + S.row_lam[r0], Ve * gr[1] + S.row_lam[r0 + 1], Ve * gr[2] + S.row_lam[r0 + 2]);
+  const V3 Ecl = sym_mul(Em, cl);
+  const float ih = 1.f / h, ih2 = 1.f / (h * h);
+  S.row_err[r0] = Ecl.x * ih;
+  S.row_err[r0 + 1] = Ecl.y * ih;
+  S.row_err[r0 + 2] = Ecl.z * ih;
+  S.row_C[r0] = Em[0] * ih2;
+  S.row_C[r0 + 1] = Em[1] * ih2;
+  S.row_C[r0 + 2] = Em[2] * ih2;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) S.t_E[(size_t)k * NT + tg] = Em[k] * ih2;
+}
+
+__device__ void assemble_contact(const Ctx &c, int cl, int buf, bool physical) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  const float h = c.A.h;
+  const int gc = E.con_off + cl;
+  const int2 bd = S.c_body[gc];
+  const float4 n4 = S.c_n[gc];
+  const V3 n = mk(n4);
+  const V3 aL = mk(S.c_aL[gc]), bL = mk(S.c_bL[gc]);
+  const V3 armA = body_arm(c, bd.x, aL);
+  const V3 armB = bd.y >= 0 ? body_arm(c, bd.y, bL) : mk(0.f, 0.f, 0.f);
+  S.c_rA[gc] = f4(armA, 0.f);
+  S.c_rB[gc] = f4(armB, 0.f);
+  if (physical) {
+    S.c_alpha[(size_t)buf * S.NC + gc] = 1.f;
+    S.c_active[(size_t)buf * S.NC + gc] = 1;
+    return;
+  }
+  const V3 pa = body_point(c, bd.x, aL);
+  const V3 pb = bd.y >= 0 ? body_point(c, bd.y, bL) : bL;
+  const float Cn = dot(n, pa - pb) - n4.w;
+  V3 d1, d2;
+  tangent_basis(n, d1, d2);
+  // complementarity preconditioner (Sec. 7 eq. rscaling)
+  float r_n, r_f;
+  if (c.A.p.rmode == NSN_R_IDENTITY) {
+    r_n = 1.f; r_f = 1.f;
+  } else if (c.A.p.rmode == NSN_R_H2) {
+    r_n = h * h; r_f = h;
+  } else {
+    const float Ann = effmass_dir(c, bd.x, armA, n, false) + effmass_dir(c, bd.y, armB, n, false);
+    const float A1 = effmass_dir(c, bd.x, armA, d1, false) + effmass_dir(c, bd.y, armB, d1, false);
+    const float A2 = effmass_dir(c, bd.x, armA, d2, false) + effmass_dir(c, bd.y, armB, d2, false);
+    r_n = h * h * Ann;
+    r_f = h * 0.5f * (A1 + A2);
+  }
+  const int r0 = row_con(E, cl);
+  const float lam_n = S.row_lam[r0], lf1 = S.row_lam[r0 + 1], lf2 = S.row_lam[r0 + 2];
+  float phi, al, be;
+  if (c.A.p.ncp == NSN_NCP_MIN) ncp_min(Cn, lam_n, r_n, phi, al, be);
+  else ncp_fb(Cn, lam_n, r_n, phi, al, be);
+  S.c_alpha[(size_t)buf * S.NC + gc] = al;
+  S.row_C[r0] = be * r_n / (h * h);
+  S.row_err[r0] = phi / h;
+  const bool active = E.mu * lam_n > 0.f;
+  S.c_active[(size_t)buf * S.NC + gc] = active ? 1 : 0;
+  if (active) {
+    const V3 vr = point_vel(c, S.r_u, S.p_u, bd.x, armA) -
+                  (bd.y >= 0 ? point_vel(c, S.r_u, S.p_u, bd.y, armB) : mk(0.f, 0.f, 0.f));
+    const float v1 = dot(d1, vr), v2 = dot(d2, vr);
+    const float vn = sqrtf(v1 * v1 + v2 * v2);
+    const float lfn = sqrtf(lf1 * lf1 + lf2 * lf2);
+    const float W = friction_w(c.A.p.ncp, vn, lam_n, lfn, E.mu, r_f);
+    S.row_C[r0 + 1] = W / h;
+    S.row_C[r0 + 2] = W / h;
+    S.row_err[r0 + 1] = v1 + W * lf1;
+    S.row_err[r0 + 2] = v2 + W * lf2;
+  } else {
+    // READING: inactive friction rows are removed (zero J); compliance r_f/h and
+    // error r_f lambda_f drive their multipliers to zero
+    S.row_C[r0 + 1] = r_f / h;
+    S.row_C[r0 + 2] = r_f / h;
+    S.row_err[r0 + 1] = r_f * lf1;
+    S.row_err[r0 + 2] = r_f * lf2;
+  }
+}
+
+// contact row combination: J_c^T v for one contact as a world-space direction applied
+// at the two points: dir = alpha v_n n + [active](v_1 d1 + v_2 d2)
+__device__ __forceinline__ V3 contact_dir(const Ctx &c, int gc, const float *src, int buf) {
+  const int r0 = row_con(c.E, gc - c.E.con_off);
+  const V3 n = mk(c.S.c_n[gc]);
+  const float al = c.S.c_alpha[(size_t)buf * c.S.NC + gc];
+  V3 dir = (al * src[r0]) * n;
+  if (c.S.c_active[(size_t)buf * c.S.NC + gc]) {
+    V3 d1, d2;
+    tangent_basis(n, d1, d2);
+    dir = dir + src[r0 + 1] * d1 + src[r0 + 2] * d2;
+  }
+  return dir;
+}
+
+// J^T src for one rigid body (6) -- pull over joint adjacency and contact ranges
+__device__ void scatter_rigid(const Ctx &c, int g, const float *src, int buf, float out[6]) {
+  const DevScene &S = c.S;
+  const EnvInfo &E = c.E;
+  for (int k = 0; k < 6; ++k) out[k] = 0.f;
+  for (int k = S.r_jadj_ptr[g]; k < S.r_jadj_ptr[g + 1]; ++k) {
+    const int ent = S.r_jadj[k];
+    const int jg = ent >> 1, side = ent & 1;
+    const int r0 = row_joint(E, jg - E.jnt_off);
+    const float *J = S.j_J + (size_t)72 * jg + 6 * side;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      const float v = src[r0 + r];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) out[q] += v * J[12 * r + q];
+    }
+  }
+  for (int gc = S.r_acon_beg[g]; gc < S.r_acon_end[g]; ++gc) {
+    const V3 d = contact_dir(c, gc, src, buf);
+    const V3 a = cross(mk(S.c_rA[gc]), d);
+    out[0] += d.x; out[1] += d.y; out[2] += d.z; out[3] += a.x; out[4] += a.y; out[5] += a.z;
+  }
+  const int b0 = S.r_bcon_beg[g], bn = S.r_bcon_cnt[g];
+  for (int k = 0; k < bn; ++k) {
+    const int gc = S.bcon_list[b0 + k];
+    const V3 d = contact_dir(c, gc, src, buf);
+    const V3 a = cross(mk(S.c_rB[gc]), d);
+    out[0] -= d.x; out[1] -= d.y; out[2] -= d.z; out[3] -= a.x; out[4] -= a.y; out[5] -= a.z;
+  }
+}
+
+// J^T src for one particle (3) -- pull over tet adjacency and contact range
+__device__ V3 scatter_particle(const Ctx &c, int p, const float *src, int buf) {
+  const DevScene &S = c.S;
+  const EnvInfo &E = c.E;
+  V3 acc = mk(0.f, 0.f, 0.f);
+  for (int k = S.p_tadj_ptr[p]; k < S.p_tadj_ptr[p + 1]; ++k) {
+    const int ent = S.p_tadj[k];
+    const int tg = ent >> 2, slot = ent & 3;
+    const int r0 = row_tet(E, tg - E.tet_off);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const float w0 = tJ(S, buf, 6 * i + 3, tg), w1 = tJ(S, buf, 6 * i + 4, tg), w2 = tJ(S, buf, 6 * i + 5, tg);
+      const float coef = slot == 0 ? -(w0 + w1 + w2) : (slot == 1 ? w0 : (slot == 2 ? w1 : w2));
+      const float sv = src[r0 + i] * coef;
+      acc = acc + sv * mk(tJ(S, buf, 6 * i, tg), tJ(S, buf, 6 * i + 1, tg), tJ(S, buf, 6 * i + 2, tg));
+    }
+  }
+  for (int gc = S.p_acon_beg[p]; gc < S.p_acon_end[p]; ++gc) acc = acc + contact_dir(c, gc, src, buf);
+  return acc;
+}
+
+// (J Y) of one element's rows (no compliance); rows written to out[], returns row count
+__device__ int gather_element(const Ctx &c, int el, const float *Y, int buf, float out[6], int &r0) {
+  const DevScene &S = c.S;
+  const EnvInfo &E = c.E;
+  if (el < E.n_jnt) {
+    const int jg = E.jnt_off + el;
+    const int4 info = S.j_info[jg];
+    r0 = row_joint(E, el);
+    const float *J = S.j_J + (size_t)72 * jg;
+    const int dA = info.y >= 0 ? body_dof(E, info.y - E.rig_off) : -1;
+    const int dB = body_dof(E, info.z - E.rig_off);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      float acc = row_dot_rigid(J + 12 * r + 6, Y, dB);
+      if (dA >= 0) acc += row_dot_rigid(J + 12 * r, Y, dA);
+      out[r] = acc;
+    }
+    return 6;
+  }
+  el -= E.n_jnt;
+  if (el < E.n_tet) {
+    const int tg = E.tet_off + el;
+    r0 = row_tet(E, el);
+    const int4 id = S.t_ids[tg];
+    const int base = E.dof_off + 6 * E.n_rig - 3 * E.par_off;
+    const V3 y0 = mk(Y[base + 3 * id.x], Y[base + 3 * id.x + 1], Y[base + 3 * id.x + 2]);
+    const V3 y1 = mk(Y[base + 3 * id.y], Y[base + 3 * id.y + 1], Y[base + 3 * id.y + 2]);
+    const V3 y2 = mk(Y[base + 3 * id.z], Y[base + 3 * id.z + 1], Y[base + 3 * id.z + 2]);
+    const V3 y3 = mk(Y[base + 3 * id.w], Y[base + 3 * id.w + 1], Y[base + 3 * id.w + 2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const V3 u = mk(tJ(S, buf, 6 * i, tg), tJ(S, buf, 6 * i + 1, tg), tJ(S, buf, 6 * i + 2, tg));
+      const float w0 = tJ(S, buf, 6 * i + 3, tg), w1 = tJ(S, buf, 6 * i + 4, tg), w2 = tJ(S, buf, 6 * i + 5, tg);
+      out[i] = dot(u, w0 * (y1 - y0) + w1 * (y2 - y0) + w2 * (y3 - y0));
+    }
+    return 3;
+  }
+  el -= E.n_tet;
+  const int gc = E.con_off + el;
+  r0 = row_con(E, el);
+  const int2 bd = S.c_body[gc];
+  const V3 n = mk(S.c_n[gc]);
+  const V3 vr = point_vel_dof(c, Y, bd.x, mk(S.c_rA[gc])) -
+                (bd.y >= 0 ? point_vel_dof(c, Y, bd.y, mk(S.c_rB[gc])) : mk(0.f, 0.f, 0.f));
+  out[0] = S.c_alpha[(size_t)buf * S.NC + gc] * dot(n, vr);
+  if (S.c_active[(size_t)buf * S.NC + gc]) {
+    V3 d1, d2;
+    tangent_basis(n, d1, d2);
+    out[1] = dot(d1, vr);
+    out[2] = dot(d2, vr);
+  } else {
+    out[1] = 0.f;
+    out[2] = 0.f;
+  }
+  return 3;
+}
+
+// compliance block times src for one element's rows (added to out)
+__device__ __forceinline__ void add_compliance(const Ctx &c, int el, int r0, int nr, const float *src, float out[6]) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  if (el >= E.n_jnt && el < E.n_jnt + E.n_tet) {
+    const int tg = E.tet_off + el - E.n_jnt;
+    float Em[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Em[k] = S.t_E[(size_t)k * S.NT + tg];
+    const V3 v = sym_mul(Em, mk(src[r0], src[r0 + 1], src[r0 + 2]));
+    out[0] += v.x; out[1] += v.y; out[2] += v.z;
+    return;
+  }
+  for (int r = 0; r < nr; ++r) out[r] += S.row_C[r0 + r] * src[r0 + r];
+}
+
+// J_i H~^-1 J_i^T of one element's rows (preconditioner diagonal without C, eps)
+__device__ int hdiag_element(const Ctx &c, int el, int buf, float out[6], int &r0) {
+  const DevScene &S = c.S;
+  const EnvInfo &E = c.E;
+  if (el < E.n_jnt) {
+    const int jg = E.jnt_off + el;
+    const int4 info = S.j_info[jg];
+    r0 = row_joint(E, el);
+    const float *J = S.j_J + (size_t)72 * jg;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      float acc = rigid_quad(c, info.z, J + 12 * r + 6);
+      if (info.y >= 0) acc += rigid_quad(c, info.y, J + 12 * r);
+      out[r] = acc;
+    }
+    return 6;
+  }
+  el -= E.n_jnt;
+  if (el < E.n_tet) {
+    const int tg = E.tet_off + el;
+    r0 = row_tet(E, el);
+    const int4 id = S.t_ids[tg];
+    const float4 H0 = S.p_H[id.x], H1 = S.p_H[id.y], H2 = S.p_H[id.z], H3 = S.p_H[id.w];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const V3 u = mk(tJ(S, buf, 6 * i, tg), tJ(S, buf, 6 * i + 1, tg), tJ(S, buf, 6 * i + 2, tg));
+      const float w0 = tJ(S, buf, 6 * i + 3, tg), w1 = tJ(S, buf, 6 * i + 4, tg), w2 = tJ(S, buf, 6 * i + 5, tg);
+      const float ws = w0 + w1 + w2;
+      const V3 u2 = mk(u.x * u.x, u.y * u.y, u.z * u.z);
+      out[i] = ws * ws * (u2.x / H0.x + u2.y / H0.y + u2.z / H0.z) +
+               w0 * w0 * (u2.x / H1.x + u2.y / H1.y + u2.z / H1.z) +
+               w1 * w1 * (u2.x / H2.x + u2.y / H2.y + u2.z / H2.z) +
+               w2 * w2 * (u2.x / H3.x + u2.y / H3.y + u2.z / H3.z);
+    }
+    return 3;
+  }
+  el -= E.n_tet;
+  const int gc = E.con_off + el;
+  r0 = row_con(E, el);
+  const int2 bd = S.c_body[gc];
+  const V3 n = mk(S.c_n[gc]);
+  const V3 rA = mk(S.c_rA[gc]), rB = mk(S.c_rB[gc]);
+  const float al = S.c_alpha[(size_t)buf * S.NC + gc];
+  out[0] = al * al * (effmass_dir(c, bd.x, rA, n, true) + effmass_dir(c, bd.y, rB, n, true));
+  if (S.c_active[(size_t)buf * S.NC + gc]) {
+    V3 d1, d2;
+    tangent_basis(n, d1, d2);
+    out[1] = effmass_dir(c, bd.x, rA, d1, true) + effmass_dir(c, bd.y, rB, d1, true);
+    out[2] = effmass_dir(c, bd.x, rA, d2, true) + effmass_dir(c, bd.y, rB, d2, true);
+  } else {
+    out[1] = 0.f;
+    out[2] = 0.f;
+  }
+  return 3;
+}
+
+// H~^-1 applied to a rigid 6-vector (in place)
+__device__ __forceinline__ void hinv_rigid(const Ctx &c, int g, float v[6]) {
+  const float im = c.S.r_inertia[g].w;
+  if (im == 0.f) {
+    for (int k = 0; k < 6; ++k) v[k] = 0.f;
+    return;
+  }
+  const V3 a = sym_mul(c.S.r_Iwinv + 6 * g, mk(v[3], v[4], v[5]));
+  v[0] *= im; v[1] *= im; v[2] *= im;
+  v[3] = a.x; v[4] = a.y; v[5] = a.z;
+}
+
+// scatter src (rows) into Y (dofs) and apply H~^-1
+__device__ void scatter_hinv(const Ctx &c, const float *src, int buf, float *Y, int tid, int BS) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  const int nb = E.n_rig + E.n_par;
+  for (int b = tid; b < nb; b += BS) {
+    if (b < E.n_rig) {
+      const int g = E.rig_off + b;
+      float v[6];
+      scatter_rigid(c, g, src, buf, v);
+      hinv_rigid(c, g, v);
+      const int d = E.dof_off + 6 * b;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) Y[d + k] = v[k];
+    } else {
+      const int p = E.par_off + b - E.n_rig;
+      const V3 a = scatter_particle(c, p, src, buf);
+      const float4 H = S.p_H[p];
+      const int d = E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
+      Y[d] = a.x / H.x;
+      Y[d + 1] = a.y / H.y;
+      Y[d + 2] = a.z / H.z;
+    }
+  }
+}
+
+// position update q = q^- + h G(q^k) u (Alg. 1; quaternion normalised every update)
+__device__ __forceinline__ void update_positions_body(const Ctx &c, int b) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  const float h = c.A.h;
+  if (b < E.n_rig) {
+    const int g = E.rig_off + b;
+    if (S.r_inertia[g].w == 0.f) return;
+    const float *u = S.r_u + 6 * g;
+    const float4 x0 = S.r_x0[g];
+    S.r_x[g] = make_float4(x0.x + h * u[0], x0.y + h * u[1], x0.z + h * u[2], 0.f);
+    const float4 q = S.r_q[g], q0 = S.r_q0[g];
+    // (1/2) Q(theta) omega, Q from Sec. 9 (rigid bodies)
+    const float t1 = q.x, t2 = q.y, t3 = q.z, t4 = q.w, w1 = u[3], w2 = u[4], w3 = u[5];
+    const float dq0 = -t2 * w1 - t3 * w2 - t4 * w3;
+    const float dq1 = t1 * w1 + t4 * w2 - t3 * w3;
+    const float dq2 = -t4 * w1 + t1 * w2 + t2 * w3;
+    const float dq3 = t3 * w1 - t2 * w2 + t1 * w3;
+    S.r_q[g] = quat_normalize(make_float4(q0.x + 0.5f * h * dq0, q0.y + 0.5f * h * dq1, q0.z + 0.5f * h * dq2,
+                                          q0.w + 0.5f * h * dq3));
+  } else {
+    const int p = E.par_off + b - E.n_rig;
+    const float4 x0 = S.p_x0[p], u = S.p_u[p];
+    S.p_x[p] = make_float4(x0.x + h * u.x, x0.y + h * u.y, x0.z + h * u.z, 0.f);
+  }
+}
+
+template <int BS>
+__device__ void assemble_all(const Ctx &c, int buf, bool physical, double tplus, int nc) {
+  const EnvInfo &E = c.E;
+  const int nel = E.n_jnt + E.n_tet + nc;
+  for (int el = threadIdx.x; el < nel; el += BS) {
+    if (el < E.n_jnt) assemble_joint(c, el, physical, tplus);
+    else if (el < E.n_jnt + E.n_tet) assemble_tet(c, el - E.n_jnt, buf, physical);
+    else assemble_contact(c, el - E.n_jnt - E.n_tet, buf, physical);
+  }
+}
+
+// --------------------------------------------------------------------------
+// Kernel 3: start iterate + Newton loop + write-back.  One workgroup per env.
+// --------------------------------------------------------------------------
+template <int BS>
+__global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first) {
+  __shared__ Red<BS> red;
+  Ctx c;
+  c.S = S;
+  const int e = S.env_order[first + blockIdx.x];
+  c.E = S.env[e];
+  c.A = A;
+  const EnvInfo &E = c.E;
+  const int tid = threadIdx.x;
+  const float h = A.h;
+  const float damp = A.p.damping, eps = A.p.eps;
+  const int nc = S.n_con[e];
+  const int nb = E.n_rig + E.n_par;
+  const int nel = E.n_jnt + E.n_tet + nc;
+  const int nrows = 6 * E.n_jnt + 3 * E.n_tet + 3 * nc;
+  const int R0 = E.row_off;
+  const int crow0 = row_con(E, 0);
+  const double tplus = S.time[e] + (double)h;
+  float *Y = S.y;
+
+  // ---- start iterate (Sec. 8.1); READING for warm starts: projected lambda0 and
+  //      u0 = u~ + h M^-1 J(q^-)^T lambda0 ----
+  const bool warm = A.p.warm != NSN_WARM_ZERO;
+  for (int r = tid; r < nrows; r += BS) {
+    const int row = R0 + r;
+    if (!warm) {
+      S.row_lam[row] = 0.f;
+    } else if (row >= crow0) {
+      const int cl = (row - crow0) / 3, k = (row - crow0) - 3 * cl;
+      float4 l = S.c_lam0[E.con_off + cl];
+      if (!(l.x == l.x) || !(l.y == l.y) || !(l.z == l.z)) l = make_float4(0.f, 0.f, 0.f, 0.f);
+      const float ln = fmaxf(l.x, 0.f);
+      const float lf = sqrtf(l.y * l.y + l.z * l.z), lim = E.mu * ln;
+      const float sc = lf > lim ? (lf > 0.f ? lim / lf : 0.f) : 1.f;
+      S.row_lam[row] = k == 0 ? ln : (k == 1 ? l.y * sc : l.z * sc);
+    }
+  }
+  for (int b = tid; b < nb; b += BS) {
+    if (b < E.n_rig) {
+      float *u = S.r_u + 6 * (E.rig_off + b);
+      for (int k = 0; k < 6; ++k) u[k] = 0.f;
+    } else {
+      const int p = E.par_off + b - E.n_rig;
+      S.p_u[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+      S.p_uprev[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+      S.p_H[p] = make_float4(S.p_m[p], S.p_m[p], S.p_m[p], 0.f);
+    }
+  }
+  __syncthreads();
+  if (warm) {
+    assemble_all<BS>(c, 0, true, tplus, nc);
+    __syncthreads();
+    for (int b = tid; b < nb; b += BS) {
+      if (b < E.n_rig) {
+        const int g = E.rig_off + b;
+        float v[6];
+        scatter_rigid(c, g, S.row_lam, 0, v);
+        hinv_rigid(c, g, v);  // H~ = M~ here
+        float *u = S.r_u + 6 * g;
+        const float *ut = S.r_ut + 6 * g;
+        for (int k = 0; k < 6; ++k) u[k] = ut[k] + h * v[k];
+      } else {
+        const int p = E.par_off + b - E.n_rig;
+        const V3 a = scatter_particle(c, p, S.row_lam, 0);
+        const float4 ut = S.p_ut[p];
+        const float im = 1.f / S.p_m[p];
+        S.p_u[p] = make_float4(ut.x + h * im * a.x, ut.y + h * im * a.y, ut.z + h * im * a.z, 0.f);
+      }
+    }
+    __syncthreads();
+    for (int b = tid; b < nb; b += BS) update_positions_body(c, b);
+    __syncthreads();
+  }
+
+  int newton_done = 0, cr_total = 0, nonfinite = 0, converged = 0;
+  float r_ncp = 0.f, r_con = 0.f, r_first = 0.f;
+  double merit = 0.0;
+  for (int k = 0; k <= A.newton_iters; ++k) {
+    const int buf = k & 1;
+    assemble_all<BS>(c, buf, false, tplus, nc);
+    __syncthreads();
+    // momentum balance g = M~(u - u~) - h J^T lambda (Sec. 6.1); geometric stiffness
+    // (Sec. 8.3, READING: secant of J^T lambda at fixed lambda between the last two
+    // iterates, particle DOFs only)
+    float rg = 0.f;
+    double m2 = 0.0;
+    for (int b = tid; b < nb; b += BS) {
+      if (b < E.n_rig) {
+        const int g = E.rig_off + b;
+        const int d = E.dof_off + 6 * b;
+        const float im = S.r_inertia[g].w;
+        if (im == 0.f) {
+          for (int q = 0; q < 6; ++q) S.g[d + q] = 0.f;
+          continue;
+        }
+        float f6[6];
+        scatter_rigid(c, g, S.row_lam, buf, f6);
+        const float *u = S.r_u + 6 * g, *ut = S.r_ut + 6 * g;
+        const V3 dv = mk(u[0] - ut[0], u[1] - ut[1], u[2] - ut[2]);
+        const V3 dw = sym_mul(S.r_Iw + 6 * g, mk(u[3] - ut[3], u[4] - ut[4], u[5] - ut[5]));
+        const float m = 1.f / im;
+        float gv[6] = {m * dv.x - h * f6[0], m * dv.y - h * f6[1], m * dv.z - h * f6[2],
+                       dw.x - h * f6[3], dw.y - h * f6[4], dw.z - h * f6[5]};
+        const V3 ia = sym_mul(S.r_Iwinv + 6 * g, mk(gv[3], gv[4], gv[5]));
+        rg = fmaxf(rg, fmaxf(fmaxf(fabsf(gv[0] * im), fabsf(gv[1] * im)), fabsf(gv[2] * im)));
+        rg = fmaxf(rg, fmaxf(fmaxf(fabsf(ia.x), fabsf(ia.y)), fabsf(ia.z)));
+        for (int q = 0; q < 6; ++q) {
+          S.g[d + q] = gv[q];
+          m2 += (double)gv[q] * (double)gv[q];
+        }
+      } else {
+        const int p = E.par_off + b - E.n_rig;
+        const int d = E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
+        const V3 f = scatter_particle(c, p, S.row_lam, buf);
+        const float m = S.p_m[p];
+        const float4 u = S.p_u[p], ut = S.p_ut[p];
+        const V3 gv = mk(m * (u.x - ut.x) - h * f.x, m * (u.y - ut.y) - h * f.y, m * (u.z - ut.z) - h * f.z);
+        float4 H = make_float4(m, m, m, 0.f);
+        if (A.p.geo_stiff && k >= 1) {
+          const V3 fh = scatter_particle(c, p, S.row_lam, buf ^ 1);
+          const float4 up = S.p_uprev[p];
+          const float du[3] = {u.x - up.x, u.y - up.y, u.z - up.z};
+          const float df[3] = {f.x - fh.x, f.y - fh.y, f.z - fh.z};
+          float hh[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const float cj = h * df[a] * du[a] / (du[a] * du[a] + kTauGS * kTauGS);
+            hh[a] = m - (cj < 0.f ? cj : 0.f);
+          }
+          H = make_float4(hh[0], hh[1], hh[2], 0.f);
+        }
+        S.p_H[p] = H;
+        S.g[d] = gv.x; S.g[d + 1] = gv.y; S.g[d + 2] = gv.z;
+        rg = fmaxf(rg, fmaxf(fmaxf(fabsf(gv.x / m), fabsf(gv.y / m)), fabsf(gv.z / m)));
+        m2 += (double)gv.x * gv.x + (double)gv.y * gv.y + (double)gv.z * gv.z;
+      }
+    }
+    float re = 0.f, rc = 0.f;
+    for (int r = tid; r < nrows; r += BS) {
+      const float ev = S.row_err[R0 + r];
+      const float a = fabsf(ev);
+      re = fmaxf(re, a);
+      if (R0 + r >= crow0) rc = fmaxf(rc, a);
+      m2 += (double)ev * ev;
+    }
+    // residual (READING: r_ncp = max(|M~^-1 g|_inf, |err|_inf)), merit |[g; err]|_2 in FP64
+    const float rmax = block_max<BS>(fmaxf(rg, re), red, 0);
+    const float rcon = block_max<BS>(rc, red, 1);
+    const double msum = block_sum<BS>(m2, red, 0);
+    r_ncp = rmax;
+    r_con = rcon;
+    merit = sqrt(msum);
+    if (k == 0) r_first = rmax;
+    if (!(rmax == rmax) || isinf(rmax)) { nonfinite = 1; break; }
+    if (A.tol > 0.f && rmax <= A.tol) { converged = 1; break; }
+    if (k == A.newton_iters) break;
+
+    // Schur right-hand side b = (1/h)(J H~^-1 g - err) and Jacobi preconditioner
+    // P = 1/(J H~^-1 J^T + C + eps)_ii (Sec. 6.2, 8.2, 8.4)
+    for (int b = tid; b < nb; b += BS) {
+      if (b < E.n_rig) {
+        const int g = E.rig_off + b;
+        const int d = E.dof_off + 6 * b;
+        float v[6];
+        for (int q = 0; q < 6; ++q) v[q] = S.g[d + q];
+        hinv_rigid(c, g, v);
+        for (int q = 0; q < 6; ++q) Y[d + q] = v[q];
+      } else {
+        const int p = E.par_off + b - E.n_rig;
+        const int d = E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
+        const float4 H = S.p_H[p];
+        Y[d] = S.g[d] / H.x; Y[d + 1] = S.g[d + 1] / H.y; Y[d + 2] = S.g[d + 2] / H.z;
+      }
+    }
+    __syncthreads();
+    for (int el = tid; el < nel; el += BS) {
+      float jy[6], dg[6];
+      int r0, r1;
+      const int nr = gather_element(c, el, Y, buf, jy, r0);
+      hdiag_element(c, el, buf, dg, r1);
+      for (int r = 0; r < nr; ++r) {
+        const int row = r0 + r;
+        const float bb = (jy[r] - S.row_err[row]) / h;
+        const float P = 1.f / (dg[r] + S.row_C[row] + eps);
+        S.row_b[row] = bb;
+        S.row_P[row] = P;
+      }
+    }
+    __syncthreads();
+
+    // ---- preconditioned conjugate residual (Sec. 8.2), x0 = 0, FP64 scalars ----
+    for (int r = tid; r < nrows; r += BS) {
+      const int row = R0 + r;
+      const float z = S.row_P[row] * S.row_b[row];
+      S.row_x[row] = 0.f;
+      S.row_z[row] = z;
+      S.row_p[row] = z;
+    }
+    __syncthreads();
+    double rho;
+    {
+      scatter_hinv(c, S.row_z, buf, Y, tid, BS);
+      __syncthreads();
+      double part = 0.0;
+      for (int el = tid; el < nel; el += BS) {
+        float w6[6];
+        int r0;
+        const int nr = gather_element(c, el, Y, buf, w6, r0);
+        add_compliance(c, el, r0, nr, S.row_z, w6);
+        for (int r = 0; r < nr; ++r) {
+          const float z = S.row_z[r0 + r];
+          const float w = w6[r] + eps * z;
+          S.row_w[r0 + r] = w;
+          S.row_q[r0 + r] = w;
+          part += (double)z * (double)w;
+        }
+      }
+      rho = block_sum<BS>(part, red, 1);
+    }
+    int done = 0;
+    for (int it = 0; it < A.cr_iters; ++it) {
+      if (!(rho > 0.0)) break;
+      double part = 0.0;
+      for (int r = tid; r < nrows; r += BS) {
+        const int row = R0 + r;
+        const float q = S.row_q[row];
+        const float s = S.row_P[row] * q;
+        S.row_b[row] = s;  // s = P q (b is no longer needed)
+        part += (double)q * (double)s;
+      }
+      const double qs = block_sum<BS>(part, red, 0);
+      if (!(qs > 0.0)) break;
+      const float alpha = (float)(rho / qs);
+      for (int r = tid; r < nrows; r += BS) {
+        const int row = R0 + r;
+        S.row_x[row] += alpha * S.row_p[row];
+        S.row_z[row] -= alpha * S.row_b[row];
+      }
+      ++done;
+      if (it == A.cr_iters - 1) break;  // the last update needs no further product
+      __syncthreads();
+      scatter_hinv(c, S.row_z, buf, Y, tid, BS);
+      __syncthreads();
+      part = 0.0;
+      for (int el = tid; el < nel; el += BS) {
+        float w6[6];
+        int r0;
+        const int nr = gather_element(c, el, Y, buf, w6, r0);
+        add_compliance(c, el, r0, nr, S.row_z, w6);
+        for (int r = 0; r < nr; ++r) {
+          const float z = S.row_z[r0 + r];
+          const float w = w6[r] + eps * z;
+          S.row_w[r0 + r] = w;
+          part += (double)z * (double)w;
+        }
+      }
+      const double rho_new = block_sum<BS>(part, red, 1);
+      const float beta = (float)(rho_new / rho);
+      rho = rho_new;
+      for (int r = tid; r < nrows; r += BS) {
+        const int row = R0 + r;
+        S.row_p[row] = S.row_z[row] + beta * S.row_p[row];
+        S.row_q[row] = S.row_w[row] + beta * S.row_q[row];
+      }
+    }
+    cr_total += done;
+    __syncthreads();
+
+    // ---- update: du = H~^-1 (h J^T dlambda - g), damped step t (Sec. 6.2, 8.1) ----
+    for (int b = tid; b < nb; b += BS) {
+      if (b < E.n_rig) {
+        const int g = E.rig_off + b;
+        const int d = E.dof_off + 6 * b;
+        float v[6];
+        scatter_rigid(c, g, S.row_x, buf, v);
+        for (int q = 0; q < 6; ++q) v[q] = h * v[q] - S.g[d + q];
+        hinv_rigid(c, g, v);
+        float *u = S.r_u + 6 * g;
+        for (int q = 0; q < 6; ++q) u[q] += damp * v[q];
+      } else {
+        const int p = E.par_off + b - E.n_rig;
+        const int d = E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
+        const V3 a = scatter_particle(c, p, S.row_x, buf);
+        const float4 H = S.p_H[p];
+        const float4 u = S.p_u[p];
+        S.p_uprev[p] = u;
+        S.p_u[p] = make_float4(u.x + damp * (h * a.x - S.g[d]) / H.x, u.y + damp * (h * a.y - S.g[d + 1]) / H.y,
+                               u.z + damp * (h * a.z - S.g[d + 2]) / H.z, 0.f);
+      }
+    }
+    __syncthreads();
+    for (int r = tid; r < nrows; r += BS) S.row_lam[R0 + r] += damp * S.row_x[R0 + r];
+    for (int b = tid; b < nb; b += BS) update_positions_body(c, b);
+    __syncthreads();
+    ++newton_done;
+  }
+
+  // ---- write-back ----
+  for (int b = tid; b < nb; b += BS) {
+    if (b < E.n_rig) {
+      const int g = E.rig_off + b;
+      if (S.r_inertia[g].w == 0.f) continue;
+      const float *u = S.r_u + 6 * g;
+      S.r_v[g] = make_float4(u[0], u[1], u[2], 0.f);
+      S.r_w[g] = make_float4(u[3], u[4], u[5], 0.f);
+    } else {
+      const int p = E.par_off + b - E.n_rig;
+      S.p_v[p] = S.p_u[p];
+    }
+  }
+  for (int i = tid; i < nc; i += BS) {
+    const int gc = E.con_off + i;
+    const int r0 = row_con(E, i);
+    S.c_prev_key[gc] = S.c_key[gc];
+    S.c_prev_lam[gc] = make_float4(S.row_lam[r0], S.row_lam[r0 + 1], S.row_lam[r0 + 2], 0.f);
+  }
+  if (tid == 0) {
+    S.n_prev[e] = nc;
+    S.time[e] = tplus;
+    nsn_step_stats st;
+    st.newton_iters = newton_done;
+    st.cr_iters = cr_total;
+    st.n_contacts = nc;
+    st.overflow = S.overflow[e];
+    st.nonfinite = nonfinite;
+    st.converged = converged;
+    st.r_ncp = r_ncp;
+    st.r_contact = r_con;
+    st.merit = merit;
+    st.r_ncp_first = r_first;
+    S.stats[e] = st;
+  }
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_features, hipStream_t st) {
+  hipLaunchKernelGGL(k_prepare<256>, dim3(s.n_envs), dim3(256), 0, st, s, a, want_features);
+  return hipGetLastError();
+}
+
+hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count,
+                         hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  switch (block) {
+    case 64: hipLaunchKernelGGL(k_newton<64>, dim3(count), dim3(64), 0, st, s, a, first); break;
+    case 128: hipLaunchKernelGGL(k_newton<128>, dim3(count), dim3(128), 0, st, s, a, first); break;
+    case 256: hipLaunchKernelGGL(k_newton<256>, dim3(count), dim3(256), 0, st, s, a, first); break;
+    case 512: hipLaunchKernelGGL(k_newton<512>, dim3(count), dim3(512), 0, st, s, a, first); break;
+    case 1024: hipLaunchKernelGGL(k_newton<1024>, dim3(count), dim3(1024), 0, st, s, a, first); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace nsn

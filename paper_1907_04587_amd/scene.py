@@ -1,0 +1,188 @@
+"""Scene: a batch of environments stepped by libnsn on one GPU."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+def params_c(p) -> L.ParamsC:
+    """C parameter struct from any object with the SolverParams fields."""
+    return L.ParamsC(ncp=int(p.ncp), rmode=int(p.rmode), damping=float(p.damping), eps=float(p.eps),
+                     geo_stiff=int(p.geo_stiff), fem_mode=int(p.fem_mode), margin=float(p.margin),
+                     warm=int(p.warm))
+
+
+def stats_to_dicts(arr):
+    return [{k: arr[k][i].item() for k in arr.dtype.names} for i in range(len(arr))]
+
+
+class _Marshal:
+    """Keeps the float32/int32 copies of the descriptors alive during create."""
+
+    def __init__(self, envs):
+        self.keep = []
+        self.c = (L.EnvDescC * len(envs))()
+        for i, d in enumerate(envs):
+            s = self.c[i]
+            s.n_rigid = d.n_rigid
+            s.n_particles = d.n_particles
+            s.n_tets = d.n_tets
+            s.n_joints = d.n_joints
+            for name in ["rigid_mass", "rigid_inertia", "rigid_x", "rigid_q", "rigid_v", "rigid_w",
+                         "rigid_extent", "particle_x", "particle_v", "particle_rest", "particle_mass",
+                         "tet_material", "joint_anchor", "joint_axis", "joint_ref", "joint_drive"]:
+                a = np.ascontiguousarray(getattr(d, name), dtype=np.float32).ravel()
+                if a.size == 0:
+                    a = np.zeros(1, np.float32)
+                self.keep.append(a)
+                setattr(s, name, L.fptr(a))
+            for name in ["rigid_shape", "tet_ids", "joint_type", "joint_body"]:
+                a = np.ascontiguousarray(getattr(d, name), dtype=np.int32).ravel()
+                if a.size == 0:
+                    a = np.zeros(1, np.int32)
+                self.keep.append(a)
+                setattr(s, name, L.iptr(a))
+            s.mu = float(d.mu)
+            s.gravity = (C.c_float * 3)(*d.gravity)
+            s.ground = int(d.ground)
+            s.max_contacts = int(d.max_contacts)
+
+
+class Scene:
+    """A batch of environments on one GPU.
+
+    envs: list of scene_inputs.EnvDesc; params: object with the SolverParams fields.
+    The device workspace is one torch uint8 tensor; the stream is torch's current
+    stream at creation (or `stream`)."""
+
+    def __init__(self, envs, params, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.lib = L.lib()
+        self.envs = list(envs)
+        self.n_envs = len(self.envs)
+        m = _Marshal(self.envs)
+        nbytes = C.c_size_t(0)
+        L.check(self.lib.nsn_query_workspace(m.c, self.n_envs, C.byref(nbytes)), "nsn_query_workspace")
+        self.workspace_bytes = int(nbytes.value)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._params = params
+        pc = params_c(params)
+        h = C.c_void_p()
+        L.check(self.lib.nsn_create_scene(m.c, self.n_envs, C.byref(pc), C.c_void_p(self.stream.cuda_stream),
+                                          C.c_void_p(self.workspace.data_ptr()), self.workspace_bytes,
+                                          C.byref(h)), "nsn_create_scene")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.nsn_destroy_scene(h)
+            self.h = None
+
+    # ---- stepping ----
+    def set_params(self, params):
+        pc = params_c(params)
+        L.check(self.lib.nsn_set_params(self.h, C.byref(pc)), "nsn_set_params")
+        self._params = params
+
+    def step(self, h, newton_iters, cr_iters, tol=0.0):
+        L.check(self.lib.nsn_step(self.h, float(h), int(newton_iters), int(cr_iters), float(tol)), "nsn_step")
+
+    def stats(self):
+        arr = (L.StatsC * self.n_envs)()
+        L.check(self.lib.nsn_get_stats(self.h, arr), "nsn_get_stats")
+        return np.frombuffer(bytes(arr), dtype=L.STATS_DTYPE).copy()
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    # ---- state I/O ----
+    def read_state(self, env):
+        d = self.envs[env]
+        rx = np.zeros((d.n_rigid, 3), np.float32); rq = np.zeros((d.n_rigid, 4), np.float32)
+        rv = np.zeros((d.n_rigid, 3), np.float32); rw = np.zeros((d.n_rigid, 3), np.float32)
+        px = np.zeros((d.n_particles, 3), np.float32); pv = np.zeros((d.n_particles, 3), np.float32)
+        t = C.c_double(0.0)
+        L.check(self.lib.nsn_read_state(self.h, env, L.fptr(rx), L.fptr(rq), L.fptr(rv), L.fptr(rw),
+                                        L.fptr(px), L.fptr(pv), C.byref(t)), "nsn_read_state")
+        return dict(rigid_x=rx, rigid_q=rq, rigid_v=rv, rigid_w=rw, particle_x=px, particle_v=pv,
+                    time=t.value)
+
+    def write_state(self, env, st):
+        d = self.envs[env]
+
+        def g(k, shape):
+            if k not in st or st[k] is None:
+                return None
+            return L.f32(np.asarray(st[k]).reshape(shape))
+        arrs = [g("rigid_x", (d.n_rigid, 3)), g("rigid_q", (d.n_rigid, 4)), g("rigid_v", (d.n_rigid, 3)),
+                g("rigid_w", (d.n_rigid, 3)), g("particle_x", (d.n_particles, 3)),
+                g("particle_v", (d.n_particles, 3))]
+        t = C.c_double(st["time"]) if "time" in st and st["time"] is not None else None
+        L.check(self.lib.nsn_write_state(self.h, env, *[L.fptr(a) for a in arrs],
+                                         C.byref(t) if t is not None else None), "nsn_write_state")
+
+    def contacts(self, env):
+        cap = self.envs[env].max_contacts
+        n = C.c_int32(0)
+        keys = np.zeros(max(cap, 1), np.int32); bodies = np.zeros((max(cap, 1), 2), np.int32)
+        geom = np.zeros((max(cap, 1), 10), np.float32); lam = np.zeros((max(cap, 1), 3), np.float32)
+        L.check(self.lib.nsn_read_contacts(self.h, env, cap, C.byref(n), L.iptr(keys), L.iptr(bodies),
+                                           L.fptr(geom), L.fptr(lam)), "nsn_read_contacts")
+        k = min(n.value, cap)
+        return dict(key=keys[:k].astype(np.int64), bodies=bodies[:k], normal=geom[:k, 0:3],
+                    a_local=geom[:k, 3:6], b_local=geom[:k, 6:9], thickness=geom[:k, 9], lam=lam[:k])
+
+    def lambdas(self, env):
+        d = self.envs[env]
+        cap = 6 * d.n_joints + 3 * d.n_tets + 3 * d.max_contacts
+        out = np.zeros(max(cap, 1), np.float32)
+        n = C.c_int32(0)
+        L.check(self.lib.nsn_read_lambda(self.h, env, cap, C.byref(n), L.fptr(out)), "nsn_read_lambda")
+        return out[:n.value]
+
+    def enable_features(self, on=True):
+        L.check(self.lib.nsn_enable_features(self.h, int(bool(on))), "nsn_enable_features")
+
+    def features(self, env):
+        cap = self.envs[env].max_contacts
+        out = np.zeros((max(cap, 1), 12), np.float32)
+        n = C.c_int32(0)
+        L.check(self.lib.nsn_read_features(self.h, env, cap, C.byref(n), L.fptr(out)), "nsn_read_features")
+        return out[:min(n.value, cap)]
+
+    def set_warm_start_model(self, blob):
+        b = L.f32(blob).ravel()
+        L.check(self.lib.nsn_set_warm_start_model(self.h, L.fptr(b), b.size), "nsn_set_warm_start_model")
+
+    def set_use_graphs(self, on):
+        L.check(self.lib.nsn_set_use_graphs(self.h, int(bool(on))), "nsn_set_use_graphs")
+
+    # ---- schedule ----
+    def env_order(self):
+        out = np.zeros(self.n_envs, np.int32)
+        L.check(self.lib.nsn_get_env_order(self.h, L.iptr(out)), "nsn_get_env_order")
+        return out
+
+    def set_schedule(self, buckets):
+        """buckets: list of (first, count, block) tiling the env order."""
+        first = np.array([b[0] for b in buckets], np.int32)
+        count = np.array([b[1] for b in buckets], np.int32)
+        block = np.array([b[2] for b in buckets], np.int32)
+        L.check(self.lib.nsn_set_schedule(self.h, len(buckets), L.iptr(first), L.iptr(count), L.iptr(block)),
+                "nsn_set_schedule")
+
+    def schedule(self):
+        cap = 64
+        n = C.c_int32(0)
+        f, c, b = np.zeros(cap, np.int32), np.zeros(cap, np.int32), np.zeros(cap, np.int32)
+        L.check(self.lib.nsn_get_schedule(self.h, cap, C.byref(n), L.iptr(f), L.iptr(c), L.iptr(b)),
+                "nsn_get_schedule")
+        return [(int(f[i]), int(c[i]), int(b[i])) for i in range(n.value)]

@@ -1,0 +1,78 @@
+"""Host-side checks of libnsn.so that need no GPU: every symbol declared in
+include/nsn.h is exported, and descriptor validation in nsn_query_workspace
+rejects malformed inputs with NSN_EINVAL / NSN_EUNSUPPORTED."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import scene_inputs as si
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1907_04587_amd import _lib as L
+    return L, L.lib()
+
+
+def test_library_exports_every_declared_symbol():
+    L, lib = _lib()
+    header = open(os.path.join(ROOT, "include", "nsn.h")).read()
+    names = sorted(set(re.findall(r"\b(nsn_\w+)\s*\(", header)))
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def _query(envs):
+    from paper_1907_04587_amd.scene import _Marshal
+    L, lib = _lib()
+    m = _Marshal(envs)
+    n = C.c_size_t(0)
+    st = lib.nsn_query_workspace(m.c, len(envs), C.byref(n))
+    return st, n.value, lib.nsn_last_error().decode()
+
+
+def test_workspace_query_valid_scenes():
+    st, n, _ = _query([si.cube_stack(0)])
+    assert st == 0 and n > 0
+    st2, n2, _ = _query([si.cube_stack(0), si.tet_block_with_boxes(0, cells=3, n_boxes=2)])
+    assert st2 == 0 and n2 > n
+
+
+@pytest.mark.parametrize("mutate,expect", [
+    (lambda d: d.tet_ids.__setitem__((0, 1), 99), -1),
+    (lambda d: d.tet_material.__setitem__((0, 1), 0.5), -1),
+    (lambda d: d.tet_material.__setitem__((0, 0), -1.0), -1),
+])
+def test_workspace_query_rejects_bad_tets(mutate, expect):
+    d = si.single_tet()
+    mutate(d)
+    st, _, msg = _query([d])
+    assert st == expect and "tet" in msg
+
+
+def test_workspace_query_rejects_bad_rigid_and_joint():
+    d = si.cube_stack(n=2)
+    d.rigid_inertia[0, 2] = 0.0
+    st, _, msg = _query([d])
+    assert st == -1 and "inertia" in msg
+    d = si.pendulum_drive()
+    d.joint_body[0] = (0, 0)
+    st, _, msg = _query([d])
+    assert st == -1 and "joint" in msg
+    d = si.cube_stack(n=1)
+    d.rigid_mass[0] = -1.0
+    st, _, _ = _query([d])
+    assert st == -1
+
+
+def test_python_layer_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_1907_04587_amd import _lib as L
+    monkeypatch.setattr(L, "_L", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        L.lib()
