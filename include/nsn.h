@@ -136,6 +136,21 @@ typedef struct {
   double r_ncp_first;   /* residual at the start iterate */
 } nsn_step_stats;
 
+/* Per-env totals accumulated by every step since the scene was created or the last
+ * nsn_reset_accumulators(). */
+typedef struct {
+  int64_t steps;
+  int64_t newton_iters;
+  int64_t cr_iters;
+  int64_t converged;        /* steps that ended with r_ncp <= tol (tol > 0) */
+  int64_t nonfinite;
+  double cr_bytes;          /* algorithmic bytes of the PCR loop: per PCR iteration
+                               332 B per tet + 228 B per contact + 880 B per joint
+                               + 12 B per body-space DOF (vectors, compressed J and
+                               compliance read/written once per iteration, J read
+                               twice), times the PCR iterations performed */
+} nsn_accum;
+
 /* Last error message of the calling thread ("" if none).  Never NULL. */
 const char *nsn_last_error(void);
 
@@ -223,6 +238,16 @@ nsn_status nsn_set_schedule(nsn_scene s, int32_t n_buckets, const int32_t *first
                             const int32_t *block);
 nsn_status nsn_get_schedule(nsn_scene s, int32_t cap, int32_t *n, int32_t *first, int32_t *count,
                             int32_t *block);
+
+/* Copy the per-env accumulators (out[n_envs], host) / reset them to zero. */
+nsn_status nsn_read_accumulators(nsn_scene s, nsn_accum *out);
+nsn_status nsn_reset_accumulators(nsn_scene s);
+
+/* Duration of the Newton kernel launch(es) of the last min(cap, steps, 1024) steps,
+ * oldest first, in ms: from the first workgroup's start to the last workgroup's end,
+ * read from the GPU wall clock inside the kernel (so it also works under hipGraph
+ * replay).  *n receives the count.  Synchronises the stream. */
+nsn_status nsn_read_kernel_times(nsn_scene s, int32_t cap, int32_t *n, double *ms);
 
 /* Device address of the per-env nsn_step_stats array (n_envs entries), valid for
  * the scene's lifetime, for readers that copy it asynchronously. */

@@ -26,6 +26,9 @@
 #define KAPPA_W 1e-4     /* READING: floor on the FB friction denominator, relative to r*mu*lambda_n */
 #define CLAMP_FEM 1e-3   /* READING: eigenvalue floor of the material Hessian, relative to 2*C1*Ve */
 #define JACOBI_SWEEPS 6
+#define TAU_NCP 1e-6      /* READING: derivative band around the NCP kink (units of C) */
+#define TAU_EIG 1e-6      /* READING: relative size below which Jacobi skips a rotation / treats
+                             eigenvalues as tied */
 #define MAX_HIST 256
 #define MLP_IN 12
 #define MLP_H 64
@@ -127,12 +130,15 @@ void orc_tangent_basis(const double *n, double *d1, double *d2) {
 
 /* Appendix A.1, FB form with the r factor: phi = C + r lam - sqrt(C^2 + r^2 lam^2);
  * alpha = d phi / dC, beta = 1 - r lam / sqrt(..) so that d phi / d lam = beta r.
- * At (0,0) the subgradient choice alpha = 0, beta = 1 of Sec. 4.2. */
+ * At (0,0) the subgradient choice alpha = 0, beta = 1 of Sec. 4.2.  READING: the
+ * derivative takes that choice whenever sqrt(C^2 + r^2 lam^2) <= TAU_NCP, i.e. when the
+ * point is (0,0) up to the rounding of positions (every resting contact starts there at
+ * the zero start iterate); phi itself is always exact. */
 void orc_ncp_fb(double C, double lam, double r, double *phi, double *alpha, double *beta) {
   double rl = r * lam;
   double rho = sqrt(C * C + rl * rl);
   *phi = C + rl - rho;
-  if (rho > 0.0) {
+  if (rho > TAU_NCP) {
     *alpha = 1.0 - C / rho;
     *beta = 1.0 - rl / rho;
   } else {
@@ -141,12 +147,16 @@ void orc_ncp_fb(double C, double lam, double r, double *phi, double *alpha, doub
   }
 }
 
-/* Appendix A.1, minimum map with r: phi = C if C <= r lam else r lam. */
+/* Appendix A.1, minimum map with r: phi = min(C, r lam); derivative of the C branch
+ * when C <= r lam.  READING: the branch test is C <= r lam + TAU_NCP so that ties up to
+ * the rounding of positions take the C branch on every precision; phi is exact. */
 void orc_ncp_min(double C, double lam, double r, double *phi, double *alpha, double *beta) {
-  if (C <= r * lam) {
-    *phi = C; *alpha = 1.0; *beta = 0.0;
+  double rl = r * lam;
+  *phi = C < rl ? C : rl;
+  if (C <= rl + TAU_NCP) {
+    *alpha = 1.0; *beta = 0.0;
   } else {
-    *phi = r * lam; *alpha = 0.0; *beta = 1.0;
+    *alpha = 0.0; *beta = 1.0;
   }
 }
 
@@ -183,12 +193,21 @@ double orc_friction_w(int ncp, double vnorm, double lam_n, double lamf_norm, dou
 
 /* Cyclic Jacobi on a symmetric 3x3 (row-major).  Fixed sweep count; pairs in the
  * order (0,1), (0,2), (1,2).  On return w holds the eigenvalues sorted descending
- * (ties keep index order) and Q the matching eigenvectors as columns. */
+ * and Q the matching eigenvectors as columns.  READING for repeated singular values
+ * (the rest state F = I): a matrix whose off-diagonals are all below TAU_EIG times its
+ * trace is taken as diagonal (no rotation), and eigenvalues within TAU_EIG relative of
+ * each other are ties that keep index order, so a basis that is arbitrary in exact
+ * arithmetic comes out the same on every precision. */
 void orc_sym_eig3(const double *Ain, double *Q, double *w) {
   double A[9], V[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   memcpy(A, Ain, sizeof A);
   static const int PP[3] = {0, 0, 1}, QQ[3] = {1, 2, 2};
-  for (int sweep = 0; sweep < JACOBI_SWEEPS; ++sweep) {
+  double tr = fabs(A[0]) + fabs(A[4]) + fabs(A[8]);
+  double off = fabs(A[1]);
+  if (fabs(A[2]) > off) off = fabs(A[2]);
+  if (fabs(A[5]) > off) off = fabs(A[5]);
+  int sweeps = off <= TAU_EIG * tr ? 0 : JACOBI_SWEEPS;
+  for (int sweep = 0; sweep < sweeps; ++sweep) {
     for (int k = 0; k < 3; ++k) {
       int p = PP[k], q = QQ[k];
       double apq = A[3 * p + q];
@@ -220,7 +239,7 @@ void orc_sym_eig3(const double *Ain, double *Q, double *w) {
   /* stable descending sort of 3 entries */
   for (int i = 1; i < 3; ++i) {
     int j = i;
-    while (j > 0 && ev[idx[j - 1]] < ev[idx[j]]) {
+    while (j > 0 && ev[idx[j]] - ev[idx[j - 1]] > TAU_EIG * (fabs(ev[idx[j]]) + fabs(ev[idx[j - 1]]))) {
       int t = idx[j]; idx[j] = idx[j - 1]; idx[j - 1] = t;
       --j;
     }

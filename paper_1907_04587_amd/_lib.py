@@ -44,6 +44,9 @@ class StatsC(C.Structure):
                 ("r_ncp_first", C.c_double)]
 
 
+ACC_DTYPE = np.dtype([("steps", np.int64), ("newton_iters", np.int64), ("cr_iters", np.int64),
+                      ("converged", np.int64), ("nonfinite", np.int64), ("cr_bytes", np.float64)])
+
 STATS_DTYPE = np.dtype([("newton_iters", np.int32), ("cr_iters", np.int32), ("n_contacts", np.int32),
                         ("overflow", np.int32), ("nonfinite", np.int32), ("converged", np.int32),
                         ("r_ncp", np.float64), ("r_contact", np.float64), ("merit", np.float64),
@@ -87,6 +90,9 @@ def lib():
     L.nsn_set_schedule.argtypes = [VP, S, I32, I32, I32]
     L.nsn_get_schedule.argtypes = [VP, S, I32, I32, I32, I32]
     L.nsn_stats_device_ptr.argtypes = [VP, C.POINTER(VP)]
+    L.nsn_read_kernel_times.argtypes = [VP, S, I32, D]
+    L.nsn_read_accumulators.argtypes = [VP, VP]
+    L.nsn_reset_accumulators.argtypes = [VP]
     L.nsn_mlp_forward.argtypes = [VP, VP, VP, C.c_int64, VP]
     L.nsn_mlp_scratch_bytes.restype = C.c_size_t
     L.nsn_mlp_scratch_bytes.argtypes = [C.c_int64]

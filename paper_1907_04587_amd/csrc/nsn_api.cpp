@@ -149,6 +149,9 @@ void layout(const Sizes &z, int n_envs, Arena &a, DevScene &S, EnvInfo *&env, in
   S.stats = a.take<nsn_step_stats>(n_envs);
   S.mlp = a.take<float>(kMlpBlob);
   S.have_mlp = 0;
+  S.tick = a.take<int>(1);
+  S.ts = a.take<unsigned long long>(2 * kTimingRing);
+  S.acc = a.take<nsn_accum>(n_envs);
 }
 
 Sizes sizes_of(const std::vector<HostEnv> &he) {
@@ -731,6 +734,42 @@ nsn_status nsn_get_schedule(nsn_scene s, int32_t cap, int32_t *n, int32_t *first
     first[i] = s->buckets[i].first;
     count[i] = s->buckets[i].count;
     block[i] = s->buckets[i].block;
+  }
+  return NSN_OK;
+}
+
+nsn_status nsn_read_accumulators(nsn_scene s, nsn_accum *out) {
+  if (!s || !out) return fail(NSN_EINVAL, "bad arguments");
+  HIP_TRY(hipMemcpyAsync(out, s->S.acc, sizeof(nsn_accum) * s->S.n_envs, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return NSN_OK;
+}
+
+nsn_status nsn_reset_accumulators(nsn_scene s) {
+  if (!s) return fail(NSN_EINVAL, "null scene");
+  HIP_TRY(hipMemsetAsync(s->S.acc, 0, sizeof(nsn_accum) * s->S.n_envs, s->stream));
+  return NSN_OK;
+}
+
+nsn_status nsn_read_kernel_times(nsn_scene s, int32_t cap, int32_t *n, double *ms) {
+  if (!s || !n || cap < 0) return fail(NSN_EINVAL, "bad arguments");
+  int tick = 0;
+  std::vector<unsigned long long> ts(2 * kTimingRing);
+  HIP_TRY(hipMemcpyAsync(&tick, s->S.tick, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipMemcpyAsync(ts.data(), s->S.ts, sizeof(unsigned long long) * 2 * kTimingRing, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  int dev = 0, rate_khz = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+  if (rate_khz <= 0) return fail(NSN_EDEVICE, "wall clock rate unavailable");
+  const int avail = std::min(tick, kTimingRing);
+  const int m = std::min(avail, cap);
+  *n = m;
+  for (int i = 0; i < m; ++i) {
+    const int step = tick - m + 1 + i;
+    const int slot = step % kTimingRing;
+    const unsigned long long a = ts[2 * slot], b = ts[2 * slot + 1];
+    ms[i] = (b > a) ? (double)(b - a) / (double)rate_khz : 0.0;
   }
   return NSN_OK;
 }

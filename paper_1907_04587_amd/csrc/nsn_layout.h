@@ -109,7 +109,18 @@ struct DevScene {
   // learned warm start
   const float *mlp;
   int have_mlp;
+
+  // launch timing: step counter and per-step (first start, last end) wall clock of
+  // the Newton kernel(s), a ring of kTimingRing steps
+  int *tick;
+  unsigned long long *ts;
+  nsn_accum *acc;
 };
+
+// algorithmic bytes of one PCR iteration (see nsn_accum)
+constexpr double kBytesTet = 332.0, kBytesContact = 228.0, kBytesJoint = 880.0, kBytesDof = 12.0;
+
+constexpr int kTimingRing = 1024;
 
 struct StepArgs {
   float h;

@@ -26,6 +26,8 @@ constexpr float kTauGS = 1e-6f;     // secant smoothing velocity (m/s)
 constexpr float kKappaW = 1e-4f;    // floor of the FB friction denominator (relative)
 constexpr float kClampFem = 1e-3f;  // eigenvalue floor of the material Hessian (relative to 2 C1 Ve)
 constexpr int kJacobiSweeps = 6;
+constexpr float kTauNcp = 1e-6f;    // derivative band around the NCP kink (units of C)
+constexpr float kTauEig = 1e-6f;    // relative Jacobi skip / eigenvalue tie tolerance
 
 // --------------------------------------------------------------------------
 // block-level reductions (fixed order -> deterministic)
@@ -98,20 +100,22 @@ __device__ __forceinline__ void ncp_fb(float C, float lam, float r, float &phi, 
   const float rl = r * lam;
   const float rho = sqrtf(C * C + rl * rl);
   phi = C + rl - rho;
-  if (rho > 0.f) {
+  if (rho > kTauNcp) {
     al = 1.f - C / rho;
     be = 1.f - rl / rho;
-  } else {  // subgradient choice at (0,0), Sec. 4.2
+  } else {  // subgradient choice at (0,0), Sec. 4.2, within rounding of the kink
     al = 0.f;
     be = 1.f;
   }
 }
 
 __device__ __forceinline__ void ncp_min(float C, float lam, float r, float &phi, float &al, float &be) {
-  if (C <= r * lam) {
-    phi = C; al = 1.f; be = 0.f;
+  const float rl = r * lam;
+  phi = fminf(C, rl);
+  if (C <= rl + kTauNcp) {
+    al = 1.f; be = 0.f;
   } else {
-    phi = r * lam; al = 0.f; be = 1.f;
+    al = 0.f; be = 1.f;
   }
 }
 
@@ -141,7 +145,11 @@ __device__ void sym_eig3(const float *Ain, M3 &Q, float w[3]) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) A[i] = Ain[i];
   float V[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
-  for (int sweep = 0; sweep < kJacobiSweeps; ++sweep) {
+  // diagonal up to rounding (the rest state): no rotation, so the basis is canonical
+  const float tr = fabsf(A[0]) + fabsf(A[4]) + fabsf(A[8]);
+  const float off = fmaxf(fabsf(A[1]), fmaxf(fabsf(A[2]), fabsf(A[5])));
+  const int sweeps = off <= kTauEig * tr ? 0 : kJacobiSweeps;
+  for (int sweep = 0; sweep < sweeps; ++sweep) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int p = k == 2 ? 1 : 0;
@@ -174,11 +182,12 @@ __device__ void sym_eig3(const float *Ain, M3 &Q, float w[3]) {
   }
   float ev[3] = {A[0], A[4], A[8]};
   int idx[3] = {0, 1, 2};
-  // stable descending sort of three entries
-  if (ev[idx[0]] < ev[idx[1]]) { int t = idx[0]; idx[0] = idx[1]; idx[1] = t; }
-  if (ev[idx[1]] < ev[idx[2]]) {
+  // descending insertion sort of three entries; near-ties keep index order
+  auto gt = [](float a, float b) { return a - b > kTauEig * (fabsf(a) + fabsf(b)); };
+  if (gt(ev[idx[1]], ev[idx[0]])) { int t = idx[0]; idx[0] = idx[1]; idx[1] = t; }
+  if (gt(ev[idx[2]], ev[idx[1]])) {
     int t = idx[1]; idx[1] = idx[2]; idx[2] = t;
-    if (ev[idx[0]] < ev[idx[1]]) { t = idx[0]; idx[0] = idx[1]; idx[1] = t; }
+    if (gt(ev[idx[1]], ev[idx[0]])) { t = idx[0]; idx[0] = idx[1]; idx[1] = t; }
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -590,6 +599,13 @@ __global__ __launch_bounds__(BS) void k_prepare(DevScene S, StepArgs A, int want
     S.p_ut[g] = make_float4(v.x + h * grav.x, v.y + h * grav.y, v.z + h * grav.z, 0.f);
   }
   if (tid == 0) s_count = 0;
+  if (e == 0 && tid == 0) {  // new timing slot for this step
+    const int t = S.tick[0] + 1;
+    S.tick[0] = t;
+    const int slot = t % kTimingRing;
+    S.ts[2 * slot] = ~0ull;
+    S.ts[2 * slot + 1] = 0ull;
+  }
   __syncthreads();
   for (int j = tid; j < E.n_jnt; j += BS) {
     const int jg = E.jnt_off + j;
@@ -1242,6 +1258,7 @@ __device__ void assemble_all(const Ctx &c, int buf, bool physical, double tplus,
 template <int BS>
 __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first) {
   __shared__ Red<BS> red;
+  const unsigned long long t_start = wall_clock64();
   Ctx c;
   c.S = S;
   const int e = S.env_order[first + blockIdx.x];
@@ -1571,6 +1588,18 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     st.merit = merit;
     st.r_ncp_first = r_first;
     S.stats[e] = st;
+    nsn_accum a = S.acc[e];
+    a.steps += 1;
+    a.newton_iters += newton_done;
+    a.cr_iters += cr_total;
+    a.converged += converged;
+    a.nonfinite += nonfinite;
+    a.cr_bytes += (double)cr_total * (kBytesTet * E.n_tet + kBytesContact * nc + kBytesJoint * E.n_jnt +
+                                      kBytesDof * (6.0 * E.n_rig + 3.0 * E.n_par));
+    S.acc[e] = a;
+    const int slot = S.tick[0] % kTimingRing;
+    atomicMin(S.ts + 2 * slot, t_start);
+    atomicMax(S.ts + 2 * slot + 1, (unsigned long long)wall_clock64());
   }
 }
 

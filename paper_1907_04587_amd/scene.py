@@ -165,6 +165,21 @@ class Scene:
     def set_use_graphs(self, on):
         L.check(self.lib.nsn_set_use_graphs(self.h, int(bool(on))), "nsn_set_use_graphs")
 
+    def accumulators(self):
+        out = np.zeros(self.n_envs, L.ACC_DTYPE)
+        L.check(self.lib.nsn_read_accumulators(self.h, out.ctypes.data), "nsn_read_accumulators")
+        return out
+
+    def reset_accumulators(self):
+        L.check(self.lib.nsn_reset_accumulators(self.h), "nsn_reset_accumulators")
+
+    def kernel_times_ms(self, cap=1024):
+        out = np.zeros(cap, np.float64)
+        n = C.c_int32(0)
+        L.check(self.lib.nsn_read_kernel_times(self.h, cap, C.byref(n), out.ctypes.data_as(L.D)),
+                "nsn_read_kernel_times")
+        return out[:n.value]
+
     # ---- schedule ----
     def env_order(self):
         out = np.zeros(self.n_envs, np.int32)

@@ -444,79 +444,73 @@ def batched_envs(n_envs=4096, base_seed=1000, **kw) -> List[EnvDesc]:
 def grasp_scene(seed=0, n_fingers=4, links_per_finger=4, link_len=0.04, link_mass=0.05,
                 link_radius=0.01, sphere_radius=0.05, sphere_cell=None, E=5e4, nu=0.45,
                 rho=1000.0, mu=0.8, kp=5.0, kd=0.05, max_contacts=1024):
-    """Articulated hand on a 6-DoF arm (3 prismatic + 3 revolute, 1 kg links, world
-    base) whose four 4-link capsule fingers squeeze a tet-FEM sphere resting on the
-    ground.  Every joint carries a PD drive following a seeded sinusoid."""
+    """Articulated hand on a 6-DoF arm (3 prismatic + 3 revolute links of 1 kg, held by
+    stiff drives) with four 4-link capsule fingers hanging around a tet-FEM sphere that
+    rests on the ground.  Finger joints are PD-driven towards seeded sinusoids that
+    curl the fingers inwards and squeeze the sphere."""
     rng = np.random.default_rng(seed)
     if sphere_cell is None:
         sphere_cell = 0.0108
-    sx, tets = sphere_tets(sphere_radius, sphere_cell, (0.0, 0.0, sphere_radius + 1e-3))
+    cz = sphere_radius + 1e-3
+    sx, tets = sphere_tets(sphere_radius, sphere_cell, (0.0, 0.0, cz))
+    sx[:, 2] += 1e-3 - sx[:, 2].min()  # voxelised sphere resting 1 mm above the ground
     d = _empty(mu=mu, max_contacts=max_contacts, name=f"grasp(seed={seed})")
     _set_tets(d, sx, tets, E, nu, rho)
     bodies, joints = [], []
-    palm_z = 2.0 * sphere_radius + 0.06
     ex, ey, ez = (1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0)
-
-    def drive(amp_max=0.6, offset=0.0):
-        return (kp, kd, rng.uniform(0.0, amp_max), rng.uniform(0.2, 1.0),
-                rng.uniform(0.0, 2 * math.pi), offset)
-
-    # arm: 3 prismatic (x, y, z) then 3 revolute (z, y, x) links, 1 kg each, small boxes
+    finger_len = links_per_finger * link_len
+    palm_half = (0.09, 0.09, 0.01)
+    palm_bottom = finger_len + 2.0 * link_radius + 0.005
+    palm_z = palm_bottom + palm_half[2]
+    arm_z = palm_z + 0.1
     arm_h = (0.02, 0.02, 0.02)
-    axes = [ex, ey, ez]
+    # arm: prismatic x, y, z from the world, then revolute z, y, x; stiff drives hold it
     prev = -1
-    for a in range(3):
-        bodies.append(_nocollide(_box(1.0, arm_h, (0.0, 0.0, palm_z + 0.1))))
+    for a, axis in enumerate([ex, ey, ez]):
+        bodies.append(_nocollide(_box(1.0, arm_h, (0.0, 0.0, arm_z))))
         idx = len(bodies) - 1
-        anchor_prev = (0.0, 0.0, palm_z + 0.1) if prev < 0 else (0.0, 0.0, 0.0)
-        joints.append(_prismatic(prev, idx, anchor_prev, (0.0, 0.0, 0.0), axes[a], axes[a],
-                                 axes[(a + 1) % 3], axes[(a + 1) % 3],
-                                 drive=(kp * 40, kd * 40, 0.0, 0.5, 0.0, 0.0)))
+        anchor_prev = (0.0, 0.0, arm_z) if prev < 0 else (0.0, 0.0, 0.0)
+        ref = [ey, ez, ex][a]
+        joints.append(_prismatic(prev, idx, anchor_prev, (0.0, 0.0, 0.0), axis, axis, ref, ref,
+                                 drive=(2e4, 2e2, rng.uniform(0.0, 0.01), rng.uniform(0.2, 1.0),
+                                        rng.uniform(0, 2 * math.pi), 0.0)))
         prev = idx
-    rot_axes = [ez, ey, ex]
-    for a in range(3):
-        bodies.append(_nocollide(_box(1.0, arm_h, (0.0, 0.0, palm_z + 0.1))))
+    for a, axis in enumerate([ez, ey, ex]):
+        bodies.append(_nocollide(_box(1.0, arm_h, (0.0, 0.0, arm_z))))
         idx = len(bodies) - 1
-        ref = ex if rot_axes[a] != ex else ey
-        joints.append(_revolute(prev, idx, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0), rot_axes[a], rot_axes[a],
-                                ref, ref, drive=(kp * 20, kd * 20, rng.uniform(0.0, 0.1),
-                                                 rng.uniform(0.2, 1.0), rng.uniform(0, 2 * math.pi), 0.0)))
+        ref = ex if axis != ex else ey
+        joints.append(_revolute(prev, idx, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0), axis, axis, ref, ref,
+                                drive=(500.0, 5.0, rng.uniform(0.0, 0.05), rng.uniform(0.2, 1.0),
+                                       rng.uniform(0, 2 * math.pi), 0.0)))
         prev = idx
-    # palm: box below the last arm link
-    palm_half = (0.04, 0.04, 0.01)
     bodies.append(_box(0.2, palm_half, (0.0, 0.0, palm_z)))
     palm = len(bodies) - 1
-    joints.append(_revolute(prev, palm, (0.0, 0.0, palm_z - (palm_z + 0.1)), (0.0, 0.0, 0.0), ez, ez, ex, ex,
-                            drive=(kp * 20, kd * 20, 0.0, 0.5, 0.0, 0.0)))
-    # fingers hanging down from the palm corners; capsule axis = body x, pointing down
-    down = quat_from_axis_angle((0, 1, 0), math.pi / 2)  # body x -> world -z
-    corners = [(0.035, 0.0), (-0.035, 0.0), (0.0, 0.035), (0.0, -0.035)][:n_fingers]
-    for (cx, cy) in corners:
-        inward = np.array([-cx, -cy, 0.0])
-        inward /= np.linalg.norm(inward)
-        hinge_axis = np.cross(np.array([0.0, 0.0, -1.0]), inward)  # world
+    joints.append(_revolute(prev, palm, (0.0, 0.0, palm_z - arm_z), (0.0, 0.0, 0.0), ez, ez, ex, ex,
+                            drive=(500.0, 5.0, 0.0, 0.5, 0.0, 0.0)))
+    # fingers around the sphere; capsule axis = body x pointing down
+    down = quat_from_axis_angle((0, 1, 0), math.pi / 2)
+    R = _quat_to_mat(down)
+    ring = sphere_radius + link_radius + 0.01
+    corners = [(ring, 0.0), (-ring, 0.0), (0.0, ring), (0.0, -ring)][:n_fingers]
+    for (fx, fy) in corners:
+        inward = np.array([-fx, -fy, 0.0]) / ring
+        hinge = np.cross(np.array([0.0, 0.0, -1.0]), inward)  # world; +angle curls inwards
+        axis_link = tuple(R.T @ hinge)
+        ref_link = tuple(R.T @ inward)
         parent = palm
-        top = palm_z - palm_half[2]
         for l in range(links_per_finger):
-            cz = top - (l + 0.5) * link_len
-            bodies.append(_capsule(link_mass, link_radius, 0.5 * link_len - link_radius * 0.5,
-                                   (cx, cy, cz), q=down))
+            zc = palm_bottom - (l + 0.5) * link_len
+            bodies.append(_capsule(link_mass, link_radius, 0.5 * link_len - link_radius,
+                                   (fx, fy, zc), q=down))
             idx = len(bodies) - 1
-            # hinge axis in body frames: palm frame = world axes; finger link frame rotated by `down`
-            R = _quat_to_mat(down)
-            axis_link = R.T @ hinge_axis
-            ref_link = R.T @ np.array([0.0, 0.0, -1.0])
             if parent == palm:
-                anchor_parent = (cx, cy, -palm_half[2])
-                axis_parent = tuple(hinge_axis)
-                ref_parent = (0.0, 0.0, -1.0)
+                anchor_parent, axis_parent, ref_parent = (fx, fy, -palm_half[2]), tuple(hinge), tuple(inward)
             else:
-                anchor_parent = (0.5 * link_len, 0.0, 0.0)
-                axis_parent = tuple(axis_link)
-                ref_parent = tuple(ref_link)
+                anchor_parent, axis_parent, ref_parent = (0.5 * link_len, 0.0, 0.0), axis_link, ref_link
             joints.append(_revolute(parent, idx, anchor_parent, (-0.5 * link_len, 0.0, 0.0),
-                                    axis_parent, tuple(axis_link), ref_parent, tuple(ref_link),
-                                    drive=drive(0.6, 0.15)))
+                                    axis_parent, axis_link, ref_parent, ref_link,
+                                    drive=(kp, kd, rng.uniform(0.0, 0.6), rng.uniform(0.2, 1.0),
+                                           rng.uniform(0.0, 2 * math.pi), 0.15)))
             parent = idx
     _set_rigid(d, bodies)
     _set_joints(d, joints)
