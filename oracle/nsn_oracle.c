@@ -1361,35 +1361,32 @@ static void start_iterate(step_t *S) {
     int r0 = row_contact(e, ci);
     S->lam[r0] = l[0]; S->lam[r0 + 1] = l[1]; S->lam[r0 + 2] = l[2];
   }
-  if (e->have_prev) {
+  if (e->have_prev)
     for (int j = 0; j < e->nj; ++j)
       for (int r = 0; r < 6; ++r) S->lam[row_joint(e, j) + r] = e->lam_joint_prev[6 * j + r];
-    for (int t = 0; t < e->nt; ++t)
-      for (int r = 0; r < 3; ++r) S->lam[row_tet(e, t) + r] = e->lam_tet_prev[3 * t + r];
-  }
-  /* u0 = u~ + h M~^-1 J(q^-)^T lambda0 with physical rows */
-  double *f = calloc(S->ndof, sizeof(double)), *mf = calloc(S->ndof, sizeof(double));
-  jrow rows[6];
-  double c6[6];
-  for (int j = 0; j < e->nj; ++j) {
-    joint_rows(e, j, rows, c6);
-    for (int r = 0; r < 6; ++r) jrow_scatter(&rows[r], S->lam[row_joint(e, j) + r], f);
-  }
-  for (int ci = 0; ci < e->nc; ++ci) {
-    double Cn;
-    contact_rows(e, &e->con[ci], &rows[0], &rows[1], &rows[2], &Cn);
-    int r0 = row_contact(e, ci);
-    for (int r = 0; r < 3; ++r) jrow_scatter(&rows[r], S->lam[r0 + r], f);
-  }
+  /* READING: a tet's multipliers are stresses in the principal basis of the current
+   * configuration, and that basis (even its row order) changes from step to step, so
+   * the previous step's values do not carry over; the warm start uses the stress of
+   * the start configuration instead, lambda0 = -V_e dPsi/ds(s(q^-)), whose force
+   * J^T lambda0 is the elastic force at q^-. */
   for (int t = 0; t < e->nt; ++t) {
-    double s[3];
-    tet_rows(e, t, rows, s, NULL, NULL);
-    int r0 = row_tet(e, t);
-    for (int r = 0; r < 3; ++r) jrow_scatter(&rows[r], S->lam[r0 + r], f);
+    jrow rows3[3];
+    double s3[3], grad[3];
+    tet_rows(e, t, rows3, s3, NULL, NULL);
+    orc_neohookean(s3, e->C1[t], e->D1[t], e->alph[t], NULL, grad, NULL);
+    for (int r = 0; r < 3; ++r) S->lam[row_tet(e, t) + r] = -e->Ve[t] * grad[r];
   }
-  apply_Minv(S, f, mf);
-  for (int i = 0; i < S->ndof; ++i) S->u[i] = S->ut[i] + S->h * mf[i];
-  free(f); free(mf);
+  /* READING: the paper leaves u0 of a warm start open.  The start velocity is the
+   * previous step's velocity u^- (static bodies stay at rest), so a warm start takes
+   * both halves of the previous solution; only lambda0 differs between the modes.
+   * (Mapping lambda0 to velocities through the inverse mass made light FEM particles
+   * overshoot under contact forces balanced by the end-of-step stress.) */
+  for (int i = 0; i < e->nr; ++i) {
+    if (is_static_rigid(e, i)) continue;
+    for (int k = 0; k < 3; ++k) { S->u[6 * i + k] = e->rv[3 * i + k]; S->u[6 * i + 3 + k] = e->rw[3 * i + k]; }
+  }
+  for (int pi = 0; pi < e->np; ++pi)
+    for (int k = 0; k < 3; ++k) S->u[particle_dof(e, pi) + k] = e->pv[3 * pi + k];
   update_positions(S);
 }
 

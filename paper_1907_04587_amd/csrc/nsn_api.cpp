@@ -180,6 +180,7 @@ struct GraphKey {
 
 struct Bucket {
   int first, count, block;
+  int lds_floats;  // body-space vector in LDS (max DOFs of the bucket), 0 = global memory
 };
 
 struct nsn_scene_s {
@@ -192,8 +193,26 @@ struct nsn_scene_s {
   std::vector<Bucket> buckets;
   std::map<GraphKey, hipGraphExec_t> graphs;
   bool use_graphs = true;
+  bool y_global = false;  // force the body-space vector into global memory
   int want_features = 0;
+  // side streams (default priority) for concurrent schedule buckets, and fork/join events
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev;
+  ~nsn_scene_s() {
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto st : side) (void)hipStreamDestroy(st);
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
 };
+
+// LDS for the body-space vector of each bucket: the largest env DOF count, if it fits
+static void set_bucket_lds(nsn_scene s) {
+  for (Bucket &b : s->buckets) {
+    int mx = 0;
+    for (int i = b.first; i < b.first + b.count; ++i) mx = std::max(mx, s->env[s->order[i]].n_dof);
+    b.lds_floats = (mx > 0 && mx <= kMaxLdsFloats && !s->y_global) ? mx : 0;
+  }
+}
 
 extern "C" {
 
@@ -427,7 +446,8 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
   for (auto &E : env) max_el = std::max(max_el, E.n_jnt + E.n_tet + E.max_con + E.n_rig + E.n_par);
   int block = 64;
   while (block < 256 && block * 4 < max_el) block *= 2;
-  s->buckets = {Bucket{0, n_envs, block}};
+  s->buckets = {Bucket{0, n_envs, block, 0}};
+  set_bucket_lds(s);
   s->use_graphs = s->stream != nullptr;
   *out = s;
   return NSN_OK;
@@ -435,7 +455,6 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
 
 nsn_status nsn_destroy_scene(nsn_scene s) {
   if (!s) return NSN_OK;
-  for (auto &kv : s->graphs) hipGraphExecDestroy(kv.second);
   delete s;
   return NSN_OK;
 }
@@ -447,9 +466,27 @@ nsn_status nsn_set_params(nsn_scene s, const nsn_solver_params *p) {
     return fail(NSN_EINVAL, "bad solver parameters");
   if (p->warm == NSN_WARM_LEARNED && !s->S.have_mlp) return fail(NSN_ESTATE, "learned warm start needs nsn_set_warm_start_model first");
   s->p = *p;
-  for (auto &kv : s->graphs) hipGraphExecDestroy(kv.second);
+  for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
   s->graphs.clear();
   return NSN_OK;
+}
+
+// Buckets after the first run on side streams forked from the scene stream, so the
+// launches of different size classes overlap; the scene stream joins them.
+static hipError_t ensure_side_streams(nsn_scene s, size_t nb) {
+  while (s->side.size() + 1 < nb) {
+    hipStream_t st;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    s->side.push_back(st);
+  }
+  while (s->ev.size() < 2 * nb) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    s->ev.push_back(ev);
+  }
+  return hipSuccess;
 }
 
 static hipError_t enqueue_step(nsn_scene s, const StepArgs &a) {
@@ -459,8 +496,31 @@ static hipError_t enqueue_step(nsn_scene s, const StepArgs &a) {
     e = launch_warm_mlp(s->S, s->stream);
     if (e != hipSuccess) return e;
   }
-  for (const Bucket &b : s->buckets) {
-    e = launch_newton(s->S, a, b.block, b.first, b.count, s->stream);
+  const size_t nb = s->buckets.size();
+  if (s->stream == nullptr || nb == 1) {
+    for (const Bucket &b : s->buckets) {
+      e = launch_newton(s->S, a, b.block, b.first, b.count, b.lds_floats, s->stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  e = ensure_side_streams(s, nb);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(s->ev[0], s->stream);
+  if (e != hipSuccess) return e;
+  for (size_t i = 1; i < nb; ++i) {
+    e = hipStreamWaitEvent(s->side[i - 1], s->ev[0], 0);
+    if (e != hipSuccess) return e;
+  }
+  for (size_t i = 0; i < nb; ++i) {
+    const Bucket &b = s->buckets[i];
+    e = launch_newton(s->S, a, b.block, b.first, b.count, b.lds_floats, i == 0 ? s->stream : s->side[i - 1]);
+    if (e != hipSuccess) return e;
+  }
+  for (size_t i = 1; i < nb; ++i) {
+    e = hipEventRecord(s->ev[i], s->side[i - 1]);
+    if (e != hipSuccess) return e;
+    e = hipStreamWaitEvent(s->stream, s->ev[i], 0);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -490,7 +550,7 @@ nsn_status nsn_step(nsn_scene s, double h, int32_t newton_iters, int32_t cr_iter
     if (ce != hipSuccess) return fail(NSN_EDEVICE, std::string("end capture: ") + hipGetErrorString(ce));
     hipGraphExec_t exec;
     hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (ie != hipSuccess) return fail(NSN_EDEVICE, std::string("instantiate: ") + hipGetErrorString(ie));
     it = s->graphs.emplace(k, exec).first;
   }
@@ -663,7 +723,7 @@ nsn_status nsn_set_warm_start_model(nsn_scene s, const float *blob, int64_t n) {
   HIP_TRY(hipMemcpyAsync((void *)s->S.mlp, blob, sizeof(float) * n, hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->S.have_mlp = 1;
-  for (auto &kv : s->graphs) hipGraphExecDestroy(kv.second);
+  for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
   s->graphs.clear();
   return NSN_OK;
 }
@@ -691,7 +751,7 @@ nsn_status nsn_read_features(nsn_scene s, int32_t env, int32_t cap, int32_t *n, 
 nsn_status nsn_enable_features(nsn_scene s, int32_t on) {
   if (!s) return fail(NSN_EINVAL, "null scene");
   s->want_features = on ? 1 : 0;
-  for (auto &kv : s->graphs) hipGraphExecDestroy(kv.second);
+  for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
   s->graphs.clear();
   return NSN_OK;
 }
@@ -717,12 +777,13 @@ nsn_status nsn_set_schedule(nsn_scene s, int32_t n_buckets, const int32_t *first
     if (first[i] != expect || count[i] < 0) return fail(NSN_EINVAL, "schedule buckets must tile the env order");
     const int bl = block[i];
     if (bl != 64 && bl != 128 && bl != 256 && bl != 512 && bl != 1024) return fail(NSN_EINVAL, "block size must be 64..1024 (power of two)");
-    b.push_back(Bucket{first[i], count[i], bl});
+    b.push_back(Bucket{first[i], count[i], bl, 0});
     expect += count[i];
   }
   if (expect != s->S.n_envs) return fail(NSN_EINVAL, "schedule must cover every env");
   s->buckets = b;
-  for (auto &kv : s->graphs) hipGraphExecDestroy(kv.second);
+  set_bucket_lds(s);
+  for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
   s->graphs.clear();
   return NSN_OK;
 }

@@ -131,9 +131,11 @@ struct StepArgs {
 
 // kernel launchers (nsn_step.hip)
 hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_features, hipStream_t st);
-// envs S.env_order[first .. first+count) with `block` threads per workgroup
-hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count,
+// envs S.env_order[first .. first+count) with `block` threads per workgroup; the
+// body-space vector lives in `lds_floats` floats of dynamic LDS (0: global memory)
+hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
                          hipStream_t st);
+constexpr int kMaxLdsFloats = 24 * 1024;  // 96 KB of LDS for the body-space vector
 // learned warm start: MLP prediction for every contact of every env (nsn_mlp.hip)
 hipError_t launch_warm_mlp(const DevScene &s, hipStream_t st);
 

@@ -286,15 +286,15 @@ __device__ __forceinline__ V3 point_vel(const Ctx &c, const float *rvec, const f
   return mk(pvec[c.E.par_off + body - c.E.n_rig]);
 }
 
-// dof index of an env-local body
-__device__ __forceinline__ int body_dof(const EnvInfo &E, int body) {
-  return body < E.n_rig ? E.dof_off + 6 * body : E.dof_off + 6 * E.n_rig + 3 * (body - E.n_rig);
+// env-local dof index of an env-local body (body-space vectors Y are per env)
+__device__ __forceinline__ int ldof(const EnvInfo &E, int body) {
+  return body < E.n_rig ? 6 * body : 6 * E.n_rig + 3 * (body - E.n_rig);
 }
 
-// velocity of a point under a dof-indexed body-space vector Y
+// velocity of a point under an env-local body-space vector Y
 __device__ __forceinline__ V3 point_vel_dof(const Ctx &c, const float *Y, int body, V3 arm) {
   if (body < 0) return mk(0.f, 0.f, 0.f);
-  const int d = body_dof(c.E, body);
+  const int d = ldof(c.E, body);
   if (body < c.E.n_rig) return mk(Y[d], Y[d + 1], Y[d + 2]) + cross(mk(Y[d + 3], Y[d + 4], Y[d + 5]), arm);
   return mk(Y[d], Y[d + 1], Y[d + 2]);
 }
@@ -796,16 +796,13 @@ __device__ __forceinline__ float tJ(const DevScene &S, int buf, int comp_, int t
 }
 
 // ---- assembly (Sec. 6.1 eq. newton_system; Appendix A/B) ----
-// physical = true: rows grad(c) G with alpha = 1 and all friction rows present,
-// Jacobians only (for the warm-start impulse).
-__device__ void assemble_joint(const Ctx &c, int jl, bool physical, double tplus) {
+__device__ void assemble_joint(const Ctx &c, int jl, double tplus) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   const float h = c.A.h;
   const int jg = E.jnt_off + jl;
   float cv[6];
   joint_rows(c, jg, S.j_J + (size_t)72 * jg, cv);
-  if (physical) return;
   const int r0 = row_joint(E, jl);
   const int4 info = S.j_info[jg];
 #pragma unroll
@@ -831,7 +828,8 @@ __device__ void assemble_joint(const Ctx &c, int jl, bool physical, double tplus
   }
 }
 
-__device__ void assemble_tet(const Ctx &c, int tl, int buf, bool physical) {
+// stress_only = true: only the warm-start multipliers of the start configuration.
+__device__ void assemble_tet(const Ctx &c, int tl, int buf, bool stress_only) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   const float h = c.A.h;
@@ -865,7 +863,6 @@ __device__ void assemble_tet(const Ctx &c, int tl, int buf, bool physical) {
     Jb[(size_t)(6 * i + 4) * NT + tg] = w.y;
     Jb[(size_t)(6 * i + 5) * NT + tg] = w.z;
   }
-  if (physical) return;
   const float4 mt = S.t_mat[tg];  // (Ve, C1, D1, alpha)
   const float Ve = mt.x, C1 = mt.y, D1 = mt.z, al = mt.w;
   // stable neo-Hookean (Appendix B) in principal stretches
@@ -873,6 +870,15 @@ __device__ void assemble_tet(const Ctx &c, int tl, int buf, bool physical) {
   const float gr[3] = {2.f * C1 * s[0] + 2.f * D1 * (J - al) * s[1] * s[2],
                        2.f * C1 * s[1] + 2.f * D1 * (J - al) * s[0] * s[2],
                        2.f * C1 * s[2] + 2.f * D1 * (J - al) * s[0] * s[1]};
+  if (stress_only) {
+    // warm start: the stress of the start configuration in its own principal basis,
+    // lambda0 = -V_e dPsi/ds (multipliers of the previous step live in another basis)
+    const int r0 = row_tet(E, tl);
+    S.row_lam[r0] = -Ve * gr[0];
+    S.row_lam[r0 + 1] = -Ve * gr[1];
+    S.row_lam[r0 + 2] = -Ve * gr[2];
+    return;
+  }
   const float k0 = 2.f * J - al;
   float H[9];
   H[0] = Ve * 2.f * (D1 * s[1] * s[1] * s[2] * s[2] + C1);
@@ -913,7 +919,7 @@ __device__ void assemble_tet(const Ctx &c, int tl, int buf, bool physical) {
   for (int k = 0; k < 6; ++k) S.t_E[(size_t)k * NT + tg] = Em[k] * ih2;
 }
 
-__device__ void assemble_contact(const Ctx &c, int cl, int buf, bool physical) {
+__device__ void assemble_contact(const Ctx &c, int cl, int buf) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   const float h = c.A.h;
@@ -926,11 +932,6 @@ __device__ void assemble_contact(const Ctx &c, int cl, int buf, bool physical) {
   const V3 armB = bd.y >= 0 ? body_arm(c, bd.y, bL) : mk(0.f, 0.f, 0.f);
   S.c_rA[gc] = f4(armA, 0.f);
   S.c_rB[gc] = f4(armB, 0.f);
-  if (physical) {
-    S.c_alpha[(size_t)buf * S.NC + gc] = 1.f;
-    S.c_active[(size_t)buf * S.NC + gc] = 1;
-    return;
-  }
   const V3 pa = body_point(c, bd.x, aL);
   const V3 pb = bd.y >= 0 ? body_point(c, bd.y, bL) : bL;
   const float Cn = dot(n, pa - pb) - n4.w;
@@ -1047,133 +1048,203 @@ __device__ V3 scatter_particle(const Ctx &c, int p, const float *src, int buf) {
   return acc;
 }
 
-// (J Y) of one element's rows (no compliance); rows written to out[], returns row count
-__device__ int gather_element(const Ctx &c, int el, const float *Y, int buf, float out[6], int &r0) {
+// ---- per-element row kernels (one unrolled path per element type) ----
+// (J Y) rows of joint jl
+__device__ __forceinline__ void joint_JY(const Ctx &c, int jl, const float *Y, float jy[6]) {
+  const EnvInfo &E = c.E;
+  const int jg = E.jnt_off + jl;
+  const int4 info = c.S.j_info[jg];
+  const float *J = c.S.j_J + (size_t)72 * jg;
+  const int dB = ldof(E, info.z - E.rig_off);
+  const int dA = info.y >= 0 ? ldof(E, info.y - E.rig_off) : -1;
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    float acc = row_dot_rigid(J + 12 * r + 6, Y, dB);
+    if (dA >= 0) acc += row_dot_rigid(J + 12 * r, Y, dA);
+    jy[r] = acc;
+  }
+}
+
+__device__ __forceinline__ void tet_JY(const Ctx &c, int tl, const float *Y, int buf, float jy[3]) {
   const DevScene &S = c.S;
   const EnvInfo &E = c.E;
-  if (el < E.n_jnt) {
-    const int jg = E.jnt_off + el;
-    const int4 info = S.j_info[jg];
-    r0 = row_joint(E, el);
-    const float *J = S.j_J + (size_t)72 * jg;
-    const int dA = info.y >= 0 ? body_dof(E, info.y - E.rig_off) : -1;
-    const int dB = body_dof(E, info.z - E.rig_off);
+  const int tg = E.tet_off + tl;
+  const int4 id = S.t_ids[tg];
+  const int base = 6 * E.n_rig - 3 * E.par_off;
+  const V3 y0 = mk(Y[base + 3 * id.x], Y[base + 3 * id.x + 1], Y[base + 3 * id.x + 2]);
+  const V3 y1 = mk(Y[base + 3 * id.y], Y[base + 3 * id.y + 1], Y[base + 3 * id.y + 2]) - y0;
+  const V3 y2 = mk(Y[base + 3 * id.z], Y[base + 3 * id.z + 1], Y[base + 3 * id.z + 2]) - y0;
+  const V3 y3 = mk(Y[base + 3 * id.w], Y[base + 3 * id.w + 1], Y[base + 3 * id.w + 2]) - y0;
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
-      float acc = row_dot_rigid(J + 12 * r + 6, Y, dB);
-      if (dA >= 0) acc += row_dot_rigid(J + 12 * r, Y, dA);
-      out[r] = acc;
-    }
-    return 6;
+  for (int i = 0; i < 3; ++i) {
+    const V3 u = mk(tJ(S, buf, 6 * i, tg), tJ(S, buf, 6 * i + 1, tg), tJ(S, buf, 6 * i + 2, tg));
+    const float w0 = tJ(S, buf, 6 * i + 3, tg), w1 = tJ(S, buf, 6 * i + 4, tg), w2 = tJ(S, buf, 6 * i + 5, tg);
+    jy[i] = dot(u, w0 * y1 + w1 * y2 + w2 * y3);
   }
-  el -= E.n_jnt;
-  if (el < E.n_tet) {
-    const int tg = E.tet_off + el;
-    r0 = row_tet(E, el);
-    const int4 id = S.t_ids[tg];
-    const int base = E.dof_off + 6 * E.n_rig - 3 * E.par_off;
-    const V3 y0 = mk(Y[base + 3 * id.x], Y[base + 3 * id.x + 1], Y[base + 3 * id.x + 2]);
-    const V3 y1 = mk(Y[base + 3 * id.y], Y[base + 3 * id.y + 1], Y[base + 3 * id.y + 2]);
-    const V3 y2 = mk(Y[base + 3 * id.z], Y[base + 3 * id.z + 1], Y[base + 3 * id.z + 2]);
-    const V3 y3 = mk(Y[base + 3 * id.w], Y[base + 3 * id.w + 1], Y[base + 3 * id.w + 2]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const V3 u = mk(tJ(S, buf, 6 * i, tg), tJ(S, buf, 6 * i + 1, tg), tJ(S, buf, 6 * i + 2, tg));
-      const float w0 = tJ(S, buf, 6 * i + 3, tg), w1 = tJ(S, buf, 6 * i + 4, tg), w2 = tJ(S, buf, 6 * i + 5, tg);
-      out[i] = dot(u, w0 * (y1 - y0) + w1 * (y2 - y0) + w2 * (y3 - y0));
-    }
-    return 3;
-  }
-  el -= E.n_tet;
-  const int gc = E.con_off + el;
-  r0 = row_con(E, el);
+}
+
+__device__ __forceinline__ void contact_JY(const Ctx &c, int cl, const float *Y, int buf, float jy[3]) {
+  const DevScene &S = c.S;
+  const int gc = c.E.con_off + cl;
   const int2 bd = S.c_body[gc];
   const V3 n = mk(S.c_n[gc]);
   const V3 vr = point_vel_dof(c, Y, bd.x, mk(S.c_rA[gc])) -
                 (bd.y >= 0 ? point_vel_dof(c, Y, bd.y, mk(S.c_rB[gc])) : mk(0.f, 0.f, 0.f));
-  out[0] = S.c_alpha[(size_t)buf * S.NC + gc] * dot(n, vr);
+  jy[0] = S.c_alpha[(size_t)buf * S.NC + gc] * dot(n, vr);
   if (S.c_active[(size_t)buf * S.NC + gc]) {
     V3 d1, d2;
     tangent_basis(n, d1, d2);
-    out[1] = dot(d1, vr);
-    out[2] = dot(d2, vr);
+    jy[1] = dot(d1, vr);
+    jy[2] = dot(d2, vr);
   } else {
-    out[1] = 0.f;
-    out[2] = 0.f;
+    jy[1] = 0.f;
+    jy[2] = 0.f;
   }
-  return 3;
 }
 
-// compliance block times src for one element's rows (added to out)
-__device__ __forceinline__ void add_compliance(const Ctx &c, int el, int r0, int nr, const float *src, float out[6]) {
-  const EnvInfo &E = c.E;
-  const DevScene &S = c.S;
-  if (el >= E.n_jnt && el < E.n_jnt + E.n_tet) {
-    const int tg = E.tet_off + el - E.n_jnt;
-    float Em[6];
+// J_i H~^-1 J_i^T of every row of an element (preconditioner diagonal without C, eps)
+__device__ __forceinline__ void joint_hdiag(const Ctx &c, int jl, float dg[6]) {
+  const int jg = c.E.jnt_off + jl;
+  const int4 info = c.S.j_info[jg];
+  const float *J = c.S.j_J + (size_t)72 * jg;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) Em[k] = S.t_E[(size_t)k * S.NT + tg];
-    const V3 v = sym_mul(Em, mk(src[r0], src[r0 + 1], src[r0 + 2]));
-    out[0] += v.x; out[1] += v.y; out[2] += v.z;
-    return;
+  for (int r = 0; r < 6; ++r) {
+    float acc = rigid_quad(c, info.z, J + 12 * r + 6);
+    if (info.y >= 0) acc += rigid_quad(c, info.y, J + 12 * r);
+    dg[r] = acc;
   }
-  for (int r = 0; r < nr; ++r) out[r] += S.row_C[r0 + r] * src[r0 + r];
 }
 
-// J_i H~^-1 J_i^T of one element's rows (preconditioner diagonal without C, eps)
-__device__ int hdiag_element(const Ctx &c, int el, int buf, float out[6], int &r0) {
+__device__ __forceinline__ void tet_hdiag(const Ctx &c, int tl, int buf, float dg[3]) {
   const DevScene &S = c.S;
-  const EnvInfo &E = c.E;
-  if (el < E.n_jnt) {
-    const int jg = E.jnt_off + el;
-    const int4 info = S.j_info[jg];
-    r0 = row_joint(E, el);
-    const float *J = S.j_J + (size_t)72 * jg;
+  const int tg = c.E.tet_off + tl;
+  const int4 id = S.t_ids[tg];
+  const float4 H0 = S.p_H[id.x], H1 = S.p_H[id.y], H2 = S.p_H[id.z], H3 = S.p_H[id.w];
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
-      float acc = rigid_quad(c, info.z, J + 12 * r + 6);
-      if (info.y >= 0) acc += rigid_quad(c, info.y, J + 12 * r);
-      out[r] = acc;
-    }
-    return 6;
+  for (int i = 0; i < 3; ++i) {
+    const V3 u = mk(tJ(S, buf, 6 * i, tg), tJ(S, buf, 6 * i + 1, tg), tJ(S, buf, 6 * i + 2, tg));
+    const float w0 = tJ(S, buf, 6 * i + 3, tg), w1 = tJ(S, buf, 6 * i + 4, tg), w2 = tJ(S, buf, 6 * i + 5, tg);
+    const float ws = w0 + w1 + w2;
+    const V3 u2 = mk(u.x * u.x, u.y * u.y, u.z * u.z);
+    dg[i] = ws * ws * (u2.x / H0.x + u2.y / H0.y + u2.z / H0.z) + w0 * w0 * (u2.x / H1.x + u2.y / H1.y + u2.z / H1.z) +
+            w1 * w1 * (u2.x / H2.x + u2.y / H2.y + u2.z / H2.z) + w2 * w2 * (u2.x / H3.x + u2.y / H3.y + u2.z / H3.z);
   }
-  el -= E.n_jnt;
-  if (el < E.n_tet) {
-    const int tg = E.tet_off + el;
-    r0 = row_tet(E, el);
-    const int4 id = S.t_ids[tg];
-    const float4 H0 = S.p_H[id.x], H1 = S.p_H[id.y], H2 = S.p_H[id.z], H3 = S.p_H[id.w];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const V3 u = mk(tJ(S, buf, 6 * i, tg), tJ(S, buf, 6 * i + 1, tg), tJ(S, buf, 6 * i + 2, tg));
-      const float w0 = tJ(S, buf, 6 * i + 3, tg), w1 = tJ(S, buf, 6 * i + 4, tg), w2 = tJ(S, buf, 6 * i + 5, tg);
-      const float ws = w0 + w1 + w2;
-      const V3 u2 = mk(u.x * u.x, u.y * u.y, u.z * u.z);
-      out[i] = ws * ws * (u2.x / H0.x + u2.y / H0.y + u2.z / H0.z) +
-               w0 * w0 * (u2.x / H1.x + u2.y / H1.y + u2.z / H1.z) +
-               w1 * w1 * (u2.x / H2.x + u2.y / H2.y + u2.z / H2.z) +
-               w2 * w2 * (u2.x / H3.x + u2.y / H3.y + u2.z / H3.z);
-    }
-    return 3;
-  }
-  el -= E.n_tet;
-  const int gc = E.con_off + el;
-  r0 = row_con(E, el);
+}
+
+__device__ __forceinline__ void contact_hdiag(const Ctx &c, int cl, int buf, float dg[3]) {
+  const DevScene &S = c.S;
+  const int gc = c.E.con_off + cl;
   const int2 bd = S.c_body[gc];
   const V3 n = mk(S.c_n[gc]);
   const V3 rA = mk(S.c_rA[gc]), rB = mk(S.c_rB[gc]);
   const float al = S.c_alpha[(size_t)buf * S.NC + gc];
-  out[0] = al * al * (effmass_dir(c, bd.x, rA, n, true) + effmass_dir(c, bd.y, rB, n, true));
+  dg[0] = al * al * (effmass_dir(c, bd.x, rA, n, true) + effmass_dir(c, bd.y, rB, n, true));
   if (S.c_active[(size_t)buf * S.NC + gc]) {
     V3 d1, d2;
     tangent_basis(n, d1, d2);
-    out[1] = effmass_dir(c, bd.x, rA, d1, true) + effmass_dir(c, bd.y, rB, d1, true);
-    out[2] = effmass_dir(c, bd.x, rA, d2, true) + effmass_dir(c, bd.y, rB, d2, true);
+    dg[1] = effmass_dir(c, bd.x, rA, d1, true) + effmass_dir(c, bd.y, rB, d1, true);
+    dg[2] = effmass_dir(c, bd.x, rA, d2, true) + effmass_dir(c, bd.y, rB, d2, true);
   } else {
-    out[1] = 0.f;
-    out[2] = 0.f;
+    dg[1] = 0.f;
+    dg[2] = 0.f;
   }
-  return 3;
+}
+
+// Schur right-hand side b = (J Y - err)/h and Jacobi preconditioner for every row
+// (Y = H~^-1 g already in place)
+template <int BS>
+__device__ void rhs_and_precond(const Ctx &c, const float *Y, int buf, int nel, float eps) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  const float ih = 1.f / c.A.h;
+  for (int el = threadIdx.x; el < nel; el += BS) {
+    if (el < E.n_jnt) {
+      float jy[6], dg[6];
+      joint_JY(c, el, Y, jy);
+      joint_hdiag(c, el, dg);
+      const int r0 = row_joint(E, el);
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        S.row_b[r0 + r] = (jy[r] - S.row_err[r0 + r]) * ih;
+        S.row_P[r0 + r] = 1.f / (dg[r] + S.row_C[r0 + r] + eps);
+      }
+    } else if (el < E.n_jnt + E.n_tet) {
+      float jy[3], dg[3];
+      const int tl = el - E.n_jnt;
+      tet_JY(c, tl, Y, buf, jy);
+      tet_hdiag(c, tl, buf, dg);
+      const int r0 = row_tet(E, tl);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        S.row_b[r0 + r] = (jy[r] - S.row_err[r0 + r]) * ih;
+        S.row_P[r0 + r] = 1.f / (dg[r] + S.row_C[r0 + r] + eps);
+      }
+    } else {
+      float jy[3], dg[3];
+      const int cl = el - E.n_jnt - E.n_tet;
+      contact_JY(c, cl, Y, buf, jy);
+      contact_hdiag(c, cl, buf, dg);
+      const int r0 = row_con(E, cl);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        S.row_b[r0 + r] = (jy[r] - S.row_err[r0 + r]) * ih;
+        S.row_P[r0 + r] = 1.f / (dg[r] + S.row_C[r0 + r] + eps);
+      }
+    }
+  }
+}
+
+// w = A z = J Y + C z + eps z for every row (Y = H~^-1 J^T z in place); returns the
+// thread's part of <z, w>.  FIRST: also q = w (initialisation of the PCR).
+template <int BS, bool FIRST>
+__device__ double matvec_rows(const Ctx &c, const float *Y, int buf, int nel, float eps) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  double part = 0.0;
+  for (int el = threadIdx.x; el < nel; el += BS) {
+    if (el < E.n_jnt) {
+      float jy[6];
+      joint_JY(c, el, Y, jy);
+      const int r0 = row_joint(E, el);
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        const float z = S.row_z[r0 + r];
+        const float w = jy[r] + S.row_C[r0 + r] * z + eps * z;
+        S.row_w[r0 + r] = w;
+        if (FIRST) S.row_q[r0 + r] = w;
+        part += (double)z * (double)w;
+      }
+    } else if (el < E.n_jnt + E.n_tet) {
+      float jy[3];
+      const int tl = el - E.n_jnt;
+      tet_JY(c, tl, Y, buf, jy);
+      const int tg = E.tet_off + tl;
+      const int r0 = row_tet(E, tl);
+      float Em[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) Em[k] = S.t_E[(size_t)k * S.NT + tg];
+      const V3 z = mk(S.row_z[r0], S.row_z[r0 + 1], S.row_z[r0 + 2]);
+      const V3 cz = sym_mul(Em, z);
+      const float w0 = jy[0] + cz.x + eps * z.x, w1 = jy[1] + cz.y + eps * z.y, w2 = jy[2] + cz.z + eps * z.z;
+      S.row_w[r0] = w0; S.row_w[r0 + 1] = w1; S.row_w[r0 + 2] = w2;
+      if (FIRST) { S.row_q[r0] = w0; S.row_q[r0 + 1] = w1; S.row_q[r0 + 2] = w2; }
+      part += (double)z.x * w0 + (double)z.y * w1 + (double)z.z * w2;
+    } else {
+      float jy[3];
+      const int cl = el - E.n_jnt - E.n_tet;
+      contact_JY(c, cl, Y, buf, jy);
+      const int r0 = row_con(E, cl);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const float z = S.row_z[r0 + r];
+        const float w = jy[r] + S.row_C[r0 + r] * z + eps * z;
+        S.row_w[r0 + r] = w;
+        if (FIRST) S.row_q[r0 + r] = w;
+        part += (double)z * (double)w;
+      }
+    }
+  }
+  return part;
 }
 
 // H~^-1 applied to a rigid 6-vector (in place)
@@ -1199,14 +1270,14 @@ __device__ void scatter_hinv(const Ctx &c, const float *src, int buf, float *Y, 
       float v[6];
       scatter_rigid(c, g, src, buf, v);
       hinv_rigid(c, g, v);
-      const int d = E.dof_off + 6 * b;
+      const int d = 6 * b;
 #pragma unroll
       for (int k = 0; k < 6; ++k) Y[d + k] = v[k];
     } else {
       const int p = E.par_off + b - E.n_rig;
       const V3 a = scatter_particle(c, p, src, buf);
       const float4 H = S.p_H[p];
-      const int d = E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
+      const int d = 6 * E.n_rig + 3 * (b - E.n_rig);
       Y[d] = a.x / H.x;
       Y[d + 1] = a.y / H.y;
       Y[d + 2] = a.z / H.z;
@@ -1242,22 +1313,23 @@ __device__ __forceinline__ void update_positions_body(const Ctx &c, int b) {
 }
 
 template <int BS>
-__device__ void assemble_all(const Ctx &c, int buf, bool physical, double tplus, int nc) {
+__device__ void assemble_all(const Ctx &c, int buf, double tplus, int nc) {
   const EnvInfo &E = c.E;
   const int nel = E.n_jnt + E.n_tet + nc;
   for (int el = threadIdx.x; el < nel; el += BS) {
-    if (el < E.n_jnt) assemble_joint(c, el, physical, tplus);
-    else if (el < E.n_jnt + E.n_tet) assemble_tet(c, el - E.n_jnt, buf, physical);
-    else assemble_contact(c, el - E.n_jnt - E.n_tet, buf, physical);
+    if (el < E.n_jnt) assemble_joint(c, el, tplus);
+    else if (el < E.n_jnt + E.n_tet) assemble_tet(c, el - E.n_jnt, buf, false);
+    else assemble_contact(c, el - E.n_jnt - E.n_tet, buf);
   }
 }
 
 // --------------------------------------------------------------------------
 // Kernel 3: start iterate + Newton loop + write-back.  One workgroup per env.
 // --------------------------------------------------------------------------
-template <int BS>
+template <int BS, bool YLDS>
 __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first) {
   __shared__ Red<BS> red;
+  extern __shared__ float y_lds[];
   const unsigned long long t_start = wall_clock64();
   Ctx c;
   c.S = S;
@@ -1275,10 +1347,12 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
   const int R0 = E.row_off;
   const int crow0 = row_con(E, 0);
   const double tplus = S.time[e] + (double)h;
-  float *Y = S.y;
+  // env-local body-space vector: in LDS when the bucket's envs fit, else in global memory
+  float *Y = YLDS ? y_lds : S.y + E.dof_off;
 
-  // ---- start iterate (Sec. 8.1); READING for warm starts: projected lambda0 and
-  //      u0 = u~ + h M^-1 J(q^-)^T lambda0 ----
+  // ---- start iterate (Sec. 8.1); READING for warm starts: projected lambda0 for
+  //      contacts, the previous multipliers for joints, the start-configuration
+  //      stress for tets, and u0 = u^- (the previous step's velocity) ----
   const bool warm = A.p.warm != NSN_WARM_ZERO;
   for (int r = tid; r < nrows; r += BS) {
     const int row = R0 + r;
@@ -1296,47 +1370,33 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
   }
   for (int b = tid; b < nb; b += BS) {
     if (b < E.n_rig) {
-      float *u = S.r_u + 6 * (E.rig_off + b);
-      for (int k = 0; k < 6; ++k) u[k] = 0.f;
+      const int g = E.rig_off + b;
+      float *u = S.r_u + 6 * g;
+      const bool mv = warm && S.r_inertia[g].w != 0.f;  // static bodies stay at rest
+      const float4 v = S.r_v[g], w = S.r_w[g];
+      u[0] = mv ? v.x : 0.f; u[1] = mv ? v.y : 0.f; u[2] = mv ? v.z : 0.f;
+      u[3] = mv ? w.x : 0.f; u[4] = mv ? w.y : 0.f; u[5] = mv ? w.z : 0.f;
     } else {
       const int p = E.par_off + b - E.n_rig;
-      S.p_u[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4 v = S.p_v[p];
+      S.p_u[p] = warm ? make_float4(v.x, v.y, v.z, 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
       S.p_uprev[p] = make_float4(0.f, 0.f, 0.f, 0.f);
       S.p_H[p] = make_float4(S.p_m[p], S.p_m[p], S.p_m[p], 0.f);
     }
   }
-  __syncthreads();
   if (warm) {
-    assemble_all<BS>(c, 0, true, tplus, nc);
-    __syncthreads();
-    for (int b = tid; b < nb; b += BS) {
-      if (b < E.n_rig) {
-        const int g = E.rig_off + b;
-        float v[6];
-        scatter_rigid(c, g, S.row_lam, 0, v);
-        hinv_rigid(c, g, v);  // H~ = M~ here
-        float *u = S.r_u + 6 * g;
-        const float *ut = S.r_ut + 6 * g;
-        for (int k = 0; k < 6; ++k) u[k] = ut[k] + h * v[k];
-      } else {
-        const int p = E.par_off + b - E.n_rig;
-        const V3 a = scatter_particle(c, p, S.row_lam, 0);
-        const float4 ut = S.p_ut[p];
-        const float im = 1.f / S.p_m[p];
-        S.p_u[p] = make_float4(ut.x + h * im * a.x, ut.y + h * im * a.y, ut.z + h * im * a.z, 0.f);
-      }
-    }
+    for (int t = tid; t < E.n_tet; t += BS) assemble_tet(c, t, 0, true);  // stress at q^-
     __syncthreads();
     for (int b = tid; b < nb; b += BS) update_positions_body(c, b);
-    __syncthreads();
   }
+  __syncthreads();
 
   int newton_done = 0, cr_total = 0, nonfinite = 0, converged = 0;
   float r_ncp = 0.f, r_con = 0.f, r_first = 0.f;
   double merit = 0.0;
   for (int k = 0; k <= A.newton_iters; ++k) {
     const int buf = k & 1;
-    assemble_all<BS>(c, buf, false, tplus, nc);
+    assemble_all<BS>(c, buf, tplus, nc);
     __syncthreads();
     // momentum balance g = M~(u - u~) - h J^T lambda (Sec. 6.1); geometric stiffness
     // (Sec. 8.3, READING: secant of J^T lambda at fixed lambda between the last two
@@ -1423,31 +1483,22 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
         float v[6];
         for (int q = 0; q < 6; ++q) v[q] = S.g[d + q];
         hinv_rigid(c, g, v);
-        for (int q = 0; q < 6; ++q) Y[d + q] = v[q];
+        for (int q = 0; q < 6; ++q) Y[6 * b + q] = v[q];
       } else {
         const int p = E.par_off + b - E.n_rig;
         const int d = E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
+        const int dl = 6 * E.n_rig + 3 * (b - E.n_rig);
         const float4 H = S.p_H[p];
-        Y[d] = S.g[d] / H.x; Y[d + 1] = S.g[d + 1] / H.y; Y[d + 2] = S.g[d + 2] / H.z;
+        Y[dl] = S.g[d] / H.x; Y[dl + 1] = S.g[d + 1] / H.y; Y[dl + 2] = S.g[d + 2] / H.z;
       }
     }
     __syncthreads();
-    for (int el = tid; el < nel; el += BS) {
-      float jy[6], dg[6];
-      int r0, r1;
-      const int nr = gather_element(c, el, Y, buf, jy, r0);
-      hdiag_element(c, el, buf, dg, r1);
-      for (int r = 0; r < nr; ++r) {
-        const int row = r0 + r;
-        const float bb = (jy[r] - S.row_err[row]) / h;
-        const float P = 1.f / (dg[r] + S.row_C[row] + eps);
-        S.row_b[row] = bb;
-        S.row_P[row] = P;
-      }
-    }
+    rhs_and_precond<BS>(c, Y, buf, nel, eps);
     __syncthreads();
 
     // ---- preconditioned conjugate residual (Sec. 8.2), x0 = 0, FP64 scalars ----
+    // per iteration: [p = z + beta p, q = w + beta q, s = P q, <q,s>] -> x += alpha p,
+    // z -= alpha s -> w = A z (scatter, H~^-1, gather), <z,w>
     for (int r = tid; r < nrows; r += BS) {
       const int row = R0 + r;
       const float z = S.row_P[row] * S.row_b[row];
@@ -1456,36 +1507,26 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       S.row_p[row] = z;
     }
     __syncthreads();
-    double rho;
-    {
-      scatter_hinv(c, S.row_z, buf, Y, tid, BS);
-      __syncthreads();
-      double part = 0.0;
-      for (int el = tid; el < nel; el += BS) {
-        float w6[6];
-        int r0;
-        const int nr = gather_element(c, el, Y, buf, w6, r0);
-        add_compliance(c, el, r0, nr, S.row_z, w6);
-        for (int r = 0; r < nr; ++r) {
-          const float z = S.row_z[r0 + r];
-          const float w = w6[r] + eps * z;
-          S.row_w[r0 + r] = w;
-          S.row_q[r0 + r] = w;
-          part += (double)z * (double)w;
-        }
-      }
-      rho = block_sum<BS>(part, red, 1);
-    }
+    scatter_hinv(c, S.row_z, buf, Y, tid, BS);
+    __syncthreads();
+    double rho = block_sum<BS>(matvec_rows<BS, true>(c, Y, buf, nel, eps), red, 1);
+    float beta = 0.f;
     int done = 0;
     for (int it = 0; it < A.cr_iters; ++it) {
       if (!(rho > 0.0)) break;
       double part = 0.0;
       for (int r = tid; r < nrows; r += BS) {
         const int row = R0 + r;
-        const float q = S.row_q[row];
-        const float s = S.row_P[row] * q;
-        S.row_b[row] = s;  // s = P q (b is no longer needed)
-        part += (double)q * (double)s;
+        float pp = S.row_p[row], qq = S.row_q[row];
+        if (it > 0) {  // direction update of the previous iteration, fused with s = P q
+          pp = S.row_z[row] + beta * pp;
+          qq = S.row_w[row] + beta * qq;
+          S.row_p[row] = pp;
+          S.row_q[row] = qq;
+        }
+        const float sv = S.row_P[row] * qq;
+        S.row_b[row] = sv;  // s = P q (b is no longer needed)
+        part += (double)qq * (double)sv;
       }
       const double qs = block_sum<BS>(part, red, 0);
       if (!(qs > 0.0)) break;
@@ -1500,27 +1541,9 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       __syncthreads();
       scatter_hinv(c, S.row_z, buf, Y, tid, BS);
       __syncthreads();
-      part = 0.0;
-      for (int el = tid; el < nel; el += BS) {
-        float w6[6];
-        int r0;
-        const int nr = gather_element(c, el, Y, buf, w6, r0);
-        add_compliance(c, el, r0, nr, S.row_z, w6);
-        for (int r = 0; r < nr; ++r) {
-          const float z = S.row_z[r0 + r];
-          const float w = w6[r] + eps * z;
-          S.row_w[r0 + r] = w;
-          part += (double)z * (double)w;
-        }
-      }
-      const double rho_new = block_sum<BS>(part, red, 1);
-      const float beta = (float)(rho_new / rho);
+      const double rho_new = block_sum<BS>(matvec_rows<BS, false>(c, Y, buf, nel, eps), red, 1);
+      beta = (float)(rho_new / rho);
       rho = rho_new;
-      for (int r = tid; r < nrows; r += BS) {
-        const int row = R0 + r;
-        S.row_p[row] = S.row_z[row] + beta * S.row_p[row];
-        S.row_q[row] = S.row_w[row] + beta * S.row_q[row];
-      }
     }
     cr_total += done;
     __syncthreads();
@@ -1611,15 +1634,26 @@ hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_feature
   return hipGetLastError();
 }
 
-hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count,
+template <int BS>
+static void launch_bs(const DevScene &s, const StepArgs &a, int first, int count, int lds_floats, hipStream_t st) {
+  if (lds_floats > 16384)
+    (void)hipFuncSetAttribute((const void *)k_newton<BS, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sizeof(float) * lds_floats);
+  if (lds_floats > 0)
+    hipLaunchKernelGGL((k_newton<BS, true>), dim3(count), dim3(BS), sizeof(float) * lds_floats, st, s, a, first);
+  else
+    hipLaunchKernelGGL((k_newton<BS, false>), dim3(count), dim3(BS), 0, st, s, a, first);
+}
+
+hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
                          hipStream_t st) {
   if (count <= 0) return hipSuccess;
   switch (block) {
-    case 64: hipLaunchKernelGGL(k_newton<64>, dim3(count), dim3(64), 0, st, s, a, first); break;
-    case 128: hipLaunchKernelGGL(k_newton<128>, dim3(count), dim3(128), 0, st, s, a, first); break;
-    case 256: hipLaunchKernelGGL(k_newton<256>, dim3(count), dim3(256), 0, st, s, a, first); break;
-    case 512: hipLaunchKernelGGL(k_newton<512>, dim3(count), dim3(512), 0, st, s, a, first); break;
-    case 1024: hipLaunchKernelGGL(k_newton<1024>, dim3(count), dim3(1024), 0, st, s, a, first); break;
+    case 64: launch_bs<64>(s, a, first, count, lds_floats, st); break;
+    case 128: launch_bs<128>(s, a, first, count, lds_floats, st); break;
+    case 256: launch_bs<256>(s, a, first, count, lds_floats, st); break;
+    case 512: launch_bs<512>(s, a, first, count, lds_floats, st); break;
+    case 1024: launch_bs<1024>(s, a, first, count, lds_floats, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -446,8 +446,9 @@ def grasp_scene(seed=0, n_fingers=4, links_per_finger=4, link_len=0.04, link_mas
                 rho=1000.0, mu=0.8, kp=5.0, kd=0.05, max_contacts=1024):
     """Articulated hand on a 6-DoF arm (3 prismatic + 3 revolute links of 1 kg, held by
     stiff drives) with four 4-link capsule fingers hanging around a tet-FEM sphere that
-    rests on the ground.  Finger joints are PD-driven towards seeded sinusoids that
-    curl the fingers inwards and squeeze the sphere."""
+    rests on the ground.  Finger joints are PD-driven towards seeded sinusoids
+    A sin(2 pi f t) (starting at the initial angle) that curl the fingers inwards onto
+    the sphere and back."""
     rng = np.random.default_rng(seed)
     if sphere_cell is None:
         sphere_cell = 0.0108
@@ -472,16 +473,14 @@ def grasp_scene(seed=0, n_fingers=4, links_per_finger=4, link_len=0.04, link_mas
         anchor_prev = (0.0, 0.0, arm_z) if prev < 0 else (0.0, 0.0, 0.0)
         ref = [ey, ez, ex][a]
         joints.append(_prismatic(prev, idx, anchor_prev, (0.0, 0.0, 0.0), axis, axis, ref, ref,
-                                 drive=(2e4, 2e2, rng.uniform(0.0, 0.01), rng.uniform(0.2, 1.0),
-                                        rng.uniform(0, 2 * math.pi), 0.0)))
+                                 drive=(2e4, 2e2, rng.uniform(0.0, 0.01), rng.uniform(0.2, 1.0), 0.0, 0.0)))
         prev = idx
     for a, axis in enumerate([ez, ey, ex]):
         bodies.append(_nocollide(_box(1.0, arm_h, (0.0, 0.0, arm_z))))
         idx = len(bodies) - 1
         ref = ex if axis != ex else ey
         joints.append(_revolute(prev, idx, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0), axis, axis, ref, ref,
-                                drive=(500.0, 5.0, rng.uniform(0.0, 0.05), rng.uniform(0.2, 1.0),
-                                       rng.uniform(0, 2 * math.pi), 0.0)))
+                                drive=(500.0, 5.0, rng.uniform(0.0, 0.05), rng.uniform(0.2, 1.0), 0.0, 0.0)))
         prev = idx
     bodies.append(_box(0.2, palm_half, (0.0, 0.0, palm_z)))
     palm = len(bodies) - 1
@@ -509,8 +508,7 @@ def grasp_scene(seed=0, n_fingers=4, links_per_finger=4, link_len=0.04, link_mas
                 anchor_parent, axis_parent, ref_parent = (0.5 * link_len, 0.0, 0.0), axis_link, ref_link
             joints.append(_revolute(parent, idx, anchor_parent, (-0.5 * link_len, 0.0, 0.0),
                                     axis_parent, axis_link, ref_parent, ref_link,
-                                    drive=(kp, kd, rng.uniform(0.0, 0.6), rng.uniform(0.2, 1.0),
-                                           rng.uniform(0.0, 2 * math.pi), 0.15)))
+                                    drive=(kp, kd, rng.uniform(0.0, 0.6), rng.uniform(0.2, 1.0), 0.0, 0.0)))
             parent = idx
     _set_rigid(d, bodies)
     _set_joints(d, joints)
