@@ -1628,6 +1628,24 @@ void orc_get_lambda(void *p, double *lam) {
   memcpy(lam, e->lam_last, e->nrows_last * sizeof(double));
 }
 
+/* Loads the previous-step multipliers (what a warm start reads): contacts by key,
+ * keys ascending, lam3 = (lambda_n, lambda_f1, lambda_f2) each, and the joint rows
+ * (6 per joint).  Lets a test start the oracle from another solver's previous step. */
+int orc_set_prev(void *p, int n, const int64_t *keys, const double *lam3, const double *lam_joint) {
+  env_t *e = (env_t *)p;
+  if (n < 0 || n > e->maxc) return -1;
+  for (int i = 1; i < n; ++i) if (keys[i] <= keys[i - 1]) return -1;
+  memset(e->prev, 0, (size_t)(e->maxc > 0 ? e->maxc : 0) * sizeof(contact));
+  for (int i = 0; i < n; ++i) {
+    e->prev[i].key = keys[i];
+    for (int k = 0; k < 3; ++k) e->prev[i].lam[k] = lam3[3 * i + k];
+  }
+  e->nprev = n;
+  for (int j = 0; j < 6 * e->nj; ++j) e->lam_joint_prev[j] = lam_joint ? lam_joint[j] : 0.0;
+  e->have_prev = 1;
+  return 0;
+}
+
 int orc_get_history(void *p, double *r, int cap) {
   env_t *e = (env_t *)p;
   int n = e->nhist < cap ? e->nhist : cap;

@@ -93,6 +93,8 @@ void orc_get_lambda(void *env, double *lam);   /* full multiplier vector of the 
 void orc_set_mlp(void *env, const double *weights, int64_t n);
 /* per-iteration residual history of the last step (r_ncp per assembly) */
 int orc_get_history(void *env, double *r, int cap);
+/* Previous-step multipliers for a warm start (keys ascending); 0 or -1 (bad input). */
+int orc_set_prev(void *env, int n, const int64_t *keys, const double *lam3, const double *lam_joint);
 /* per-row data of the final assembly of the last step */
 int orc_get_rows_debug(void *env, double *err, double *cdiag, double *pdiag, int cap);
 

@@ -75,6 +75,7 @@ def lib():
         L.orc_get_lambda.argtypes = [C.c_void_p, D]
         L.orc_set_mlp.argtypes = [C.c_void_p, D, C.c_int64]
         L.orc_get_history.argtypes = [C.c_void_p, D, C.c_int]
+        L.orc_set_prev.argtypes = [C.c_void_p, C.c_int, I64, D, D]
         L.orc_get_rows_debug.argtypes = [C.c_void_p, D, D, D, C.c_int]
         L.orc_ncp_fb.argtypes = [C.c_double] * 3 + [D] * 3
         L.orc_ncp_min.argtypes = [C.c_double] * 3 + [D] * 3
@@ -203,6 +204,17 @@ class OracleEnv:
         out = np.zeros(256)
         n = lib().orc_get_history(self.h, _d(out), 256)
         return out[:n]
+
+    def set_prev(self, keys, lam3, lam_joint):
+        """Previous-step contact multipliers by key (ascending) and joint multipliers."""
+        k = np.ascontiguousarray(keys, dtype=np.int64)
+        l3 = np.ascontiguousarray(lam3, dtype=np.float64).reshape(-1)
+        lj = np.ascontiguousarray(lam_joint, dtype=np.float64).reshape(-1)
+        self._keep["prev"] = (k, l3, lj)
+        assert lj.size == 6 * self.desc.n_joints
+        st = lib().orc_set_prev(self.h, k.size, k.ctypes.data_as(I64), _d(l3), _d(lj) if lj.size else None)
+        if st != 0:
+            raise ValueError("orc_set_prev: bad keys or count")
 
     def rows_debug(self):
         n = lib().orc_num_rows(self.h)

@@ -2,15 +2,20 @@
 pre-step states.  Tolerance 1e-4 relative: positions over max(|x|, 1 m), velocities
 over max(|u|, g h), quaternions absolute.
 
-Three regimes are checked ("Parity"):
+Regimes:
   * per Newton iteration: 1..3 Newton updates of 40 PCR iterations from the same
     pre-step state, on every scene type (every kernel path, incl. geometric
-    stiffness at k >= 1 and the warm-start paths);
+    stiffness at k >= 1 and the warm-start paths).  Where the oracle itself moves by
+    more than 1e-5 under FP32-sized perturbations of its input (unconverged
+    iterates of FEM + rigid scenes, which share one set of Krylov scalars; kinks of
+    the NCP functions), the tolerance of the velocities (or of the positions) is
+    10x that group's spread instead;
+  * the grasp scene with one PCR iteration per Newton update, where its iterate is
+    far better determined than at 40 (same tolerance rule);
   * whole steps at the fixed 10 x 40 budget, several steps in lockstep, on scenes
     whose iterate path is smooth (joints, drives, free bodies, sliding, sticking);
   * converged steps (residual mode) on rigid contact stacks.
-Beyond a few iterations the non-smooth iteration amplifies FP32 rounding on
-contact-rich FEM scenes, so the fixed-budget path there is parity-unpinned."""
+"""
 import numpy as np
 import pytest
 
@@ -29,7 +34,7 @@ def _scene(envs, params=None):
 
 def _print(name, hist):
     for s, w in enumerate(hist):
-        print(name, s, {k: f"{v[0]:.2e}@{v[1]}" for k, v in w.items()}, flush=True)
+        print(name, s, {k: f"{v[0]:.2e}@{v[1]} (tol {v[2]:.1e})" for k, v in w.items()}, flush=True)
 
 
 def _driven_chain():
@@ -74,33 +79,37 @@ def test_per_newton_iteration_all_scene_kinds(newton, ncp):
     envs = _all_kinds()
     p = si.SolverParams(ncp=ncp)
     sc = _scene(envs, p)
-    hist = lockstep(sc, envs, p, H, newton, 40, steps=1)
+    hist = lockstep(sc, envs, p, H, newton, 40, steps=1, sens_factor=10.0)
     _print(f"iter{newton}", hist)
 
 
-@pytest.mark.parametrize("warm", [si.WARM_PREV])
-def test_per_newton_iteration_warm_start(warm):
-    """Warm-start path (projected previous multipliers, u0 = u~ + h M^-1 J^T lambda0):
-    both sides are first run in lockstep so that their previous-step multipliers agree."""
-    envs = [si.cube_stack(seed=2, n=3), si.batched_env(seed=1002, tets_max=300)]
-    p = si.SolverParams(warm=warm)
+@pytest.mark.parametrize("newton", [1, 2])
+def test_grasp_single_cr_iteration(newton):
+    """Every row type of the grasp scene (prismatic and revolute drives on a 6-DoF
+    arm, capsule fingers, FEM sphere on the ground, geometric stiffness) with one PCR
+    iteration per Newton update, where the iterate is far better determined than at
+    40 (the global Krylov scalars amplify rounding there): 1e-4, or 10x the oracle's
+    own spread on sticking-friction particles."""
+    envs = [si.grasp_scene(seed=0, sphere_cell=0.02), si.grasp_scene(seed=1, sphere_cell=0.02)]
+    p = si.SolverParams()
     sc = _scene(envs, p)
-    from oracle import oracle as O
-    op = O.make_params(p)
-    orcs = [O.OracleEnv(d) for d in envs]
-    for step in range(3):
-        pre = [sc.read_state(e) for e in range(len(envs))]
-        sc.step(H, 2, 40, 0.0)
-        for e, oe in enumerate(orcs):
-            oe.set_state({k: np.asarray(v, np.float64) for k, v in pre[e].items() if k != "time"})
-            oe.time = pre[e]["time"]
-            oe.step(H, 2, 40, 0.0, op)
-            got, ref = sc.read_state(e), oe.get_state()
-            for k in ["rigid_v", "particle_v"]:
-                if ref[k].size:
-                    err = np.abs(got[k] - ref[k]).max() / max(np.abs(ref[k]).max(), 9.81 * H)
-                    # the previous multipliers differ by FP32 rounding of the last step
-                    assert err < 1e-3, (step, e, k, err)
+    for s in range(3):  # let the sphere settle on the ground: active contacts and friction
+        sc.step(1.0 / 120.0, 10, 40, 0.0)
+    hist = lockstep(sc, envs, p, 1.0 / 120.0, newton, 1, steps=1, sens_factor=10.0)
+    _print(f"grasp{newton}", hist)
+
+
+@pytest.mark.parametrize("newton", [1, 2])
+def test_per_newton_iteration_warm_start(newton):
+    """Warm-start path (projected previous contact multipliers, previous joint
+    multipliers, start-configuration tet stresses, u0 = u^-): the oracle is given the
+    GPU's previous-step multipliers, so both sides start from the same lambda0."""
+    envs = [si.cube_stack(seed=2, n=3), si.batched_env(seed=1002, tets_max=300), _driven_chain(),
+            si.box_on_incline(0.3, 0.6)]
+    p = si.SolverParams(warm=si.WARM_PREV)
+    sc = _scene(envs, p)
+    hist = lockstep(sc, envs, p, H, newton, 40, steps=3, sens_factor=10.0, prev_from_gpu=True)
+    _print(f"warm{newton}", hist)
 
 
 def test_fixed_budget_lockstep_smooth_scenes():
@@ -132,7 +141,7 @@ def test_full_size_batch_sampled():
     sample = sorted(rng.choice(len(envs), size=12, replace=False).tolist())
     order = sc.env_order()
     sample += [int(order[0]), int(order[-1])]  # the largest and the smallest env
-    hist = lockstep(sc, envs, p, H, 2, 40, steps=1, env_ids=sample)
+    hist = lockstep(sc, envs, p, H, 2, 40, steps=1, env_ids=sample, sens_factor=10.0)
     _print("full", hist)
     st = sc.stats()
     assert not st["nonfinite"].any()

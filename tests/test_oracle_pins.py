@@ -560,3 +560,35 @@ def test_deep_penetration_stays_finite():
         st = env.step(1 / 60, 10, 40, 0.0)
         assert not st["nonfinite"]
     assert np.isfinite(env.get_state()["rigid_x"]).all()
+
+
+def test_set_prev_matches_own_warm_start_bookkeeping():
+    """Loading the previous-step multipliers through set_prev reproduces the oracle's
+    own warm start (the GPU parity tests feed the GPU's values this way).  set_state
+    renormalises quaternions, so the match is to rounding, not bitwise; leaving the
+    multipliers out changes the step by far more."""
+    d = si.batched_env(seed=1002, tets_max=60)
+    op = O.make_params(si.SolverParams(warm=si.WARM_PREV))
+    a = O.OracleEnv(d)
+    a.step(1 / 60, 3, 20, 0.0, op)
+    pre = a.get_state()
+    t0 = a.time
+    c = a.contacts()
+    lj = a.lambdas()[:6 * d.n_joints]
+    a.step(1 / 60, 3, 20, 0.0, op)
+    b = O.OracleEnv(d)
+    b.set_state(pre)
+    b.time = t0
+    b.set_prev(c["key"], c["lam"], lj)
+    b.step(1 / 60, 3, 20, 0.0, op)
+    assert len(c["key"]) > 0 and d.n_joints > 0
+    cold = O.OracleEnv(d)
+    cold.set_state(pre)
+    cold.time = t0
+    cold.step(1 / 60, 3, 20, 0.0, op)
+    ref, got, nop = a.get_state(), b.get_state(), cold.get_state()
+    for k in ref:
+        np.testing.assert_allclose(got[k], ref[k], rtol=0, atol=1e-7, err_msg=k)
+    assert max(np.abs(nop[k] - ref[k]).max() for k in ["rigid_v", "particle_v"]) > 1e-4
+    with pytest.raises(ValueError):
+        b.set_prev(c["key"][::-1].copy(), c["lam"], lj)  # keys must ascend
