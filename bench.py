@@ -169,7 +169,7 @@ def main():
     log(f"generating {args.envs} envs")
     envs = si.batched_envs(args.envs, base_seed=1000)
     model_blob = None
-    model_path = os.path.join(ROOT, "paper_1907_04587_amd", "weights", "warm_start_mlp.npy")
+    model_path = os.path.join(ROOT, "paper_1907_04587_amd", "weights", "warm_start_batched.npy")
     if os.path.exists(model_path):
         model_blob = np.load(model_path, allow_pickle=False)
     arms = [a for a in args.arms.split(",") if a and (a != "learned" or model_blob is not None)]
