@@ -23,7 +23,8 @@
 
 #define MAXENT 4
 #define TAU_GS 1e-6      /* READING: secant smoothing velocity scale (m/s) */
-#define KAPPA_W 1e-4     /* READING: floor on the FB friction denominator, relative to r*mu*lambda_n */
+#define KAPPA_W 1e-4     /* READING: FB friction denominator at or below which W is infinite, relative to r*mu*lambda_n */
+#define TAU_CR 1e-12     /* READING: PCR stops once <z, A z> falls below this fraction of its start */
 #define CLAMP_FEM 1e-3   /* READING: eigenvalue floor of the material Hessian, relative to 2*C1*Ve */
 #define JACOBI_SWEEPS 6
 #define TAU_NCP 1e-6      /* READING: derivative band around the NCP kink (units of C) */
@@ -163,11 +164,15 @@ void orc_ncp_min(double C, double lam, double r, double *phi, double *alpha, dou
 /* Sec. 4.3 eq. (friction_w) and Appendix A.2: the friction compliance W of one
  * contact with mu*lam_n > 0.  FB form (READING of the A.2 expressions: the
  * velocity magnitude enters unsquared; the fixed-point numerator is evaluated in a
- * cancellation-free way and the denominator is floored at KAPPA_W * r * mu * lam_n):
+ * cancellation-free way):
  *   s   = mu lam_n - |lam_f|
  *   num = sqrt(|v|^2 + r^2 s^2) - r s       (= |D^T u|^{n+1})
  *   den = |v| + r |lam_f| - num             (= r |lam_f|^{n+1})
- *   W   = r num / max(den, KAPPA_W r mu lam_n)
+ *   W   = r num / den
+ * READING: once |lam_f| leaves the cone far enough (about 2 mu lam_n at small slip),
+ * the fixed point asks for a friction magnitude |lam_f|^{n+1} <= 0, i.e. no friction
+ * force; W is then infinite (returned as INFINITY for den <= KAPPA_W r mu lam_n), and
+ * the row takes its W -> infinity limit, lam_f -> 0 (the form of inactive friction).
  * Minimum map: W = 0 if |v| <= r s, else (|v| - r s) / (mu lam_n). */
 double orc_friction_w(int ncp, double vnorm, double lam_n, double lamf_norm, double mu, double r) {
   double s = mu * lam_n - lamf_norm;
@@ -182,8 +187,7 @@ double orc_friction_w(int ncp, double vnorm, double lam_n, double lamf_norm, dou
   else
     num = root - r * s;
   double den = vnorm + r * lamf_norm - num;
-  double fl = KAPPA_W * r * mu * lam_n;
-  if (den < fl) den = fl;
+  if (den <= KAPPA_W * r * mu * lam_n) return INFINITY;
   return r * num / den;
 }
 
@@ -358,8 +362,9 @@ void orc_compliance3(const double *H, double floor_, int mode, double *E) {
 
 /* ------------------------------------------------------------------------- */
 /* Preconditioned conjugate residual (Sec. 8.2; Saad's CR with a left Jacobi  */
-/* preconditioner).  READING: x0 = 0, exactly `iters` iterations, breakdown    */
-/* guard on rho <= 0 or <q, Pq> <= 0.                                          */
+/* preconditioner).  READING: x0 = 0, at most `iters` iterations; stops when   */
+/* rho = <z, Az> <= TAU_CR rho_0 (the residual is at rounding level: further   */
+/* steps only amplify rounding) or <q, Pq> <= 0.                               */
 /* ------------------------------------------------------------------------- */
 typedef void (*orc_apply_fn)(void *ctx, const double *in, double *out);
 
@@ -374,8 +379,9 @@ static int pcr_solve(int n, orc_apply_fn apply, void *ctx, const double *b, cons
     apply(ctx, z, w);
     double rho = 0.0;
     for (int i = 0; i < n; ++i) { q[i] = w[i]; rho += z[i] * w[i]; }
+    const double rho_stop = TAU_CR * rho;
     for (int it = 0; it < iters; ++it) {
-      if (!(rho > 0.0)) break;
+      if (!(rho > rho_stop) || !(rho > 0.0)) break;
       double qs = 0.0;
       for (int i = 0; i < n; ++i) { s[i] = P[i] * q[i]; qs += q[i] * s[i]; }
       if (!(qs > 0.0)) break;
@@ -1246,18 +1252,22 @@ static void assemble(step_t *S) {
     S->Cblk[9 * r0] = be * r_n / (h * h);
     S->err[r0] = phi / h;
     /* friction (Sec. 4.3, Appendix A.2): active iff mu lam_n > 0 */
+    double v1 = 0.0, v2 = 0.0, W = INFINITY;
     if (e->mu * lam_n > 0.0) {
-      double v1 = jrow_dot(rt1, S->u), v2 = jrow_dot(rt2, S->u);
+      v1 = jrow_dot(rt1, S->u); v2 = jrow_dot(rt2, S->u);
       double vn = sqrt(v1 * v1 + v2 * v2);
       double lfn = sqrt(lf1 * lf1 + lf2 * lf2);
-      double W = orc_friction_w(p->ncp, vn, lam_n, lfn, e->mu, r_f);
+      W = orc_friction_w(p->ncp, vn, lam_n, lfn, e->mu, r_f);
+    }
+    if (isfinite(W)) {
       S->Cblk[9 * (r0 + 1)] = W / h;
       S->Cblk[9 * (r0 + 2)] = W / h;
       S->err[r0 + 1] = v1 + W * lf1;
       S->err[r0 + 2] = v2 + W * lf2;
     } else {
-      /* READING: inactive friction rows are zeroed; compliance r_f/h and error
-       * r_f lambda_f drive the multipliers to zero (Delta lambda_f = -lambda_f). */
+      /* READING: inactive friction rows (mu lam_n <= 0, or W infinite) are zeroed;
+       * compliance r_f/h and error r_f lambda_f drive the multipliers to zero
+       * (Delta lambda_f = -lambda_f). */
       rt1->nent = 0; rt2->nent = 0;
       S->Cblk[9 * (r0 + 1)] = r_f / h;
       S->Cblk[9 * (r0 + 2)] = r_f / h;

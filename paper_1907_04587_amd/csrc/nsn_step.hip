@@ -23,7 +23,8 @@
 namespace nsn {
 
 constexpr float kTauGS = 1e-6f;     // secant smoothing velocity (m/s)
-constexpr float kKappaW = 1e-4f;    // floor of the FB friction denominator (relative)
+constexpr float kKappaW = 1e-4f;    // FB friction denominator at or below which W is infinite (relative)
+constexpr double kTauCR = 1e-12;    // PCR stops once <z, A z> falls below this fraction of its start
 constexpr float kClampFem = 1e-3f;  // eigenvalue floor of the material Hessian (relative to 2 C1 Ve)
 constexpr int kJacobiSweeps = 6;
 constexpr float kTauNcp = 1e-6f;    // derivative band around the NCP kink (units of C)
@@ -120,8 +121,9 @@ __device__ __forceinline__ void ncp_min(float C, float lam, float r, float &phi,
 }
 
 // Friction compliance W (Sec. 4.3 eq. friction_w, Appendix A.2) with the velocity
-// magnitude unsquared, a cancellation-free fixed-point numerator and the
-// denominator floored at kKappaW r mu lam_n.
+// magnitude unsquared and a cancellation-free fixed-point numerator.  When the
+// fixed point asks for a non-positive friction magnitude (den = r |lam_f|^{n+1} at or
+// below kKappaW r mu lam_n) W is infinite: the caller then drives lam_f to zero.
 __device__ __forceinline__ float friction_w(int ncp, float vn, float lam_n, float lfn, float mu, float r) {
   const float s = mu * lam_n - lfn;
   if (ncp == NSN_NCP_MIN) {
@@ -130,9 +132,8 @@ __device__ __forceinline__ float friction_w(int ncp, float vn, float lam_n, floa
   }
   const float root = sqrtf(vn * vn + r * r * s * s);
   const float num = s > 0.f ? vn * vn / (root + r * s) : root - r * s;
-  float den = vn + r * lfn - num;
-  const float fl = kKappaW * r * mu * lam_n;
-  den = den < fl ? fl : den;
+  const float den = vn + r * lfn - num;
+  if (den <= kKappaW * r * mu * lam_n) return __builtin_huge_valf();
   return r * num / den;
 }
 
@@ -958,22 +959,26 @@ __device__ void assemble_contact(const Ctx &c, int cl, int buf) {
   S.c_alpha[(size_t)buf * S.NC + gc] = al;
   S.row_C[r0] = be * r_n / (h * h);
   S.row_err[r0] = phi / h;
-  const bool active = E.mu * lam_n > 0.f;
-  S.c_active[(size_t)buf * S.NC + gc] = active ? 1 : 0;
-  if (active) {
+  float v1 = 0.f, v2 = 0.f, W = __builtin_huge_valf();
+  if (E.mu * lam_n > 0.f) {
     const V3 vr = point_vel(c, S.r_u, S.p_u, bd.x, armA) -
                   (bd.y >= 0 ? point_vel(c, S.r_u, S.p_u, bd.y, armB) : mk(0.f, 0.f, 0.f));
-    const float v1 = dot(d1, vr), v2 = dot(d2, vr);
+    v1 = dot(d1, vr);
+    v2 = dot(d2, vr);
     const float vn = sqrtf(v1 * v1 + v2 * v2);
     const float lfn = sqrtf(lf1 * lf1 + lf2 * lf2);
-    const float W = friction_w(c.A.p.ncp, vn, lam_n, lfn, E.mu, r_f);
+    W = friction_w(c.A.p.ncp, vn, lam_n, lfn, E.mu, r_f);
+  }
+  const bool active = W < __builtin_huge_valf();
+  S.c_active[(size_t)buf * S.NC + gc] = active ? 1 : 0;
+  if (active) {
     S.row_C[r0 + 1] = W / h;
     S.row_C[r0 + 2] = W / h;
     S.row_err[r0 + 1] = v1 + W * lf1;
     S.row_err[r0 + 2] = v2 + W * lf2;
   } else {
-    // READING: inactive friction rows are removed (zero J); compliance r_f/h and
-    // error r_f lambda_f drive their multipliers to zero
+    // READING: inactive friction rows (mu lam_n <= 0, or W infinite) are removed
+    // (zero J); compliance r_f/h and error r_f lambda_f drive their multipliers to zero
     S.row_C[r0 + 1] = r_f / h;
     S.row_C[r0 + 2] = r_f / h;
     S.row_err[r0 + 1] = r_f * lf1;
@@ -1510,10 +1515,12 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     scatter_hinv(c, S.row_z, buf, Y, tid, BS);
     __syncthreads();
     double rho = block_sum<BS>(matvec_rows<BS, true>(c, Y, buf, nel, eps), red, 1);
+    // READING: stop once <z, A z> is at rounding level relative to its start
+    const double rho_stop = kTauCR * rho;
     float beta = 0.f;
     int done = 0;
     for (int it = 0; it < A.cr_iters; ++it) {
-      if (!(rho > 0.0)) break;
+      if (!(rho > rho_stop) || !(rho > 0.0)) break;
       double part = 0.0;
       for (int r = tid; r < nrows; r += BS) {
         const int row = R0 + r;
