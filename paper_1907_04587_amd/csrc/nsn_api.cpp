@@ -126,12 +126,14 @@ void layout(const Sizes &z, int n_envs, Arena &a, DevScene &S, EnvInfo *&env, in
   S.feat = a.take<int2>(z.NF);
   S.t_ids = a.take<int4>(z.NT); S.t_Dminv = a.take<float>(9 * (size_t)z.NT); S.t_mat = a.take<float4>(z.NT);
   S.t_J = a.take<float>(2 * 18 * (size_t)z.NT); S.t_E = a.take<float>(6 * (size_t)z.NT);
+  S.t_cj = a.take<float4>(4 * (size_t)z.NT);
   S.j_info = a.take<int4>(z.NJ); S.j_frame = a.take<float4>(6 * (size_t)z.NJ);
   S.j_drive = a.take<float4>(2 * (size_t)z.NJ); S.j_theta0 = a.take<float>(z.NJ);
   S.j_J = a.take<float>(72 * (size_t)z.NJ);
+  S.j_cj = a.take<float>(12 * (size_t)z.NJ);
   S.c_key = a.take<int>(z.NC); S.c_body = a.take<int2>(z.NC); S.c_n = a.take<float4>(z.NC);
   S.c_aL = a.take<float4>(z.NC); S.c_bL = a.take<float4>(z.NC); S.c_rA = a.take<float4>(z.NC);
-  S.c_rB = a.take<float4>(z.NC); S.c_alpha = a.take<float>(2 * (size_t)z.NC);
+  S.c_rB = a.take<float4>(z.NC); S.c_cj = a.take<float4>(z.NC); S.c_alpha = a.take<float>(2 * (size_t)z.NC);
   S.c_active = a.take<int>(2 * (size_t)z.NC); S.c_lam0 = a.take<float4>(z.NC);
   S.c_feat = a.take<float>(12 * (size_t)z.NC); S.c_prev_key = a.take<int>(z.NC);
   S.c_prev_lam = a.take<float4>(z.NC); S.n_prev = a.take<int>(n_envs);

@@ -62,6 +62,7 @@ struct DevScene {
   const float4 *t_mat;             // (Ve, C1, D1, alpha)
   float *t_J;                      // 2 x 18 x NT : u_i(3), w_i(3) per stretch row, ping-pong
   float *t_E;                      // 6 x NT : E (xx yy zz xy xz yz)
+  float4 *t_cj;                    // 4 x NT : J^T v of a tet, per particle slot (slot-major)
 
   // joints
   const int4 *j_info;              // (type, A global or -1, B global, has_drive)
@@ -69,6 +70,7 @@ struct DevScene {
   const float4 *j_drive;           // 2 per joint: (kp, kd, amp, freq), (phase, offset, -, -)
   float *j_theta0;                 // drive coordinate at q^-
   float *j_J;                      // NJ x 6 rows x 12 (J_A, J_B)
+  float *j_cj;                     // NJ x 12 : J^T v of a joint for its bodies A and B
 
   // contacts (capacity NC)
   int *c_key;
@@ -77,6 +79,7 @@ struct DevScene {
   float4 *c_n;                     // normal, thickness
   float4 *c_aL, *c_bL;             // feature / target points (body frame or world)
   float4 *c_rA, *c_rB;             // world arms at the current iterate
+  float4 *c_cj;                    // world direction of a contact's J^T v
   float *c_alpha;                  // 2 x NC ping-pong (normal row scale alpha)
   int *c_active;                   // 2 x NC ping-pong (friction rows active)
   float4 *c_lam0;                  // warm-start multipliers

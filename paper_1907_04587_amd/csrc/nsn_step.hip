@@ -1055,6 +1055,81 @@ __device__ V3 scatter_particle(const Ctx &c, int p, const float *src, int buf) {
 
 // ---- per-element row kernels (one unrolled path per element type) ----
 // (J Y) rows of joint jl
+// ---- J^T v in two passes: every element writes its contribution once (coalesced,
+// element-parallel), then every body sums the contributions of its elements in a
+// fixed order (deterministic, no atomics) ----
+__device__ __forceinline__ void joint_contrib(const Ctx &c, int jl, const float *src) {
+  const int jg = c.E.jnt_off + jl;
+  const int r0 = row_joint(c.E, jl);
+  const float *J = c.S.j_J + (size_t)72 * jg;
+  float o[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) o[q] = 0.f;
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    const float v = src[r0 + r];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) o[q] += v * J[12 * r + q];
+  }
+  float *dst = c.S.j_cj + (size_t)12 * jg;
+#pragma unroll
+  for (int q = 0; q < 12; ++q) dst[q] = o[q];
+}
+
+// z = the tet's three row values (already loaded)
+__device__ __forceinline__ void tet_contrib(const Ctx &c, int tl, const float z[3], int buf) {
+  const DevScene &S = c.S;
+  const int tg = c.E.tet_off + tl;
+  V3 a0 = mk(0.f, 0.f, 0.f), a1 = a0, a2 = a0, a3 = a0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const V3 zu = z[i] * mk(tJ(S, buf, 6 * i, tg), tJ(S, buf, 6 * i + 1, tg), tJ(S, buf, 6 * i + 2, tg));
+    const float w0 = tJ(S, buf, 6 * i + 3, tg), w1 = tJ(S, buf, 6 * i + 4, tg), w2 = tJ(S, buf, 6 * i + 5, tg);
+    a1 = a1 + w0 * zu;
+    a2 = a2 + w1 * zu;
+    a3 = a3 + w2 * zu;
+    a0 = a0 - (w0 + w1 + w2) * zu;
+  }
+  S.t_cj[tg] = f4(a0, 0.f);
+  S.t_cj[(size_t)S.NT + tg] = f4(a1, 0.f);
+  S.t_cj[(size_t)2 * S.NT + tg] = f4(a2, 0.f);
+  S.t_cj[(size_t)3 * S.NT + tg] = f4(a3, 0.f);
+}
+
+__device__ __forceinline__ void gather_rigid(const Ctx &c, int g, float out[6]) {
+  const DevScene &S = c.S;
+  for (int k = 0; k < 6; ++k) out[k] = 0.f;
+  for (int k = S.r_jadj_ptr[g]; k < S.r_jadj_ptr[g + 1]; ++k) {
+    const int ent = S.r_jadj[k];
+    const float *o = S.j_cj + (size_t)12 * (ent >> 1) + 6 * (ent & 1);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) out[q] += o[q];
+  }
+  for (int gc = S.r_acon_beg[g]; gc < S.r_acon_end[g]; ++gc) {
+    const V3 d = mk(S.c_cj[gc]);
+    const V3 a = cross(mk(S.c_rA[gc]), d);
+    out[0] += d.x; out[1] += d.y; out[2] += d.z; out[3] += a.x; out[4] += a.y; out[5] += a.z;
+  }
+  const int b0 = S.r_bcon_beg[g], bn = S.r_bcon_cnt[g];
+  for (int k = 0; k < bn; ++k) {
+    const int gc = S.bcon_list[b0 + k];
+    const V3 d = mk(S.c_cj[gc]);
+    const V3 a = cross(mk(S.c_rB[gc]), d);
+    out[0] -= d.x; out[1] -= d.y; out[2] -= d.z; out[3] -= a.x; out[4] -= a.y; out[5] -= a.z;
+  }
+}
+
+__device__ __forceinline__ V3 gather_particle(const Ctx &c, int p) {
+  const DevScene &S = c.S;
+  V3 acc = mk(0.f, 0.f, 0.f);
+  for (int k = S.p_tadj_ptr[p]; k < S.p_tadj_ptr[p + 1]; ++k) {
+    const int ent = S.p_tadj[k];
+    acc = acc + mk(S.t_cj[(size_t)(ent & 3) * S.NT + (ent >> 2)]);
+  }
+  for (int gc = S.p_acon_beg[p]; gc < S.p_acon_end[p]; ++gc) acc = acc + mk(S.c_cj[gc]);
+  return acc;
+}
+
 __device__ __forceinline__ void joint_JY(const Ctx &c, int jl, const float *Y, float jy[6]) {
   const EnvInfo &E = c.E;
   const int jg = E.jnt_off + jl;
@@ -1264,8 +1339,8 @@ __device__ __forceinline__ void hinv_rigid(const Ctx &c, int g, float v[6]) {
   v[3] = a.x; v[4] = a.y; v[5] = a.z;
 }
 
-// scatter src (rows) into Y (dofs) and apply H~^-1
-__device__ void scatter_hinv(const Ctx &c, const float *src, int buf, float *Y, int tid, int BS) {
+// Y = H~^-1 (sum of the element contributions) for every body of the env
+__device__ void gather_hinv(const Ctx &c, float *Y, int tid, int BS) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   const int nb = E.n_rig + E.n_par;
@@ -1273,19 +1348,65 @@ __device__ void scatter_hinv(const Ctx &c, const float *src, int buf, float *Y, 
     if (b < E.n_rig) {
       const int g = E.rig_off + b;
       float v[6];
-      scatter_rigid(c, g, src, buf, v);
+      gather_rigid(c, g, v);
       hinv_rigid(c, g, v);
       const int d = 6 * b;
 #pragma unroll
       for (int k = 0; k < 6; ++k) Y[d + k] = v[k];
     } else {
       const int p = E.par_off + b - E.n_rig;
-      const V3 a = scatter_particle(c, p, src, buf);
+      const V3 a = gather_particle(c, p);
       const float4 H = S.p_H[p];
       const int d = 6 * E.n_rig + 3 * (b - E.n_rig);
       Y[d] = a.x / H.x;
       Y[d + 1] = a.y / H.y;
       Y[d + 2] = a.z / H.z;
+    }
+  }
+}
+
+// One PCR row: INIT z = P b, x = 0, p = z; else x += alpha p, z -= alpha s (s in b).
+template <bool INIT>
+__device__ __forceinline__ float pcr_row(const DevScene &S, int row, float alpha) {
+  if (INIT) {
+    const float z = S.row_P[row] * S.row_b[row];
+    S.row_x[row] = 0.f;
+    S.row_z[row] = z;
+    S.row_p[row] = z;
+    return z;
+  }
+  S.row_x[row] += alpha * S.row_p[row];
+  const float z = S.row_z[row] - alpha * S.row_b[row];
+  S.row_z[row] = z;
+  return z;
+}
+
+// Element pass of the PCR: the rows of every element are updated (pcr_row) and the
+// element then writes its J^T z contribution for the body pass (gather_hinv).
+template <int BS, bool INIT>
+__device__ void pcr_update_contrib(const Ctx &c, int buf, int nel, float alpha) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  for (int el = threadIdx.x; el < nel; el += BS) {
+    if (el < E.n_jnt) {
+      const int r0 = row_joint(E, el);
+#pragma unroll
+      for (int r = 0; r < 6; ++r) pcr_row<INIT>(S, r0 + r, alpha);
+      joint_contrib(c, el, S.row_z);
+    } else if (el < E.n_jnt + E.n_tet) {
+      const int tl = el - E.n_jnt;
+      const int r0 = row_tet(E, tl);
+      float z[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) z[r] = pcr_row<INIT>(S, r0 + r, alpha);
+      tet_contrib(c, tl, z, buf);
+    } else {
+      const int cl = el - E.n_jnt - E.n_tet;
+      const int r0 = row_con(E, cl);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) pcr_row<INIT>(S, r0 + r, alpha);
+      const int gc = E.con_off + cl;
+      S.c_cj[gc] = f4(contact_dir(c, gc, S.row_z, buf), 0.f);
     }
   }
 }
@@ -1502,17 +1623,12 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     __syncthreads();
 
     // ---- preconditioned conjugate residual (Sec. 8.2), x0 = 0, FP64 scalars ----
-    // per iteration: [p = z + beta p, q = w + beta q, s = P q, <q,s>] -> x += alpha p,
-    // z -= alpha s -> w = A z (scatter, H~^-1, gather), <z,w>
-    for (int r = tid; r < nrows; r += BS) {
-      const int row = R0 + r;
-      const float z = S.row_P[row] * S.row_b[row];
-      S.row_x[row] = 0.f;
-      S.row_z[row] = z;
-      S.row_p[row] = z;
-    }
+    // per iteration: [p = z + beta p, q = w + beta q, s = P q, <q,s>] -> element pass:
+    // x += alpha p, z -= alpha s, J^T z per element -> body pass: Y = H~^-1 (sum) ->
+    // element pass: w = J Y + C z + eps z, <z,w>
+    pcr_update_contrib<BS, true>(c, buf, nel, 0.f);
     __syncthreads();
-    scatter_hinv(c, S.row_z, buf, Y, tid, BS);
+    gather_hinv(c, Y, tid, BS);
     __syncthreads();
     double rho = block_sum<BS>(matvec_rows<BS, true>(c, Y, buf, nel, eps), red, 1);
     // READING: stop once <z, A z> is at rounding level relative to its start
@@ -1538,15 +1654,14 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       const double qs = block_sum<BS>(part, red, 0);
       if (!(qs > 0.0)) break;
       const float alpha = (float)(rho / qs);
-      for (int r = tid; r < nrows; r += BS) {
-        const int row = R0 + r;
-        S.row_x[row] += alpha * S.row_p[row];
-        S.row_z[row] -= alpha * S.row_b[row];
-      }
       ++done;
-      if (it == A.cr_iters - 1) break;  // the last update needs no further product
+      if (it == A.cr_iters - 1) {  // the last update needs no further product
+        for (int r = tid; r < nrows; r += BS) S.row_x[R0 + r] += alpha * S.row_p[R0 + r];
+        break;
+      }
+      pcr_update_contrib<BS, false>(c, buf, nel, alpha);  // x, z and the J^T z contributions
       __syncthreads();
-      scatter_hinv(c, S.row_z, buf, Y, tid, BS);
+      gather_hinv(c, Y, tid, BS);
       __syncthreads();
       const double rho_new = block_sum<BS>(matvec_rows<BS, false>(c, Y, buf, nel, eps), red, 1);
       beta = (float)(rho_new / rho);
