@@ -1119,10 +1119,25 @@ __device__ __forceinline__ void gather_rigid(const Ctx &c, int g, float out[6]) 
   }
 }
 
+// Sums run in CSR order; four entries are loaded ahead of their use so that the
+// dependent index -> contribution loads overlap (same rounding as one at a time).
 __device__ __forceinline__ V3 gather_particle(const Ctx &c, int p) {
   const DevScene &S = c.S;
   V3 acc = mk(0.f, 0.f, 0.f);
-  for (int k = S.p_tadj_ptr[p]; k < S.p_tadj_ptr[p + 1]; ++k) {
+  const int k0 = S.p_tadj_ptr[p], k1 = S.p_tadj_ptr[p + 1];
+  int k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    const int e0 = S.p_tadj[k], e1 = S.p_tadj[k + 1], e2 = S.p_tadj[k + 2], e3 = S.p_tadj[k + 3];
+    const float4 c0 = S.t_cj[(size_t)(e0 & 3) * S.NT + (e0 >> 2)];
+    const float4 c1 = S.t_cj[(size_t)(e1 & 3) * S.NT + (e1 >> 2)];
+    const float4 c2 = S.t_cj[(size_t)(e2 & 3) * S.NT + (e2 >> 2)];
+    const float4 c3 = S.t_cj[(size_t)(e3 & 3) * S.NT + (e3 >> 2)];
+    acc = acc + mk(c0);
+    acc = acc + mk(c1);
+    acc = acc + mk(c2);
+    acc = acc + mk(c3);
+  }
+  for (; k < k1; ++k) {
     const int ent = S.p_tadj[k];
     acc = acc + mk(S.t_cj[(size_t)(ent & 3) * S.NT + (ent >> 2)]);
   }
@@ -1637,19 +1652,34 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     int done = 0;
     for (int it = 0; it < A.cr_iters; ++it) {
       if (!(rho > rho_stop) || !(rho > 0.0)) break;
+      // direction update of the previous iteration, fused with s = P q; two rows per
+      // pass with all loads issued first
       double part = 0.0;
-      for (int r = tid; r < nrows; r += BS) {
-        const int row = R0 + r;
-        float pp = S.row_p[row], qq = S.row_q[row];
-        if (it > 0) {  // direction update of the previous iteration, fused with s = P q
-          pp = S.row_z[row] + beta * pp;
-          qq = S.row_w[row] + beta * qq;
-          S.row_p[row] = pp;
-          S.row_q[row] = qq;
+      for (int r = tid; r < nrows; r += 2 * BS) {
+        const int ra = R0 + r, rb = R0 + min(r + BS, nrows - 1);
+        const bool hb = r + BS < nrows;
+        float pa = S.row_p[ra], qa = S.row_q[ra], Pa = S.row_P[ra];
+        float pb = S.row_p[rb], qb = S.row_q[rb], Pb = S.row_P[rb];
+        if (it > 0) {
+          const float za = S.row_z[ra], wa = S.row_w[ra], zb = S.row_z[rb], wb = S.row_w[rb];
+          pa = za + beta * pa;
+          qa = wa + beta * qa;
+          pb = zb + beta * pb;
+          qb = wb + beta * qb;
+          S.row_p[ra] = pa;
+          S.row_q[ra] = qa;
+          if (hb) {
+            S.row_p[rb] = pb;
+            S.row_q[rb] = qb;
+          }
         }
-        const float sv = S.row_P[row] * qq;
-        S.row_b[row] = sv;  // s = P q (b is no longer needed)
-        part += (double)qq * (double)sv;
+        const float sa = Pa * qa, sb = Pb * qb;
+        S.row_b[ra] = sa;  // s = P q (b is no longer needed)
+        part += (double)qa * (double)sa;
+        if (hb) {
+          S.row_b[rb] = sb;
+          part += (double)qb * (double)sb;
+        }
       }
       const double qs = block_sum<BS>(part, red, 0);
       if (!(qs > 0.0)) break;
