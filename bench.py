@@ -143,14 +143,14 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--envs", type=int, default=4096)
     ap.add_argument("--newton", type=int, default=50)
     ap.add_argument("--cr", type=int, default=40)
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--arms", default="zero,prev,learned")
     ap.add_argument("--schedule", action="store_true", help="autotune the launch schedule first")
-    ap.add_argument("--cpu-envs", type=int, default=32)
+    ap.add_argument("--cpu-envs", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

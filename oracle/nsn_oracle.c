@@ -1473,10 +1473,27 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
   double *b = calloc(nr_alloc, sizeof(double)), *P = calloc(nr_alloc, sizeof(double));
   double *x = calloc(nr_alloc, sizeof(double)), *du = calloc(nd, sizeof(double));
 
-  start_iterate(&S);
-  e->nhist = 0;
   int newton_done = 0, cr_total = 0;
   double r_ncp = 0, r_con = 0, merit = 0;
+  orc_params pzero = *p;
+  pzero.warm = 0;
+  /* READING (recovery, not in the paper): a warm-started step whose iterate turns
+   * non-finite is rerun from the paper's plain start u0 = 0, lambda0 = 0 at q^-;
+   * the work of both attempts is counted. */
+  for (int attempt = 0; attempt < 2; ++attempt) {
+  if (attempt == 1) {
+    S.p = &pzero;
+    memcpy(e->rx, S.x0, 3 * e->nr * sizeof(double));
+    memcpy(e->rq, S.q0, 4 * e->nr * sizeof(double));
+    memcpy(e->px, S.px0, 3 * e->np * sizeof(double));
+    for (int pi = 0; pi < e->np; ++pi)
+      for (int k = 0; k < 3; ++k) S.Hdiag[3 * pi + k] = e->pm[pi];
+    S.have_prev = 0;
+    st->nonfinite = 0;
+    st->fallback = 1;
+  }
+  start_iterate(&S);
+  e->nhist = 0;
   for (int k = 0; k <= N; ++k) {
     assemble(&S);
     /* momentum balance g = M~(u - u~) - h J^T lambda (Sec. 6.1) */
@@ -1540,6 +1557,9 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
     update_positions(&S);
     ++newton_done;
   }
+  if (!st->nonfinite || S.p->warm == 0) break;
+  }
+  S.p = p;
   st->newton_iters = newton_done;
   st->cr_iters = cr_total;
   st->r_ncp = r_ncp;

@@ -68,7 +68,7 @@ typedef struct {
   int32_t n_contacts;
   int32_t overflow;       /* contacts dropped beyond max_contacts */
   int32_t nonfinite;
-  int32_t pad;
+  int32_t fallback;       /* 1 if a warm-started step went non-finite and was rerun from the plain start */
   double r_ncp;           /* final max(|M^-1 g|_inf, |err|_inf) */
   double r_contact;       /* same, contact rows only */
   double merit;           /* final |[g; err]|_2 */

@@ -45,10 +45,12 @@ class StatsC(C.Structure):
 
 
 ACC_DTYPE = np.dtype([("steps", np.int64), ("newton_iters", np.int64), ("cr_iters", np.int64),
-                      ("converged", np.int64), ("nonfinite", np.int64), ("cr_bytes", np.float64)])
+                      ("converged", np.int64), ("nonfinite", np.int64), ("fallbacks", np.int64),
+                      ("cr_bytes", np.float64)])
 
 STATS_DTYPE = np.dtype([("newton_iters", np.int32), ("cr_iters", np.int32), ("n_contacts", np.int32),
                         ("overflow", np.int32), ("nonfinite", np.int32), ("converged", np.int32),
+                        ("fallback", np.int32), ("pad", np.int32),
                         ("r_ncp", np.float64), ("r_contact", np.float64), ("merit", np.float64),
                         ("r_ncp_first", np.float64)])
 

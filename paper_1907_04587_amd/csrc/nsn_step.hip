@@ -1453,6 +1453,21 @@ __device__ __forceinline__ void update_positions_body(const Ctx &c, int b) {
   }
 }
 
+// back to q^- (the rerun of a failed warm start)
+__device__ __forceinline__ void restore_positions_body(const Ctx &c, int b) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  if (b < E.n_rig) {
+    const int g = E.rig_off + b;
+    if (S.r_inertia[g].w == 0.f) return;
+    S.r_x[g] = S.r_x0[g];
+    S.r_q[g] = S.r_q0[g];
+  } else {
+    const int p = E.par_off + b - E.n_rig;
+    S.p_x[p] = S.p_x0[p];
+  }
+}
+
 template <int BS>
 __device__ void assemble_all(const Ctx &c, int buf, double tplus, int nc) {
   const EnvInfo &E = c.E;
@@ -1494,7 +1509,20 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
   // ---- start iterate (Sec. 8.1); READING for warm starts: projected lambda0 for
   //      contacts, the previous multipliers for joints, the start-configuration
   //      stress for tets, and u0 = u^- (the previous step's velocity) ----
-  const bool warm = A.p.warm != NSN_WARM_ZERO;
+  int newton_done = 0, cr_total = 0, nonfinite = 0, converged = 0, fallback = 0;
+  float r_ncp = 0.f, r_con = 0.f, r_first = 0.f;
+  double merit = 0.0;
+  // READING (recovery, not in the paper): a warm-started step whose iterate turns
+  // non-finite is rerun from the plain start u0 = 0, lambda0 = 0 at q^-; the work of
+  // both attempts is counted.  nonfinite is block-uniform (a block reduction).
+  for (int attempt = 0; attempt < 2; ++attempt) {
+  const bool warm = attempt == 0 && A.p.warm != NSN_WARM_ZERO;
+  if (attempt == 1) {
+    for (int b = tid; b < nb; b += BS) restore_positions_body(c, b);
+    nonfinite = 0;
+    fallback = 1;
+    __syncthreads();
+  }
   for (int r = tid; r < nrows; r += BS) {
     const int row = R0 + r;
     if (!warm) {
@@ -1532,9 +1560,6 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
   }
   __syncthreads();
 
-  int newton_done = 0, cr_total = 0, nonfinite = 0, converged = 0;
-  float r_ncp = 0.f, r_con = 0.f, r_first = 0.f;
-  double merit = 0.0;
   for (int k = 0; k <= A.newton_iters; ++k) {
     const int buf = k & 1;
     assemble_all<BS>(c, buf, tplus, nc);
@@ -1728,6 +1753,8 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     __syncthreads();
     ++newton_done;
   }
+  if (!nonfinite || !warm) break;
+  }
 
   // ---- write-back ----
   for (int b = tid; b < nb; b += BS) {
@@ -1758,6 +1785,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     st.overflow = S.overflow[e];
     st.nonfinite = nonfinite;
     st.converged = converged;
+    st.fallback = fallback;
     st.r_ncp = r_ncp;
     st.r_contact = r_con;
     st.merit = merit;
@@ -1769,6 +1797,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     a.cr_iters += cr_total;
     a.converged += converged;
     a.nonfinite += nonfinite;
+    a.fallbacks += fallback;
     a.cr_bytes += (double)cr_total * (kBytesTet * E.n_tet + kBytesContact * nc + kBytesJoint * E.n_jnt +
                                       kBytesDof * (6.0 * E.n_rig + 3.0 * E.n_par));
     S.acc[e] = a;

@@ -43,6 +43,8 @@ def train_mlp(x, t, epochs=20, batch=4096, lr=2e-3, seed=0, log=None, device="cu
     import torch
 
     lib = L.lib()
+    if not (np.isfinite(x).all() and np.isfinite(t).all()):
+        raise ValueError("training data holds non-finite values")
     xm, xs, ym, ys = standardisation(x, t)
     xn = torch.tensor((x - xm) / xs, dtype=torch.float32, device=device)
     tn = torch.tensor((t - ym) / ys, dtype=torch.float32, device=device)
@@ -113,13 +115,17 @@ def generate_dataset(envs, steps, h, newton_iters=50, cr_iters=40, tol=1e-6, war
         sc.step(h, newton_iters, cr_iters, tol)
         if s < warmup:
             continue
+        st = sc.stats()
         for e in range(len(envs)):
+            if st["nonfinite"][e] or st["fallback"][e]:
+                continue  # a step that failed from its start teaches nothing
             f = sc.features(e)
             if len(f) == 0:
                 continue
-            lam = sc.contacts(e)["lam"]
-            xs.append(f)
-            ts.append(lam[:len(f)])
+            lam = sc.contacts(e)["lam"][:len(f)]
+            ok = np.isfinite(f).all(1) & np.isfinite(lam).all(1)
+            xs.append(f[ok])
+            ts.append(lam[ok])
         if log and (s + 1) % 20 == 0:
             log(f"dataset step {s + 1}/{warmup + steps}: {sum(len(a) for a in xs)} contacts")
     return np.concatenate(xs), np.concatenate(ts)

@@ -76,3 +76,38 @@ def test_python_layer_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         L.lib()
+
+
+def test_record_types_match_c_structs(tmp_path):
+    """The binding's numpy record types have the sizes and field offsets of the C
+    structs in include/nsn.h (compiled here with the host C compiler)."""
+    import shutil
+    import subprocess
+
+    from paper_1907_04587_amd import _lib as L
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    inc = os.path.join(ROOT, "include")
+    fields = {"nsn_step_stats": L.STATS_DTYPE, "nsn_accum": L.ACC_DTYPE}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "nsn.h"', "int main(void) {"]
+    for st, dt in fields.items():
+        lines.append(f'  printf("{st} size %zu\\n", sizeof({st}));')
+        for name in dt.names:
+            if name != "pad":
+                lines.append(f'  printf("{st} {name} %zu\\n", offsetof({st}, {name}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            st, name, val = ln.split()
+            got[(st, name)] = int(val)
+    for st, dt in fields.items():
+        assert got[(st, "size")] == dt.itemsize, st
+        for name in dt.names:
+            if name != "pad":
+                assert got[(st, name)] == dt.fields[name][1], (st, name)

@@ -628,3 +628,32 @@ def test_set_prev_matches_own_warm_start_bookkeeping():
     assert max(np.abs(nop[k] - ref[k]).max() for k in ["rigid_v", "particle_v"]) > 1e-4
     with pytest.raises(ValueError):
         b.set_prev(c["key"][::-1].copy(), c["lam"], lj)  # keys must ascend
+
+
+def test_warm_start_nonfinite_falls_back_to_plain_start():
+    """Recovery rule: a warm-started step whose iterate turns non-finite (here an
+    infinite previous normal multiplier) is rerun from the plain start, and then
+    equals the plain step from the same state exactly."""
+    d = si.cube_stack(seed=0, n=2)
+    h = 1 / 60
+    a = O.OracleEnv(d)
+    a.step(h, 5, 20, 0.0, O.make_params(warm=0))
+    pre, t0 = a.get_state(), a.time
+    c = a.contacts()
+    bad = np.array(c["lam"])
+    bad[:, 0] = np.inf
+    w = O.OracleEnv(d)
+    w.set_state(pre)
+    w.time = t0
+    w.set_prev(c["key"], bad, np.zeros(0))
+    st = w.step(h, 5, 20, 0.0, O.make_params(warm=1))
+    assert st["fallback"] == 1 and st["nonfinite"] == 0
+    z = O.OracleEnv(d)
+    z.set_state(pre)
+    z.time = t0
+    stz = z.step(h, 5, 20, 0.0, O.make_params(warm=0))
+    assert stz["fallback"] == 0
+    for k, v in z.get_state().items():
+        assert np.array_equal(v, w.get_state()[k]), k
+    # the failed attempt stopped at its first residual (no update), so it adds no work
+    assert st["newton_iters"] == stz["newton_iters"] and st["cr_iters"] == stz["cr_iters"]
