@@ -132,6 +132,9 @@ typedef struct {
   int32_t converged;    /* 1 if r_ncp <= tol at exit (tol > 0) */
   int32_t fallback;     /* 1 if a warm-started step went non-finite and was rerun
                            from the plain start (u0 = 0, lambda0 = 0) */
+  int32_t watchdog;     /* 1 if the iteration diverged (merit beyond 1e6 times the
+                           step's best, or non-finite) and the step returned its
+                           lowest-merit iterate */
   double r_ncp;         /* max(|M^-1 g|_inf, |err|_inf) at the final iterate (FP64) */
   double r_contact;     /* same over contact rows only */
   double merit;         /* |[g; err]|_2 at the final iterate (FP64 accumulation) */
@@ -147,6 +150,7 @@ typedef struct {
   int64_t converged;        /* steps that ended with r_ncp <= tol (tol > 0) */
   int64_t nonfinite;
   int64_t fallbacks;        /* warm-started steps rerun from the plain start */
+  int64_t watchdogs;        /* steps that returned their lowest-merit iterate */
   double cr_bytes;          /* algorithmic bytes of the PCR loop: per PCR iteration
                                332 B per tet + 228 B per contact + 880 B per joint
                                + 12 B per body-space DOF (vectors, compressed J and

@@ -25,6 +25,7 @@
 #define TAU_GS 1e-6      /* READING: secant smoothing velocity scale (m/s) */
 #define KAPPA_W 1e-4     /* READING: FB friction denominator at or below which W is infinite, relative to r*mu*lambda_n */
 #define TAU_CR 1e-12     /* READING: PCR stops once <z, A z> falls below this fraction of its start */
+#define WATCH_BLOWUP 1e6 /* READING: watchdog, merit growth over the step's best that ends the step */
 #define CLAMP_FEM 1e-3   /* READING: eigenvalue floor of the material Hessian, relative to 2*C1*Ve */
 #define JACOBI_SWEEPS 6
 #define TAU_NCP 1e-6      /* READING: derivative band around the NCP kink (units of C) */
@@ -1475,6 +1476,10 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
 
   int newton_done = 0, cr_total = 0;
   double r_ncp = 0, r_con = 0, merit = 0;
+  /* the step's best iterate (lowest merit) for the watchdog */
+  double *best_lam = calloc(nr_alloc, sizeof(double)), *best_u = calloc(nd, sizeof(double));
+  double *best_rx = calloc(3 * e->nr + 1, sizeof(double)), *best_rq = calloc(4 * e->nr + 1, sizeof(double));
+  double *best_px = calloc(3 * e->np + 1, sizeof(double));
   orc_params pzero = *p;
   pzero.warm = 0;
   /* READING (recovery, not in the paper): a warm-started step whose iterate turns
@@ -1494,6 +1499,12 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
   }
   start_iterate(&S);
   e->nhist = 0;
+  /* READING (Sec. 8.1 names watchdog strategies without using one): the step keeps
+   * its lowest-merit iterate; when the merit grows past WATCH_BLOWUP times that best,
+   * or turns non-finite outside a warm attempt, the iteration stops and the step
+   * returns the best iterate.  Ordinary non-monotone steps are far below that. */
+  double best_merit = INFINITY, best_r = 0, best_rc = 0;
+  int have_best = 0, restore = 0;
   for (int k = 0; k <= N; ++k) {
     assemble(&S);
     /* momentum balance g = M~(u - u~) - h J^T lambda (Sec. 6.1) */
@@ -1532,7 +1543,21 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
     merit = sqrt(m2);
     if (k == 0) st->r_ncp_first = r_ncp;
     if (e->nhist < MAX_HIST) e->hist[e->nhist++] = r_ncp;
-    if (!(r_ncp == r_ncp) || isinf(r_ncp)) { st->nonfinite = 1; break; }
+    int finite_now = r_ncp == r_ncp && !isinf(r_ncp) && merit == merit && !isinf(merit);
+    if (finite_now && merit < best_merit) {
+      best_merit = merit; best_r = r_ncp; best_rc = r_con; have_best = 1;
+      memcpy(best_lam, S.lam, S.nrows * sizeof(double));
+      memcpy(best_u, S.u, S.ndof * sizeof(double));
+      memcpy(best_rx, e->rx, 3 * e->nr * sizeof(double));
+      memcpy(best_rq, e->rq, 4 * e->nr * sizeof(double));
+      memcpy(best_px, e->px, 3 * e->np * sizeof(double));
+    }
+    if (!finite_now) {
+      if (S.p->warm != 0 || !have_best) { st->nonfinite = 1; break; }
+      restore = 1;
+      break;
+    }
+    if (merit > WATCH_BLOWUP * best_merit) { restore = 1; break; }
     if (k == N || r_ncp <= tol) break;
     /* Schur right-hand side and Jacobi preconditioner (Sec. 6.2, 8.2, 8.4) */
     apply_Hinv(&S, g, tmp);
@@ -1557,8 +1582,18 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
     update_positions(&S);
     ++newton_done;
   }
+  if (restore) {
+    memcpy(S.lam, best_lam, S.nrows * sizeof(double));
+    memcpy(S.u, best_u, S.ndof * sizeof(double));
+    memcpy(e->rx, best_rx, 3 * e->nr * sizeof(double));
+    memcpy(e->rq, best_rq, 4 * e->nr * sizeof(double));
+    memcpy(e->px, best_px, 3 * e->np * sizeof(double));
+    r_ncp = best_r; r_con = best_rc; merit = best_merit;
+    st->watchdog = 1;
+  }
   if (!st->nonfinite || S.p->warm == 0) break;
   }
+  free(best_lam); free(best_u); free(best_rx); free(best_rq); free(best_px);
   S.p = p;
   st->newton_iters = newton_done;
   st->cr_iters = cr_total;

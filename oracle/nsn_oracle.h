@@ -69,6 +69,8 @@ typedef struct {
   int32_t overflow;       /* contacts dropped beyond max_contacts */
   int32_t nonfinite;
   int32_t fallback;       /* 1 if a warm-started step went non-finite and was rerun from the plain start */
+  int32_t watchdog;       /* 1 if the step diverged and returned its lowest-merit iterate */
+  int32_t pad;
   double r_ncp;           /* final max(|M^-1 g|_inf, |err|_inf) */
   double r_contact;       /* same, contact rows only */
   double merit;           /* final |[g; err]|_2 */

@@ -44,6 +44,7 @@ class Stats(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("cr_iters", C.c_int32),
                 ("n_contacts", C.c_int32), ("overflow", C.c_int32),
                 ("nonfinite", C.c_int32), ("fallback", C.c_int32),
+                ("watchdog", C.c_int32), ("pad", C.c_int32),
                 ("r_ncp", C.c_double), ("r_contact", C.c_double), ("merit", C.c_double),
                 ("r_ncp_first", C.c_double)]
 

@@ -37,20 +37,13 @@ class ParamsC(C.Structure):
                 ("margin", C.c_float), ("warm", C.c_int32)]
 
 
-class StatsC(C.Structure):
-    _fields_ = [("newton_iters", C.c_int32), ("cr_iters", C.c_int32), ("n_contacts", C.c_int32),
-                ("overflow", C.c_int32), ("nonfinite", C.c_int32), ("converged", C.c_int32),
-                ("r_ncp", C.c_double), ("r_contact", C.c_double), ("merit", C.c_double),
-                ("r_ncp_first", C.c_double)]
-
-
 ACC_DTYPE = np.dtype([("steps", np.int64), ("newton_iters", np.int64), ("cr_iters", np.int64),
                       ("converged", np.int64), ("nonfinite", np.int64), ("fallbacks", np.int64),
-                      ("cr_bytes", np.float64)])
+                      ("watchdogs", np.int64), ("cr_bytes", np.float64)])
 
 STATS_DTYPE = np.dtype([("newton_iters", np.int32), ("cr_iters", np.int32), ("n_contacts", np.int32),
                         ("overflow", np.int32), ("nonfinite", np.int32), ("converged", np.int32),
-                        ("fallback", np.int32), ("pad", np.int32),
+                        ("fallback", np.int32), ("watchdog", np.int32),
                         ("r_ncp", np.float64), ("r_contact", np.float64), ("merit", np.float64),
                         ("r_ncp_first", np.float64)])
 
@@ -79,7 +72,7 @@ def lib():
     L.nsn_destroy_scene.argtypes = [VP]
     L.nsn_set_params.argtypes = [VP, C.POINTER(ParamsC)]
     L.nsn_step.argtypes = [VP, C.c_double, S, S, C.c_double]
-    L.nsn_get_stats.argtypes = [VP, C.POINTER(StatsC)]
+    L.nsn_get_stats.argtypes = [VP, VP]
     L.nsn_read_state.argtypes = [VP, S, F, F, F, F, F, F, D]
     L.nsn_write_state.argtypes = [VP, S, F, F, F, F, F, F, D]
     L.nsn_read_contacts.argtypes = [VP, S, S, I32, I32, I32, F, F]

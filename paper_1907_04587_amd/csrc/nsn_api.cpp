@@ -146,6 +146,9 @@ void layout(const Sizes &z, int n_envs, Arena &a, DevScene &S, EnvInfo *&env, in
   S.row_p = a.take<float>(z.NROW); S.row_q = a.take<float>(z.NROW); S.row_w = a.take<float>(z.NROW);
   S.row_err = a.take<float>(z.NROW); S.row_P = a.take<float>(z.NROW); S.row_C = a.take<float>(z.NROW);
   S.row_b = a.take<float>(z.NROW);
+  S.row_lam_best = a.take<float>(z.NROW); S.r_u_best = a.take<float>(6 * (size_t)z.NR);
+  S.r_x_best = a.take<float4>(z.NR); S.r_q_best = a.take<float4>(z.NR);
+  S.p_u_best = a.take<float4>(z.NP); S.p_x_best = a.take<float4>(z.NP);
   S.y = a.take<float>(z.NDOF); S.g = a.take<float>(z.NDOF); S.f = a.take<float>(z.NDOF);
   S.n_con = a.take<int>(n_envs); S.overflow = a.take<int>(n_envs); S.time = a.take<double>(n_envs);
   S.stats = a.take<nsn_step_stats>(n_envs);

@@ -100,6 +100,9 @@ struct DevScene {
 
   // rows (capacity NROW)
   float *row_lam, *row_x, *row_z, *row_p, *row_q, *row_w, *row_err, *row_P, *row_C, *row_b;
+  // the step's lowest-merit iterate (watchdog)
+  float *row_lam_best, *r_u_best;
+  float4 *r_x_best, *r_q_best, *p_u_best, *p_x_best;
 
   // body space (NDOF)
   float *y, *g, *f;

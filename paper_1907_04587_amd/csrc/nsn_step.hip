@@ -25,6 +25,7 @@ namespace nsn {
 constexpr float kTauGS = 1e-6f;     // secant smoothing velocity (m/s)
 constexpr float kKappaW = 1e-4f;    // FB friction denominator at or below which W is infinite (relative)
 constexpr double kTauCR = 1e-12;    // PCR stops once <z, A z> falls below this fraction of its start
+constexpr double kWatchBlowup = 1e6; // watchdog: merit growth over the step's best that ends the step
 constexpr float kClampFem = 1e-3f;  // eigenvalue floor of the material Hessian (relative to 2 C1 Ve)
 constexpr int kJacobiSweeps = 6;
 constexpr float kTauNcp = 1e-6f;    // derivative band around the NCP kink (units of C)
@@ -1453,6 +1454,34 @@ __device__ __forceinline__ void update_positions_body(const Ctx &c, int b) {
   }
 }
 
+// the env's iterate (multipliers, velocities, positions) into / out of the best slot
+__device__ void keep_best(const Ctx &c, int nrows, bool restore) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  const int nb = E.n_rig + E.n_par;
+  for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
+    const int row = E.row_off + r;
+    if (restore) S.row_lam[row] = S.row_lam_best[row];
+    else S.row_lam_best[row] = S.row_lam[row];
+  }
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    if (b < E.n_rig) {
+      const int g = E.rig_off + b;
+      float *u = S.r_u + 6 * g, *ub = S.r_u_best + 6 * g;
+      for (int k = 0; k < 6; ++k) {
+        if (restore) u[k] = ub[k];
+        else ub[k] = u[k];
+      }
+      if (restore) { S.r_x[g] = S.r_x_best[g]; S.r_q[g] = S.r_q_best[g]; }
+      else { S.r_x_best[g] = S.r_x[g]; S.r_q_best[g] = S.r_q[g]; }
+    } else {
+      const int p = E.par_off + b - E.n_rig;
+      if (restore) { S.p_u[p] = S.p_u_best[p]; S.p_x[p] = S.p_x_best[p]; }
+      else { S.p_u_best[p] = S.p_u[p]; S.p_x_best[p] = S.p_x[p]; }
+    }
+  }
+}
+
 // back to q^- (the rerun of a failed warm start)
 __device__ __forceinline__ void restore_positions_body(const Ctx &c, int b) {
   const EnvInfo &E = c.E;
@@ -1509,7 +1538,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
   // ---- start iterate (Sec. 8.1); READING for warm starts: projected lambda0 for
   //      contacts, the previous multipliers for joints, the start-configuration
   //      stress for tets, and u0 = u^- (the previous step's velocity) ----
-  int newton_done = 0, cr_total = 0, nonfinite = 0, converged = 0, fallback = 0;
+  int newton_done = 0, cr_total = 0, nonfinite = 0, converged = 0, fallback = 0, watchdog = 0;
   float r_ncp = 0.f, r_con = 0.f, r_first = 0.f;
   double merit = 0.0;
   // READING (recovery, not in the paper): a warm-started step whose iterate turns
@@ -1523,6 +1552,13 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     fallback = 1;
     __syncthreads();
   }
+  // READING (Sec. 8.1 names watchdog strategies without using one): the step keeps
+  // its lowest-merit iterate; when the merit grows past kWatchBlowup times that best,
+  // or turns non-finite outside a warm attempt, the iteration stops and the step
+  // returns the best iterate.  All the quantities deciding this are block-uniform.
+  double best_merit = __builtin_huge_val();
+  float best_r = 0.f, best_rc = 0.f;
+  bool have_best = false, restore = false;
   for (int r = tid; r < nrows; r += BS) {
     const int row = R0 + r;
     if (!warm) {
@@ -1636,7 +1672,20 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     r_con = rcon;
     merit = sqrt(msum);
     if (k == 0) r_first = rmax;
-    if (!(rmax == rmax) || isinf(rmax)) { nonfinite = 1; break; }
+    const bool finite_now = rmax == rmax && !isinf(rmax) && msum == msum && !isinf(msum);
+    if (finite_now && merit < best_merit) {
+      best_merit = merit;
+      best_r = rmax;
+      best_rc = rcon;
+      have_best = true;
+      keep_best(c, nrows, false);
+    }
+    if (!finite_now) {
+      if (warm || !have_best) { nonfinite = 1; break; }
+      restore = true;
+      break;
+    }
+    if (merit > kWatchBlowup * best_merit) { restore = true; break; }
     if (A.tol > 0.f && rmax <= A.tol) { converged = 1; break; }
     if (k == A.newton_iters) break;
 
@@ -1753,6 +1802,15 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     __syncthreads();
     ++newton_done;
   }
+  if (restore) {
+    __syncthreads();
+    keep_best(c, nrows, true);
+    r_ncp = best_r;
+    r_con = best_rc;
+    merit = best_merit;
+    watchdog = 1;
+    __syncthreads();
+  }
   if (!nonfinite || !warm) break;
   }
 
@@ -1786,6 +1844,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     st.nonfinite = nonfinite;
     st.converged = converged;
     st.fallback = fallback;
+    st.watchdog = watchdog;
     st.r_ncp = r_ncp;
     st.r_contact = r_con;
     st.merit = merit;
@@ -1798,6 +1857,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     a.converged += converged;
     a.nonfinite += nonfinite;
     a.fallbacks += fallback;
+    a.watchdogs += watchdog;
     a.cr_bytes += (double)cr_total * (kBytesTet * E.n_tet + kBytesContact * nc + kBytesJoint * E.n_jnt +
                                       kBytesDof * (6.0 * E.n_rig + 3.0 * E.n_par));
     S.acc[e] = a;

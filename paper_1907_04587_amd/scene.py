@@ -96,9 +96,9 @@ class Scene:
         L.check(self.lib.nsn_step(self.h, float(h), int(newton_iters), int(cr_iters), float(tol)), "nsn_step")
 
     def stats(self):
-        arr = (L.StatsC * self.n_envs)()
-        L.check(self.lib.nsn_get_stats(self.h, arr), "nsn_get_stats")
-        return np.frombuffer(bytes(arr), dtype=L.STATS_DTYPE).copy()
+        out = np.zeros(self.n_envs, L.STATS_DTYPE)
+        L.check(self.lib.nsn_get_stats(self.h, out.ctypes.data), "nsn_get_stats")
+        return out
 
     def synchronize(self):
         self.stream.synchronize()

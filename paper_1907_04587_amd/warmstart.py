@@ -45,6 +45,11 @@ def train_mlp(x, t, epochs=20, batch=4096, lr=2e-3, seed=0, log=None, device="cu
     lib = L.lib()
     if not (np.isfinite(x).all() and np.isfinite(t).all()):
         raise ValueError("training data holds non-finite values")
+    # steps that diverged leave a few multipliers orders of magnitude above the rest;
+    # they would set the target scale, so every column is clipped to its
+    # 0.05..99.95 % quantiles (a warm start need not reproduce them)
+    x = np.clip(x, *np.quantile(x, [5e-4, 1 - 5e-4], axis=0))
+    t = np.clip(t, *np.quantile(t, [5e-4, 1 - 5e-4], axis=0))
     xm, xs, ym, ys = standardisation(x, t)
     xn = torch.tensor((x - xm) / xs, dtype=torch.float32, device=device)
     tn = torch.tensor((t - ym) / ys, dtype=torch.float32, device=device)
@@ -75,11 +80,14 @@ def train_mlp(x, t, epochs=20, batch=4096, lr=2e-3, seed=0, log=None, device="cu
             L.check(lib.nsn_mlp_adam(w.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), N_PARAMS,
                                      C.c_float(lr_ep), C.c_float(0.9), C.c_float(0.999), C.c_float(1e-8), step,
                                      C.c_void_p(stream)), "nsn_mlp_adam")
-            tot += loss.item() * nb
+            lv = loss.item()
+            if not np.isfinite(lv):
+                raise FloatingPointError(f"training loss became non-finite in epoch {ep + 1}")
+            tot += lv * nb
             cnt += nb
         hist.append(tot / cnt)
         if log:
-            log(f"epoch {ep + 1}/{epochs} loss {hist[-1]:.5f}")
+            log(f"epoch {ep + 1}/{epochs} loss {hist[-1]:.5e}")
     blob = np.concatenate([w.cpu().numpy(), xm, xs, ym, ys]).astype(np.float32)
     return blob, hist
 

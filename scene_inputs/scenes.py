@@ -405,16 +405,24 @@ def batched_env(seed, tets_max=3000, boxes=(5, 40), joints_max=12, max_contacts=
                 joints.append(_revolute(ia, ib, (h + 0.5 * gap, 0.0, 0.0), (-h - 0.5 * gap, 0.0, 0.0),
                                         (0.0, 1.0, 0.0), (0.0, 1.0, 0.0),
                                         (1.0, 0.0, 0.0), (1.0, 0.0, 0.0)))
-    # free boxes: some dropped on the block, the rest stacked on the ground at x < -0.6
+    # free boxes: some dropped on the block, the rest stacked on the ground at x < -0.6.
+    # Dropped boxes sit in a grid of cells over the block top (pitch 0.22 m: a 0.15 m box
+    # turned about z spans up to 0.212 m), at most two layers 0.17 m apart, starting
+    # 1-2 cm above the block, so that no two bodies overlap at t = 0.
     n_free = n_boxes - len(bodies)
     on_block = n_free // 3 if block_top > 0 else 0
+    lx, ly = nx * cell, ny * cell
+    pitch = 0.22
+    ncx, ncy = max(1, int(lx // pitch)), max(1, int(ly // pitch))
+    on_block = min(on_block, 2 * ncx * ncy)
     for b in range(on_block):
+        layer, slot = divmod(b, ncx * ncy)
+        i, j = divmod(slot, ncy)
         s = rng.uniform(0.05, 0.15)
         h = 0.5 * s
-        lx, ly = nx * cell, ny * cell
-        px = rng.uniform(min(h, 0.5 * lx), max(lx - h, 0.5 * lx))
-        py = rng.uniform(min(h, 0.5 * ly), max(ly - h, 0.5 * ly))
-        pz = block_top + h + rng.uniform(0.0, 0.05) + 0.15 * b
+        px = (i + 0.5) * lx / ncx + rng.uniform(-5e-3, 5e-3)
+        py = (j + 0.5) * ly / ncy + rng.uniform(-5e-3, 5e-3)
+        pz = block_top + 0.01 + rng.uniform(0.0, 0.01) + h + 0.17 * layer
         bodies.append(_box(1000.0 * s ** 3, (h, h, h), (px, py, pz),
                            q=quat_from_axis_angle((0, 0, 1), rng.uniform(0, 2 * math.pi))))
     rest = n_free - on_block

@@ -79,8 +79,9 @@ def test_python_layer_fails_loudly_without_library(monkeypatch, tmp_path):
 
 
 def test_record_types_match_c_structs(tmp_path):
-    """The binding's numpy record types have the sizes and field offsets of the C
-    structs in include/nsn.h (compiled here with the host C compiler)."""
+    """The binding's numpy record types and ctypes structures have the sizes and field
+    offsets of the C structs in include/nsn.h (compiled here with the host C
+    compiler).  A stale mirror lets the library write past a host buffer."""
     import shutil
     import subprocess
 
@@ -89,12 +90,14 @@ def test_record_types_match_c_structs(tmp_path):
         pytest.skip("no host C compiler")
     inc = os.path.join(ROOT, "include")
     fields = {"nsn_step_stats": L.STATS_DTYPE, "nsn_accum": L.ACC_DTYPE}
+    cstructs = {"nsn_env_desc": L.EnvDescC, "nsn_solver_params": L.ParamsC}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "nsn.h"', "int main(void) {"]
-    for st, dt in fields.items():
+    names = {st: [n for n in dt.names if n != "pad"] for st, dt in fields.items()}
+    names.update({st: [f[0] for f in cls._fields_] for st, cls in cstructs.items()})
+    for st, ns in names.items():
         lines.append(f'  printf("{st} size %zu\\n", sizeof({st}));')
-        for name in dt.names:
-            if name != "pad":
-                lines.append(f'  printf("{st} {name} %zu\\n", offsetof({st}, {name}));')
+        for name in ns:
+            lines.append(f'  printf("{st} {name} %zu\\n", offsetof({st}, {name}));')
     lines += ["  return 0;", "}"]
     src = tmp_path / "probe.c"
     src.write_text("\n".join(lines))
@@ -111,3 +114,7 @@ def test_record_types_match_c_structs(tmp_path):
         for name in dt.names:
             if name != "pad":
                 assert got[(st, name)] == dt.fields[name][1], (st, name)
+    for st, cls in cstructs.items():
+        assert got[(st, "size")] == C.sizeof(cls), st
+        for name, _ in cls._fields_:
+            assert got[(st, name)] == getattr(cls, name).offset, (st, name)
