@@ -126,7 +126,7 @@ void layout(const Sizes &z, int n_envs, Arena &a, DevScene &S, EnvInfo *&env, in
   S.feat = a.take<int2>(z.NF);
   S.t_ids = a.take<int4>(z.NT); S.t_Dminv = a.take<float>(9 * (size_t)z.NT); S.t_mat = a.take<float4>(z.NT);
   S.t_J = a.take<float>(2 * 18 * (size_t)z.NT); S.t_E = a.take<float>(6 * (size_t)z.NT);
-  S.t_cj = a.take<float4>(4 * (size_t)z.NT);
+  S.t_dst = a.take<int4>(z.NT); S.p_cj = a.take<float4>(z.NTADJ);
   S.j_info = a.take<int4>(z.NJ); S.j_frame = a.take<float4>(6 * (size_t)z.NJ);
   S.j_drive = a.take<float4>(2 * (size_t)z.NJ); S.j_theta0 = a.take<float>(z.NJ);
   S.j_J = a.take<float>(72 * (size_t)z.NJ);
@@ -276,6 +276,7 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
   std::vector<int4> j_info(z.NJ);
   std::vector<float4> j_frame(6 * (size_t)z.NJ), j_drive(2 * (size_t)z.NJ);
   std::vector<int> tadj_ptr(z.NP + 1, 0), tadj(std::max(z.NTADJ, 1)), jadj_ptr(z.NR + 1, 0), jadj(std::max(z.NJADJ, 1));
+  std::vector<int4> t_dst(std::max(z.NT, 1));
   int ro = 0, po = 0, to = 0, jo = 0, co = 0, rowo = 0, dofo = 0, fo = 0;
   for (int e = 0; e < n_envs; ++e) {
     const nsn_env_desc &d = envs[e];
@@ -380,7 +381,12 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
     std::vector<int> fill(tadj_ptr.begin(), tadj_ptr.end() - 1);
     for (int t = 0; t < z.NT; ++t) {
       const int ids[4] = {t_ids[t].x, t_ids[t].y, t_ids[t].z, t_ids[t].w};
-      for (int k = 0; k < 4; ++k) tadj[fill[ids[k]]++] = (t << 2) | k;
+      int pos[4];
+      for (int k = 0; k < 4; ++k) {
+        pos[k] = fill[ids[k]]++;
+        tadj[pos[k]] = (t << 2) | k;
+      }
+      t_dst[t] = make_int4(pos[0], pos[1], pos[2], pos[3]);
     }
   }
   for (int j = 0; j < z.NJ; ++j) {
@@ -431,6 +437,7 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
   HIP_TRY(up((void *)S.j_drive, j_drive.data(), sizeof(float4) * 2 * (size_t)z.NJ));
   HIP_TRY(up((void *)S.p_tadj_ptr, tadj_ptr.data(), sizeof(int) * (z.NP + 1)));
   HIP_TRY(up((void *)S.p_tadj, tadj.data(), sizeof(int) * z.NTADJ));
+  HIP_TRY(up((void *)S.t_dst, t_dst.data(), sizeof(int4) * z.NT));
   HIP_TRY(up((void *)S.r_jadj_ptr, jadj_ptr.data(), sizeof(int) * (z.NR + 1)));
   HIP_TRY(up((void *)S.r_jadj, jadj.data(), sizeof(int) * z.NJADJ));
   HIP_TRY(hipStreamSynchronize(st_));

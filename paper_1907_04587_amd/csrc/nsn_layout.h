@@ -62,7 +62,8 @@ struct DevScene {
   const float4 *t_mat;             // (Ve, C1, D1, alpha)
   float *t_J;                      // 2 x 18 x NT : u_i(3), w_i(3) per stretch row, ping-pong
   float *t_E;                      // 6 x NT : E (xx yy zz xy xz yz)
-  float4 *t_cj;                    // 4 x NT : J^T v of a tet, per particle slot (slot-major)
+  const int4 *t_dst;               // per tet: positions of its 4 slots in the particle lists
+  float4 *p_cj;                    // NTADJ : J^T v of the tets, in particle-list order
 
   // joints
   const int4 *j_info;              // (type, A global or -1, B global, has_drive)

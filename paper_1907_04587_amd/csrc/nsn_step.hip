@@ -1091,10 +1091,12 @@ __device__ __forceinline__ void tet_contrib(const Ctx &c, int tl, const float z[
     a3 = a3 + w2 * zu;
     a0 = a0 - (w0 + w1 + w2) * zu;
   }
-  S.t_cj[tg] = f4(a0, 0.f);
-  S.t_cj[(size_t)S.NT + tg] = f4(a1, 0.f);
-  S.t_cj[(size_t)2 * S.NT + tg] = f4(a2, 0.f);
-  S.t_cj[(size_t)3 * S.NT + tg] = f4(a3, 0.f);
+  // straight into the particles' adjacency order (positions fixed at scene creation)
+  const int4 dst = S.t_dst[tg];
+  S.p_cj[dst.x] = f4(a0, 0.f);
+  S.p_cj[dst.y] = f4(a1, 0.f);
+  S.p_cj[dst.z] = f4(a2, 0.f);
+  S.p_cj[dst.w] = f4(a3, 0.f);
 }
 
 __device__ __forceinline__ void gather_rigid(const Ctx &c, int g, float out[6]) {
@@ -1120,28 +1122,21 @@ __device__ __forceinline__ void gather_rigid(const Ctx &c, int g, float out[6]) 
   }
 }
 
-// Sums run in CSR order; four entries are loaded ahead of their use so that the
-// dependent index -> contribution loads overlap (same rounding as one at a time).
+// The tets wrote their contributions in this particle's adjacency order: a contiguous
+// run, summed in that order with eight loads in flight.
 __device__ __forceinline__ V3 gather_particle(const Ctx &c, int p) {
   const DevScene &S = c.S;
   V3 acc = mk(0.f, 0.f, 0.f);
   const int k0 = S.p_tadj_ptr[p], k1 = S.p_tadj_ptr[p + 1];
   int k = k0;
-  for (; k + 4 <= k1; k += 4) {
-    const int e0 = S.p_tadj[k], e1 = S.p_tadj[k + 1], e2 = S.p_tadj[k + 2], e3 = S.p_tadj[k + 3];
-    const float4 c0 = S.t_cj[(size_t)(e0 & 3) * S.NT + (e0 >> 2)];
-    const float4 c1 = S.t_cj[(size_t)(e1 & 3) * S.NT + (e1 >> 2)];
-    const float4 c2 = S.t_cj[(size_t)(e2 & 3) * S.NT + (e2 >> 2)];
-    const float4 c3 = S.t_cj[(size_t)(e3 & 3) * S.NT + (e3 >> 2)];
-    acc = acc + mk(c0);
-    acc = acc + mk(c1);
-    acc = acc + mk(c2);
-    acc = acc + mk(c3);
+  for (; k + 8 <= k1; k += 8) {
+    float4 v[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[m] = S.p_cj[k + m];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) acc = acc + mk(v[m]);
   }
-  for (; k < k1; ++k) {
-    const int ent = S.p_tadj[k];
-    acc = acc + mk(S.t_cj[(size_t)(ent & 3) * S.NT + (ent >> 2)]);
-  }
+  for (; k < k1; ++k) acc = acc + mk(S.p_cj[k]);
   for (int gc = S.p_acon_beg[p]; gc < S.p_acon_end[p]; ++gc) acc = acc + mk(S.c_cj[gc]);
   return acc;
 }
