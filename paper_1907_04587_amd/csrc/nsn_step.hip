@@ -38,6 +38,7 @@ template <int BS>
 struct Red {
   static constexpr int NW = BS / 64;
   double d[2][NW > 0 ? NW : 1];
+  double d3[3][NW > 0 ? NW : 1];
   float f[2][NW > 0 ? NW : 1];
 };
 
@@ -62,6 +63,25 @@ __device__ __forceinline__ double block_sum(double v, Red<BS> &r, int slot) {
 #pragma unroll
   for (int i = 0; i < Red<BS>::NW; ++i) s += r.d[slot][i];
   return s;
+}
+
+// three sums in one barrier
+template <int BS>
+__device__ __forceinline__ void block_sum3(double v[3], Red<BS> &r) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v[k] = wave_sum(v[k]);
+    if (lane == 0) r.d3[k][w] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < Red<BS>::NW; ++i) s += r.d3[k][i];
+    v[k] = s;
+  }
 }
 
 template <int BS>
@@ -1285,13 +1305,20 @@ __device__ void rhs_and_precond(const Ctx &c, const float *Y, int buf, int nel, 
   }
 }
 
-// w = A z = J Y + C z + eps z for every row (Y = H~^-1 J^T z in place); returns the
-// thread's part of <z, w>.  FIRST: also q = w (initialisation of the PCR).
+// w = A z = J Y + C z + eps z for every row (Y = H~^-1 J^T z in place); adds the
+// thread's parts of <z, w>, <w, P w> and <w, P q> to part[0..2].  FIRST: also q = w
+// (initialisation of the PCR).
+__device__ __forceinline__ void mv_dots(const DevScene &S, int row, float z, float w, double part[3]) {
+  const float Pw = S.row_P[row] * w;
+  part[0] += (double)z * (double)w;
+  part[1] += (double)w * (double)Pw;
+  part[2] += (double)Pw * (double)S.row_q[row];
+}
+
 template <int BS, bool FIRST>
-__device__ double matvec_rows(const Ctx &c, const float *Y, int buf, int nel, float eps) {
+__device__ void matvec_rows(const Ctx &c, const float *Y, int buf, int nel, float eps, double part[3]) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
-  double part = 0.0;
   for (int el = threadIdx.x; el < nel; el += BS) {
     if (el < E.n_jnt) {
       float jy[6];
@@ -1303,7 +1330,7 @@ __device__ double matvec_rows(const Ctx &c, const float *Y, int buf, int nel, fl
         const float w = jy[r] + S.row_C[r0 + r] * z + eps * z;
         S.row_w[r0 + r] = w;
         if (FIRST) S.row_q[r0 + r] = w;
-        part += (double)z * (double)w;
+        mv_dots(S, r0 + r, z, w, part);
       }
     } else if (el < E.n_jnt + E.n_tet) {
       float jy[3];
@@ -1319,7 +1346,9 @@ __device__ double matvec_rows(const Ctx &c, const float *Y, int buf, int nel, fl
       const float w0 = jy[0] + cz.x + eps * z.x, w1 = jy[1] + cz.y + eps * z.y, w2 = jy[2] + cz.z + eps * z.z;
       S.row_w[r0] = w0; S.row_w[r0 + 1] = w1; S.row_w[r0 + 2] = w2;
       if (FIRST) { S.row_q[r0] = w0; S.row_q[r0 + 1] = w1; S.row_q[r0 + 2] = w2; }
-      part += (double)z.x * w0 + (double)z.y * w1 + (double)z.z * w2;
+      mv_dots(S, r0, z.x, w0, part);
+      mv_dots(S, r0 + 1, z.y, w1, part);
+      mv_dots(S, r0 + 2, z.z, w2, part);
     } else {
       float jy[3];
       const int cl = el - E.n_jnt - E.n_tet;
@@ -1331,11 +1360,10 @@ __device__ double matvec_rows(const Ctx &c, const float *Y, int buf, int nel, fl
         const float w = jy[r] + S.row_C[r0 + r] * z + eps * z;
         S.row_w[r0 + r] = w;
         if (FIRST) S.row_q[r0 + r] = w;
-        part += (double)z * (double)w;
+        mv_dots(S, r0 + r, z, w, part);
       }
     }
   }
-  return part;
 }
 
 // H~^-1 applied to a rigid 6-vector (in place)
@@ -1376,9 +1404,11 @@ __device__ void gather_hinv(const Ctx &c, float *Y, int tid, int BS) {
   }
 }
 
-// One PCR row: INIT z = P b, x = 0, p = z; else x += alpha p, z -= alpha s (s in b).
+// One PCR row.  INIT: z = P b, x = 0, p = z.  Else the direction update of the
+// previous iteration (upd: p = z + beta p, q = w + beta q) followed by this
+// iteration's x += alpha p, z -= alpha P q.
 template <bool INIT>
-__device__ __forceinline__ float pcr_row(const DevScene &S, int row, float alpha) {
+__device__ __forceinline__ float pcr_row(const DevScene &S, int row, float alpha, float beta, bool upd) {
   if (INIT) {
     const float z = S.row_P[row] * S.row_b[row];
     S.row_x[row] = 0.f;
@@ -1386,8 +1416,16 @@ __device__ __forceinline__ float pcr_row(const DevScene &S, int row, float alpha
     S.row_p[row] = z;
     return z;
   }
-  S.row_x[row] += alpha * S.row_p[row];
-  const float z = S.row_z[row] - alpha * S.row_b[row];
+  float p = S.row_p[row], q = S.row_q[row];
+  const float z0 = S.row_z[row], P = S.row_P[row], x = S.row_x[row];
+  if (upd) {
+    p = z0 + beta * p;
+    q = S.row_w[row] + beta * q;
+    S.row_p[row] = p;
+    S.row_q[row] = q;
+  }
+  S.row_x[row] = x + alpha * p;
+  const float z = z0 - alpha * (P * q);
   S.row_z[row] = z;
   return z;
 }
@@ -1395,27 +1433,27 @@ __device__ __forceinline__ float pcr_row(const DevScene &S, int row, float alpha
 // Element pass of the PCR: the rows of every element are updated (pcr_row) and the
 // element then writes its J^T z contribution for the body pass (gather_hinv).
 template <int BS, bool INIT>
-__device__ void pcr_update_contrib(const Ctx &c, int buf, int nel, float alpha) {
+__device__ void pcr_update_contrib(const Ctx &c, int buf, int nel, float alpha, float beta, bool upd) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   for (int el = threadIdx.x; el < nel; el += BS) {
     if (el < E.n_jnt) {
       const int r0 = row_joint(E, el);
 #pragma unroll
-      for (int r = 0; r < 6; ++r) pcr_row<INIT>(S, r0 + r, alpha);
+      for (int r = 0; r < 6; ++r) pcr_row<INIT>(S, r0 + r, alpha, beta, upd);
       joint_contrib(c, el, S.row_z);
     } else if (el < E.n_jnt + E.n_tet) {
       const int tl = el - E.n_jnt;
       const int r0 = row_tet(E, tl);
       float z[3];
 #pragma unroll
-      for (int r = 0; r < 3; ++r) z[r] = pcr_row<INIT>(S, r0 + r, alpha);
+      for (int r = 0; r < 3; ++r) z[r] = pcr_row<INIT>(S, r0 + r, alpha, beta, upd);
       tet_contrib(c, tl, z, buf);
     } else {
       const int cl = el - E.n_jnt - E.n_tet;
       const int r0 = row_con(E, cl);
 #pragma unroll
-      for (int r = 0; r < 3; ++r) pcr_row<INIT>(S, r0 + r, alpha);
+      for (int r = 0; r < 3; ++r) pcr_row<INIT>(S, r0 + r, alpha, beta, upd);
       const int gc = E.con_off + cl;
       S.c_cj[gc] = f4(contact_dir(c, gc, S.row_z, buf), 0.f);
     }
@@ -1710,61 +1748,47 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     // per iteration: [p = z + beta p, q = w + beta q, s = P q, <q,s>] -> element pass:
     // x += alpha p, z -= alpha s, J^T z per element -> body pass: Y = H~^-1 (sum) ->
     // element pass: w = J Y + C z + eps z, <z,w>
-    pcr_update_contrib<BS, true>(c, buf, nel, 0.f);
+    // Single-reduction form of the same recurrences: the matvec pass also sums
+    // <w, P w> and <w, P q>, so that <q', P q'> of the next direction q' = w + beta q
+    // follows as <w,Pw> + 2 beta <w,Pq> + beta^2 <q,Pq>, and the direction update is
+    // fused into the next element pass (one pass and one barrier fewer per iteration).
+    pcr_update_contrib<BS, true>(c, buf, nel, 0.f, 0.f, false);
     __syncthreads();
     gather_hinv(c, Y, tid, BS);
     __syncthreads();
-    double rho = block_sum<BS>(matvec_rows<BS, true>(c, Y, buf, nel, eps), red, 1);
+    double dots[3] = {0.0, 0.0, 0.0};
+    matvec_rows<BS, true>(c, Y, buf, nel, eps, dots);
+    block_sum3<BS>(dots, red);
+    double rho = dots[0], qs = dots[1];
     // READING: stop once <z, A z> is at rounding level relative to its start
     const double rho_stop = kTauCR * rho;
     float beta = 0.f;
     int done = 0;
     for (int it = 0; it < A.cr_iters; ++it) {
       if (!(rho > rho_stop) || !(rho > 0.0)) break;
-      // direction update of the previous iteration, fused with s = P q; two rows per
-      // pass with all loads issued first
-      double part = 0.0;
-      for (int r = tid; r < nrows; r += 2 * BS) {
-        const int ra = R0 + r, rb = R0 + min(r + BS, nrows - 1);
-        const bool hb = r + BS < nrows;
-        float pa = S.row_p[ra], qa = S.row_q[ra], Pa = S.row_P[ra];
-        float pb = S.row_p[rb], qb = S.row_q[rb], Pb = S.row_P[rb];
-        if (it > 0) {
-          const float za = S.row_z[ra], wa = S.row_w[ra], zb = S.row_z[rb], wb = S.row_w[rb];
-          pa = za + beta * pa;
-          qa = wa + beta * qa;
-          pb = zb + beta * pb;
-          qb = wb + beta * qb;
-          S.row_p[ra] = pa;
-          S.row_q[ra] = qa;
-          if (hb) {
-            S.row_p[rb] = pb;
-            S.row_q[rb] = qb;
-          }
-        }
-        const float sa = Pa * qa, sb = Pb * qb;
-        S.row_b[ra] = sa;  // s = P q (b is no longer needed)
-        part += (double)qa * (double)sa;
-        if (hb) {
-          S.row_b[rb] = sb;
-          part += (double)qb * (double)sb;
-        }
-      }
-      const double qs = block_sum<BS>(part, red, 0);
       if (!(qs > 0.0)) break;
       const float alpha = (float)(rho / qs);
       ++done;
       if (it == A.cr_iters - 1) {  // the last update needs no further product
-        for (int r = tid; r < nrows; r += BS) S.row_x[R0 + r] += alpha * S.row_p[R0 + r];
+        for (int r = tid; r < nrows; r += BS) {
+          const int row = R0 + r;
+          const float p = it > 0 ? S.row_z[row] + beta * S.row_p[row] : S.row_p[row];
+          S.row_x[row] += alpha * p;
+        }
         break;
       }
-      pcr_update_contrib<BS, false>(c, buf, nel, alpha);  // x, z and the J^T z contributions
+      // direction update, x += alpha p, z -= alpha P q, J^T z contributions
+      pcr_update_contrib<BS, false>(c, buf, nel, alpha, beta, it > 0);
       __syncthreads();
       gather_hinv(c, Y, tid, BS);
       __syncthreads();
-      const double rho_new = block_sum<BS>(matvec_rows<BS, false>(c, Y, buf, nel, eps), red, 1);
-      beta = (float)(rho_new / rho);
-      rho = rho_new;
+      dots[0] = dots[1] = dots[2] = 0.0;
+      matvec_rows<BS, false>(c, Y, buf, nel, eps, dots);
+      block_sum3<BS>(dots, red);
+      const double b = dots[0] / rho;
+      qs = dots[1] + 2.0 * b * dots[2] + b * b * qs;
+      beta = (float)b;
+      rho = dots[0];
     }
     cr_total += done;
     __syncthreads();
