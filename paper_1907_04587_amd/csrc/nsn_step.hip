@@ -1119,6 +1119,14 @@ __device__ __forceinline__ void tet_contrib(const Ctx &c, int tl, const float z[
   S.p_cj[dst.w] = f4(a3, 0.f);
 }
 
+__device__ __forceinline__ void acc_wrench(float out[6], V3 d, V3 arm, float sgn) {
+  const V3 a = cross(arm, d);
+  out[0] += sgn * d.x; out[1] += sgn * d.y; out[2] += sgn * d.z;
+  out[3] += sgn * a.x; out[4] += sgn * a.y; out[5] += sgn * a.z;
+}
+
+// Sums in adjacency order; contact entries four at a time with their loads first
+// (a box low in a stack has tens of contacts: this loop is the body pass's longest).
 __device__ __forceinline__ void gather_rigid(const Ctx &c, int g, float out[6]) {
   const DevScene &S = c.S;
   for (int k = 0; k < 6; ++k) out[k] = 0.f;
@@ -1128,17 +1136,37 @@ __device__ __forceinline__ void gather_rigid(const Ctx &c, int g, float out[6]) 
 #pragma unroll
     for (int q = 0; q < 6; ++q) out[q] += o[q];
   }
-  for (int gc = S.r_acon_beg[g]; gc < S.r_acon_end[g]; ++gc) {
-    const V3 d = mk(S.c_cj[gc]);
-    const V3 a = cross(mk(S.c_rA[gc]), d);
-    out[0] += d.x; out[1] += d.y; out[2] += d.z; out[3] += a.x; out[4] += a.y; out[5] += a.z;
+  const int a1 = S.r_acon_end[g];
+  int gc = S.r_acon_beg[g];
+  for (; gc + 4 <= a1; gc += 4) {
+    float4 d[4], r[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      d[m] = S.c_cj[gc + m];
+      r[m] = S.c_rA[gc + m];
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc_wrench(out, mk(d[m]), mk(r[m]), 1.f);
   }
+  for (; gc < a1; ++gc) acc_wrench(out, mk(S.c_cj[gc]), mk(S.c_rA[gc]), 1.f);
   const int b0 = S.r_bcon_beg[g], bn = S.r_bcon_cnt[g];
-  for (int k = 0; k < bn; ++k) {
-    const int gc = S.bcon_list[b0 + k];
-    const V3 d = mk(S.c_cj[gc]);
-    const V3 a = cross(mk(S.c_rB[gc]), d);
-    out[0] -= d.x; out[1] -= d.y; out[2] -= d.z; out[3] -= a.x; out[4] -= a.y; out[5] -= a.z;
+  int k = 0;
+  for (; k + 4 <= bn; k += 4) {
+    int id[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) id[m] = S.bcon_list[b0 + k + m];
+    float4 d[4], r[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      d[m] = S.c_cj[id[m]];
+      r[m] = S.c_rB[id[m]];
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc_wrench(out, mk(d[m]), mk(r[m]), -1.f);
+  }
+  for (; k < bn; ++k) {
+    const int id = S.bcon_list[b0 + k];
+    acc_wrench(out, mk(S.c_cj[id]), mk(S.c_rB[id]), -1.f);
   }
 }
 
