@@ -1022,57 +1022,6 @@ __device__ __forceinline__ V3 contact_dir(const Ctx &c, int gc, const float *src
   return dir;
 }
 
-// J^T src for one rigid body (6) -- pull over joint adjacency and contact ranges
-__device__ void scatter_rigid(const Ctx &c, int g, const float *src, int buf, float out[6]) {
-  const DevScene &S = c.S;
-  const EnvInfo &E = c.E;
-  for (int k = 0; k < 6; ++k) out[k] = 0.f;
-  for (int k = S.r_jadj_ptr[g]; k < S.r_jadj_ptr[g + 1]; ++k) {
-    const int ent = S.r_jadj[k];
-    const int jg = ent >> 1, side = ent & 1;
-    const int r0 = row_joint(E, jg - E.jnt_off);
-    const float *J = S.j_J + (size_t)72 * jg + 6 * side;
-#pragma unroll
-    for (int r = 0; r < 6; ++r) {
-      const float v = src[r0 + r];
-#pragma unroll
-      for (int q = 0; q < 6; ++q) out[q] += v * J[12 * r + q];
-    }
-  }
-  for (int gc = S.r_acon_beg[g]; gc < S.r_acon_end[g]; ++gc) {
-    const V3 d = contact_dir(c, gc, src, buf);
-    const V3 a = cross(mk(S.c_rA[gc]), d);
-    out[0] += d.x; out[1] += d.y; out[2] += d.z; out[3] += a.x; out[4] += a.y; out[5] += a.z;
-  }
-  const int b0 = S.r_bcon_beg[g], bn = S.r_bcon_cnt[g];
-  for (int k = 0; k < bn; ++k) {
-    const int gc = S.bcon_list[b0 + k];
-    const V3 d = contact_dir(c, gc, src, buf);
-    const V3 a = cross(mk(S.c_rB[gc]), d);
-    out[0] -= d.x; out[1] -= d.y; out[2] -= d.z; out[3] -= a.x; out[4] -= a.y; out[5] -= a.z;
-  }
-}
-
-// J^T src for one particle (3) -- pull over tet adjacency and contact range
-__device__ V3 scatter_particle(const Ctx &c, int p, const float *src, int buf) {
-  const DevScene &S = c.S;
-  const EnvInfo &E = c.E;
-  V3 acc = mk(0.f, 0.f, 0.f);
-  for (int k = S.p_tadj_ptr[p]; k < S.p_tadj_ptr[p + 1]; ++k) {
-    const int ent = S.p_tadj[k];
-    const int tg = ent >> 2, slot = ent & 3;
-    const int r0 = row_tet(E, tg - E.tet_off);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const float w0 = tJ(S, buf, 6 * i + 3, tg), w1 = tJ(S, buf, 6 * i + 4, tg), w2 = tJ(S, buf, 6 * i + 5, tg);
-      const float coef = slot == 0 ? -(w0 + w1 + w2) : (slot == 1 ? w0 : (slot == 2 ? w1 : w2));
-      const float sv = src[r0 + i] * coef;
-      acc = acc + sv * mk(tJ(S, buf, 6 * i, tg), tJ(S, buf, 6 * i + 1, tg), tJ(S, buf, 6 * i + 2, tg));
-    }
-  }
-  for (int gc = S.p_acon_beg[p]; gc < S.p_acon_end[p]; ++gc) acc = acc + contact_dir(c, gc, src, buf);
-  return acc;
-}
 
 // ---- per-element row kernels (one unrolled path per element type) ----
 // (J Y) rows of joint jl
@@ -1432,6 +1381,26 @@ __device__ void gather_hinv(const Ctx &c, float *Y, int tid, int BS) {
   }
 }
 
+// J^T src contributions of every element (src: one value per row; buf: which
+// Jacobian of the ping-pong pair); joints only when their bodies need them.
+template <int BS>
+__device__ void contrib_pass(const Ctx &c, const float *src, int buf, int nel, bool joints) {
+  const EnvInfo &E = c.E;
+  for (int el = threadIdx.x; el < nel; el += BS) {
+    if (el < E.n_jnt) {
+      if (joints) joint_contrib(c, el, src);
+    } else if (el < E.n_jnt + E.n_tet) {
+      const int tl = el - E.n_jnt;
+      const int r0 = row_tet(E, tl);
+      const float z[3] = {src[r0], src[r0 + 1], src[r0 + 2]};
+      tet_contrib(c, tl, z, buf);
+    } else {
+      const int gc = E.con_off + el - E.n_jnt - E.n_tet;
+      c.S.c_cj[gc] = f4(contact_dir(c, gc, src, buf), 0.f);
+    }
+  }
+}
+
 // One PCR row.  INIT: z = P b, x = 0, p = z.  Else the direction update of the
 // previous iteration (upd: p = z + beta p, q = w + beta q) followed by this
 // iteration's x += alpha p, z -= alpha P q.
@@ -1666,6 +1635,9 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     // iterates, particle DOFs only)
     float rg = 0.f;
     double m2 = 0.0;
+    contrib_pass<BS>(c, S.row_lam, buf, nel, true);
+    __syncthreads();
+    const bool secant = A.p.geo_stiff && k >= 1;
     for (int b = tid; b < nb; b += BS) {
       if (b < E.n_rig) {
         const int g = E.rig_off + b;
@@ -1676,7 +1648,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
           continue;
         }
         float f6[6];
-        scatter_rigid(c, g, S.row_lam, buf, f6);
+        gather_rigid(c, g, f6);
         const float *u = S.r_u + 6 * g, *ut = S.r_ut + 6 * g;
         const V3 dv = mk(u[0] - ut[0], u[1] - ut[1], u[2] - ut[2]);
         const V3 dw = sym_mul(S.r_Iw + 6 * g, mk(u[3] - ut[3], u[4] - ut[4], u[5] - ut[5]));
@@ -1693,28 +1665,40 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       } else {
         const int p = E.par_off + b - E.n_rig;
         const int d = E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
-        const V3 f = scatter_particle(c, p, S.row_lam, buf);
+        const V3 f = gather_particle(c, p);
         const float m = S.p_m[p];
         const float4 u = S.p_u[p], ut = S.p_ut[p];
         const V3 gv = mk(m * (u.x - ut.x) - h * f.x, m * (u.y - ut.y) - h * f.y, m * (u.z - ut.z) - h * f.z);
-        float4 H = make_float4(m, m, m, 0.f);
-        if (A.p.geo_stiff && k >= 1) {
-          const V3 fh = scatter_particle(c, p, S.row_lam, buf ^ 1);
-          const float4 up = S.p_uprev[p];
-          const float du[3] = {u.x - up.x, u.y - up.y, u.z - up.z};
-          const float df[3] = {f.x - fh.x, f.y - fh.y, f.z - fh.z};
-          float hh[3];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const float cj = h * df[a] * du[a] / (du[a] * du[a] + kTauGS * kTauGS);
-            hh[a] = m - (cj < 0.f ? cj : 0.f);
-          }
-          H = make_float4(hh[0], hh[1], hh[2], 0.f);
+        if (secant) {
+          S.f[d] = f.x; S.f[d + 1] = f.y; S.f[d + 2] = f.z;
+        } else {
+          S.p_H[p] = make_float4(m, m, m, 0.f);
         }
-        S.p_H[p] = H;
         S.g[d] = gv.x; S.g[d + 1] = gv.y; S.g[d + 2] = gv.z;
         rg = fmaxf(rg, fmaxf(fmaxf(fabsf(gv.x / m), fabsf(gv.y / m)), fabsf(gv.z / m)));
         m2 += (double)gv.x * gv.x + (double)gv.y * gv.y + (double)gv.z * gv.z;
+      }
+    }
+    if (secant) {
+      // the same forces with the previous iterate's Jacobians (particles only)
+      __syncthreads();
+      contrib_pass<BS>(c, S.row_lam, buf ^ 1, nel, false);
+      __syncthreads();
+      for (int b = E.n_rig + tid; b < nb; b += BS) {
+        const int p = E.par_off + b - E.n_rig;
+        const int d = E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
+        const V3 fh = gather_particle(c, p);
+        const float m = S.p_m[p];
+        const float4 u = S.p_u[p], up = S.p_uprev[p];
+        const float du[3] = {u.x - up.x, u.y - up.y, u.z - up.z};
+        const float df[3] = {S.f[d] - fh.x, S.f[d + 1] - fh.y, S.f[d + 2] - fh.z};
+        float hh[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float cj = h * df[a] * du[a] / (du[a] * du[a] + kTauGS * kTauGS);
+          hh[a] = m - (cj < 0.f ? cj : 0.f);
+        }
+        S.p_H[p] = make_float4(hh[0], hh[1], hh[2], 0.f);
       }
     }
     float re = 0.f, rc = 0.f;
@@ -1822,12 +1806,14 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     __syncthreads();
 
     // ---- update: du = H~^-1 (h J^T dlambda - g), damped step t (Sec. 6.2, 8.1) ----
+    contrib_pass<BS>(c, S.row_x, buf, nel, true);
+    __syncthreads();
     for (int b = tid; b < nb; b += BS) {
       if (b < E.n_rig) {
         const int g = E.rig_off + b;
         const int d = E.dof_off + 6 * b;
         float v[6];
-        scatter_rigid(c, g, S.row_x, buf, v);
+        gather_rigid(c, g, v);
         for (int q = 0; q < 6; ++q) v[q] = h * v[q] - S.g[d + q];
         hinv_rigid(c, g, v);
         float *u = S.r_u + 6 * g;
@@ -1835,7 +1821,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       } else {
         const int p = E.par_off + b - E.n_rig;
         const int d = E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
-        const V3 a = scatter_particle(c, p, S.row_x, buf);
+        const V3 a = gather_particle(c, p);
         const float4 H = S.p_H[p];
         const float4 u = S.p_u[p];
         S.p_uprev[p] = u;
