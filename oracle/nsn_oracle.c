@@ -26,6 +26,8 @@
 #define KAPPA_W 1e-4     /* READING: FB friction denominator at or below which W is infinite, relative to r*mu*lambda_n */
 #define TAU_CR 1e-12     /* READING: PCR stops once <z, A z> falls below this fraction of its start */
 #define WATCH_BLOWUP 1e6 /* READING: watchdog, merit growth over the step's best that ends the step */
+#define LS_SIGMA 1e-4    /* READING: line search, sufficient decrease merit <= (1 - sigma t) merit_k */
+#define LS_TMIN (1.0 / 64.0) /* READING: line search, smallest step fraction (then accepted) */
 #define CLAMP_FEM 1e-3   /* READING: eigenvalue floor of the material Hessian, relative to 2*C1*Ve */
 #define JACOBI_SWEEPS 6
 #define TAU_NCP 1e-6      /* READING: derivative band around the NCP kink (units of C) */
@@ -469,7 +471,7 @@ typedef struct {
   int have_prev;
   /* scratch sized at create */
   int ndof, maxrows;
-  double *hist;
+  double *hist, *mhist;  /* r_ncp and merit of every accepted iterate of the last step */
   int nhist;
   double *dbg_err, *dbg_cdiag, *dbg_pdiag;
   int dbg_rows;
@@ -572,7 +574,7 @@ void *orc_create(const orc_desc *d, char *err, int errlen) {
   e->ground = d->ground;
   e->ndof = 6 * nr + 3 * np;
   e->maxrows = 6 * nj + 3 * e->maxc + 3 * nt;
-  ALLOC(e->hist, MAX_HIST);
+  ALLOC(e->hist, MAX_HIST); ALLOC(e->mhist, MAX_HIST);
   ALLOC(e->dbg_err, e->maxrows); ALLOC(e->dbg_cdiag, e->maxrows); ALLOC(e->dbg_pdiag, e->maxrows);
   ALLOC(e->lam_last, e->maxrows);
 #undef ALLOC
@@ -587,7 +589,7 @@ void orc_destroy(void *p) {
   free(e->tid); free(e->Dminv); free(e->Ve); free(e->C1); free(e->D1); free(e->alph);
   free(e->jtype); free(e->jbody); free(e->janc); free(e->jaxis); free(e->jref); free(e->jdrive);
   free(e->con); free(e->prev); free(e->lam_joint_prev); free(e->lam_tet_prev);
-  free(e->hist); free(e->dbg_err); free(e->dbg_cdiag); free(e->dbg_pdiag); free(e->lam_last);
+  free(e->hist); free(e->mhist); free(e->dbg_err); free(e->dbg_cdiag); free(e->dbg_pdiag); free(e->lam_last);
   free(e->mlp);
   free(e);
 }
@@ -1480,6 +1482,8 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
   double *best_lam = calloc(nr_alloc, sizeof(double)), *best_u = calloc(nd, sizeof(double));
   double *best_rx = calloc(3 * e->nr + 1, sizeof(double)), *best_rq = calloc(4 * e->nr + 1, sizeof(double));
   double *best_px = calloc(3 * e->np + 1, sizeof(double));
+  /* line search: the accepted iterate k and its direction */
+  double *lam_k = calloc(nr_alloc, sizeof(double)), *rq_k = calloc(4 * e->nr + 1, sizeof(double));
   orc_params pzero = *p;
   pzero.warm = 0;
   /* READING (recovery, not in the paper): a warm-started step whose iterate turns
@@ -1505,6 +1509,12 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
    * returns the best iterate.  Ordinary non-monotone steps are far below that. */
   double best_merit = INFINITY, best_r = 0, best_rc = 0;
   int have_best = 0, restore = 0;
+  /* Sec. 8.1 (optional globalisation, READING of the details): with line search on,
+   * the full Newton step (t = 1) is tried first; while the merit at the trial point
+   * exceeds (1 - LS_SIGMA t) times the accepted iterate's, t is halved down to LS_TMIN
+   * (then accepted).  Trial points are assembled and evaluated like iterates but do
+   * not count as Newton iterations. */
+  double ls_t = 1.0, merit_k = INFINITY;
   for (int k = 0; k <= N; ++k) {
     assemble(&S);
     /* momentum balance g = M~(u - u~) - h J^T lambda (Sec. 6.1) */
@@ -1542,8 +1552,17 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
     r_con = rc;
     merit = sqrt(m2);
     if (k == 0) st->r_ncp_first = r_ncp;
-    if (e->nhist < MAX_HIST) e->hist[e->nhist++] = r_ncp;
     int finite_now = r_ncp == r_ncp && !isinf(r_ncp) && merit == merit && !isinf(merit);
+    if (p->line_search && k > 0 && ls_t > LS_TMIN && (!finite_now || merit > (1.0 - LS_SIGMA * ls_t) * merit_k)) {
+      ls_t *= 0.5;
+      for (int r = 0; r < S.nrows; ++r) S.lam[r] = lam_k[r] + ls_t * x[r];
+      for (int i = 0; i < S.ndof; ++i) S.u[i] = S.uprev[i] + ls_t * du[i];
+      memcpy(e->rq, rq_k, 4 * e->nr * sizeof(double));
+      update_positions(&S);
+      --k;
+      continue;
+    }
+    if (e->nhist < MAX_HIST) { e->mhist[e->nhist] = merit; e->hist[e->nhist++] = r_ncp; }
     if (finite_now && merit < best_merit) {
       best_merit = merit; best_r = r_ncp; best_rc = r_con; have_best = 1;
       memcpy(best_lam, S.lam, S.nrows * sizeof(double));
@@ -1577,8 +1596,15 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
     memcpy(S.uprev, S.u, S.ndof * sizeof(double));
     memcpy(S.Jprev, S.J, S.nrows * sizeof(jrow));
     S.have_prev = 1;
-    for (int r = 0; r < S.nrows; ++r) S.lam[r] += p->damping * x[r];
-    for (int i = 0; i < S.ndof; ++i) S.u[i] += p->damping * du[i];
+    const double tstep = p->line_search ? 1.0 : p->damping;
+    if (p->line_search) {
+      memcpy(lam_k, S.lam, S.nrows * sizeof(double));
+      memcpy(rq_k, e->rq, 4 * e->nr * sizeof(double));
+      merit_k = merit;
+      ls_t = 1.0;
+    }
+    for (int r = 0; r < S.nrows; ++r) S.lam[r] += tstep * x[r];
+    for (int i = 0; i < S.ndof; ++i) S.u[i] += tstep * du[i];
     update_positions(&S);
     ++newton_done;
   }
@@ -1594,6 +1620,7 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
   if (!st->nonfinite || S.p->warm == 0) break;
   }
   free(best_lam); free(best_u); free(best_rx); free(best_rq); free(best_px);
+  free(lam_k); free(rq_k);
   S.p = p;
   st->newton_iters = newton_done;
   st->cr_iters = cr_total;
@@ -1715,6 +1742,13 @@ int orc_get_history(void *p, double *r, int cap) {
   env_t *e = (env_t *)p;
   int n = e->nhist < cap ? e->nhist : cap;
   memcpy(r, e->hist, n * sizeof(double));
+  return n;
+}
+
+int orc_get_merit_history(void *p, double *m, int cap) {
+  env_t *e = (env_t *)p;
+  int n = e->nhist < cap ? e->nhist : cap;
+  memcpy(m, e->mhist, n * sizeof(double));
   return n;
 }
 

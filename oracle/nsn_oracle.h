@@ -59,7 +59,7 @@ typedef struct {
   int32_t fem_mode;   /* 0 projected full 3x3 compliance, 1 diagonal */
   double margin;      /* contact creation distance */
   int32_t warm;       /* 0 zero start, 1 previous-step multipliers, 2 learned */
-  int32_t pad;
+  int32_t line_search; /* 1: back-tracking on the L2 merit from t = 1 instead of the constant damping */
 } orc_params;
 
 typedef struct {
@@ -95,6 +95,8 @@ void orc_get_lambda(void *env, double *lam);   /* full multiplier vector of the 
 void orc_set_mlp(void *env, const double *weights, int64_t n);
 /* per-iteration residual history of the last step (r_ncp per assembly) */
 int orc_get_history(void *env, double *r, int cap);
+/* Merit |[g; err]|_2 of every accepted iterate of the last step (count returned). */
+int orc_get_merit_history(void *env, double *m, int cap);
 /* Previous-step multipliers for a warm start (keys ascending); 0 or -1 (bad input). */
 int orc_set_prev(void *env, int n, const int64_t *keys, const double *lam3, const double *lam_joint);
 /* per-row data of the final assembly of the last step */

@@ -37,7 +37,7 @@ class _Desc(C.Structure):
 class Params(C.Structure):
     _fields_ = [("ncp", C.c_int32), ("rmode", C.c_int32), ("damping", C.c_double),
                 ("eps", C.c_double), ("geo_stiff", C.c_int32), ("fem_mode", C.c_int32),
-                ("margin", C.c_double), ("warm", C.c_int32), ("pad", C.c_int32)]
+                ("margin", C.c_double), ("warm", C.c_int32), ("line_search", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -76,6 +76,7 @@ def lib():
         L.orc_get_lambda.argtypes = [C.c_void_p, D]
         L.orc_set_mlp.argtypes = [C.c_void_p, D, C.c_int64]
         L.orc_get_history.argtypes = [C.c_void_p, D, C.c_int]
+        L.orc_get_merit_history.argtypes = [C.c_void_p, D, C.c_int]
         L.orc_set_prev.argtypes = [C.c_void_p, C.c_int, I64, D, D]
         L.orc_get_rows_debug.argtypes = [C.c_void_p, D, D, D, C.c_int]
         L.orc_ncp_fb.argtypes = [C.c_double] * 3 + [D] * 3
@@ -110,7 +111,7 @@ def _i32(a):
 def make_params(sp=None, **kw):
     """Oracle parameter struct from a scene_inputs.SolverParams (or keywords)."""
     vals = dict(ncp=0, rmode=2, damping=0.75, eps=1e-6, geo_stiff=1, fem_mode=0,
-                margin=5e-3, warm=0)
+                margin=5e-3, warm=0, line_search=0)
     if sp is not None:
         for k in vals:
             vals[k] = getattr(sp, k)
@@ -216,6 +217,11 @@ class OracleEnv:
         st = lib().orc_set_prev(self.h, k.size, k.ctypes.data_as(I64), _d(l3), _d(lj) if lj.size else None)
         if st != 0:
             raise ValueError("orc_set_prev: bad keys or count")
+
+    def merit_history(self):
+        out = np.zeros(256)
+        n = lib().orc_get_merit_history(self.h, _d(out), 256)
+        return out[:n]
 
     def rows_debug(self):
         n = lib().orc_num_rows(self.h)

@@ -44,6 +44,7 @@ class SolverParams:
     fem_mode: int = FEM_FULL_PROJECTED
     margin: float = 5e-3           # contact creation distance
     warm: int = WARM_ZERO
+    line_search: int = 0           # 1: back-tracking on the L2 merit (frictionless scenes)
 
 
 @dataclasses.dataclass

@@ -657,3 +657,29 @@ def test_warm_start_nonfinite_falls_back_to_plain_start():
         assert np.array_equal(v, w.get_state()[k]), k
     # the failed attempt stopped at its first residual (no update), so it adds no work
     assert st["newton_iters"] == stz["newton_iters"] and st["cr_iters"] == stz["cr_iters"]
+
+
+# ------------------------------------------------------------- line search (Sec. 8.1)
+@pytest.mark.parametrize("scene", ["lcp", "stack"])
+def test_line_search_sufficient_decrease_and_same_solution(scene):
+    """Sec. 8.1's back-tracking line search on the L2 merit (frictionless problems):
+    every accepted iterate decreases the merit by the sufficient-decrease factor (or
+    the step fraction reached its floor 1/64, which decreases it at least by
+    1 - 1e-4/64), and the converged state equals the damped iteration's."""
+    d = si.particles_vs_planes_lcp(seed=2) if scene == "lcp" else si.cube_stack(seed=3, n=4, mu=0.0)
+    h = 1 / 60
+    a, b = O.OracleEnv(d), O.OracleEnv(d)
+    for s in range(3):
+        st = a.step(h, 100, 80, 1e-10, O.make_params(line_search=1, damping=1.0))
+        m = a.merit_history()
+        assert st["r_ncp"] <= 1e-10 and len(m) >= 2
+        assert (m[1:] <= (1 - 1e-4 / 64) * m[:-1]).all(), m
+        stb = b.step(h, 200, 80, 1e-10, O.make_params(line_search=0, damping=0.75))
+        assert stb["r_ncp"] <= 1e-10
+        assert st["newton_iters"] < stb["newton_iters"]
+        A, B = a.get_state(), b.get_state()
+        for k in ["rigid_v", "particle_v"]:
+            if A[k].size:
+                np.testing.assert_allclose(A[k], B[k], atol=1e-7, err_msg=k)
+        b.set_state(A)
+        b.time = a.time
