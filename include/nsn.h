@@ -121,6 +121,9 @@ typedef struct {
   int32_t fem_mode;  /* NSN_FEM_* */
   float margin;      /* contact creation distance (m) */
   int32_t warm;      /* NSN_WARM_* */
+  int32_t line_search; /* 1: back-tracking line search on the L2 merit from the full
+                          step (Sec. 8.1; for frictionless scenes) instead of the
+                          constant damping; 0 (default): constant damping */
 } nsn_solver_params;
 
 typedef struct {

@@ -104,6 +104,9 @@ struct DevScene {
   // the step's lowest-merit iterate (watchdog)
   float *row_lam_best, *r_u_best;
   float4 *r_x_best, *r_q_best, *p_u_best, *p_x_best;
+  // line search: the accepted iterate k (particle velocities in p_uprev) and its direction
+  float *row_lam_k, *r_u_k, *du;
+  float4 *r_q_k;
 
   // body space (NDOF)
   float *y, *g, *f;

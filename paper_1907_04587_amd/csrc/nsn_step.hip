@@ -26,6 +26,8 @@ constexpr float kTauGS = 1e-6f;     // secant smoothing velocity (m/s)
 constexpr float kKappaW = 1e-4f;    // FB friction denominator at or below which W is infinite (relative)
 constexpr double kTauCR = 1e-12;    // PCR stops once <z, A z> falls below this fraction of its start
 constexpr double kWatchBlowup = 1e6; // watchdog: merit growth over the step's best that ends the step
+constexpr double kLsSigma = 1e-4;    // line search: sufficient decrease merit <= (1 - sigma t) merit_k
+constexpr float kLsTmin = 1.f / 64.f; // line search: smallest step fraction (then accepted)
 constexpr float kClampFem = 1e-3f;  // eigenvalue floor of the material Hessian (relative to 2 C1 Ve)
 constexpr int kJacobiSweeps = 6;
 constexpr float kTauNcp = 1e-6f;    // derivative band around the NCP kink (units of C)
@@ -1589,6 +1591,12 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
   double best_merit = __builtin_huge_val();
   float best_r = 0.f, best_rc = 0.f;
   bool have_best = false, restore = false;
+  // Sec. 8.1 (optional globalisation, READING of the details): with line search on,
+  // the full step is tried first; while the merit at the trial point exceeds
+  // (1 - kLsSigma t) times the accepted iterate's, t is halved down to kLsTmin (then
+  // accepted).  Trial points are evaluated like iterates but are not Newton iterations.
+  float ls_t = 1.f;
+  double merit_k = __builtin_huge_val();
   for (int r = tid; r < nrows; r += BS) {
     const int row = R0 + r;
     if (!warm) {
@@ -1718,6 +1726,30 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     merit = sqrt(msum);
     if (k == 0) r_first = rmax;
     const bool finite_now = rmax == rmax && !isinf(rmax) && msum == msum && !isinf(msum);
+    if (A.p.line_search && k > 0 && ls_t > kLsTmin &&
+        (!finite_now || merit > (1.0 - kLsSigma * (double)ls_t) * merit_k)) {
+      ls_t *= 0.5f;
+      for (int r = tid; r < nrows; r += BS) S.row_lam[R0 + r] = S.row_lam_k[R0 + r] + ls_t * S.row_x[R0 + r];
+      for (int b = tid; b < nb; b += BS) {
+        if (b < E.n_rig) {
+          const int g = E.rig_off + b;
+          if (S.r_inertia[g].w == 0.f) continue;
+          float *u = S.r_u + 6 * g;
+          const float *uk = S.r_u_k + 6 * g, *dv = S.du + E.dof_off + 6 * b;
+          for (int q = 0; q < 6; ++q) u[q] = uk[q] + ls_t * dv[q];
+          S.r_q[g] = S.r_q_k[g];  // positions from G(q^k)
+        } else {
+          const int p = E.par_off + b - E.n_rig;
+          const float *dv = S.du + E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
+          const float4 uk = S.p_uprev[p];
+          S.p_u[p] = make_float4(uk.x + ls_t * dv[0], uk.y + ls_t * dv[1], uk.z + ls_t * dv[2], 0.f);
+        }
+        update_positions_body(c, b);
+      }
+      __syncthreads();
+      --k;
+      continue;
+    }
     if (finite_now && merit < best_merit) {
       best_merit = merit;
       best_r = rmax;
@@ -1806,6 +1838,11 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     __syncthreads();
 
     // ---- update: du = H~^-1 (h J^T dlambda - g), damped step t (Sec. 6.2, 8.1) ----
+    const float tstep = A.p.line_search ? 1.f : damp;
+    if (A.p.line_search) {
+      merit_k = merit;
+      ls_t = 1.f;
+    }
     contrib_pass<BS>(c, S.row_x, buf, nel, true);
     __syncthreads();
     for (int b = tid; b < nb; b += BS) {
@@ -1817,20 +1854,34 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
         for (int q = 0; q < 6; ++q) v[q] = h * v[q] - S.g[d + q];
         hinv_rigid(c, g, v);
         float *u = S.r_u + 6 * g;
-        for (int q = 0; q < 6; ++q) u[q] += damp * v[q];
+        if (A.p.line_search) {
+          for (int q = 0; q < 6; ++q) {
+            S.r_u_k[6 * g + q] = u[q];
+            S.du[d + q] = v[q];
+          }
+          S.r_q_k[g] = S.r_q[g];
+        }
+        for (int q = 0; q < 6; ++q) u[q] += tstep * v[q];
       } else {
         const int p = E.par_off + b - E.n_rig;
         const int d = E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
         const V3 a = gather_particle(c, p);
         const float4 H = S.p_H[p];
         const float4 u = S.p_u[p];
+        const float dv[3] = {(h * a.x - S.g[d]) / H.x, (h * a.y - S.g[d + 1]) / H.y, (h * a.z - S.g[d + 2]) / H.z};
+        if (A.p.line_search) {
+          S.du[d] = dv[0]; S.du[d + 1] = dv[1]; S.du[d + 2] = dv[2];
+        }
         S.p_uprev[p] = u;
-        S.p_u[p] = make_float4(u.x + damp * (h * a.x - S.g[d]) / H.x, u.y + damp * (h * a.y - S.g[d + 1]) / H.y,
-                               u.z + damp * (h * a.z - S.g[d + 2]) / H.z, 0.f);
+        S.p_u[p] = make_float4(u.x + tstep * dv[0], u.y + tstep * dv[1], u.z + tstep * dv[2], 0.f);
       }
     }
     __syncthreads();
-    for (int r = tid; r < nrows; r += BS) S.row_lam[R0 + r] += damp * S.row_x[R0 + r];
+    for (int r = tid; r < nrows; r += BS) {
+      const int row = R0 + r;
+      if (A.p.line_search) S.row_lam_k[row] = S.row_lam[row];
+      S.row_lam[row] += tstep * S.row_x[row];
+    }
     for (int b = tid; b < nb; b += BS) update_positions_body(c, b);
     __syncthreads();
     ++newton_done;

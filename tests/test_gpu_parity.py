@@ -115,6 +115,18 @@ def test_per_newton_iteration_warm_start(newton):
     _print(f"warm{newton}", hist)
 
 
+@pytest.mark.parametrize("newton", [2, 4, 8])
+def test_line_search_frictionless(newton):
+    """Sec. 8.1's back-tracking line search (full step first, halved on insufficient
+    merit decrease) on frictionless scenes, against the oracle."""
+    envs = [si.particles_vs_planes_lcp(seed=3), si.cube_stack(seed=4, n=4, mu=0.0), _driven_chain(),
+            si.tet_block_with_boxes(seed=1, cells=3, n_boxes=2, mu=0.0)]
+    p = si.SolverParams(line_search=1, damping=1.0)
+    sc = _scene(envs, p)
+    hist = lockstep(sc, envs, p, H, newton, 40, steps=2, sens_factor=10.0)
+    _print(f"linesearch{newton}", hist)
+
+
 def test_fixed_budget_lockstep_smooth_scenes():
     envs = [si.free_particle(), si.particle_on_plane(v=(0.5, 0.2, 0.0)), si.spinning_box(),
             _driven_chain(), si.pendulum_drive(), si.box_on_incline(0.3, 0.6), si.cube_stack(seed=1, n=2)]
