@@ -77,6 +77,10 @@ typedef int32_t nsn_status;
 #define NSN_WARM_PREV 1    /* previous-step multipliers (contacts matched by key) */
 #define NSN_WARM_LEARNED 2 /* contact multipliers predicted by the warm-start MLP */
 
+/* linear solver of the Newton system (Sec. 8.2) */
+#define NSN_LINEAR_PCR 0 /* preconditioned conjugate residual: the method */
+#define NSN_LINEAR_PCG 1 /* preconditioned conjugate gradient: the comparison solver */
+
 /* One environment.  Pointers are host float32/int32 arrays, sizes as noted.
  * A rigid body with mass 0 is a static obstacle.  Particles take their mass from
  * the tets that use them (rho V_e / 4 each) plus particle_mass.  Tet rest shapes
@@ -124,6 +128,7 @@ typedef struct {
   int32_t line_search; /* 1: back-tracking line search on the L2 merit from the full
                           step (Sec. 8.1; for frictionless scenes) instead of the
                           constant damping; 0 (default): constant damping */
+  int32_t linear;    /* NSN_LINEAR_* (default PCR) */
 } nsn_solver_params;
 
 typedef struct {

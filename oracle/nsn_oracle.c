@@ -409,6 +409,41 @@ static int pcr_solve(int n, orc_apply_fn apply, void *ctx, const double *b, cons
   return done;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Preconditioned conjugate gradient (the comparison solver of Sec. 8.2 and    */
+/* the solver study): Jacobi preconditioner P, x0 = 0, at most `iters`        */
+/* iterations; READING: stops when <r, P r> <= TAU_CR <r0, P r0> or            */
+/* <p, A p> <= 0.  hist[k] = sqrt(r^T P r) after iteration k.                  */
+/* ------------------------------------------------------------------------- */
+static int pcg_solve(int n, orc_apply_fn apply, void *ctx, const double *b, const double *P,
+                     int iters, double *x, double *hist) {
+  double *r = calloc(n, sizeof(double)), *z = calloc(n, sizeof(double));
+  double *p = calloc(n, sizeof(double)), *w = calloc(n, sizeof(double));
+  int done = 0;
+  double rz = 0.0;
+  for (int i = 0; i < n; ++i) { x[i] = 0.0; r[i] = b[i]; z[i] = P[i] * r[i]; p[i] = z[i]; rz += r[i] * z[i]; }
+  const double rz_stop = TAU_CR * rz;
+  for (int it = 0; it < iters; ++it) {
+    if (!(rz > rz_stop) || !(rz > 0.0)) break;
+    apply(ctx, p, w);
+    double pw = 0.0;
+    for (int i = 0; i < n; ++i) pw += p[i] * w[i];
+    if (!(pw > 0.0)) break;
+    double alpha = rz / pw;
+    for (int i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * w[i]; }
+    ++done;
+    double rz_new = 0.0;
+    for (int i = 0; i < n; ++i) { z[i] = P[i] * r[i]; rz_new += r[i] * z[i]; }
+    if (hist) hist[it] = sqrt(rz_new);
+    if (it == iters - 1) break;
+    double beta = rz_new / rz;
+    rz = rz_new;
+    for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+  }
+  free(r); free(z); free(p); free(w);
+  return done;
+}
+
 typedef struct { int n; const double *A; } dense_ctx;
 static void dense_apply(void *c, const double *in, double *out) {
   dense_ctx *d = (dense_ctx *)c;
@@ -422,6 +457,12 @@ int orc_pcr_dense(int n, const double *A, const double *b, const double *P, int 
                   double *x, double *hist) {
   dense_ctx c = {n, A};
   return pcr_solve(n, dense_apply, &c, b, P, iters, x, hist);
+}
+
+int orc_pcg_dense(int n, const double *A, const double *b, const double *P, int iters,
+                  double *x, double *hist) {
+  dense_ctx c = {n, A};
+  return pcg_solve(n, dense_apply, &c, b, P, iters, x, hist);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -1586,7 +1627,8 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
       P[r] = 1.0 / (row_hdiag(&S, &S.J[r]) + S.Cblk[9 * b0 + 3 * ri + ri] + p->eps);
     }
     schur_ctx sc = {&S, tmp, tmp2};
-    int done = pcr_solve(S.nrows, schur_apply, &sc, b, P, M, x, NULL);
+    int done = p->linear == 1 ? pcg_solve(S.nrows, schur_apply, &sc, b, P, M, x, NULL)
+                              : pcr_solve(S.nrows, schur_apply, &sc, b, P, M, x, NULL);
     cr_total += done;
     /* du = H~^-1 (h J^T dlambda - g); damped update (Sec. 6.2, 8.1) */
     memset(f, 0, nd * sizeof(double));

@@ -60,6 +60,8 @@ typedef struct {
   double margin;      /* contact creation distance */
   int32_t warm;       /* 0 zero start, 1 previous-step multipliers, 2 learned */
   int32_t line_search; /* 1: back-tracking on the L2 merit from t = 1 instead of the constant damping */
+  int32_t linear;      /* 0 preconditioned conjugate residual (the method), 1 preconditioned conjugate gradient */
+  int32_t pad;
 } orc_params;
 
 typedef struct {
@@ -112,6 +114,7 @@ void orc_lame(double E, double nu, double *C1, double *D1, double *alpha);
 void orc_neohookean(const double *s, double C1, double D1, double alpha, double *psi,
                     double *grad, double *hess);
 void orc_compliance3(const double *H, double floor_, int mode, double *E);
+int orc_pcg_dense(int n, const double *A, const double *b, const double *P, int iters, double *x, double *hist);
 int orc_pcr_dense(int n, const double *A, const double *b, const double *P, int iters,
                   double *x, double *hist);
 void orc_quat_kinematic(const double *q, double *Q /* 4x3 */);

@@ -37,7 +37,8 @@ class _Desc(C.Structure):
 class Params(C.Structure):
     _fields_ = [("ncp", C.c_int32), ("rmode", C.c_int32), ("damping", C.c_double),
                 ("eps", C.c_double), ("geo_stiff", C.c_int32), ("fem_mode", C.c_int32),
-                ("margin", C.c_double), ("warm", C.c_int32), ("line_search", C.c_int32)]
+                ("margin", C.c_double), ("warm", C.c_int32), ("line_search", C.c_int32),
+                ("linear", C.c_int32), ("pad", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -89,6 +90,7 @@ def lib():
         L.orc_neohookean.argtypes = [D, C.c_double, C.c_double, C.c_double, D, D, D]
         L.orc_compliance3.argtypes = [D, C.c_double, C.c_int, D]
         L.orc_pcr_dense.argtypes = [C.c_int, D, D, D, C.c_int, D, D]
+        L.orc_pcg_dense.argtypes = [C.c_int, D, D, D, C.c_int, D, D]
         L.orc_quat_kinematic.argtypes = [D, D]
         L.orc_tangent_basis.argtypes = [D, D, D]
         L.orc_mlp_num_params.restype = C.c_int64
@@ -111,7 +113,7 @@ def _i32(a):
 def make_params(sp=None, **kw):
     """Oracle parameter struct from a scene_inputs.SolverParams (or keywords)."""
     vals = dict(ncp=0, rmode=2, damping=0.75, eps=1e-6, geo_stiff=1, fem_mode=0,
-                margin=5e-3, warm=0, line_search=0)
+                margin=5e-3, warm=0, line_search=0, linear=0)
     if sp is not None:
         for k in vals:
             vals[k] = getattr(sp, k)
@@ -298,6 +300,16 @@ def compliance3(H, floor_, mode=0):
     E = np.zeros(9)
     lib().orc_compliance3(_d(H), floor_, int(mode), _d(E))
     return E.reshape(3, 3)
+
+
+def pcg_dense(A, b, P, iters):
+    A = np.ascontiguousarray(A, np.float64)
+    n = A.shape[0]
+    b = np.ascontiguousarray(b, np.float64)
+    P = np.ascontiguousarray(P, np.float64)
+    x, hist = np.zeros(n), np.zeros(max(iters, 1))
+    done = lib().orc_pcg_dense(n, _d(A), _d(b), _d(P), int(iters), _d(x), _d(hist))
+    return x, hist[:done]
 
 
 def pcr_dense(A, b, P, iters):

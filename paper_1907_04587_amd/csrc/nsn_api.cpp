@@ -248,7 +248,7 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
   if (!workspace || ((uintptr_t)workspace & 255)) return fail(NSN_EINVAL, "workspace must be a 256-byte aligned device pointer");
   if (p->ncp < 0 || p->ncp > 1 || p->rmode < 0 || p->rmode > 2 || p->warm < 0 || p->warm > 2 ||
       p->fem_mode < 0 || p->fem_mode > 1 || !(p->damping > 0.f) || !(p->eps >= 0.f) || !(p->margin >= 0.f) ||
-      p->line_search < 0 || p->line_search > 1)
+      p->line_search < 0 || p->line_search > 1 || p->linear < 0 || p->linear > 1)
     return fail(NSN_EINVAL, "bad solver parameters");
   size_t need = 0;
   nsn_status st = nsn_query_workspace(envs, n_envs, &need);
@@ -478,7 +478,7 @@ nsn_status nsn_set_params(nsn_scene s, const nsn_solver_params *p) {
   if (!s || !p) return fail(NSN_EINVAL, "nsn_set_params: bad arguments");
   if (p->ncp < 0 || p->ncp > 1 || p->rmode < 0 || p->rmode > 2 || p->warm < 0 || p->warm > 2 ||
       p->fem_mode < 0 || p->fem_mode > 1 || !(p->damping > 0.f) || !(p->eps >= 0.f) || !(p->margin >= 0.f) ||
-      p->line_search < 0 || p->line_search > 1)
+      p->line_search < 0 || p->line_search > 1 || p->linear < 0 || p->linear > 1)
     return fail(NSN_EINVAL, "bad solver parameters");
   if (p->warm == NSN_WARM_LEARNED && !s->S.have_mlp) return fail(NSN_ESTATE, "learned warm start needs nsn_set_warm_start_model first");
   s->p = *p;

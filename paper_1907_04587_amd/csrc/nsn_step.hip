@@ -1792,47 +1792,95 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     // per iteration: [p = z + beta p, q = w + beta q, s = P q, <q,s>] -> element pass:
     // x += alpha p, z -= alpha s, J^T z per element -> body pass: Y = H~^-1 (sum) ->
     // element pass: w = J Y + C z + eps z, <z,w>
-    // Single-reduction form of the same recurrences: the matvec pass also sums
-    // <w, P w> and <w, P q>, so that <q', P q'> of the next direction q' = w + beta q
-    // follows as <w,Pw> + 2 beta <w,Pq> + beta^2 <q,Pq>, and the direction update is
-    // fused into the next element pass (one pass and one barrier fewer per iteration).
-    pcr_update_contrib<BS, true>(c, buf, nel, 0.f, 0.f, false);
-    __syncthreads();
-    gather_hinv(c, Y, tid, BS);
-    __syncthreads();
-    double dots[3] = {0.0, 0.0, 0.0};
-    matvec_rows<BS, true>(c, Y, buf, nel, eps, dots);
-    block_sum3<BS>(dots, red);
-    double rho = dots[0], qs = dots[1];
-    // READING: stop once <z, A z> is at rounding level relative to its start
-    const double rho_stop = kTauCR * rho;
-    float beta = 0.f;
     int done = 0;
-    for (int it = 0; it < A.cr_iters; ++it) {
-      if (!(rho > rho_stop) || !(rho > 0.0)) break;
-      if (!(qs > 0.0)) break;
-      const float alpha = (float)(rho / qs);
-      ++done;
-      if (it == A.cr_iters - 1) {  // the last update needs no further product
+    if (A.p.linear == NSN_LINEAR_PCG) {
+      // ---- preconditioned conjugate gradient (the comparison solver), x0 = 0 ----
+      // storage: direction d in row_z (so that the contribution and matvec passes
+      // apply A to it), residual r in row_p, A d in row_w
+      double rz = 0.0;
+      for (int r = tid; r < nrows; r += BS) {
+        const int row = R0 + r;
+        const float rv = S.row_b[row], zv = S.row_P[row] * rv;
+        S.row_x[row] = 0.f;
+        S.row_p[row] = rv;
+        S.row_z[row] = zv;
+        rz += (double)rv * (double)zv;
+      }
+      rz = block_sum<BS>(rz, red, 0);
+      const double rz_stop = kTauCR * rz;
+      for (int it = 0; it < A.cr_iters; ++it) {
+        if (!(rz > rz_stop) || !(rz > 0.0)) break;
+        contrib_pass<BS>(c, S.row_z, buf, nel, true);
+        __syncthreads();
+        gather_hinv(c, Y, tid, BS);
+        __syncthreads();
+        double dots[3] = {0.0, 0.0, 0.0};
+        matvec_rows<BS, false>(c, Y, buf, nel, eps, dots);
+        block_sum3<BS>(dots, red);
+        const double pw = dots[0];
+        if (!(pw > 0.0)) break;
+        const float alpha = (float)(rz / pw);
+        ++done;
+        double part = 0.0;
         for (int r = tid; r < nrows; r += BS) {
           const int row = R0 + r;
-          const float p = it > 0 ? S.row_z[row] + beta * S.row_p[row] : S.row_p[row];
-          S.row_x[row] += alpha * p;
+          S.row_x[row] += alpha * S.row_z[row];
+          const float rv = S.row_p[row] - alpha * S.row_w[row];
+          S.row_p[row] = rv;
+          part += (double)rv * (double)(S.row_P[row] * rv);
         }
-        break;
+        const double rz_new = block_sum<BS>(part, red, 1);
+        if (it == A.cr_iters - 1) break;
+        const float beta = (float)(rz_new / rz);
+        rz = rz_new;
+        for (int r = tid; r < nrows; r += BS) {
+          const int row = R0 + r;
+          S.row_z[row] = S.row_P[row] * S.row_p[row] + beta * S.row_z[row];
+        }
+        __syncthreads();
       }
-      // direction update, x += alpha p, z -= alpha P q, J^T z contributions
-      pcr_update_contrib<BS, false>(c, buf, nel, alpha, beta, it > 0);
+    } else {
+      // Single-reduction form of the same recurrences: the matvec pass also sums
+      // <w, P w> and <w, P q>, so that <q', P q'> of the next direction q' = w + beta q
+      // follows as <w,Pw> + 2 beta <w,Pq> + beta^2 <q,Pq>, and the direction update is
+      // fused into the next element pass (one pass and one barrier fewer per iteration).
+      pcr_update_contrib<BS, true>(c, buf, nel, 0.f, 0.f, false);
       __syncthreads();
       gather_hinv(c, Y, tid, BS);
       __syncthreads();
-      dots[0] = dots[1] = dots[2] = 0.0;
-      matvec_rows<BS, false>(c, Y, buf, nel, eps, dots);
+      double dots[3] = {0.0, 0.0, 0.0};
+      matvec_rows<BS, true>(c, Y, buf, nel, eps, dots);
       block_sum3<BS>(dots, red);
-      const double b = dots[0] / rho;
-      qs = dots[1] + 2.0 * b * dots[2] + b * b * qs;
-      beta = (float)b;
-      rho = dots[0];
+      double rho = dots[0], qs = dots[1];
+      // READING: stop once <z, A z> is at rounding level relative to its start
+      const double rho_stop = kTauCR * rho;
+      float beta = 0.f;
+      for (int it = 0; it < A.cr_iters; ++it) {
+        if (!(rho > rho_stop) || !(rho > 0.0)) break;
+        if (!(qs > 0.0)) break;
+        const float alpha = (float)(rho / qs);
+        ++done;
+        if (it == A.cr_iters - 1) {  // the last update needs no further product
+          for (int r = tid; r < nrows; r += BS) {
+            const int row = R0 + r;
+            const float p = it > 0 ? S.row_z[row] + beta * S.row_p[row] : S.row_p[row];
+            S.row_x[row] += alpha * p;
+          }
+          break;
+        }
+        // direction update, x += alpha p, z -= alpha P q, J^T z contributions
+        pcr_update_contrib<BS, false>(c, buf, nel, alpha, beta, it > 0);
+        __syncthreads();
+        gather_hinv(c, Y, tid, BS);
+        __syncthreads();
+        dots[0] = dots[1] = dots[2] = 0.0;
+        matvec_rows<BS, false>(c, Y, buf, nel, eps, dots);
+        block_sum3<BS>(dots, red);
+        const double b = dots[0] / rho;
+        qs = dots[1] + 2.0 * b * dots[2] + b * b * qs;
+        beta = (float)b;
+        rho = dots[0];
+      }
     }
     cr_total += done;
     __syncthreads();

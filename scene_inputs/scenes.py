@@ -45,6 +45,7 @@ class SolverParams:
     margin: float = 5e-3           # contact creation distance
     warm: int = WARM_ZERO
     line_search: int = 0           # 1: back-tracking on the L2 merit (frictionless scenes)
+    linear: int = 0                # 0 PCR (the method), 1 PCG (comparison solver)
 
 
 @dataclasses.dataclass
@@ -323,6 +324,20 @@ def cube_stack(seed=0, n=8, side=0.1, mass=1.0, mu=0.5, jitter=1e-3):
         j = rng.uniform(-jitter, jitter, size=2)
         bodies.append(_box(mass, (half, half, half), (j[0], j[1], half + side * k)))
     d = _empty(mu=mu, max_contacts=128, name=f"cube_stack(seed={seed})")
+    _set_rigid(d, bodies)
+    return d.finalize()
+
+
+def heavy_stack(seed=0, n=5, side=0.1, base_mass=8.0, ratio=8.0, mu=0.5, jitter=1e-3):
+    """Stack of `n` cubes whose masses grow geometrically upwards, m_k = base * ratio^k
+    (the heavy stack of the paper's rigid tests: 8, 64, ..., 32768 kg, 4096:1)."""
+    rng = np.random.default_rng(seed)
+    half = 0.5 * side
+    bodies = []
+    for k in range(n):
+        j = rng.uniform(-jitter, jitter, size=2)
+        bodies.append(_box(base_mass * ratio ** k, (half, half, half), (j[0], j[1], half + side * k)))
+    d = _empty(mu=mu, max_contacts=128, name=f"heavy_stack(seed={seed},n={n})")
     _set_rigid(d, bodies)
     return d.finalize()
 

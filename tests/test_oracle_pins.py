@@ -683,3 +683,54 @@ def test_line_search_sufficient_decrease_and_same_solution(scene):
                 np.testing.assert_allclose(A[k], B[k], atol=1e-7, err_msg=k)
         b.set_state(A)
         b.time = a.time
+
+
+# ------------------------------------------------------------ PCG (solver study, Sec. 8.2)
+def test_pcg_matches_direct_solve_and_minimises_energy_over_krylov_space():
+    """Preconditioned CG: after n iterations it solves the system; its k-th iterate
+    minimises the A-norm of the error over span{(PA)^j P b} (what distinguishes it
+    from CR, which minimises the P-norm of the residual)."""
+    rng = np.random.default_rng(9)
+    for n in [3, 8, 20]:
+        B = rng.normal(size=(n, n))
+        A = B @ B.T + n * np.eye(n)
+        b = rng.normal(size=n)
+        P = 1 / np.diag(A)
+        x, _ = O.pcg_dense(A, b, P, n)
+        assert np.linalg.norm(A @ x - b) <= 1e-5 * np.linalg.norm(b)
+    n = 12
+    B = rng.normal(size=(n, n))
+    A = B @ B.T + 0.5 * np.eye(n)
+    b = rng.normal(size=n)
+    P = 1 / np.diag(A)
+    xs = np.linalg.solve(A, b)
+    Lc = np.linalg.cholesky(A)
+    for k in range(1, 7):
+        x, _ = O.pcg_dense(A, b, P, k)
+        K = [P * b]
+        for _ in range(k - 1):
+            K.append(P * (A @ K[-1]))
+        K = np.stack(K, axis=1)
+        # min_c |L^T (K c - xs)|  (A-norm of the error)
+        c, *_ = np.linalg.lstsq(Lc.T @ K, Lc.T @ xs, rcond=None)
+        np.testing.assert_allclose(x, K @ c, rtol=1e-6, atol=1e-8)
+
+
+def test_pcg_residual_not_monotone_where_pcr_is():
+    """The observation behind choosing CR (Sec. 8.2): on an ill-conditioned SPD system
+    the preconditioned residual of CG rises between iterations, CR's never does."""
+    rng = np.random.default_rng(11)
+    found = False
+    for trial in range(20):
+        n = 30
+        Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+        A = Q @ np.diag(np.logspace(0, 5, n)) @ Q.T
+        b = rng.normal(size=n)
+        P = 1 / np.diag(A)
+        _, hg = O.pcg_dense(A, b, P, 25)
+        _, hr = O.pcr_dense(A, b, P, 25)
+        assert (np.diff(hr) <= 1e-12 * hr[0]).all()
+        if (np.diff(hg) > 1e-6 * hg[0]).any():
+            found = True
+            break
+    assert found
