@@ -1377,6 +1377,54 @@ static void update_positions(step_t *S) {
     for (int k = 0; k < 3; ++k) e->px[3 * p + k] = S->px0[3 * p + k] + h * S->u[particle_dof(e, p) + k];
 }
 
+/* ------------------------------------------------------------------------- */
+/* Islands (Sec. 11 suggests them): dynamic bodies connected by joints, tets  */
+/* or contacts; static bodies and the world connect nothing.  Union by the    */
+/* smaller index, so every island is named by its lowest body (deterministic). */
+/* Rows take the island of their element's dynamic body; rows touching no     */
+/* dynamic body form one extra group.                                          */
+/* ------------------------------------------------------------------------- */
+static int uf_find(int *par, int a) {
+  while (par[a] != a) { par[a] = par[par[a]]; a = par[a]; }
+  return a;
+}
+static void uf_union(int *par, int a, int b) {
+  a = uf_find(par, a); b = uf_find(par, b);
+  if (a < b) par[b] = a; else if (b < a) par[a] = b;
+}
+static int body_dynamic(const env_t *e, int b) { return b >= 0 && (b >= e->nr || !is_static_rigid(e, b)); }
+
+static void row_islands(const env_t *e, int *row_isl) {
+  int nb = e->nr + e->np;
+  int *par = malloc((nb + 1) * sizeof(int));
+  for (int i = 0; i <= nb; ++i) par[i] = i;
+  for (int j = 0; j < e->nj; ++j) {
+    int a = e->jbody[2 * j], b = e->jbody[2 * j + 1];
+    if (body_dynamic(e, a) && body_dynamic(e, b)) uf_union(par, a, b);
+  }
+  for (int t = 0; t < e->nt; ++t)
+    for (int k = 1; k < 4; ++k) uf_union(par, e->nr + e->tid[4 * t], e->nr + e->tid[4 * t + k]);
+  for (int ci = 0; ci < e->nc; ++ci) {
+    const contact *c = &e->con[ci];
+    if (body_dynamic(e, c->fa) && body_dynamic(e, c->tb)) uf_union(par, c->fa, c->tb);
+  }
+  for (int j = 0; j < e->nj; ++j) {
+    int a = e->jbody[2 * j], b = e->jbody[2 * j + 1];
+    int isl = body_dynamic(e, b) ? uf_find(par, b) : (body_dynamic(e, a) ? uf_find(par, a) : nb);
+    for (int r = 0; r < 6; ++r) row_isl[6 * j + r] = isl;
+  }
+  for (int ci = 0; ci < e->nc; ++ci) {
+    const contact *c = &e->con[ci];
+    int isl = body_dynamic(e, c->fa) ? uf_find(par, c->fa) : (body_dynamic(e, c->tb) ? uf_find(par, c->tb) : nb);
+    for (int r = 0; r < 3; ++r) row_isl[6 * e->nj + 3 * ci + r] = isl;
+  }
+  for (int t = 0; t < e->nt; ++t) {
+    int isl = uf_find(par, e->nr + e->tid[4 * t]);
+    for (int r = 0; r < 3; ++r) row_isl[6 * e->nj + 3 * e->nc + 3 * t + r] = isl;
+  }
+  free(par);
+}
+
 static int prev_lookup(const env_t *e, int64_t key) {
   int lo = 0, hi = e->nprev - 1;
   while (lo <= hi) {
@@ -1516,6 +1564,8 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
   double *tmp = calloc(nd, sizeof(double)), *tmp2 = calloc(nd, sizeof(double));
   double *b = calloc(nr_alloc, sizeof(double)), *P = calloc(nr_alloc, sizeof(double));
   double *x = calloc(nr_alloc, sizeof(double)), *du = calloc(nd, sizeof(double));
+  int *row_isl = calloc(nr_alloc, sizeof(int));
+  if (p->islands) row_islands(e, row_isl);
 
   int newton_done = 0, cr_total = 0;
   double r_ncp = 0, r_con = 0, merit = 0;
@@ -1627,8 +1677,27 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
       P[r] = 1.0 / (row_hdiag(&S, &S.J[r]) + S.Cblk[9 * b0 + 3 * ri + ri] + p->eps);
     }
     schur_ctx sc = {&S, tmp, tmp2};
-    int done = p->linear == 1 ? pcg_solve(S.nrows, schur_apply, &sc, b, P, M, x, NULL)
-                              : pcr_solve(S.nrows, schur_apply, &sc, b, P, M, x, NULL);
+    int done = 0;
+    if (p->islands && p->linear == 0) {
+      /* READING of Sec. 11's island remedy: one PCR per island.  A is block diagonal
+       * over islands, so the PCR of the right-hand side restricted to an island stays
+       * in that island's rows; the solution is the sum of the island solutions. */
+      for (int r = 0; r < S.nrows; ++r) x[r] = 0.0;
+      double *bi = calloc(nr_alloc, sizeof(double)), *xi = calloc(nr_alloc, sizeof(double));
+      for (int r0 = 0; r0 < S.nrows; ++r0) {
+        int isl = row_isl[r0], first = 1;
+        for (int r = 0; r < r0; ++r) if (row_isl[r] == isl) { first = 0; break; }
+        if (!first) continue;
+        for (int r = 0; r < S.nrows; ++r) bi[r] = row_isl[r] == isl ? b[r] : 0.0;
+        int di = pcr_solve(S.nrows, schur_apply, &sc, bi, P, M, xi, NULL);
+        if (di > done) done = di;
+        for (int r = 0; r < S.nrows; ++r) if (row_isl[r] == isl) x[r] = xi[r];
+      }
+      free(bi); free(xi);
+    } else {
+      done = p->linear == 1 ? pcg_solve(S.nrows, schur_apply, &sc, b, P, M, x, NULL)
+                            : pcr_solve(S.nrows, schur_apply, &sc, b, P, M, x, NULL);
+    }
     cr_total += done;
     /* du = H~^-1 (h J^T dlambda - g); damped update (Sec. 6.2, 8.1) */
     memset(f, 0, nd * sizeof(double));
@@ -1706,7 +1775,7 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
   free(S.x0); free(S.q0); free(S.px0); free(S.Iw); free(S.Iwinv); free(S.ut); free(S.u); free(S.uprev);
   free(S.Hdiag); free(S.theta_minus); free(S.lam); free(S.J); free(S.Jprev); free(S.err); free(S.Cblk);
   free(S.blk_start); free(S.blk_size); free(S.row_kind);
-  free(g); free(f); free(fhat); free(tmp); free(tmp2); free(b); free(P); free(x); free(du);
+  free(g); free(f); free(fhat); free(tmp); free(tmp2); free(b); free(P); free(x); free(du); free(row_isl);
   return st->nonfinite ? -4 : 0;
 }
 

@@ -61,7 +61,7 @@ typedef struct {
   int32_t warm;       /* 0 zero start, 1 previous-step multipliers, 2 learned */
   int32_t line_search; /* 1: back-tracking on the L2 merit from t = 1 instead of the constant damping */
   int32_t linear;      /* 0 preconditioned conjugate residual (the method), 1 preconditioned conjugate gradient */
-  int32_t pad;
+  int32_t islands;     /* 1: one PCR per island of the env (independent CR scalars) */
 } orc_params;
 
 typedef struct {

@@ -38,7 +38,7 @@ class Params(C.Structure):
     _fields_ = [("ncp", C.c_int32), ("rmode", C.c_int32), ("damping", C.c_double),
                 ("eps", C.c_double), ("geo_stiff", C.c_int32), ("fem_mode", C.c_int32),
                 ("margin", C.c_double), ("warm", C.c_int32), ("line_search", C.c_int32),
-                ("linear", C.c_int32), ("pad", C.c_int32)]
+                ("linear", C.c_int32), ("islands", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -113,7 +113,7 @@ def _i32(a):
 def make_params(sp=None, **kw):
     """Oracle parameter struct from a scene_inputs.SolverParams (or keywords)."""
     vals = dict(ncp=0, rmode=2, damping=0.75, eps=1e-6, geo_stiff=1, fem_mode=0,
-                margin=5e-3, warm=0, line_search=0, linear=0)
+                margin=5e-3, warm=0, line_search=0, linear=0, islands=0)
     if sp is not None:
         for k in vals:
             vals[k] = getattr(sp, k)

@@ -46,6 +46,7 @@ class SolverParams:
     warm: int = WARM_ZERO
     line_search: int = 0           # 1: back-tracking on the L2 merit (frictionless scenes)
     linear: int = 0                # 0 PCR (the method), 1 PCG (comparison solver)
+    islands: int = 0               # 1: independent PCR scalars per island of an env
 
 
 @dataclasses.dataclass

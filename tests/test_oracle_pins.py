@@ -734,3 +734,25 @@ def test_pcg_residual_not_monotone_where_pcr_is():
             found = True
             break
     assert found
+
+
+# ------------------------------------------------------------------ islands (Sec. 11)
+def test_islands_solve_the_same_system():
+    """One PCR per island (independent CR scalars) solves the same block-diagonal
+    system: with the linear solves run to convergence the step is the same as with
+    one PCR over the whole env; an env with a single island gives identical steps."""
+    h = 1 / 60
+    multi = si.batched_env(seed=1005, tets_max=0)  # stacks and chains: several islands
+    for d, exact in [(multi, False), (si.cube_stack(seed=1, n=3), True)]:
+        a, b = O.OracleEnv(d), O.OracleEnv(d)
+        for _ in range(3):
+            a.step(h, 8, 400, 0.0, O.make_params(islands=1))
+            b.step(h, 8, 400, 0.0, O.make_params(islands=0))
+        A, B = a.get_state(), b.get_state()
+        for k in A:
+            if A[k].size:
+                if exact:
+                    assert np.array_equal(A[k], B[k]), k
+                else:
+                    # the rounding-level PCR stop is relative to each island's own start
+                    np.testing.assert_allclose(A[k], B[k], atol=1e-6, err_msg=k)
