@@ -12,7 +12,7 @@ from .scenes import (  # noqa: F401
     NCP_FB, NCP_MIN, RMODE_IDENTITY, RMODE_H2, RMODE_H2_EFFMASS,
     FEM_FULL_PROJECTED, FEM_DIAGONAL, WARM_ZERO, WARM_PREV, WARM_LEARNED,
     box_inertia, capsule_inertia, hex_grid_tets, sphere_tets,
-    cube_stack, heavy_stack, tet_block_with_boxes, grasp_scene, batched_env, batched_envs,
+    cube_stack, heavy_stack, stretched_sheet, tet_block_with_boxes, grasp_scene, batched_env, batched_envs,
     particle_on_plane, free_particle, spinning_box, box_on_incline,
     particles_vs_planes_lcp, single_tet, pendulum_drive, round_to_f32,
 )

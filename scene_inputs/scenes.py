@@ -329,6 +329,27 @@ def cube_stack(seed=0, n=8, side=0.1, mass=1.0, mu=0.5, jitter=1e-3):
     return d.finalize()
 
 
+def stretched_sheet(speed=0.5, nx=8, ny=4, cell=0.05, E=1e5, nu=0.45, rho=1000.0):
+    """A neo-Hookean sheet (nx x ny x 1 hexes, 5 tets each) pulled apart in x: the
+    particles of both end columns are made heavy (1e6 kg) and given opposite x
+    velocities, so they move almost kinematically and the strain grows by about
+    2 speed h / (nx cell) per step.  No gravity, no ground (the paper's material
+    extension / stretched-sheet test)."""
+    x, tets = hex_grid_tets(nx, ny, 1, cell, origin=(0.0, 0.0, 0.0))
+    d = _empty(mu=0.0, max_contacts=1, name=f"stretched_sheet(speed={speed})")
+    _set_tets(d, x, tets, E, nu, rho)
+    d.gravity = np.zeros(3)
+    d.ground = 0
+    px = np.asarray(d.particle_x)[:, 0]
+    left, right = px < 0.5 * cell, px > px.max() - 0.5 * cell
+    d.particle_mass = np.asarray(d.particle_mass, np.float64).copy()
+    d.particle_mass[left | right] = 1e6
+    d.particle_v = np.zeros((len(px), 3))
+    d.particle_v[left, 0] = -speed
+    d.particle_v[right, 0] = speed
+    return d.finalize()
+
+
 def heavy_stack(seed=0, n=5, side=0.1, base_mass=8.0, ratio=8.0, mu=0.5, jitter=1e-3):
     """Stack of `n` cubes whose masses grow geometrically upwards, m_k = base * ratio^k
     (the heavy stack of the paper's rigid tests: 8, 64, ..., 32768 kg, 4096:1)."""
