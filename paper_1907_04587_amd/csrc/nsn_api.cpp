@@ -456,12 +456,20 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
     d.joint_type = d.joint_body = nullptr;
     d.joint_anchor = d.joint_axis = d.joint_ref = d.joint_drive = nullptr;
   }
-  // default schedule: one launch; block size from the largest env
-  int max_el = 0;
-  for (auto &E : env) max_el = std::max(max_el, E.n_jnt + E.n_tet + E.max_con + E.n_rig + E.n_par);
-  int block = 64;
-  while (block < 256 && block * 4 < max_el) block *= 2;
-  s->buckets = {Bucket{0, n_envs, block, 0}};
+  // default schedule.  Large batches: the heavier half of the envs (launch order is by
+  // decreasing work) with 1024 threads each, the lighter half with 128 (what the
+  // schedule autotuner finds on the uneven 4096-env batch).  Otherwise one launch with
+  // the block size from the largest env.
+  if (n_envs >= 1024) {
+    const int half = n_envs / 2;
+    s->buckets = {Bucket{0, half, 1024, 0}, Bucket{half, n_envs - half, 128, 0}};
+  } else {
+    int max_el = 0;
+    for (auto &E : env) max_el = std::max(max_el, E.n_jnt + E.n_tet + E.max_con + E.n_rig + E.n_par);
+    int block = 64;
+    while (block < 256 && block * 4 < max_el) block *= 2;
+    s->buckets = {Bucket{0, n_envs, block, 0}};
+  }
   set_bucket_lds(s);
   s->use_graphs = s->stream != nullptr;
   *out = s;
