@@ -364,6 +364,103 @@ void orc_compliance3(const double *H, double floor_, int mode, double *E) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* Linear Hookean constant-strain tet (Sec. 9.2, linear materials)            */
+/* ------------------------------------------------------------------------- */
+
+/* strain order of Sec. 9.2: (e_xx, e_yy, e_zz, e_yz, e_xz, e_xy) as index pairs */
+static const int LIN_A[6] = {0, 1, 2, 1, 0, 0}, LIN_B[6] = {0, 1, 2, 2, 2, 1};
+
+/* READING: the strain of a linear tet is taken in the element's rotated frame (the
+ * paper's material-extension test names the linear model co-rotational):
+ * e = S - I with F = R S the polar decomposition, R = U V^T and S = V diag(s) V^T from
+ * the signed SVD (det R = +1 also for inverted elements).  Shear entries are tensor
+ * components, e_yz = (S_yz + S_zy)/2 - 0. */
+static void corot_strain(const double *F, double *R, double *eps6) {
+  double U[9], s[3], V[9];
+  orc_svd3(F, U, s, V);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double r = 0.0;
+      for (int k = 0; k < 3; ++k) r += U[3 * i + k] * V[3 * j + k];
+      R[3 * i + j] = r;
+    }
+  for (int q = 0; q < 6; ++q) {
+    int a = LIN_A[q], b = LIN_B[q];
+    double Sab = 0.0;
+    for (int k = 0; k < 3; ++k) Sab += V[3 * a + k] * s[k] * V[3 * b + k];
+    eps6[q] = Sab - (a == b ? 1.0 : 0.0);
+  }
+}
+
+/* READING: ds/dx at fixed R.  With D_s = [x1-x0, x2-x0, x3-x0] and F = D_s D_m^-1,
+ * (R^T F)_ab = sum_j R_:a . (x_j - x0) (D_m^-1)_jb, so the row of e_ab has the entry
+ * (R_:a (D_m^-1)_jb + R_:b (D_m^-1)_ja)/2 at vertex j = 1..3 and minus their sum at
+ * vertex 0.  For an isotropic K_e, J^T c is then the exact gradient of the energy
+ * (the rotation's derivative pairs a skew matrix with the symmetric S c). */
+static void corot_rows(const double *R, const double *Dminv, double g[6][4][3]) {
+  for (int q = 0; q < 6; ++q) {
+    int a = LIN_A[q], b = LIN_B[q];
+    for (int k = 0; k < 3; ++k) g[q][0][k] = 0.0;
+    for (int j = 1; j <= 3; ++j)
+      for (int k = 0; k < 3; ++k) {
+        double v = 0.5 * (R[3 * k + a] * Dminv[3 * (j - 1) + b] + R[3 * k + b] * Dminv[3 * (j - 1) + a]);
+        g[q][j][k] = v;
+        g[q][0][k] -= v;
+      }
+  }
+}
+
+/* Sec. 9.2: U = V_e (1/2) s^T K_e s, c = dU/ds = V_e K_e s.  READING: isotropic K_e from
+ * the Lame parameters, for tensor shear strains: normal block lambda 1 1^T + 2 mu I,
+ * shear diagonal 4 mu (so that s^T K_e s / 2 = mu e:e + lambda tr(e)^2 / 2). */
+static void lin_stiffness(double mu, double la, double *K36) {
+  memset(K36, 0, 36 * sizeof(double));
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) K36[6 * i + j] = la + (i == j ? 2.0 * mu : 0.0);
+  for (int i = 3; i < 6; ++i) K36[6 * i + i] = 4.0 * mu;
+}
+
+/* E = (V_e K_e)^-1 (Sec. 9.2, a constant): the normal block inverted as a 3x3 matrix,
+ * the shear diagonal entry by entry. */
+static void lin_compliance(double mu, double la, double Ve, double *C36) {
+  double K[36], Kn[9], En[9];
+  lin_stiffness(mu, la, K);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Kn[3 * i + j] = Ve * K[6 * i + j];
+  m3_inv(Kn, En);
+  memset(C36, 0, 36 * sizeof(double));
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C36[6 * i + j] = En[3 * i + j];
+  for (int i = 3; i < 6; ++i) C36[6 * i + i] = 1.0 / (Ve * K[6 * i + i]);
+}
+
+static void lame_mu_lambda(double E, double nu, double *mu, double *la) {
+  *mu = E / (2.0 * (1.0 + nu));
+  *la = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+}
+
+void orc_linear_tet(const double *Dminv, const double *x12, double E, double nu, double Ve, double *eps6,
+                    double *rows72, double *c6, double *C36) {
+  double Ds[9], F[9], R[9], g[6][4][3], K[36], mu, la;
+  for (int c = 0; c < 3; ++c)
+    for (int r = 0; r < 3; ++r) Ds[3 * r + c] = x12[3 * (c + 1) + r] - x12[r];
+  m3_mul(Ds, Dminv, F);
+  corot_strain(F, R, eps6);
+  corot_rows(R, Dminv, g);
+  for (int q = 0; q < 6; ++q)
+    for (int j = 0; j < 4; ++j)
+      for (int k = 0; k < 3; ++k) rows72[12 * q + 3 * j + k] = g[q][j][k];
+  lame_mu_lambda(E, nu, &mu, &la);
+  lin_stiffness(mu, la, K);
+  for (int i = 0; i < 6; ++i) {
+    double acc = 0.0;
+    for (int j = 0; j < 6; ++j) acc += K[6 * i + j] * eps6[j];
+    c6[i] = Ve * acc;
+  }
+  lin_compliance(mu, la, Ve, C36);
+}
+
+/* ------------------------------------------------------------------------- */
 /* Preconditioned conjugate residual (Sec. 8.2; Saad's CR with a left Jacobi  */
 /* preconditioner).  READING: x0 = 0, at most `iters` iterations; stops when   */
 /* rho = <z, Az> <= TAU_CR rho_0 (the residual is at rounding level: further   */
@@ -497,6 +594,8 @@ typedef struct {
   /* tets */
   int *tid;
   double *Dminv, *Ve, *C1, *D1, *alph;
+  double *lmu, *llam;      /* Lame parameters (linear tets) */
+  int tet_model, tet_rows; /* ORC_TET_*; rows per tet: 3 (principal stretches) or 6 (strains) */
   /* joints */
   int *jtype, *jbody;
   double *janc, *jaxis, *jref, *jdrive;
@@ -508,7 +607,7 @@ typedef struct {
   int nc, overflow;
   contact *prev;   /* last step's contacts (sorted by key) */
   int nprev;
-  double *lam_joint_prev, *lam_tet_prev;  /* joint rows (6 each), tet rows (3 each) */
+  double *lam_joint_prev, *lam_tet_prev;  /* joint rows (6 each), tet rows (tet_rows each) */
   int have_prev;
   /* scratch sized at create */
   int ndof, maxrows;
@@ -534,17 +633,24 @@ void *orc_create(const orc_desc *d, char *err, int errlen) {
   env_t *e = calloc(1, sizeof(env_t));
   e->nr = d->n_rigid; e->np = d->n_particles; e->nt = d->n_tets; e->nj = d->n_joints;
   e->maxc = d->max_contacts;
+  e->tet_model = d->tet_model;
+  e->tet_rows = d->tet_model == ORC_TET_LINEAR ? 6 : 3;
   int nr = e->nr, np = e->np, nt = e->nt, nj = e->nj;
 #define ALLOC(p, n) p = calloc((size_t)((n) > 0 ? (n) : 1), sizeof(*(p)))
   ALLOC(e->rm, nr); ALLOC(e->rI, 3 * nr); ALLOC(e->rx, 3 * nr); ALLOC(e->rq, 4 * nr);
   ALLOC(e->rv, 3 * nr); ALLOC(e->rw, 3 * nr); ALLOC(e->rext, 3 * nr); ALLOC(e->rshape, nr);
   ALLOC(e->px, 3 * np); ALLOC(e->pv, 3 * np); ALLOC(e->pm, np);
   ALLOC(e->tid, 4 * nt); ALLOC(e->Dminv, 9 * nt); ALLOC(e->Ve, nt); ALLOC(e->C1, nt);
-  ALLOC(e->D1, nt); ALLOC(e->alph, nt);
+  ALLOC(e->D1, nt); ALLOC(e->alph, nt); ALLOC(e->lmu, nt); ALLOC(e->llam, nt);
   ALLOC(e->jtype, nj); ALLOC(e->jbody, 2 * nj); ALLOC(e->janc, 6 * nj); ALLOC(e->jaxis, 6 * nj);
   ALLOC(e->jref, 6 * nj); ALLOC(e->jdrive, 6 * nj);
   ALLOC(e->con, e->maxc); ALLOC(e->prev, e->maxc);
-  ALLOC(e->lam_joint_prev, 6 * nj); ALLOC(e->lam_tet_prev, 3 * nt);
+  ALLOC(e->lam_joint_prev, 6 * nj); ALLOC(e->lam_tet_prev, e->tet_rows * nt);
+  if (d->tet_model != ORC_TET_NEOHOOKEAN && d->tet_model != ORC_TET_LINEAR) {
+    snprintf(err, errlen, "unknown tet model %d", d->tet_model);
+    orc_destroy(e);
+    return NULL;
+  }
   for (int i = 0; i < nr; ++i) {
     e->rm[i] = d->rigid_mass[i];
     for (int k = 0; k < 3; ++k) {
@@ -590,6 +696,7 @@ void *orc_create(const orc_desc *d, char *err, int errlen) {
     double E = d->tet_material[3 * t], nu = d->tet_material[3 * t + 1], rho = d->tet_material[3 * t + 2];
     if (!(E > 0) || !(nu > -1 && nu < 0.5) || !(rho > 0)) { snprintf(err, errlen, "tet %d: bad material", t); orc_destroy(e); return NULL; }
     orc_lame(E, nu, &e->C1[t], &e->D1[t], &e->alph[t]);
+    lame_mu_lambda(E, nu, &e->lmu[t], &e->llam[t]);
     /* READING: lumped particle mass, rho V_e / 4 per tet vertex (Sec. 9.3). */
     for (int k = 0; k < 4; ++k) e->pm[e->tid[4 * t + k]] += rho * e->Ve[t] / 4.0;
   }
@@ -614,7 +721,7 @@ void *orc_create(const orc_desc *d, char *err, int errlen) {
   for (int k = 0; k < 3; ++k) e->grav[k] = d->gravity[k];
   e->ground = d->ground;
   e->ndof = 6 * nr + 3 * np;
-  e->maxrows = 6 * nj + 3 * e->maxc + 3 * nt;
+  e->maxrows = 6 * nj + 3 * e->maxc + e->tet_rows * nt;
   ALLOC(e->hist, MAX_HIST); ALLOC(e->mhist, MAX_HIST);
   ALLOC(e->dbg_err, e->maxrows); ALLOC(e->dbg_cdiag, e->maxrows); ALLOC(e->dbg_pdiag, e->maxrows);
   ALLOC(e->lam_last, e->maxrows);
@@ -627,7 +734,7 @@ void orc_destroy(void *p) {
   if (!e) return;
   free(e->rm); free(e->rI); free(e->rx); free(e->rq); free(e->rv); free(e->rw); free(e->rext); free(e->rshape);
   free(e->px); free(e->pv); free(e->pm);
-  free(e->tid); free(e->Dminv); free(e->Ve); free(e->C1); free(e->D1); free(e->alph);
+  free(e->tid); free(e->Dminv); free(e->Ve); free(e->C1); free(e->D1); free(e->alph); free(e->lmu); free(e->llam);
   free(e->jtype); free(e->jbody); free(e->janc); free(e->jaxis); free(e->jref); free(e->jdrive);
   free(e->con); free(e->prev); free(e->lam_joint_prev); free(e->lam_tet_prev);
   free(e->hist); free(e->mhist); free(e->dbg_err); free(e->dbg_cdiag); free(e->dbg_pdiag); free(e->lam_last);
@@ -1219,10 +1326,43 @@ static void tet_rows(const env_t *e, int t, jrow *rows, double *s, double *Sout_
   }
 }
 
-/* Row layout of an environment: joints (6 rows each), contacts (3 each), tets (3 each). */
+/* Linear tet rows (Sec. 9.2): the six strains of the current configuration and their
+ * rows ds/dx (READING: at fixed R, see corot_rows); the stress c = V_e K_e s. */
+static void linear_tet_rows(const env_t *e, int t, jrow *rows, double *eps6, double *c6) {
+  const int *id = e->tid + 4 * t;
+  double x12[12], Ds[9], F[9], R[9], g[6][4][3];
+  for (int k = 0; k < 4; ++k)
+    for (int a = 0; a < 3; ++a) x12[3 * k + a] = e->px[3 * id[k] + a];
+  for (int c = 0; c < 3; ++c)
+    for (int r = 0; r < 3; ++r) Ds[3 * r + c] = x12[3 * (c + 1) + r] - x12[r];
+  m3_mul(Ds, e->Dminv + 9 * t, F);
+  corot_strain(F, R, eps6);
+  if (rows) {
+    corot_rows(R, e->Dminv + 9 * t, g);
+    for (int q = 0; q < 6; ++q) {
+      jrow *r = &rows[q];
+      r->nent = 4;
+      for (int k = 0; k < 4; ++k) {
+        r->dof[k] = particle_dof(e, id[k]);
+        r->nd[k] = 3;
+        for (int a = 0; a < 3; ++a) r->c[k][a] = g[q][k][a];
+        for (int a = 3; a < 6; ++a) r->c[k][a] = 0;
+      }
+    }
+  }
+  double K[36];
+  lin_stiffness(e->lmu[t], e->llam[t], K);
+  for (int i = 0; i < 6; ++i) {
+    double acc = 0.0;
+    for (int j = 0; j < 6; ++j) acc += K[6 * i + j] * eps6[j];
+    c6[i] = e->Ve[t] * acc;
+  }
+}
+
+/* Row layout of an environment: joints (6 rows each), contacts (3 each), tets (3 or 6 each). */
 static int row_joint(const env_t *e, int j) { (void)e; return 6 * j; }
 static int row_contact(const env_t *e, int c) { return 6 * e->nj + 3 * c; }
-static int row_tet(const env_t *e, int t) { return 6 * e->nj + 3 * e->nc + 3 * t; }
+static int row_tet(const env_t *e, int t) { return 6 * e->nj + 3 * e->nc + e->tet_rows * t; }
 
 /* r-factors of one contact (Sec. 7 eq. rscaling).  READING: friction uses the mean of
  * the two tangent diagonals, identity mode r = 1, h^2 mode r_n = h^2, r_f = h. */
@@ -1320,7 +1460,27 @@ static void assemble(step_t *S) {
     }
   }
   /* tets (Sec. 9.1-9.2: generalised compliance of a continuum material) */
-  for (int t = 0; t < e->nt; ++t) {
+  for (int t = 0; t < e->nt && e->tet_model == ORC_TET_LINEAR; ++t) {
+    /* linear material: 6 strain rows, constant compliance E = (V_e K_e)^-1, which is
+     * block diagonal (normal strains 3x3, shears 1x1); err = E (c + lambda) / h */
+    int r0 = row_tet(e, t);
+    double eps[6], c6[6], C36[36];
+    linear_tet_rows(e, t, S->J + r0, eps, c6);
+    lin_compliance(e->lmu[t], e->llam[t], e->Ve[t], C36);
+    for (int q = 0; q < 6; ++q) {
+      double acc = 0.0;
+      for (int k = 0; k < 6; ++k) acc += C36[6 * q + k] * (c6[k] + S->lam[r0 + k]);
+      S->err[r0 + q] = acc / h;
+      S->row_kind[r0 + q] = 3;
+      S->blk_start[r0 + q] = q < 3 ? r0 : r0 + q;
+      S->blk_size[r0 + q] = q < 3 ? 3 : 1;
+      memset(S->Cblk + 9 * (r0 + q), 0, 9 * sizeof(double));
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) S->Cblk[9 * r0 + 3 * i + j] = C36[6 * i + j] / (h * h);
+    for (int q = 3; q < 6; ++q) S->Cblk[9 * (r0 + q)] = C36[6 * q + q] / (h * h);
+  }
+  for (int t = 0; t < e->nt && e->tet_model == ORC_TET_NEOHOOKEAN; ++t) {
     int r0 = row_tet(e, t);
     double s[3];
     tet_rows(e, t, S->J + r0, s, NULL, NULL);
@@ -1420,7 +1580,7 @@ static void row_islands(const env_t *e, int *row_isl) {
   }
   for (int t = 0; t < e->nt; ++t) {
     int isl = uf_find(par, e->nr + e->tid[4 * t]);
-    for (int r = 0; r < 3; ++r) row_isl[6 * e->nj + 3 * e->nc + 3 * t + r] = isl;
+    for (int r = 0; r < e->tet_rows; ++r) row_isl[row_tet(e, t) + r] = isl;
   }
   free(par);
 }
@@ -1470,8 +1630,15 @@ static void start_iterate(step_t *S) {
    * configuration, and that basis (even its row order) changes from step to step, so
    * the previous step's values do not carry over; the warm start uses the stress of
    * the start configuration instead, lambda0 = -V_e dPsi/ds(s(q^-)), whose force
-   * J^T lambda0 is the elastic force at q^-. */
-  for (int t = 0; t < e->nt; ++t) {
+   * J^T lambda0 is the elastic force at q^-.  The strains of a linear tet live in its
+   * rotated frame, which turns with the element, and take the same rule,
+   * lambda0 = -V_e K_e s(q^-). */
+  for (int t = 0; t < e->nt && e->tet_model == ORC_TET_LINEAR; ++t) {
+    double eps[6], c6[6];
+    linear_tet_rows(e, t, NULL, eps, c6);
+    for (int r = 0; r < 6; ++r) S->lam[row_tet(e, t) + r] = -c6[r];
+  }
+  for (int t = 0; t < e->nt && e->tet_model == ORC_TET_NEOHOOKEAN; ++t) {
     jrow rows3[3];
     double s3[3], grad[3];
     tet_rows(e, t, rows3, s3, NULL, NULL);
@@ -1552,7 +1719,7 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
   generate_contacts(&S);
   st->n_contacts = e->nc;
   st->overflow = e->overflow;
-  S.nrows = 6 * e->nj + 3 * e->nc + 3 * e->nt;
+  S.nrows = 6 * e->nj + 3 * e->nc + e->tet_rows * e->nt;
   int nr_alloc = S.nrows > 0 ? S.nrows : 1;
   S.lam = calloc(nr_alloc, sizeof(double));
   S.J = calloc(nr_alloc, sizeof(jrow)); S.Jprev = calloc(nr_alloc, sizeof(jrow));
@@ -1764,7 +1931,7 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
   for (int j = 0; j < e->nj; ++j)
     for (int r = 0; r < 6; ++r) e->lam_joint_prev[6 * j + r] = S.lam[row_joint(e, j) + r];
   for (int t = 0; t < e->nt; ++t)
-    for (int r = 0; r < 3; ++r) e->lam_tet_prev[3 * t + r] = S.lam[row_tet(e, t) + r];
+    for (int r = 0; r < e->tet_rows; ++r) e->lam_tet_prev[e->tet_rows * t + r] = S.lam[row_tet(e, t) + r];
   e->have_prev = 1;
   e->time = S.t_plus;
   for (int i = 0; i < e->nr && !st->nonfinite; ++i)

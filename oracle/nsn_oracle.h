@@ -48,7 +48,11 @@ typedef struct {
   double gravity[3];
   int32_t ground;                /* plane z = 0 with normal +z */
   int32_t max_contacts;
+  int32_t tet_model;             /* ORC_TET_NEOHOOKEAN (3 rows per tet) or ORC_TET_LINEAR (6) */
 } orc_desc;
+
+#define ORC_TET_NEOHOOKEAN 0 /* stable neo-Hookean in principal stretches (App. B) */
+#define ORC_TET_LINEAR 1     /* linear Hookean on six co-rotated strains (Sec. 9.2) */
 
 typedef struct {
   int32_t ncp;        /* 0 Fischer-Burmeister, 1 minimum map */
@@ -114,6 +118,11 @@ void orc_lame(double E, double nu, double *C1, double *D1, double *alpha);
 void orc_neohookean(const double *s, double C1, double D1, double alpha, double *psi,
                     double *grad, double *hess);
 void orc_compliance3(const double *H, double floor_, int mode, double *E);
+/* Linear tet of Sec. 9.2 at node positions x12 (4 x 3): strains eps6 (xx yy zz yz xz
+ * xy), constraint rows rows72 (6 x 12, node-major), stress c6 = V_e K_e eps6 and the
+ * compliance C36 = (V_e K_e)^-1 (6 x 6). */
+void orc_linear_tet(const double *Dminv, const double *x12, double E, double nu, double Ve, double *eps6,
+                    double *rows72, double *c6, double *C36);
 int orc_pcg_dense(int n, const double *A, const double *b, const double *P, int iters, double *x, double *hist);
 int orc_pcr_dense(int n, const double *A, const double *b, const double *P, int iters,
                   double *x, double *hist);

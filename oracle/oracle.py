@@ -30,7 +30,7 @@ class _Desc(C.Structure):
         ("n_joints", C.c_int32), ("joint_type", I32), ("joint_body", I32),
         ("joint_anchor", D), ("joint_axis", D), ("joint_ref", D), ("joint_drive", D),
         ("mu", C.c_double), ("gravity", C.c_double * 3), ("ground", C.c_int32),
-        ("max_contacts", C.c_int32),
+        ("max_contacts", C.c_int32), ("tet_model", C.c_int32),
     ]
 
 
@@ -89,6 +89,7 @@ def lib():
         L.orc_lame.argtypes = [C.c_double, C.c_double, D, D, D]
         L.orc_neohookean.argtypes = [D, C.c_double, C.c_double, C.c_double, D, D, D]
         L.orc_compliance3.argtypes = [D, C.c_double, C.c_int, D]
+        L.orc_linear_tet.argtypes = [D, D, C.c_double, C.c_double, C.c_double, D, D, D, D]
         L.orc_pcr_dense.argtypes = [C.c_int, D, D, D, C.c_int, D, D]
         L.orc_pcg_dense.argtypes = [C.c_int, D, D, D, C.c_int, D, D]
         L.orc_quat_kinematic.argtypes = [D, D]
@@ -151,6 +152,7 @@ class OracleEnv:
         s.gravity = (C.c_double * 3)(*desc.gravity)
         s.ground = desc.ground
         s.max_contacts = desc.max_contacts
+        s.tet_model = int(getattr(desc, "tet_model", 0))
         err = C.create_string_buffer(256)
         self.h = L.orc_create(C.byref(s), err, 256)
         if not self.h:
@@ -300,6 +302,16 @@ def compliance3(H, floor_, mode=0):
     E = np.zeros(9)
     lib().orc_compliance3(_d(H), floor_, int(mode), _d(E))
     return E.reshape(3, 3)
+
+
+def linear_tet(Dminv, x, E, nu, Ve):
+    """Linear tet of Sec. 9.2 at node positions x (4 x 3): strains (xx yy zz yz xz xy),
+    rows ds/dx (6 x 4 x 3), stress V_e K_e s and compliance (V_e K_e)^-1 (6 x 6)."""
+    Dm = np.ascontiguousarray(Dminv, np.float64).reshape(9)
+    x = np.ascontiguousarray(x, np.float64).reshape(12)
+    eps, rows, c, Cm = np.zeros(6), np.zeros(72), np.zeros(6), np.zeros(36)
+    lib().orc_linear_tet(_d(Dm), _d(x), E, nu, Ve, _d(eps), _d(rows), _d(c), _d(Cm))
+    return eps, rows.reshape(6, 4, 3), c, Cm.reshape(6, 6)
 
 
 def pcg_dense(A, b, P, iters):

@@ -28,6 +28,7 @@ NCP_FB, NCP_MIN = 0, 1
 RMODE_IDENTITY, RMODE_H2, RMODE_H2_EFFMASS = 0, 1, 2
 FEM_FULL_PROJECTED, FEM_DIAGONAL = 0, 1
 WARM_ZERO, WARM_PREV, WARM_LEARNED = 0, 1, 2
+TET_NEOHOOKEAN, TET_LINEAR = 0, 1
 
 
 def round_to_f32(a):
@@ -75,6 +76,7 @@ class EnvDesc:
     gravity: tuple = (0.0, 0.0, -9.81)
     ground: int = 1
     max_contacts: int = 256
+    tet_model: int = 0   # TET_NEOHOOKEAN (3 rows per tet) or TET_LINEAR (6 rows per tet)
     name: str = ""
 
     @property
@@ -125,10 +127,15 @@ class EnvDesc:
         self.gravity = tuple(float(np.float32(g)) for g in self.gravity)
         self.ground = int(self.ground)
         self.max_contacts = int(self.max_contacts)
+        self.tet_model = int(self.tet_model)
         return self
 
     def rows_estimate(self):
-        return 6 * self.n_joints + 3 * self.max_contacts + 3 * self.n_tets
+        return 6 * self.n_joints + 3 * self.max_contacts + self.tet_rows * self.n_tets
+
+    @property
+    def tet_rows(self):
+        return 6 if self.tet_model == TET_LINEAR else 3
 
 
 # ----------------------------------------------------------------------------
@@ -350,6 +357,30 @@ def stretched_sheet(speed=0.5, nx=8, ny=4, cell=0.05, E=1e5, nu=0.45, rho=1000.0
     return d.finalize()
 
 
+def extension_bar(stretch=1.0, tet_model=TET_NEOHOOKEAN, speed=0.0, nx=12, ny=2, nz=2, cell=0.05, E=1e5,
+                  nu=0.45, rho=1000.0):
+    """A bar of nx x ny x nz hexes (5 tets each) along x, pre-stretched by the factor
+    1 + stretch with its cross-section at rest size.  The particles of both end
+    sections are heavy (1e6 kg): at rest they hold the length and the interior relaxes;
+    with speed > 0 the two ends move apart at that speed each and stretch the bar
+    gradually.  No gravity, no ground (the material-extension test: linear against
+    hyperelastic volume change, E = 1e5 Pa, nu = 0.45)."""
+    x, tets = hex_grid_tets(nx, ny, nz, cell, origin=(0.0, 0.0, 0.0))
+    d = _empty(mu=0.0, max_contacts=1, tet_model=tet_model,
+               name=f"extension_bar(stretch={stretch},model={tet_model})")
+    _set_tets(d, x, tets, E, nu, rho)
+    d.particle_x = x * np.array([1.0 + stretch, 1.0, 1.0])
+    d.gravity = np.zeros(3)
+    d.ground = 0
+    px = x[:, 0]
+    ends = (px < 0.5 * cell) | (px > px.max() - 0.5 * cell)
+    d.particle_mass = np.where(ends, 1e6, 0.0)
+    d.particle_v = np.zeros_like(x)
+    d.particle_v[px < 0.5 * cell, 0] = -speed
+    d.particle_v[px > px.max() - 0.5 * cell, 0] = speed
+    return d.finalize()
+
+
 def heavy_stack(seed=0, n=5, side=0.1, base_mass=8.0, ratio=8.0, mu=0.5, jitter=1e-3):
     """Stack of `n` cubes whose masses grow geometrically upwards, m_k = base * ratio^k
     (the heavy stack of the paper's rigid tests: 8, 64, ..., 32768 kg, 4096:1)."""
@@ -365,12 +396,14 @@ def heavy_stack(seed=0, n=5, side=0.1, base_mass=8.0, ratio=8.0, mu=0.5, jitter=
 
 
 def tet_block_with_boxes(seed=0, cells=12, side=0.6, n_boxes=16, E=1e5, nu=0.45, rho=1000.0,
-                         mu=0.6, max_contacts=2048):
-    """Neo-Hookean block (cells^3 hexes, 5 tets each) on the ground with boxes dropped on it."""
+                         mu=0.6, max_contacts=2048, tet_model=TET_NEOHOOKEAN):
+    """Elastic block (cells^3 hexes, 5 tets each; neo-Hookean unless `tet_model` says
+    linear) on the ground with boxes dropped on it."""
     rng = np.random.default_rng(seed)
     cell = side / cells
     x, tets = hex_grid_tets(cells, cells, cells, cell, origin=(-0.5 * side, -0.5 * side, 0.0))
-    d = _empty(mu=mu, max_contacts=max_contacts, name=f"tet_block(seed={seed},cells={cells})")
+    d = _empty(mu=mu, max_contacts=max_contacts, tet_model=tet_model,
+               name=f"tet_block(seed={seed},cells={cells},model={tet_model})")
     _set_tets(d, x, tets, E, nu, rho)
     bodies = []
     for _ in range(n_boxes):
@@ -641,7 +674,7 @@ def particles_vs_planes_lcp(seed=0, n_particles=4, h=1.0 / 60.0):
 
 
 def single_tet(perturb=0.0, seed=0, E=1e5, nu=0.45, rho=1000.0, n_tets=1, gravity=(0.0, 0.0, 0.0),
-               deform=None):
+               deform=None, tet_model=TET_NEOHOOKEAN):
     """1..5 tets from one hex (contact-free), optionally deformed by a matrix `deform`
     about the centroid and perturbed by noise of scale `perturb`."""
     rng = np.random.default_rng(seed)
@@ -652,7 +685,7 @@ def single_tet(perturb=0.0, seed=0, E=1e5, nu=0.45, rho=1000.0, n_tets=1, gravit
     remap[used] = np.arange(len(used))
     x = x[used]
     tets = remap[tets].astype(np.int32)
-    d = _empty(ground=0, gravity=gravity, name=f"single_tet(n={n_tets})")
+    d = _empty(ground=0, gravity=gravity, tet_model=tet_model, name=f"single_tet(n={n_tets})")
     _set_tets(d, x, tets, E, nu, rho)
     xd = x.copy()
     if deform is not None:
