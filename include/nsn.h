@@ -73,6 +73,11 @@ typedef int32_t nsn_status;
 #define NSN_FEM_FULL_PROJECTED 0 /* E = (d2U/ds2)^-1 projected to positive definite */
 #define NSN_FEM_DIAGONAL 1       /* diagonal approximation of E */
 
+/* tet material model of an env (Sec. 9.2) */
+#define NSN_TET_NEOHOOKEAN 0 /* stable neo-Hookean in principal stretches (App. B): 3 rows per tet */
+#define NSN_TET_LINEAR 1     /* linear Hookean on six co-rotated strains: 6 rows per tet, constant
+                                compliance (V_e K_e)^-1 of an isotropic K_e from (E, nu) */
+
 #define NSN_WARM_ZERO 0    /* u0 = 0, lambda0 = 0 (Sec. 8.1) */
 #define NSN_WARM_PREV 1    /* previous-step multipliers (contacts matched by key) */
 #define NSN_WARM_LEARNED 2 /* contact multipliers predicted by the warm-start MLP */
@@ -114,6 +119,7 @@ typedef struct {
   float gravity[3];
   int32_t ground;             /* 1: static plane z = 0 with normal +z */
   int32_t max_contacts;       /* contact capacity; extra contacts are dropped and counted */
+  int32_t tet_model;          /* NSN_TET_* of all tets of the env */
 } nsn_env_desc;
 
 typedef struct {
@@ -160,7 +166,8 @@ typedef struct {
   int64_t fallbacks;        /* warm-started steps rerun from the plain start */
   int64_t watchdogs;        /* steps that returned their lowest-merit iterate */
   double cr_bytes;          /* algorithmic bytes of the PCR loop: per PCR iteration
-                               332 B per tet + 228 B per contact + 880 B per joint
+                               332 B per tet (476 B per linear tet) + 228 B per
+                               contact + 880 B per joint
                                + 12 B per body-space DOF (vectors, compressed J and
                                compliance read/written once per iteration, J read
                                twice), times the PCR iterations performed */
@@ -220,8 +227,9 @@ nsn_status nsn_write_state(nsn_scene s, int32_t env, const float *rigid_x, const
 nsn_status nsn_read_contacts(nsn_scene s, int32_t env, int32_t cap, int32_t *n, int32_t *keys,
                              int32_t *bodies, float *geom, float *lam);
 
-/* Full multiplier vector of one env in row order (joints: 6 rows each, tets: 3 each,
- * contacts: 3 each); *n receives the row count.  Synchronises. */
+/* Full multiplier vector of one env in row order (joints: 6 rows each, tets: 3 each
+ * or 6 for NSN_TET_LINEAR, contacts: 3 each); *n receives the row count.
+ * Synchronises. */
 nsn_status nsn_read_lambda(nsn_scene s, int32_t env, int32_t cap, int32_t *n, float *lam);
 
 /* Warm-start model for NSN_WARM_LEARNED: float32 blob of 9347 MLP parameters

@@ -27,7 +27,7 @@ class EnvDescC(C.Structure):
         ("n_joints", C.c_int32), ("joint_type", I32), ("joint_body", I32),
         ("joint_anchor", F), ("joint_axis", F), ("joint_ref", F), ("joint_drive", F),
         ("mu", C.c_float), ("gravity", C.c_float * 3), ("ground", C.c_int32),
-        ("max_contacts", C.c_int32),
+        ("max_contacts", C.c_int32), ("tet_model", C.c_int32),
     ]
 
 

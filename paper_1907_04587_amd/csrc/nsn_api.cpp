@@ -46,11 +46,12 @@ struct Arena {
 };
 
 struct HostEnv {
-  int n_rig, n_par, n_tet, n_jnt, max_con, n_feat, n_targets;
+  int n_rig, n_par, n_tet, n_jnt, max_con, n_feat, n_targets, tet_rows;
 };
 
 struct Sizes {
   int NR = 0, NP = 0, NT = 0, NJ = 0, NC = 0, NROW = 0, NDOF = 0, NF = 0, NTADJ = 0, NJADJ = 0;
+  int any_linear = 0;
 };
 
 nsn_status validate_env(const nsn_env_desc &d, int e, HostEnv &he) {
@@ -63,6 +64,7 @@ nsn_status validate_env(const nsn_env_desc &d, int e, HostEnv &he) {
   if (d.n_particles > 0 && (!d.particle_x || !d.particle_v || !d.particle_rest))
     return bad("missing particle arrays");
   if (d.n_tets > 0 && (!d.tet_ids || !d.tet_material)) return bad("missing tet arrays");
+  if (d.tet_model != NSN_TET_NEOHOOKEAN && d.tet_model != NSN_TET_LINEAR) return bad("unknown tet model");
   if (d.n_joints > 0 && (!d.joint_type || !d.joint_body || !d.joint_anchor || !d.joint_axis || !d.joint_ref ||
                          !d.joint_drive))
     return bad("missing joint arrays");
@@ -98,6 +100,7 @@ nsn_status validate_env(const nsn_env_desc &d, int e, HostEnv &he) {
   he.n_rig = d.n_rigid;
   he.n_par = d.n_particles;
   he.n_tet = d.n_tets;
+  he.tet_rows = d.tet_model == NSN_TET_LINEAR ? 6 : 3;
   he.n_jnt = d.n_joints;
   he.max_con = d.max_contacts;
   he.n_feat = nfeat;
@@ -111,6 +114,7 @@ nsn_status validate_env(const nsn_env_desc &d, int e, HostEnv &he) {
 void layout(const Sizes &z, int n_envs, Arena &a, DevScene &S, EnvInfo *&env, int *&order) {
   S.n_envs = n_envs;
   S.NR = z.NR; S.NP = z.NP; S.NT = z.NT; S.NJ = z.NJ; S.NC = z.NC; S.NROW = z.NROW; S.NDOF = z.NDOF;
+  S.any_linear = z.any_linear;
   env = a.take<EnvInfo>(n_envs);
   order = a.take<int>(n_envs);
   S.env = env;
@@ -165,7 +169,8 @@ Sizes sizes_of(const std::vector<HostEnv> &he) {
   Sizes z;
   for (const auto &h : he) {
     z.NR += h.n_rig; z.NP += h.n_par; z.NT += h.n_tet; z.NJ += h.n_jnt; z.NC += h.max_con;
-    z.NROW += 6 * h.n_jnt + 3 * h.n_tet + 3 * h.max_con;
+    z.NROW += 6 * h.n_jnt + h.tet_rows * h.n_tet + 3 * h.max_con;
+    if (h.tet_rows == 6 && h.n_tet > 0) z.any_linear = 1;
     z.NDOF += 6 * h.n_rig + 3 * h.n_par;
     z.NF += h.n_feat;
     z.NTADJ += 4 * h.n_tet;
@@ -288,10 +293,10 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
     E.rig_off = ro; E.n_rig = h.n_rig; E.par_off = po; E.n_par = h.n_par;
     E.tet_off = to; E.n_tet = h.n_tet; E.jnt_off = jo; E.n_jnt = h.n_jnt;
     E.con_off = co; E.max_con = h.max_con; E.row_off = rowo;
-    E.row_cap = 6 * h.n_jnt + 3 * h.n_tet + 3 * h.max_con;
+    E.row_cap = 6 * h.n_jnt + h.tet_rows * h.n_tet + 3 * h.max_con;
     E.dof_off = dofo; E.n_dof = 6 * h.n_rig + 3 * h.n_par;
     E.feat_off = fo; E.n_feat = h.n_feat; E.n_targets = h.n_targets; E.ground = d.ground ? 1 : 0;
-    E.bcon_off = co; E.pad0 = 0;
+    E.bcon_off = co; E.tet_model = d.tet_model;
     E.mu = d.mu; E.gx = d.gravity[0]; E.gy = d.gravity[1]; E.gz = d.gravity[2];
     for (int i = 0; i < h.n_rig; ++i) {
       const int g = ro + i;
@@ -346,7 +351,8 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
       const double E = d.tet_material[3 * t], nu = d.tet_material[3 * t + 1], rho = d.tet_material[3 * t + 2];
       // READING of the material constants: C1 = mu/2, D1 = (lambda+mu)/2, alpha = 1 + mu/(lambda+mu)
       const double mu = E / (2.0 * (1.0 + nu)), la = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
-      t_mat[g] = make_float4((float)Ve, (float)(0.5 * mu), (float)(0.5 * (la + mu)), (float)(1.0 + mu / (la + mu)));
+      if (d.tet_model == NSN_TET_LINEAR) t_mat[g] = make_float4((float)Ve, (float)mu, (float)la, 0.f);
+      else t_mat[g] = make_float4((float)Ve, (float)(0.5 * mu), (float)(0.5 * (la + mu)), (float)(1.0 + mu / (la + mu)));
       // READING: lumped particle mass rho V_e / 4 per vertex (Sec. 9.3)
       for (int k = 0; k < 4; ++k) p_m[po + id[k]] += (float)(rho * Ve / 4.0);
     }
@@ -730,7 +736,7 @@ nsn_status nsn_read_lambda(nsn_scene s, int32_t env, int32_t cap, int32_t *n, fl
   int nc = 0;
   HIP_TRY(hipMemcpyAsync(&nc, s->S.n_con + env, sizeof(int), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
-  const int rows = 6 * E.n_jnt + 3 * E.n_tet + 3 * nc;
+  const int rows = 6 * E.n_jnt + (E.tet_model == NSN_TET_LINEAR ? 6 : 3) * E.n_tet + 3 * nc;
   *n = rows;
   const int m = std::min(rows, cap);
   if (m > 0 && lam) {

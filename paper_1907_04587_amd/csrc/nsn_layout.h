@@ -23,11 +23,11 @@ struct EnvInfo {
   int tet_off, n_tet;      // tetrahedra
   int jnt_off, n_jnt;      // joints
   int con_off, max_con;    // contact slots
-  int row_off, row_cap;    // rows: joints (6 each), tets (3 each), contacts (3 each)
+  int row_off, row_cap;    // rows: joints (6 each), tets (3 or 6 each), contacts (3 each)
   int dof_off, n_dof;      // body space: 6 per rigid body, 3 per particle
   int feat_off, n_feat;    // rigid collision features (box vertices, capsule ends)
   int n_targets, ground;   // (ground ? 1 : 0) + n_rig
-  int bcon_off, pad0;      // target-side contact lists
+  int bcon_off, tet_model; // target-side contact lists; NSN_TET_* of all the env's tets
   float mu, gx, gy, gz;
 };
 
@@ -36,6 +36,7 @@ struct EnvInfo {
 struct DevScene {
   int n_envs;
   int NR, NP, NT, NJ, NC, NROW, NDOF;  // totals over all envs
+  int any_linear;                      // some env has NSN_TET_LINEAR tets
   const EnvInfo *env;
   const int *env_order;  // envs sorted by decreasing work (launch order)
 
@@ -59,9 +60,10 @@ struct DevScene {
   // tets (component-major SoA)
   const int4 *t_ids;
   const float *t_Dminv;            // 9 x NT
-  const float4 *t_mat;             // (Ve, C1, D1, alpha)
-  float *t_J;                      // 2 x 18 x NT : u_i(3), w_i(3) per stretch row, ping-pong
-  float *t_E;                      // 6 x NT : E (xx yy zz xy xz yz)
+  const float4 *t_mat;             // (Ve, C1, D1, alpha); linear tets (Ve, mu, lambda, 0)
+  float *t_J;                      // 2 x 18 x NT, ping-pong: u_i(3), w_i(3) per stretch row;
+                                   // linear tets: the rotation R (9, row-major)
+  float *t_E;                      // 6 x NT : E / h^2 (xx yy zz xy xz yz); linear tets: normal block
   const int4 *t_dst;               // per tet: positions of its 4 slots in the particle lists
   float4 *p_cj;                    // NTADJ : J^T v of the tets, in particle-list order
 
@@ -129,6 +131,7 @@ struct DevScene {
 
 // algorithmic bytes of one PCR iteration (see nsn_accum)
 constexpr double kBytesTet = 332.0, kBytesContact = 228.0, kBytesJoint = 880.0, kBytesDof = 12.0;
+constexpr double kBytesLinTet = 476.0;  // a linear tet (6 rows)
 
 constexpr int kTimingRing = 1024;
 

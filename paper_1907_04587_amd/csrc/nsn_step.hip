@@ -453,12 +453,15 @@ __device__ __forceinline__ float rigid_quad(const Ctx &c, int g, const float *J6
 }
 
 // --------------------------------------------------------------------------
-// element index space of an env: [joints | tets | contacts]
+// element index space of an env: [joints | tets | contacts]; a tet has 3 rows
+// (principal stretches) or 6 (strains of a linear tet), uniform over the env
 // --------------------------------------------------------------------------
+__device__ __forceinline__ bool lin_tets(const EnvInfo &E) { return E.tet_model == NSN_TET_LINEAR; }
+__device__ __forceinline__ int tet_nrows(const EnvInfo &E) { return lin_tets(E) ? 6 : 3; }
 __device__ __forceinline__ int row_joint(const EnvInfo &E, int jl) { return E.row_off + 6 * jl; }
-__device__ __forceinline__ int row_tet(const EnvInfo &E, int tl) { return E.row_off + 6 * E.n_jnt + 3 * tl; }
+__device__ __forceinline__ int row_tet(const EnvInfo &E, int tl) { return E.row_off + 6 * E.n_jnt + tet_nrows(E) * tl; }
 __device__ __forceinline__ int row_con(const EnvInfo &E, int cl) {
-  return E.row_off + 6 * E.n_jnt + 3 * E.n_tet + 3 * cl;
+  return E.row_off + 6 * E.n_jnt + tet_nrows(E) * E.n_tet + 3 * cl;
 }
 
 // --------------------------------------------------------------------------
@@ -852,6 +855,177 @@ __device__ void assemble_joint(const Ctx &c, int jl, double tplus) {
   }
 }
 
+// ---- linear tets (Sec. 9.2, linear materials): six strains s = (xx yy zz yz xz xy)
+// in the element's rotated frame (READING: s = S - I of the polar decomposition
+// F = R S, R = U V^T of the signed SVD, rows ds/dx at fixed R), isotropic Hooke
+// c = V_e K_e s, constant compliance (V_e K_e)^-1.  The ping-pong Jacobian slot of a
+// linear tet holds R (row-major); D_m^-1 is the rest-shape constant.  Row of e_ab at
+// vertex j = 1..3: (R_:a (D_m^-1)_jb + R_:b (D_m^-1)_ja) / 2, vertex 0 minus their sum.
+constexpr int kLinA[6] = {0, 1, 2, 1, 0, 0}, kLinB[6] = {0, 1, 2, 2, 2, 1};
+
+__device__ __forceinline__ void ltet_load(const DevScene &S, int buf, int tg, float R[9], float B[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R[k] = tJ(S, buf, k, tg);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) B[k] = S.t_Dminv[(size_t)k * S.NT + tg];
+}
+
+// stress_only = true: only the warm-start multipliers -c of the start configuration
+__device__ void assemble_ltet(const Ctx &c, int tl, int buf, bool stress_only) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  const float h = c.A.h;
+  const int NT = S.NT;
+  const int tg = E.tet_off + tl;
+  const int4 id = S.t_ids[tg];
+  M3 Dmi;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Dmi.m[k] = S.t_Dminv[(size_t)k * NT + tg];
+  const V3 x0 = mk(S.p_x[id.x]);
+  const V3 e1 = mk(S.p_x[id.y]) - x0, e2 = mk(S.p_x[id.z]) - x0, e3 = mk(S.p_x[id.w]) - x0;
+  M3 Ds = {{e1.x, e2.x, e3.x, e1.y, e2.y, e3.y, e1.z, e2.z, e3.z}};
+  M3 F;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      F.m[3 * i + j] = Ds.m[3 * i] * Dmi.m[j] + Ds.m[3 * i + 1] * Dmi.m[3 + j] + Ds.m[3 * i + 2] * Dmi.m[6 + j];
+  M3 U, V;
+  float sv[3];
+  svd3(F, U, sv, V);
+  float eps[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int a = kLinA[q], b = kLinB[q];
+    eps[q] = V.m[3 * a] * sv[0] * V.m[3 * b] + V.m[3 * a + 1] * sv[1] * V.m[3 * b + 1] +
+             V.m[3 * a + 2] * sv[2] * V.m[3 * b + 2] - (a == b ? 1.f : 0.f);
+  }
+  const float4 mt = S.t_mat[tg];  // linear tets: (Ve, mu, lambda, -)
+  const float Ve = mt.x, mu = mt.y, la = mt.z;
+  const float tr = eps[0] + eps[1] + eps[2];
+  float cs[6];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) cs[q] = Ve * (2.f * mu * eps[q] + la * tr);
+#pragma unroll
+  for (int q = 3; q < 6; ++q) cs[q] = Ve * 4.f * mu * eps[q];
+  const int r0 = row_tet(E, tl);
+  if (stress_only) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) S.row_lam[r0 + q] = -cs[q];
+    return;
+  }
+  float *Jb = S.t_J + (size_t)buf * 18 * NT;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Jb[(size_t)(3 * i + j) * NT + tg] = U.m[3 * i] * V.m[3 * j] + U.m[3 * i + 1] * V.m[3 * j + 1] + U.m[3 * i + 2] * V.m[3 * j + 2];
+  // (V_e K_e)^-1: normal block (I - g 1 1^T) / (2 mu V_e) with g = lambda / (2 mu + 3 lambda),
+  // shear entries 1 / (4 mu V_e)
+  const float f = 1.f / (2.f * mu * Ve), g = la / (2.f * mu + 3.f * la);
+  const float En_d = f * (1.f - g), En_o = -f * g, Es = 1.f / (4.f * mu * Ve);
+  float cl[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) cl[q] = cs[q] + S.row_lam[r0 + q];
+  const float ih = 1.f / h, ih2 = ih * ih;
+  const float sn = cl[0] + cl[1] + cl[2];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    S.row_err[r0 + q] = (En_d * cl[q] + En_o * (sn - cl[q])) * ih;
+    S.row_C[r0 + q] = En_d * ih2;
+  }
+#pragma unroll
+  for (int q = 3; q < 6; ++q) {
+    S.row_err[r0 + q] = Es * cl[q] * ih;
+    S.row_C[r0 + q] = Es * ih2;
+  }
+  // normal block for the matvec, same layout as a neo-Hookean tet's E (xx yy zz xy xz yz)
+#pragma unroll
+  for (int k = 0; k < 3; ++k) S.t_E[(size_t)k * NT + tg] = En_d * ih2;
+#pragma unroll
+  for (int k = 3; k < 6; ++k) S.t_E[(size_t)k * NT + tg] = En_o * ih2;
+}
+
+// J z of a linear tet: the strain rates of the vertex values y (6 rows)
+__device__ __forceinline__ void ltet_JY(const Ctx &c, int tl, const float *Y, int buf, float jy[6]) {
+  const DevScene &S = c.S;
+  const EnvInfo &E = c.E;
+  const int tg = E.tet_off + tl;
+  const int4 id = S.t_ids[tg];
+  const int base = 6 * E.n_rig - 3 * E.par_off;
+  const V3 y0 = mk(Y[base + 3 * id.x], Y[base + 3 * id.x + 1], Y[base + 3 * id.x + 2]);
+  const V3 y[3] = {mk(Y[base + 3 * id.y], Y[base + 3 * id.y + 1], Y[base + 3 * id.y + 2]) - y0,
+                   mk(Y[base + 3 * id.z], Y[base + 3 * id.z + 1], Y[base + 3 * id.z + 2]) - y0,
+                   mk(Y[base + 3 * id.w], Y[base + 3 * id.w + 1], Y[base + 3 * id.w + 2]) - y0};
+  float R[9], B[9];
+  ltet_load(S, buf, tg, R, B);
+  // G = R^T Y_s D_m^-1
+  float T[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) T[3 * a + j] = R[a] * y[j].x + R[3 + a] * y[j].y + R[6 + a] * y[j].z;
+  float G[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) G[3 * a + b] = T[3 * a] * B[b] + T[3 * a + 1] * B[3 + b] + T[3 * a + 2] * B[6 + b];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) jy[q] = 0.5f * (G[3 * kLinA[q] + kLinB[q]] + G[3 * kLinB[q] + kLinA[q]]);
+}
+
+// J^T z of a linear tet into its particle-list slots: vertex j = 1..3 gets column j of
+// R Z D_m^-T with Z the symmetric tensor of z (off-diagonal entries z/2), vertex 0
+// minus their sum
+__device__ __forceinline__ void ltet_contrib(const Ctx &c, int tl, const float z[6], int buf) {
+  const DevScene &S = c.S;
+  const int tg = c.E.tet_off + tl;
+  float R[9], B[9];
+  ltet_load(S, buf, tg, R, B);
+  const float Z[9] = {z[0], 0.5f * z[5], 0.5f * z[4], 0.5f * z[5], z[1], 0.5f * z[3], 0.5f * z[4], 0.5f * z[3], z[2]};
+  float M[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) M[3 * k + b] = R[3 * k] * Z[b] + R[3 * k + 1] * Z[3 + b] + R[3 * k + 2] * Z[6 + b];
+  V3 a[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    a[j] = mk(M[0] * B[3 * j] + M[1] * B[3 * j + 1] + M[2] * B[3 * j + 2],
+              M[3] * B[3 * j] + M[4] * B[3 * j + 1] + M[5] * B[3 * j + 2],
+              M[6] * B[3 * j] + M[7] * B[3 * j + 1] + M[8] * B[3 * j + 2]);
+  const V3 a0 = mk(0.f, 0.f, 0.f) - (a[0] + a[1] + a[2]);
+  const int4 dst = S.t_dst[tg];
+  S.p_cj[dst.x] = f4(a0, 0.f);
+  S.p_cj[dst.y] = f4(a[0], 0.f);
+  S.p_cj[dst.z] = f4(a[1], 0.f);
+  S.p_cj[dst.w] = f4(a[2], 0.f);
+}
+
+// J_i H~^-1 J_i^T of the 6 rows of a linear tet
+__device__ __forceinline__ void ltet_hdiag(const Ctx &c, int tl, int buf, float dg[6]) {
+  const DevScene &S = c.S;
+  const int tg = c.E.tet_off + tl;
+  const int4 id = S.t_ids[tg];
+  const float4 Hv[4] = {S.p_H[id.x], S.p_H[id.y], S.p_H[id.z], S.p_H[id.w]};
+  float R[9], B[9];
+  ltet_load(S, buf, tg, R, B);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int a = kLinA[q], b = kLinB[q];
+    const V3 ra = mk(R[a], R[3 + a], R[6 + a]), rb = mk(R[b], R[3 + b], R[6 + b]);
+    V3 g0 = mk(0.f, 0.f, 0.f);
+    float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const V3 gj = 0.5f * (B[3 * j + b] * ra + B[3 * j + a] * rb);
+      g0 = g0 - gj;
+      acc += gj.x * gj.x / Hv[j + 1].x + gj.y * gj.y / Hv[j + 1].y + gj.z * gj.z / Hv[j + 1].z;
+    }
+    dg[q] = acc + g0.x * g0.x / Hv[0].x + g0.y * g0.y / Hv[0].y + g0.z * g0.z / Hv[0].z;
+  }
+}
+
 // stress_only = true: only the warm-start multipliers of the start configuration.
 __device__ void assemble_tet(const Ctx &c, int tl, int buf, bool stress_only) {
   const EnvInfo &E = c.E;
@@ -1242,7 +1416,7 @@ __device__ __forceinline__ void contact_hdiag(const Ctx &c, int cl, int buf, flo
 
 // Schur right-hand side b = (J Y - err)/h and Jacobi preconditioner for every row
 // (Y = H~^-1 g already in place)
-template <int BS>
+template <int BS, bool LIN>
 __device__ void rhs_and_precond(const Ctx &c, const float *Y, int buf, int nel, float eps) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
@@ -1253,6 +1427,17 @@ __device__ void rhs_and_precond(const Ctx &c, const float *Y, int buf, int nel, 
       joint_JY(c, el, Y, jy);
       joint_hdiag(c, el, dg);
       const int r0 = row_joint(E, el);
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        S.row_b[r0 + r] = (jy[r] - S.row_err[r0 + r]) * ih;
+        S.row_P[r0 + r] = 1.f / (dg[r] + S.row_C[r0 + r] + eps);
+      }
+    } else if (LIN && el < E.n_jnt + E.n_tet && lin_tets(E)) {
+      float jy[6], dg[6];
+      const int tl = el - E.n_jnt;
+      ltet_JY(c, tl, Y, buf, jy);
+      ltet_hdiag(c, tl, buf, dg);
+      const int r0 = row_tet(E, tl);
 #pragma unroll
       for (int r = 0; r < 6; ++r) {
         S.row_b[r0 + r] = (jy[r] - S.row_err[r0 + r]) * ih;
@@ -1294,7 +1479,7 @@ __device__ __forceinline__ void mv_dots(const DevScene &S, int row, float z, flo
   part[2] += (double)Pw * (double)S.row_q[row];
 }
 
-template <int BS, bool FIRST>
+template <int BS, bool FIRST, bool LIN>
 __device__ void matvec_rows(const Ctx &c, const float *Y, int buf, int nel, float eps, double part[3]) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
@@ -1310,6 +1495,32 @@ __device__ void matvec_rows(const Ctx &c, const float *Y, int buf, int nel, floa
         S.row_w[r0 + r] = w;
         if (FIRST) S.row_q[r0 + r] = w;
         mv_dots(S, r0 + r, z, w, part);
+      }
+    } else if (LIN && el < E.n_jnt + E.n_tet && lin_tets(E)) {
+      // linear tet: normal rows with the 3x3 compliance block, shear rows diagonal
+      float jy[6];
+      const int tl = el - E.n_jnt;
+      ltet_JY(c, tl, Y, buf, jy);
+      const int tg = E.tet_off + tl;
+      const int r0 = row_tet(E, tl);
+      float Em[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) Em[k] = S.t_E[(size_t)k * S.NT + tg];
+      const V3 z = mk(S.row_z[r0], S.row_z[r0 + 1], S.row_z[r0 + 2]);
+      const V3 cz = sym_mul(Em, z);
+      const float w0 = jy[0] + cz.x + eps * z.x, w1 = jy[1] + cz.y + eps * z.y, w2 = jy[2] + cz.z + eps * z.z;
+      S.row_w[r0] = w0; S.row_w[r0 + 1] = w1; S.row_w[r0 + 2] = w2;
+      if (FIRST) { S.row_q[r0] = w0; S.row_q[r0 + 1] = w1; S.row_q[r0 + 2] = w2; }
+      mv_dots(S, r0, z.x, w0, part);
+      mv_dots(S, r0 + 1, z.y, w1, part);
+      mv_dots(S, r0 + 2, z.z, w2, part);
+#pragma unroll
+      for (int r = 3; r < 6; ++r) {
+        const float zr = S.row_z[r0 + r];
+        const float w = jy[r] + S.row_C[r0 + r] * zr + eps * zr;
+        S.row_w[r0 + r] = w;
+        if (FIRST) S.row_q[r0 + r] = w;
+        mv_dots(S, r0 + r, zr, w, part);
       }
     } else if (el < E.n_jnt + E.n_tet) {
       float jy[3];
@@ -1385,12 +1596,17 @@ __device__ void gather_hinv(const Ctx &c, float *Y, int tid, int BS) {
 
 // J^T src contributions of every element (src: one value per row; buf: which
 // Jacobian of the ping-pong pair); joints only when their bodies need them.
-template <int BS>
+template <int BS, bool LIN>
 __device__ void contrib_pass(const Ctx &c, const float *src, int buf, int nel, bool joints) {
   const EnvInfo &E = c.E;
   for (int el = threadIdx.x; el < nel; el += BS) {
     if (el < E.n_jnt) {
       if (joints) joint_contrib(c, el, src);
+    } else if (LIN && el < E.n_jnt + E.n_tet && lin_tets(E)) {
+      const int tl = el - E.n_jnt;
+      const int r0 = row_tet(E, tl);
+      const float z[6] = {src[r0], src[r0 + 1], src[r0 + 2], src[r0 + 3], src[r0 + 4], src[r0 + 5]};
+      ltet_contrib(c, tl, z, buf);
     } else if (el < E.n_jnt + E.n_tet) {
       const int tl = el - E.n_jnt;
       const int r0 = row_tet(E, tl);
@@ -1431,7 +1647,7 @@ __device__ __forceinline__ float pcr_row(const DevScene &S, int row, float alpha
 
 // Element pass of the PCR: the rows of every element are updated (pcr_row) and the
 // element then writes its J^T z contribution for the body pass (gather_hinv).
-template <int BS, bool INIT>
+template <int BS, bool INIT, bool LIN>
 __device__ void pcr_update_contrib(const Ctx &c, int buf, int nel, float alpha, float beta, bool upd) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
@@ -1441,6 +1657,13 @@ __device__ void pcr_update_contrib(const Ctx &c, int buf, int nel, float alpha, 
 #pragma unroll
       for (int r = 0; r < 6; ++r) pcr_row<INIT>(S, r0 + r, alpha, beta, upd);
       joint_contrib(c, el, S.row_z);
+    } else if (LIN && el < E.n_jnt + E.n_tet && lin_tets(E)) {
+      const int tl = el - E.n_jnt;
+      const int r0 = row_tet(E, tl);
+      float z[6];
+#pragma unroll
+      for (int r = 0; r < 6; ++r) z[r] = pcr_row<INIT>(S, r0 + r, alpha, beta, upd);
+      ltet_contrib(c, tl, z, buf);
     } else if (el < E.n_jnt + E.n_tet) {
       const int tl = el - E.n_jnt;
       const int r0 = row_tet(E, tl);
@@ -1529,12 +1752,13 @@ __device__ __forceinline__ void restore_positions_body(const Ctx &c, int b) {
   }
 }
 
-template <int BS>
+template <int BS, bool LIN>
 __device__ void assemble_all(const Ctx &c, int buf, double tplus, int nc) {
   const EnvInfo &E = c.E;
   const int nel = E.n_jnt + E.n_tet + nc;
   for (int el = threadIdx.x; el < nel; el += BS) {
     if (el < E.n_jnt) assemble_joint(c, el, tplus);
+    else if (LIN && el < E.n_jnt + E.n_tet && lin_tets(E)) assemble_ltet(c, el - E.n_jnt, buf, false);
     else if (el < E.n_jnt + E.n_tet) assemble_tet(c, el - E.n_jnt, buf, false);
     else assemble_contact(c, el - E.n_jnt - E.n_tet, buf);
   }
@@ -1543,7 +1767,7 @@ __device__ void assemble_all(const Ctx &c, int buf, double tplus, int nc) {
 // --------------------------------------------------------------------------
 // Kernel 3: start iterate + Newton loop + write-back.  One workgroup per env.
 // --------------------------------------------------------------------------
-template <int BS, bool YLDS>
+template <int BS, bool YLDS, bool LIN>
 __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first) {
   __shared__ Red<BS> red;
   extern __shared__ float y_lds[];
@@ -1560,7 +1784,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
   const int nc = S.n_con[e];
   const int nb = E.n_rig + E.n_par;
   const int nel = E.n_jnt + E.n_tet + nc;
-  const int nrows = 6 * E.n_jnt + 3 * E.n_tet + 3 * nc;
+  const int nrows = 6 * E.n_jnt + tet_nrows(E) * E.n_tet + 3 * nc;
   const int R0 = E.row_off;
   const int crow0 = row_con(E, 0);
   const double tplus = S.time[e] + (double)h;
@@ -1628,7 +1852,10 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     }
   }
   if (warm) {
-    for (int t = tid; t < E.n_tet; t += BS) assemble_tet(c, t, 0, true);  // stress at q^-
+    for (int t = tid; t < E.n_tet; t += BS) {  // stress at q^-
+      if (LIN && lin_tets(E)) assemble_ltet(c, t, 0, true);
+      else assemble_tet(c, t, 0, true);
+    }
     __syncthreads();
     for (int b = tid; b < nb; b += BS) update_positions_body(c, b);
   }
@@ -1636,14 +1863,14 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
 
   for (int k = 0; k <= A.newton_iters; ++k) {
     const int buf = k & 1;
-    assemble_all<BS>(c, buf, tplus, nc);
+    assemble_all<BS, LIN>(c, buf, tplus, nc);
     __syncthreads();
     // momentum balance g = M~(u - u~) - h J^T lambda (Sec. 6.1); geometric stiffness
     // (Sec. 8.3, READING: secant of J^T lambda at fixed lambda between the last two
     // iterates, particle DOFs only)
     float rg = 0.f;
     double m2 = 0.0;
-    contrib_pass<BS>(c, S.row_lam, buf, nel, true);
+    contrib_pass<BS, LIN>(c, S.row_lam, buf, nel, true);
     __syncthreads();
     const bool secant = A.p.geo_stiff && k >= 1;
     for (int b = tid; b < nb; b += BS) {
@@ -1690,7 +1917,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     if (secant) {
       // the same forces with the previous iterate's Jacobians (particles only)
       __syncthreads();
-      contrib_pass<BS>(c, S.row_lam, buf ^ 1, nel, false);
+      contrib_pass<BS, LIN>(c, S.row_lam, buf ^ 1, nel, false);
       __syncthreads();
       for (int b = E.n_rig + tid; b < nb; b += BS) {
         const int p = E.par_off + b - E.n_rig;
@@ -1785,7 +2012,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       }
     }
     __syncthreads();
-    rhs_and_precond<BS>(c, Y, buf, nel, eps);
+    rhs_and_precond<BS, LIN>(c, Y, buf, nel, eps);
     __syncthreads();
 
     // ---- preconditioned conjugate residual (Sec. 8.2), x0 = 0, FP64 scalars ----
@@ -1810,12 +2037,12 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       const double rz_stop = kTauCR * rz;
       for (int it = 0; it < A.cr_iters; ++it) {
         if (!(rz > rz_stop) || !(rz > 0.0)) break;
-        contrib_pass<BS>(c, S.row_z, buf, nel, true);
+        contrib_pass<BS, LIN>(c, S.row_z, buf, nel, true);
         __syncthreads();
         gather_hinv(c, Y, tid, BS);
         __syncthreads();
         double dots[3] = {0.0, 0.0, 0.0};
-        matvec_rows<BS, false>(c, Y, buf, nel, eps, dots);
+        matvec_rows<BS, false, LIN>(c, Y, buf, nel, eps, dots);
         block_sum3<BS>(dots, red);
         const double pw = dots[0];
         if (!(pw > 0.0)) break;
@@ -1844,12 +2071,12 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       // <w, P w> and <w, P q>, so that <q', P q'> of the next direction q' = w + beta q
       // follows as <w,Pw> + 2 beta <w,Pq> + beta^2 <q,Pq>, and the direction update is
       // fused into the next element pass (one pass and one barrier fewer per iteration).
-      pcr_update_contrib<BS, true>(c, buf, nel, 0.f, 0.f, false);
+      pcr_update_contrib<BS, true, LIN>(c, buf, nel, 0.f, 0.f, false);
       __syncthreads();
       gather_hinv(c, Y, tid, BS);
       __syncthreads();
       double dots[3] = {0.0, 0.0, 0.0};
-      matvec_rows<BS, true>(c, Y, buf, nel, eps, dots);
+      matvec_rows<BS, true, LIN>(c, Y, buf, nel, eps, dots);
       block_sum3<BS>(dots, red);
       double rho = dots[0], qs = dots[1];
       // READING: stop once <z, A z> is at rounding level relative to its start
@@ -1869,12 +2096,12 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
           break;
         }
         // direction update, x += alpha p, z -= alpha P q, J^T z contributions
-        pcr_update_contrib<BS, false>(c, buf, nel, alpha, beta, it > 0);
+        pcr_update_contrib<BS, false, LIN>(c, buf, nel, alpha, beta, it > 0);
         __syncthreads();
         gather_hinv(c, Y, tid, BS);
         __syncthreads();
         dots[0] = dots[1] = dots[2] = 0.0;
-        matvec_rows<BS, false>(c, Y, buf, nel, eps, dots);
+        matvec_rows<BS, false, LIN>(c, Y, buf, nel, eps, dots);
         block_sum3<BS>(dots, red);
         const double b = dots[0] / rho;
         qs = dots[1] + 2.0 * b * dots[2] + b * b * qs;
@@ -1891,7 +2118,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       merit_k = merit;
       ls_t = 1.f;
     }
-    contrib_pass<BS>(c, S.row_x, buf, nel, true);
+    contrib_pass<BS, LIN>(c, S.row_x, buf, nel, true);
     __syncthreads();
     for (int b = tid; b < nb; b += BS) {
       if (b < E.n_rig) {
@@ -1990,7 +2217,8 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     a.nonfinite += nonfinite;
     a.fallbacks += fallback;
     a.watchdogs += watchdog;
-    a.cr_bytes += (double)cr_total * (kBytesTet * E.n_tet + kBytesContact * nc + kBytesJoint * E.n_jnt +
+    a.cr_bytes += (double)cr_total * ((lin_tets(E) ? kBytesLinTet : kBytesTet) * E.n_tet + kBytesContact * nc +
+                                      kBytesJoint * E.n_jnt +
                                       kBytesDof * (6.0 * E.n_rig + 3.0 * E.n_par));
     S.acc[e] = a;
     const int slot = S.tick[0] % kTimingRing;
@@ -2007,15 +2235,23 @@ hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_feature
   return hipGetLastError();
 }
 
-template <int BS>
+// LIN: the instantiation with the linear-tet paths (scenes that hold linear tets);
+// without them the neo-Hookean paths keep their register allocation
+template <int BS, bool LIN>
 static void launch_bs(const DevScene &s, const StepArgs &a, int first, int count, int lds_floats, hipStream_t st) {
   if (lds_floats > 16384)
-    (void)hipFuncSetAttribute((const void *)k_newton<BS, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_newton<BS, true, LIN>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sizeof(float) * lds_floats);
   if (lds_floats > 0)
-    hipLaunchKernelGGL((k_newton<BS, true>), dim3(count), dim3(BS), sizeof(float) * lds_floats, st, s, a, first);
+    hipLaunchKernelGGL((k_newton<BS, true, LIN>), dim3(count), dim3(BS), sizeof(float) * lds_floats, st, s, a, first);
   else
-    hipLaunchKernelGGL((k_newton<BS, false>), dim3(count), dim3(BS), 0, st, s, a, first);
+    hipLaunchKernelGGL((k_newton<BS, false, LIN>), dim3(count), dim3(BS), 0, st, s, a, first);
+}
+
+template <int BS>
+static void launch_bs(const DevScene &s, const StepArgs &a, int first, int count, int lds_floats, hipStream_t st) {
+  if (s.any_linear) launch_bs<BS, true>(s, a, first, count, lds_floats, st);
+  else launch_bs<BS, false>(s, a, first, count, lds_floats, st);
 }
 
 hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,

@@ -50,6 +50,7 @@ class _Marshal:
             s.gravity = (C.c_float * 3)(*d.gravity)
             s.ground = int(d.ground)
             s.max_contacts = int(d.max_contacts)
+            s.tet_model = int(getattr(d, "tet_model", 0))
 
 
 class Scene:
@@ -143,7 +144,7 @@ class Scene:
 
     def lambdas(self, env):
         d = self.envs[env]
-        cap = 6 * d.n_joints + 3 * d.n_tets + 3 * d.max_contacts
+        cap = 6 * d.n_joints + (6 if getattr(d, "tet_model", 0) == 1 else 3) * d.n_tets + 3 * d.max_contacts
         out = np.zeros(max(cap, 1), np.float32)
         n = C.c_int32(0)
         L.check(self.lib.nsn_read_lambda(self.h, env, cap, C.byref(n), L.fptr(out)), "nsn_read_lambda")
