@@ -120,11 +120,13 @@ def cpu_baseline(envs, args):
                       f"{args.cr} PCR), previous-step warm start, one env per thread, {wall:.1f} s"}
 
 
-def traffic_from_profile(per_launch_bytes):
-    """HBM traffic of the Newton kernel from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel sources; else None."""
+def traffic_from_profile(tet_model):
+    """HBM traffic of the Newton kernel from the committed rocprofv3 counter summary of
+    the same workload (tet model), if it was taken on the current kernel sources; else
+    None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "newton_kernel_traffic.json")
+    name = "newton_kernel_traffic.json" if tet_model == "neohookean" else f"newton_kernel_traffic_{tet_model}.json"
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -149,6 +151,8 @@ def main():
     ap.add_argument("--cr", type=int, default=40)
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--arms", default="zero,prev,learned")
+    ap.add_argument("--tet-model", choices=["neohookean", "linear"], default="neohookean",
+                    help="material of the envs' tet blocks (linear: six co-rotated strain rows per tet)")
     ap.add_argument("--schedule", action="store_true", help="autotune the launch schedule first")
     ap.add_argument("--cpu-envs", type=int, default=256)
     ap.add_argument("--cpu-steps", type=int, default=4)
@@ -179,7 +183,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 5}))
         return
     log(f"generating {args.envs} envs")
-    envs = si.batched_envs(args.envs, base_seed=1000)
+    tet_model = si.TET_LINEAR if args.tet_model == "linear" else si.TET_NEOHOOKEAN
+    envs = si.batched_envs(args.envs, base_seed=1000, tet_model=tet_model)
     model_blob = None
     model_path = os.path.join(ROOT, "paper_1907_04587_amd", "weights", "warm_start_batched.npy")
     if os.path.exists(model_path):
@@ -190,12 +195,15 @@ def main():
         log(f"arm {arm}")
         results[arm] = run_arm(envs, arm, args, model_blob if arm == "learned" else None)
         log(f"arm {arm}: {json.dumps(results[arm])}")
-    plain = max((a for a in results if a in ("zero", "prev")), key=lambda a: results[a]["env_steps_per_s"])
+    plains = [a for a in results if a in ("zero", "prev")]
+    plain = max(plains, key=lambda a: results[a]["env_steps_per_s"]) if plains else None
     head = "learned" if "learned" in results else plain
+    if head is None:
+        sys.exit("bench.py: no arm to report (--arms)")
     r = results[head]
     roof = None
     if r.get("achieved_gbs"):
-        traffic = traffic_from_profile(r["cr_bytes_per_launch"])
+        traffic = traffic_from_profile(args.tet_model)
         roof = {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "nsn::k_newton", "kernel_ms": round(r["newton_kernel_ms"], 3),
@@ -218,7 +226,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.envs} uneven envs (5-40 boxes, 0-12 revolute joints, 0-3000 "
-                               f"neo-Hookean tets), h=1/60, residual mode tol={args.tol}, "
+                               f"{'linear co-rotated' if args.tet_model == 'linear' else 'neo-Hookean'} "
+                               f"tets), h=1/60, residual mode tol={args.tol}, "
                                f"<= {args.newton} Newton x {args.cr} PCR",
                    "n_envs": args.envs, "arm": head, "plain_arm": plain},
         "cr_iters_per_s": round(r["env_cr_iters_per_s"], 1),

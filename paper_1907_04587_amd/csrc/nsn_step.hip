@@ -870,29 +870,15 @@ __device__ __forceinline__ void ltet_load(const DevScene &S, int buf, int tg, fl
   for (int k = 0; k < 9; ++k) B[k] = S.t_Dminv[(size_t)k * S.NT + tg];
 }
 
+// Linear-tet tail of the assembly, given the signed SVD F = U diag(sv) V^T;
 // stress_only = true: only the warm-start multipliers -c of the start configuration
-__device__ void assemble_ltet(const Ctx &c, int tl, int buf, bool stress_only) {
+__device__ __forceinline__ void assemble_ltet_tail(const Ctx &c, int tl, int buf, bool stress_only, const M3 &U,
+                                                   const float sv[3], const M3 &V) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   const float h = c.A.h;
   const int NT = S.NT;
   const int tg = E.tet_off + tl;
-  const int4 id = S.t_ids[tg];
-  M3 Dmi;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) Dmi.m[k] = S.t_Dminv[(size_t)k * NT + tg];
-  const V3 x0 = mk(S.p_x[id.x]);
-  const V3 e1 = mk(S.p_x[id.y]) - x0, e2 = mk(S.p_x[id.z]) - x0, e3 = mk(S.p_x[id.w]) - x0;
-  M3 Ds = {{e1.x, e2.x, e3.x, e1.y, e2.y, e3.y, e1.z, e2.z, e3.z}};
-  M3 F;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      F.m[3 * i + j] = Ds.m[3 * i] * Dmi.m[j] + Ds.m[3 * i + 1] * Dmi.m[3 + j] + Ds.m[3 * i + 2] * Dmi.m[6 + j];
-  M3 U, V;
-  float sv[3];
-  svd3(F, U, sv, V);
   float eps[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
@@ -1026,7 +1012,10 @@ __device__ __forceinline__ void ltet_hdiag(const Ctx &c, int tl, int buf, float 
   }
 }
 
-// stress_only = true: only the warm-start multipliers of the start configuration.
+// Both tet models share F and its signed SVD (one body, so that the linear-capable
+// kernel stays within the inliner's budget); stress_only = true: only the
+// warm-start multipliers of the start configuration.
+template <bool LIN>
 __device__ void assemble_tet(const Ctx &c, int tl, int buf, bool stress_only) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
@@ -1049,6 +1038,10 @@ __device__ void assemble_tet(const Ctx &c, int tl, int buf, bool stress_only) {
   M3 U, V;
   float s[3];
   svd3(F, U, s, V);
+  if (LIN && lin_tets(E)) {
+    assemble_ltet_tail(c, tl, buf, stress_only, U, s, V);
+    return;
+  }
   // rows ds_i/dx: u_i * (Dm^-1 v_i)_j for vertices 1..3, minus their sum for vertex 0
   float *Jb = S.t_J + (size_t)buf * 18 * NT;
 #pragma unroll
@@ -1758,8 +1751,7 @@ __device__ void assemble_all(const Ctx &c, int buf, double tplus, int nc) {
   const int nel = E.n_jnt + E.n_tet + nc;
   for (int el = threadIdx.x; el < nel; el += BS) {
     if (el < E.n_jnt) assemble_joint(c, el, tplus);
-    else if (LIN && el < E.n_jnt + E.n_tet && lin_tets(E)) assemble_ltet(c, el - E.n_jnt, buf, false);
-    else if (el < E.n_jnt + E.n_tet) assemble_tet(c, el - E.n_jnt, buf, false);
+    else if (el < E.n_jnt + E.n_tet) assemble_tet<LIN>(c, el - E.n_jnt, buf, false);
     else assemble_contact(c, el - E.n_jnt - E.n_tet, buf);
   }
 }
@@ -1852,10 +1844,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     }
   }
   if (warm) {
-    for (int t = tid; t < E.n_tet; t += BS) {  // stress at q^-
-      if (LIN && lin_tets(E)) assemble_ltet(c, t, 0, true);
-      else assemble_tet(c, t, 0, true);
-    }
+    for (int t = tid; t < E.n_tet; t += BS) assemble_tet<LIN>(c, t, 0, true);  // stress at q^-
     __syncthreads();
     for (int b = tid; b < nb; b += BS) update_positions_body(c, b);
   }

@@ -418,16 +418,17 @@ def tet_block_with_boxes(seed=0, cells=12, side=0.6, n_boxes=16, E=1e5, nu=0.45,
     return d.finalize()
 
 
-def batched_env(seed, tets_max=3000, boxes=(5, 40), joints_max=12, max_contacts=1024):
+def batched_env(seed, tets_max=3000, boxes=(5, 40), joints_max=12, max_contacts=1024, tet_model=TET_NEOHOOKEAN):
     """One environment of the uneven batch: a seeded number of boxes (some stacked on
     the ground, some dropped on a tet block, some hinged into chains), 0..joints_max
-    revolute joints and 0..tets_max tets."""
+    revolute joints and 0..tets_max tets (neo-Hookean unless `tet_model` says linear;
+    the model does not change the geometry or the random draws)."""
     rng = np.random.default_rng(seed)
     n_boxes = int(rng.integers(boxes[0], boxes[1] + 1))
     n_joints = int(rng.integers(0, joints_max + 1))
     n_tet_target = int(rng.integers(0, tets_max + 1))
     mu = float(rng.uniform(0.3, 1.0))
-    d = _empty(mu=mu, max_contacts=max_contacts, name=f"batched_env(seed={seed})")
+    d = _empty(mu=mu, max_contacts=max_contacts, tet_model=tet_model, name=f"batched_env(seed={seed})")
     cell = 0.05
     # near-cubic grid with 5*nx*ny*nz <= target
     nhex = n_tet_target // 5
