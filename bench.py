@@ -41,7 +41,7 @@ def run_arm(envs, arm, args, model_blob=None):
     from paper_1907_04587_amd import Scene
 
     warm = {"zero": si.WARM_ZERO, "prev": si.WARM_PREV, "learned": si.WARM_LEARNED}[arm]
-    p = si.SolverParams(warm=si.WARM_ZERO)
+    p = si.SolverParams(warm=si.WARM_ZERO, islands=int(args.islands))
     sc = Scene(envs, p)
     if model_blob is not None:
         sc.set_warm_start_model(model_blob)
@@ -151,6 +151,7 @@ def main():
     ap.add_argument("--cr", type=int, default=40)
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--arms", default="zero,prev,learned")
+    ap.add_argument("--islands", action="store_true", help="one PCR per island of an env (Sec. 11 option)")
     ap.add_argument("--tet-model", choices=["neohookean", "linear"], default="neohookean",
                     help="material of the envs' tet blocks (linear: six co-rotated strain rows per tet)")
     ap.add_argument("--schedule", action="store_true", help="autotune the launch schedule first")
@@ -228,6 +229,7 @@ def main():
         "config": {"workload": f"{args.envs} uneven envs (5-40 boxes, 0-12 revolute joints, 0-3000 "
                                f"{'linear co-rotated' if args.tet_model == 'linear' else 'neo-Hookean'} "
                                f"tets), h=1/60, residual mode tol={args.tol}, "
+                               f"{'one PCR per island, ' if args.islands else ''}"
                                f"<= {args.newton} Newton x {args.cr} PCR",
                    "n_envs": args.envs, "arm": head, "plain_arm": plain},
         "cr_iters_per_s": round(r["env_cr_iters_per_s"], 1),

@@ -135,6 +135,9 @@ typedef struct {
                           step (Sec. 8.1; for frictionless scenes) instead of the
                           constant damping; 0 (default): constant damping */
   int32_t linear;    /* NSN_LINEAR_* (default PCR) */
+  int32_t islands;   /* 1: one PCR per island of an env (dynamic bodies connected by joints,
+                        tets and contacts; Sec. 11), each with its own scalars and stop;
+                        PCR only.  0 (default): one PCR over the whole env */
 } nsn_solver_params;
 
 typedef struct {

@@ -35,7 +35,7 @@ class ParamsC(C.Structure):
     _fields_ = [("ncp", C.c_int32), ("rmode", C.c_int32), ("damping", C.c_float),
                 ("eps", C.c_float), ("geo_stiff", C.c_int32), ("fem_mode", C.c_int32),
                 ("margin", C.c_float), ("warm", C.c_int32), ("line_search", C.c_int32),
-                ("linear", C.c_int32)]
+                ("linear", C.c_int32), ("islands", C.c_int32)]
 
 
 ACC_DTYPE = np.dtype([("steps", np.int64), ("newton_iters", np.int64), ("cr_iters", np.int64),

@@ -6,9 +6,12 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnsn.so")
-SOURCES = ["nsn_step.hip", "nsn_mlp.hip", "nsn_api.cpp"]
+SOURCES = ["nsn_step.hip", "nsn_step_ext.hip", "nsn_mlp.hip", "nsn_api.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# per-source extra flags: the extended Newton kernel needs every context-taking
+# function inlined (a larger basic-block budget for the AMDGPU inliner)
+EXTRA = {"nsn_step_ext.hip": ["-mllvm", "-amdgpu-inline-max-bb=20000"]}
 
 
 def build(verbose=False, jobs=4):
@@ -18,7 +21,7 @@ def build(verbose=False, jobs=4):
         obj = os.path.join(CSRC, "_build", src + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = ["hipcc"] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = ["hipcc"] + FLAGS + EXTRA.get(src, []) + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd))

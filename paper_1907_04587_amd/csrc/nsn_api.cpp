@@ -156,6 +156,13 @@ void layout(const Sizes &z, int n_envs, Arena &a, DevScene &S, EnvInfo *&env, in
   S.row_lam_k = a.take<float>(z.NROW); S.r_u_k = a.take<float>(6 * (size_t)z.NR);
   S.r_q_k = a.take<float4>(z.NR); S.du = a.take<float>(z.NDOF);
   S.y = a.take<float>(z.NDOF); S.g = a.take<float>(z.NDOF); S.f = a.take<float>(z.NDOF);
+  // islands: per element (joints, tets, contact slots), per body, and per env
+  // n_rig + n_par + 2 island slots (the bodies, the static group, one spare)
+  const size_t nel = (size_t)z.NJ + z.NT + z.NC, nslot = (size_t)z.NR + z.NP + 2 * (size_t)n_envs;
+  S.b_lab = a.take<int>((size_t)z.NR + z.NP);
+  S.el_isl = a.take<int>(nel); S.el_perm = a.take<int>(nel); S.el_dots = a.take<double>(3 * nel);
+  S.isl_cnt = a.take<int>(nslot); S.isl_off = a.take<int>(nslot); S.isl_run = a.take<int>(nslot);
+  S.isl_list = a.take<int>(nslot); S.isl = a.take<IslState>(nslot); S.isl_n = a.take<int>(n_envs);
   S.n_con = a.take<int>(n_envs); S.overflow = a.take<int>(n_envs); S.time = a.take<double>(n_envs);
   S.stats = a.take<nsn_step_stats>(n_envs);
   S.mlp = a.take<float>(kMlpBlob);
@@ -253,7 +260,8 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
   if (!workspace || ((uintptr_t)workspace & 255)) return fail(NSN_EINVAL, "workspace must be a 256-byte aligned device pointer");
   if (p->ncp < 0 || p->ncp > 1 || p->rmode < 0 || p->rmode > 2 || p->warm < 0 || p->warm > 2 ||
       p->fem_mode < 0 || p->fem_mode > 1 || !(p->damping > 0.f) || !(p->eps >= 0.f) || !(p->margin >= 0.f) ||
-      p->line_search < 0 || p->line_search > 1 || p->linear < 0 || p->linear > 1)
+      p->line_search < 0 || p->line_search > 1 || p->linear < 0 || p->linear > 1 || p->islands < 0 ||
+      p->islands > 1)
     return fail(NSN_EINVAL, "bad solver parameters");
   size_t need = 0;
   nsn_status st = nsn_query_workspace(envs, n_envs, &need);
@@ -492,7 +500,8 @@ nsn_status nsn_set_params(nsn_scene s, const nsn_solver_params *p) {
   if (!s || !p) return fail(NSN_EINVAL, "nsn_set_params: bad arguments");
   if (p->ncp < 0 || p->ncp > 1 || p->rmode < 0 || p->rmode > 2 || p->warm < 0 || p->warm > 2 ||
       p->fem_mode < 0 || p->fem_mode > 1 || !(p->damping > 0.f) || !(p->eps >= 0.f) || !(p->margin >= 0.f) ||
-      p->line_search < 0 || p->line_search > 1 || p->linear < 0 || p->linear > 1)
+      p->line_search < 0 || p->line_search > 1 || p->linear < 0 || p->linear > 1 || p->islands < 0 ||
+      p->islands > 1)
     return fail(NSN_EINVAL, "bad solver parameters");
   if (p->warm == NSN_WARM_LEARNED && !s->S.have_mlp) return fail(NSN_ESTATE, "learned warm start needs nsn_set_warm_start_model first");
   s->p = *p;

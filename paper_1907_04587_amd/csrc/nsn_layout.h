@@ -31,6 +31,13 @@ struct EnvInfo {
   float mu, gx, gy, gz;
 };
 
+// PCR scalars of one island (island mode)
+struct IslState {
+  double rho, qs, stop;
+  float alpha, beta;
+  int active, pad;
+};
+
 // Pointers into the workspace.  Indices stored in the tables are global
 // (already offset by the env's base) unless noted.
 struct DevScene {
@@ -113,6 +120,18 @@ struct DevScene {
   // body space (NDOF)
   float *y, *g, *f;
 
+  // islands (rebuilt every step in island mode).  Element index space of an env:
+  // [joints | tets | contact slots] from jnt_off + tet_off + con_off; island slots of
+  // an env: rig_off + par_off + 2 env, one per body (named by the island's lowest
+  // env-local body index) plus the static group (index n_rig + n_par)
+  int *b_lab;                      // NR + NP: island of every body (-1: static)
+  int *el_isl, *el_perm;           // island of every element; elements grouped by island
+  double *el_dots;                 // 3 per element: its part of the PCR dots
+  int *isl_cnt, *isl_off, *isl_run, *isl_list;  // per island slot: size, start in el_perm,
+                                                // placement counter; non-empty islands
+  IslState *isl;
+  int *isl_n;                      // per env: number of non-empty islands
+
   // per env dynamic
   int *n_con, *overflow;
   double *time;
@@ -148,6 +167,9 @@ hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_feature
 // body-space vector lives in `lds_floats` floats of dynamic LDS (0: global memory)
 hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
                          hipStream_t st);
+// the same for the extended instantiation (linear tets, islands; nsn_step_ext.hip)
+hipError_t launch_newton_ext(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
+                             hipStream_t st);
 constexpr int kMaxLdsFloats = 24 * 1024;  // 96 KB of LDS for the body-space vector
 // learned warm start: MLP prediction for every contact of every env (nsn_mlp.hip)
 hipError_t launch_warm_mlp(const DevScene &s, hipStream_t st);

@@ -1015,7 +1015,7 @@ __device__ __forceinline__ void ltet_hdiag(const Ctx &c, int tl, int buf, float 
 // Both tet models share F and its signed SVD (one body, so that the linear-capable
 // kernel stays within the inliner's budget); stress_only = true: only the
 // warm-start multipliers of the start configuration.
-template <bool LIN>
+template <bool EXT>
 __device__ void assemble_tet(const Ctx &c, int tl, int buf, bool stress_only) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
@@ -1038,7 +1038,7 @@ __device__ void assemble_tet(const Ctx &c, int tl, int buf, bool stress_only) {
   M3 U, V;
   float s[3];
   svd3(F, U, s, V);
-  if (LIN && lin_tets(E)) {
+  if (EXT && lin_tets(E)) {
     assemble_ltet_tail(c, tl, buf, stress_only, U, s, V);
     return;
   }
@@ -1409,7 +1409,7 @@ __device__ __forceinline__ void contact_hdiag(const Ctx &c, int cl, int buf, flo
 
 // Schur right-hand side b = (J Y - err)/h and Jacobi preconditioner for every row
 // (Y = H~^-1 g already in place)
-template <int BS, bool LIN>
+template <int BS, bool EXT>
 __device__ void rhs_and_precond(const Ctx &c, const float *Y, int buf, int nel, float eps) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
@@ -1425,7 +1425,7 @@ __device__ void rhs_and_precond(const Ctx &c, const float *Y, int buf, int nel, 
         S.row_b[r0 + r] = (jy[r] - S.row_err[r0 + r]) * ih;
         S.row_P[r0 + r] = 1.f / (dg[r] + S.row_C[r0 + r] + eps);
       }
-    } else if (LIN && el < E.n_jnt + E.n_tet && lin_tets(E)) {
+    } else if (EXT && el < E.n_jnt + E.n_tet && lin_tets(E)) {
       float jy[6], dg[6];
       const int tl = el - E.n_jnt;
       ltet_JY(c, tl, Y, buf, jy);
@@ -1472,11 +1472,15 @@ __device__ __forceinline__ void mv_dots(const DevScene &S, int row, float z, flo
   part[2] += (double)Pw * (double)S.row_q[row];
 }
 
-template <int BS, bool FIRST, bool LIN>
-__device__ void matvec_rows(const Ctx &c, const float *Y, int buf, int nel, float eps, double part[3]) {
+// Island mode (EXT, isl): every element stores its own three partial sums in el_dots
+// (summed per island in element order afterwards) instead of adding them to part.
+template <int BS, bool FIRST, bool EXT>
+__device__ void matvec_rows(const Ctx &c, const float *Y, int buf, int nel, float eps, double part_[3], bool isl = false) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   for (int el = threadIdx.x; el < nel; el += BS) {
+    double el3[3] = {0.0, 0.0, 0.0};
+    double *part = (EXT && isl) ? el3 : part_;
     if (el < E.n_jnt) {
       float jy[6];
       joint_JY(c, el, Y, jy);
@@ -1489,7 +1493,7 @@ __device__ void matvec_rows(const Ctx &c, const float *Y, int buf, int nel, floa
         if (FIRST) S.row_q[r0 + r] = w;
         mv_dots(S, r0 + r, z, w, part);
       }
-    } else if (LIN && el < E.n_jnt + E.n_tet && lin_tets(E)) {
+    } else if (EXT && el < E.n_jnt + E.n_tet && lin_tets(E)) {
       // linear tet: normal rows with the 3x3 compliance block, shear rows diagonal
       float jy[6];
       const int tl = el - E.n_jnt;
@@ -1546,6 +1550,10 @@ __device__ void matvec_rows(const Ctx &c, const float *Y, int buf, int nel, floa
         mv_dots(S, r0 + r, z, w, part);
       }
     }
+    if (EXT && isl) {
+      double *d = S.el_dots + 3 * (size_t)(E.jnt_off + E.tet_off + E.con_off + el);
+      d[0] = el3[0]; d[1] = el3[1]; d[2] = el3[2];
+    }
   }
 }
 
@@ -1589,13 +1597,13 @@ __device__ void gather_hinv(const Ctx &c, float *Y, int tid, int BS) {
 
 // J^T src contributions of every element (src: one value per row; buf: which
 // Jacobian of the ping-pong pair); joints only when their bodies need them.
-template <int BS, bool LIN>
+template <int BS, bool EXT>
 __device__ void contrib_pass(const Ctx &c, const float *src, int buf, int nel, bool joints) {
   const EnvInfo &E = c.E;
   for (int el = threadIdx.x; el < nel; el += BS) {
     if (el < E.n_jnt) {
       if (joints) joint_contrib(c, el, src);
-    } else if (LIN && el < E.n_jnt + E.n_tet && lin_tets(E)) {
+    } else if (EXT && el < E.n_jnt + E.n_tet && lin_tets(E)) {
       const int tl = el - E.n_jnt;
       const int r0 = row_tet(E, tl);
       const float z[6] = {src[r0], src[r0 + 1], src[r0 + 2], src[r0 + 3], src[r0 + 4], src[r0 + 5]};
@@ -1640,35 +1648,50 @@ __device__ __forceinline__ float pcr_row(const DevScene &S, int row, float alpha
 
 // Element pass of the PCR: the rows of every element are updated (pcr_row) and the
 // element then writes its J^T z contribution for the body pass (gather_hinv).
-template <int BS, bool INIT, bool LIN>
-__device__ void pcr_update_contrib(const Ctx &c, int buf, int nel, float alpha, float beta, bool upd) {
+// Island mode (EXT, isl): alpha and beta are the element's island's, and the rows of an
+// island that has stopped keep their values (the element still writes its J^T z).
+template <int BS, bool INIT, bool EXT>
+__device__ void pcr_update_contrib(const Ctx &c, int buf, int nel, float alpha_, float beta_, bool upd_,
+                                   bool isl = false, int ib = 0) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   for (int el = threadIdx.x; el < nel; el += BS) {
+    float alpha = alpha_, beta = beta_;
+    bool upd = upd_, act = true;
+    if (EXT && isl && !INIT) {
+      const IslState &I = S.isl[ib + S.el_isl[E.jnt_off + E.tet_off + E.con_off + el]];
+      alpha = I.alpha;
+      beta = I.beta;
+      act = I.active != 0;
+    }
     if (el < E.n_jnt) {
       const int r0 = row_joint(E, el);
+      if (act) {
 #pragma unroll
-      for (int r = 0; r < 6; ++r) pcr_row<INIT>(S, r0 + r, alpha, beta, upd);
+        for (int r = 0; r < 6; ++r) pcr_row<INIT>(S, r0 + r, alpha, beta, upd);
+      }
       joint_contrib(c, el, S.row_z);
-    } else if (LIN && el < E.n_jnt + E.n_tet && lin_tets(E)) {
+    } else if (EXT && el < E.n_jnt + E.n_tet && lin_tets(E)) {
       const int tl = el - E.n_jnt;
       const int r0 = row_tet(E, tl);
       float z[6];
 #pragma unroll
-      for (int r = 0; r < 6; ++r) z[r] = pcr_row<INIT>(S, r0 + r, alpha, beta, upd);
+      for (int r = 0; r < 6; ++r) z[r] = act ? pcr_row<INIT>(S, r0 + r, alpha, beta, upd) : S.row_z[r0 + r];
       ltet_contrib(c, tl, z, buf);
     } else if (el < E.n_jnt + E.n_tet) {
       const int tl = el - E.n_jnt;
       const int r0 = row_tet(E, tl);
       float z[3];
 #pragma unroll
-      for (int r = 0; r < 3; ++r) z[r] = pcr_row<INIT>(S, r0 + r, alpha, beta, upd);
+      for (int r = 0; r < 3; ++r) z[r] = act ? pcr_row<INIT>(S, r0 + r, alpha, beta, upd) : S.row_z[r0 + r];
       tet_contrib(c, tl, z, buf);
     } else {
       const int cl = el - E.n_jnt - E.n_tet;
       const int r0 = row_con(E, cl);
+      if (act) {
 #pragma unroll
-      for (int r = 0; r < 3; ++r) pcr_row<INIT>(S, r0 + r, alpha, beta, upd);
+        for (int r = 0; r < 3; ++r) pcr_row<INIT>(S, r0 + r, alpha, beta, upd);
+      }
       const int gc = E.con_off + cl;
       S.c_cj[gc] = f4(contact_dir(c, gc, S.row_z, buf), 0.f);
     }
@@ -1745,21 +1768,220 @@ __device__ __forceinline__ void restore_positions_body(const Ctx &c, int b) {
   }
 }
 
-template <int BS, bool LIN>
+template <int BS, bool EXT>
 __device__ void assemble_all(const Ctx &c, int buf, double tplus, int nc) {
   const EnvInfo &E = c.E;
   const int nel = E.n_jnt + E.n_tet + nc;
   for (int el = threadIdx.x; el < nel; el += BS) {
     if (el < E.n_jnt) assemble_joint(c, el, tplus);
-    else if (el < E.n_jnt + E.n_tet) assemble_tet<LIN>(c, el - E.n_jnt, buf, false);
+    else if (el < E.n_jnt + E.n_tet) assemble_tet<EXT>(c, el - E.n_jnt, buf, false);
     else assemble_contact(c, el - E.n_jnt - E.n_tet, buf);
   }
 }
 
 // --------------------------------------------------------------------------
+// Islands (option; Sec. 11 names them as the remedy for the Krylov scalars one PCR
+// shares over all the bodies of an env).  An island is the dynamic bodies connected
+// through joints, tets and contacts (static bodies and the world connect nothing),
+// named by its lowest env-local body index; an element belongs to the island of its
+// dynamic body (joints: B before A; contacts: the feature body before the target),
+// elements without one to the static group n_rig + n_par.  A is block diagonal over
+// islands, so each island runs its own PCR with its own scalars and stop.
+// --------------------------------------------------------------------------
+// labels and counters change through atomics (performed in L2): read them coherently
+__device__ __forceinline__ int ld_coherent(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// rows of element el: first row and count
+__device__ __forceinline__ void el_rows(const EnvInfo &E, int el, int &r0, int &nr) {
+  if (el < E.n_jnt) { r0 = row_joint(E, el); nr = 6; }
+  else if (el < E.n_jnt + E.n_tet) { r0 = row_tet(E, el - E.n_jnt); nr = tet_nrows(E); }
+  else { r0 = row_con(E, el - E.n_jnt - E.n_tet); nr = 3; }
+}
+
+__device__ __forceinline__ bool body_dyn(const Ctx &c, int b) {
+  return b >= 0 && (b >= c.E.n_rig || c.S.r_inertia[c.E.rig_off + b].w != 0.f);
+}
+
+// env-local bodies an element unites (joints and contacts: only when both are dynamic)
+__device__ __forceinline__ int unite_bodies(const Ctx &c, int el, int bd[4]) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  if (el < E.n_jnt) {
+    const int4 info = S.j_info[E.jnt_off + el];
+    const int a = info.y >= 0 ? info.y - E.rig_off : -1, b = info.z - E.rig_off;
+    if (!body_dyn(c, a) || !body_dyn(c, b)) return 0;
+    bd[0] = a; bd[1] = b;
+    return 2;
+  }
+  if (el < E.n_jnt + E.n_tet) {
+    const int4 id = S.t_ids[E.tet_off + el - E.n_jnt];
+    bd[0] = E.n_rig + id.x - E.par_off; bd[1] = E.n_rig + id.y - E.par_off;
+    bd[2] = E.n_rig + id.z - E.par_off; bd[3] = E.n_rig + id.w - E.par_off;
+    return 4;
+  }
+  const int2 cb = S.c_body[E.con_off + el - E.n_jnt - E.n_tet];
+  if (!body_dyn(c, cb.x) || !body_dyn(c, cb.y)) return 0;
+  bd[0] = cb.x; bd[1] = cb.y;
+  return 2;
+}
+
+__device__ __forceinline__ int element_island(const Ctx &c, int el, const int *lab) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  const int nb = E.n_rig + E.n_par;
+  if (el < E.n_jnt) {
+    const int4 info = S.j_info[E.jnt_off + el];
+    const int a = info.y >= 0 ? info.y - E.rig_off : -1, b = info.z - E.rig_off;
+    return body_dyn(c, b) ? ld_coherent(lab + b) : (body_dyn(c, a) ? ld_coherent(lab + a) : nb);
+  }
+  if (el < E.n_jnt + E.n_tet) return ld_coherent(lab + E.n_rig + S.t_ids[E.tet_off + el - E.n_jnt].x - E.par_off);
+  const int2 cb = S.c_body[E.con_off + el - E.n_jnt - E.n_tet];
+  return body_dyn(c, cb.x) ? ld_coherent(lab + cb.x) : (body_dyn(c, cb.y) ? ld_coherent(lab + cb.y) : nb);
+}
+
+// Island of every body and element, and the elements grouped by island in element
+// order (el_perm, isl_off); the non-empty islands in isl_list.  Once per step.
+template <int BS>
+__device__ void island_setup(const Ctx &c, int e, int nel, Red<BS> &red) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  const int tid = threadIdx.x;
+  const int nb = E.n_rig + E.n_par;
+  const int eb = E.jnt_off + E.tet_off + E.con_off, ib = E.rig_off + E.par_off + 2 * e;
+  int *lab = S.b_lab + E.rig_off + E.par_off;
+  for (int b = tid; b < nb; b += BS) lab[b] = body_dyn(c, b) ? b : -1;
+  for (int k = tid; k < nb + 2; k += BS) {
+    S.isl_cnt[ib + k] = 0;
+    S.isl_run[ib + k] = 0;
+  }
+  __syncthreads();
+  // Minimum-label propagation with pointer jumping.  Labels only fall and always name
+  // a body of the same island; the fixed point (every uniting element's bodies share a
+  // label that labels itself) names each island by its lowest body.  Each round moves
+  // the minimum at least one edge further, so nb + 1 rounds reach it.
+  for (int round = 0; round <= nb + 1; ++round) {
+    float changed = 0.f;
+    for (int el = tid; el < nel; el += BS) {
+      int bd[4];
+      const int n = unite_bodies(c, el, bd);
+      if (n < 2) continue;
+      int m = ld_coherent(lab + bd[0]);
+      for (int i = 1; i < n; ++i) m = min(m, ld_coherent(lab + bd[i]));
+      for (int i = 0; i < n; ++i)
+        if (atomicMin(&lab[bd[i]], m) > m) changed = 1.f;
+    }
+    __syncthreads();
+    for (int b = tid; b < nb; b += BS) {
+      const int l = ld_coherent(lab + b);
+      if (l >= 0) {
+        const int l2 = ld_coherent(lab + l);
+        if (l2 < l && atomicMin(&lab[b], l2) > l2) changed = 1.f;
+      }
+    }
+    if (block_max<BS>(changed, red, 0) == 0.f) break;
+    __syncthreads();
+  }
+  __syncthreads();
+  for (int el = tid; el < nel; el += BS) {
+    const int k = element_island(c, el, lab);
+    S.el_isl[eb + el] = k;
+    atomicAdd(&S.isl_cnt[ib + k], 1);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int off = 0, K = 0;
+    for (int k = 0; k <= nb; ++k) {
+      S.isl_off[ib + k] = off;
+      const int n = ld_coherent(S.isl_cnt + ib + k);
+      if (n > 0) S.isl_list[ib + K++] = k;
+      off += n;
+    }
+    S.isl_off[ib + nb + 1] = off;
+    S.isl_n[e] = K;
+  }
+  __syncthreads();
+  // stable grouping: the first wave walks the elements in order, 64 at a time; a
+  // lane's place is its island's start + the island's count so far + the lanes before
+  // it with the same island (the count is advanced atomically by the last such lane)
+  if (tid < 64) {
+    for (int base = 0; base < nel; base += 64) {
+      const int el = base + tid;
+      const int k = el < nel ? S.el_isl[eb + el] : -1;
+      int rank = 0, last = 0;
+      for (int j = 0; j < 64; ++j) {
+        const int kj = __shfl(k, j, 64);
+        if (kj == k) {
+          if (j < tid) ++rank;
+          last = j;
+        }
+      }
+      int old = 0;
+      if (k >= 0 && tid == last) old = atomicAdd(&S.isl_run[ib + k], rank + 1);
+      old = __shfl(old, last, 64);
+      if (k >= 0) S.el_perm[eb + S.isl_off[ib + k] + old + rank] = el;
+    }
+  }
+  __syncthreads();
+}
+
+// One wave per island: its three dots summed in element order (fixed, deterministic),
+// then its scalars.  first: the start of the PCR (rho = <z,w>, <q,Pq> = <w,Pw>, stop
+// level, beta = 0); else the single-reduction recurrences of an active island.  Then
+// the check at the top of the next iteration (rho above its stop level and positive,
+// <q,Pq> positive) and alpha = rho / <q,Pq>.  Returns 1 on a lane that saw an active
+// island, else 0.
+template <int BS>
+__device__ float island_reduce(const Ctx &c, int e, bool first) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int eb = E.jnt_off + E.tet_off + E.con_off, ib = E.rig_off + E.par_off + 2 * e;
+  const int K = S.isl_n[e];
+  float any = 0.f;
+  for (int i = w; i < K; i += BS / 64) {
+    const int k = S.isl_list[ib + i];
+    const int o0 = S.isl_off[ib + k], o1 = S.isl_off[ib + k + 1];
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+    for (int q = o0 + lane; q < o1; q += 64) {
+      const double *d = S.el_dots + 3 * (size_t)(eb + S.el_perm[eb + q]);
+      d0 += d[0];
+      d1 += d[1];
+      d2 += d[2];
+    }
+    d0 = wave_sum(d0);
+    d1 = wave_sum(d1);
+    d2 = wave_sum(d2);
+    if (lane == 0) {
+      IslState I = S.isl[ib + k];
+      if (first) {
+        I.rho = d0;
+        I.qs = d1;
+        I.stop = kTauCR * d0;
+        I.beta = 0.f;
+        I.active = 1;
+      } else if (I.active) {
+        const double b = d0 / I.rho;
+        I.qs = d1 + 2.0 * b * d2 + b * b * I.qs;
+        I.beta = (float)b;
+        I.rho = d0;
+      }
+      if (I.active) I.active = (I.rho > I.stop) && (I.rho > 0.0) && (I.qs > 0.0);
+      if (I.active) {
+        I.alpha = (float)(I.rho / I.qs);
+        any = 1.f;
+      }
+      S.isl[ib + k] = I;
+    }
+  }
+  return any;
+}
+
+// --------------------------------------------------------------------------
 // Kernel 3: start iterate + Newton loop + write-back.  One workgroup per env.
 // --------------------------------------------------------------------------
-template <int BS, bool YLDS, bool LIN>
+template <int BS, bool YLDS, bool EXT>
 __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first) {
   __shared__ Red<BS> red;
   extern __shared__ float y_lds[];
@@ -1778,6 +2000,9 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
   const int nel = E.n_jnt + E.n_tet + nc;
   const int nrows = 6 * E.n_jnt + tet_nrows(E) * E.n_tet + 3 * nc;
   const int R0 = E.row_off;
+  // island mode: one PCR per island (the extended instantiation only)
+  const bool isl_mode = EXT && A.p.islands && A.p.linear == NSN_LINEAR_PCR;
+  if (isl_mode) island_setup<BS>(c, e, nel, red);
   const int crow0 = row_con(E, 0);
   const double tplus = S.time[e] + (double)h;
   // env-local body-space vector: in LDS when the bucket's envs fit, else in global memory
@@ -1844,7 +2069,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     }
   }
   if (warm) {
-    for (int t = tid; t < E.n_tet; t += BS) assemble_tet<LIN>(c, t, 0, true);  // stress at q^-
+    for (int t = tid; t < E.n_tet; t += BS) assemble_tet<EXT>(c, t, 0, true);  // stress at q^-
     __syncthreads();
     for (int b = tid; b < nb; b += BS) update_positions_body(c, b);
   }
@@ -1852,14 +2077,14 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
 
   for (int k = 0; k <= A.newton_iters; ++k) {
     const int buf = k & 1;
-    assemble_all<BS, LIN>(c, buf, tplus, nc);
+    assemble_all<BS, EXT>(c, buf, tplus, nc);
     __syncthreads();
     // momentum balance g = M~(u - u~) - h J^T lambda (Sec. 6.1); geometric stiffness
     // (Sec. 8.3, READING: secant of J^T lambda at fixed lambda between the last two
     // iterates, particle DOFs only)
     float rg = 0.f;
     double m2 = 0.0;
-    contrib_pass<BS, LIN>(c, S.row_lam, buf, nel, true);
+    contrib_pass<BS, EXT>(c, S.row_lam, buf, nel, true);
     __syncthreads();
     const bool secant = A.p.geo_stiff && k >= 1;
     for (int b = tid; b < nb; b += BS) {
@@ -1906,7 +2131,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     if (secant) {
       // the same forces with the previous iterate's Jacobians (particles only)
       __syncthreads();
-      contrib_pass<BS, LIN>(c, S.row_lam, buf ^ 1, nel, false);
+      contrib_pass<BS, EXT>(c, S.row_lam, buf ^ 1, nel, false);
       __syncthreads();
       for (int b = E.n_rig + tid; b < nb; b += BS) {
         const int p = E.par_off + b - E.n_rig;
@@ -2001,7 +2226,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       }
     }
     __syncthreads();
-    rhs_and_precond<BS, LIN>(c, Y, buf, nel, eps);
+    rhs_and_precond<BS, EXT>(c, Y, buf, nel, eps);
     __syncthreads();
 
     // ---- preconditioned conjugate residual (Sec. 8.2), x0 = 0, FP64 scalars ----
@@ -2026,12 +2251,12 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       const double rz_stop = kTauCR * rz;
       for (int it = 0; it < A.cr_iters; ++it) {
         if (!(rz > rz_stop) || !(rz > 0.0)) break;
-        contrib_pass<BS, LIN>(c, S.row_z, buf, nel, true);
+        contrib_pass<BS, EXT>(c, S.row_z, buf, nel, true);
         __syncthreads();
         gather_hinv(c, Y, tid, BS);
         __syncthreads();
         double dots[3] = {0.0, 0.0, 0.0};
-        matvec_rows<BS, false, LIN>(c, Y, buf, nel, eps, dots);
+        matvec_rows<BS, false, EXT>(c, Y, buf, nel, eps, dots);
         block_sum3<BS>(dots, red);
         const double pw = dots[0];
         if (!(pw > 0.0)) break;
@@ -2055,17 +2280,55 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
         }
         __syncthreads();
       }
+    } else if (EXT && isl_mode) {
+      // ---- one PCR per island: the single-reduction recurrences below with each
+      //      island's own scalars and stop; done counts the iterations in which some
+      //      island was active (the largest island count) ----
+      const int ib = E.rig_off + E.par_off + 2 * e, eb = E.jnt_off + E.tet_off + E.con_off;
+      pcr_update_contrib<BS, true, EXT>(c, buf, nel, 0.f, 0.f, false);
+      __syncthreads();
+      gather_hinv(c, Y, tid, BS);
+      __syncthreads();
+      double dots[3] = {0.0, 0.0, 0.0};
+      matvec_rows<BS, true, EXT>(c, Y, buf, nel, eps, dots, true);
+      __syncthreads();
+      float any = block_max<BS>(island_reduce<BS>(c, e, true), red, 1);
+      for (int it = 0; it < A.cr_iters; ++it) {
+        if (any == 0.f) break;
+        ++done;
+        if (it == A.cr_iters - 1) {  // the last update needs no further product
+          for (int el = tid; el < nel; el += BS) {
+            const IslState &I = S.isl[ib + S.el_isl[eb + el]];
+            if (!I.active) continue;
+            int r0, nr;
+            el_rows(E, el, r0, nr);
+            for (int r = 0; r < nr; ++r) {
+              const int row = r0 + r;
+              const float p = it > 0 ? S.row_z[row] + I.beta * S.row_p[row] : S.row_p[row];
+              S.row_x[row] += I.alpha * p;
+            }
+          }
+          break;
+        }
+        pcr_update_contrib<BS, false, EXT>(c, buf, nel, 0.f, 0.f, it > 0, true, ib);
+        __syncthreads();
+        gather_hinv(c, Y, tid, BS);
+        __syncthreads();
+        matvec_rows<BS, false, EXT>(c, Y, buf, nel, eps, dots, true);
+        __syncthreads();
+        any = block_max<BS>(island_reduce<BS>(c, e, false), red, 1);
+      }
     } else {
       // Single-reduction form of the same recurrences: the matvec pass also sums
       // <w, P w> and <w, P q>, so that <q', P q'> of the next direction q' = w + beta q
       // follows as <w,Pw> + 2 beta <w,Pq> + beta^2 <q,Pq>, and the direction update is
       // fused into the next element pass (one pass and one barrier fewer per iteration).
-      pcr_update_contrib<BS, true, LIN>(c, buf, nel, 0.f, 0.f, false);
+      pcr_update_contrib<BS, true, EXT>(c, buf, nel, 0.f, 0.f, false);
       __syncthreads();
       gather_hinv(c, Y, tid, BS);
       __syncthreads();
       double dots[3] = {0.0, 0.0, 0.0};
-      matvec_rows<BS, true, LIN>(c, Y, buf, nel, eps, dots);
+      matvec_rows<BS, true, EXT>(c, Y, buf, nel, eps, dots);
       block_sum3<BS>(dots, red);
       double rho = dots[0], qs = dots[1];
       // READING: stop once <z, A z> is at rounding level relative to its start
@@ -2085,12 +2348,12 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
           break;
         }
         // direction update, x += alpha p, z -= alpha P q, J^T z contributions
-        pcr_update_contrib<BS, false, LIN>(c, buf, nel, alpha, beta, it > 0);
+        pcr_update_contrib<BS, false, EXT>(c, buf, nel, alpha, beta, it > 0);
         __syncthreads();
         gather_hinv(c, Y, tid, BS);
         __syncthreads();
         dots[0] = dots[1] = dots[2] = 0.0;
-        matvec_rows<BS, false, LIN>(c, Y, buf, nel, eps, dots);
+        matvec_rows<BS, false, EXT>(c, Y, buf, nel, eps, dots);
         block_sum3<BS>(dots, red);
         const double b = dots[0] / rho;
         qs = dots[1] + 2.0 * b * dots[2] + b * b * qs;
@@ -2107,7 +2370,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       merit_k = merit;
       ls_t = 1.f;
     }
-    contrib_pass<BS, LIN>(c, S.row_x, buf, nel, true);
+    contrib_pass<BS, EXT>(c, S.row_x, buf, nel, true);
     __syncthreads();
     for (int b = tid; b < nb; b += BS) {
       if (b < E.n_rig) {
@@ -2217,44 +2480,60 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
 }
 
 // --------------------------------------------------------------------------
-// launchers
+// launchers.  The extended instantiation (EXT: linear tets, islands) is built in its
+// own translation unit (nsn_step_ext.hip includes this file with NSN_STEP_EXT_TU),
+// with a larger basic-block budget for the inliner: at the default budget that
+// kernel leaves functions taking the Ctx out of line, which puts the Ctx (about 1 KB)
+// in scratch memory.  The default instantiation keeps the default budget.
 // --------------------------------------------------------------------------
+template <int BS, bool EXT>
+static void launch_bs(const DevScene &s, const StepArgs &a, int first, int count, int lds_floats, hipStream_t st) {
+  if (lds_floats > 16384)
+    (void)hipFuncSetAttribute((const void *)k_newton<BS, true, EXT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sizeof(float) * lds_floats);
+  if (lds_floats > 0)
+    hipLaunchKernelGGL((k_newton<BS, true, EXT>), dim3(count), dim3(BS), sizeof(float) * lds_floats, st, s, a, first);
+  else
+    hipLaunchKernelGGL((k_newton<BS, false, EXT>), dim3(count), dim3(BS), 0, st, s, a, first);
+}
+
+#ifdef NSN_STEP_EXT_TU
+constexpr bool kExtTU = true;
+#else
+constexpr bool kExtTU = false;
+#endif
+
+static hipError_t launch_tu(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
+                            hipStream_t st) {
+  switch (block) {
+    case 64: launch_bs<64, kExtTU>(s, a, first, count, lds_floats, st); break;
+    case 128: launch_bs<128, kExtTU>(s, a, first, count, lds_floats, st); break;
+    case 256: launch_bs<256, kExtTU>(s, a, first, count, lds_floats, st); break;
+    case 512: launch_bs<512, kExtTU>(s, a, first, count, lds_floats, st); break;
+    case 1024: launch_bs<1024, kExtTU>(s, a, first, count, lds_floats, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+#ifdef NSN_STEP_EXT_TU
+hipError_t launch_newton_ext(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
+                             hipStream_t st) {
+  return launch_tu(s, a, block, first, count, lds_floats, st);
+}
+#else
 hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_features, hipStream_t st) {
   hipLaunchKernelGGL(k_prepare<256>, dim3(s.n_envs), dim3(256), 0, st, s, a, want_features);
   return hipGetLastError();
 }
 
-// LIN: the instantiation with the linear-tet paths (scenes that hold linear tets);
-// without them the neo-Hookean paths keep their register allocation
-template <int BS, bool LIN>
-static void launch_bs(const DevScene &s, const StepArgs &a, int first, int count, int lds_floats, hipStream_t st) {
-  if (lds_floats > 16384)
-    (void)hipFuncSetAttribute((const void *)k_newton<BS, true, LIN>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)sizeof(float) * lds_floats);
-  if (lds_floats > 0)
-    hipLaunchKernelGGL((k_newton<BS, true, LIN>), dim3(count), dim3(BS), sizeof(float) * lds_floats, st, s, a, first);
-  else
-    hipLaunchKernelGGL((k_newton<BS, false, LIN>), dim3(count), dim3(BS), 0, st, s, a, first);
-}
-
-template <int BS>
-static void launch_bs(const DevScene &s, const StepArgs &a, int first, int count, int lds_floats, hipStream_t st) {
-  if (s.any_linear) launch_bs<BS, true>(s, a, first, count, lds_floats, st);
-  else launch_bs<BS, false>(s, a, first, count, lds_floats, st);
-}
-
 hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
                          hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  switch (block) {
-    case 64: launch_bs<64>(s, a, first, count, lds_floats, st); break;
-    case 128: launch_bs<128>(s, a, first, count, lds_floats, st); break;
-    case 256: launch_bs<256>(s, a, first, count, lds_floats, st); break;
-    case 512: launch_bs<512>(s, a, first, count, lds_floats, st); break;
-    case 1024: launch_bs<1024>(s, a, first, count, lds_floats, st); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  if (s.any_linear || (a.p.islands && a.p.linear == NSN_LINEAR_PCR))
+    return launch_newton_ext(s, a, block, first, count, lds_floats, st);
+  return launch_tu(s, a, block, first, count, lds_floats, st);
 }
+#endif
 
 }  // namespace nsn

@@ -13,7 +13,7 @@ def params_c(p) -> L.ParamsC:
     return L.ParamsC(ncp=int(p.ncp), rmode=int(p.rmode), damping=float(p.damping), eps=float(p.eps),
                      geo_stiff=int(p.geo_stiff), fem_mode=int(p.fem_mode), margin=float(p.margin),
                      warm=int(p.warm), line_search=int(getattr(p, "line_search", 0)),
-                     linear=int(getattr(p, "linear", 0)))
+                     linear=int(getattr(p, "linear", 0)), islands=int(getattr(p, "islands", 0)))
 
 
 def stats_to_dicts(arr):

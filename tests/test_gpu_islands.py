@@ -1,0 +1,85 @@
+"""Island mode on the GPU (one PCR per island of an env, Sec. 11's remedy for the
+Krylov scalars shared over all bodies): parity with the oracle's island mode per
+Newton iteration, the same converged state as the whole-env PCR, and bitwise
+repeatability (islands are found and summed in a fixed order)."""
+import numpy as np
+import pytest
+
+import scene_inputs as si
+from tests.parity_util import lockstep
+
+pytestmark = pytest.mark.gpu
+
+H = 1.0 / 60.0
+
+
+def _scene(envs, params):
+    from paper_1907_04587_amd import Scene
+    return Scene(envs, params)
+
+
+def _print(name, hist):
+    for s, w in enumerate(hist):
+        print(name, s, {k: f"{v[0]:.2e}@{v[1]} (tol {v[2]:.1e})" for k, v in w.items()}, flush=True)
+
+
+def _island_kinds():
+    return [
+        si.batched_env(seed=1005, tets_max=0),            # separate stacks and hinged chains
+        si.batched_env(seed=1000, tets_max=600),          # the same with a tet block under boxes
+        si.particles_vs_planes_lcp(seed=1),               # every particle its own island
+        si.cube_stack(seed=1),                            # one island
+        si.tet_block_with_boxes(seed=0, cells=3, n_boxes=3, tet_model=si.TET_LINEAR),
+        si.pendulum_drive(),                              # a joint to the world
+    ]
+
+
+@pytest.mark.parametrize("newton", [1, 2, 3])
+def test_per_newton_iteration_islands(newton):
+    envs = _island_kinds()
+    p = si.SolverParams(islands=1)
+    sc = _scene(envs, p)
+    for _ in range(2):  # let the boxes land: contacts between dynamic bodies join islands
+        sc.step(H, 10, 40, 0.0)
+    hist = lockstep(sc, envs, p, H, newton, 40, steps=1, sens_factor=10.0)
+    _print(f"isl{newton}", hist)
+
+
+def test_islands_reach_the_same_converged_state():
+    """A is block diagonal over islands, so converged steps with and without islands
+    agree (rigid scenes, residual mode)."""
+    envs = [si.batched_env(seed=1005, tets_max=0), si.cube_stack(seed=2), si.particles_vs_planes_lcp(seed=2)]
+    a = _scene(envs, si.SolverParams(islands=1))
+    b = _scene(envs, si.SolverParams(islands=0))
+    for s in range(3):
+        a.step(H, 100, 40, 1e-5)
+        b.step(H, 100, 40, 1e-5)
+        sa, sb = a.stats(), b.stats()
+        print("step", s, "converged", sa["converged"], sb["converged"], "newton", sa["newton_iters"],
+              sb["newton_iters"], flush=True)
+        for e in range(len(envs)):
+            if not (sa["converged"][e] and sb["converged"][e]):
+                continue
+            xa, xb = a.read_state(e), b.read_state(e)
+            for k in ("rigid_x", "particle_x"):
+                if len(xa[k]):
+                    assert np.abs(xa[k] - xb[k]).max() < 1e-4, (s, e, k)
+            for k in ("rigid_v", "particle_v"):
+                if len(xa[k]):
+                    assert np.abs(xa[k] - xb[k]).max() < 1e-3 * max(1.0, np.abs(xb[k]).max()), (s, e, k)
+            # states are copied across so the next step starts from the same state
+            b.write_state(e, a.read_state(e))
+    assert a.stats()["converged"].any()
+
+
+def test_islands_bitwise_repeatable():
+    envs = _island_kinds()
+    outs = []
+    for _ in range(2):
+        sc = _scene(envs, si.SolverParams(islands=1))
+        for _ in range(3):
+            sc.step(H, 8, 40, 0.0)
+        outs.append([sc.read_state(e) for e in range(len(envs))])
+    for e in range(len(envs)):
+        for k in outs[0][e]:
+            assert np.array_equal(outs[0][e][k], outs[1][e][k]), (e, k)
