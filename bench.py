@@ -152,6 +152,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--arms", default="zero,prev,learned")
     ap.add_argument("--islands", action="store_true", help="one PCR per island of an env (Sec. 11 option)")
+    ap.add_argument("--tets-max", type=int, default=3000, help="largest tet block of an env (0: rigid only)")
     ap.add_argument("--tet-model", choices=["neohookean", "linear"], default="neohookean",
                     help="material of the envs' tet blocks (linear: six co-rotated strain rows per tet)")
     ap.add_argument("--schedule", action="store_true", help="autotune the launch schedule first")
@@ -185,7 +186,7 @@ def main():
         return
     log(f"generating {args.envs} envs")
     tet_model = si.TET_LINEAR if args.tet_model == "linear" else si.TET_NEOHOOKEAN
-    envs = si.batched_envs(args.envs, base_seed=1000, tet_model=tet_model)
+    envs = si.batched_envs(args.envs, base_seed=1000, tet_model=tet_model, tets_max=args.tets_max)
     model_blob = None
     model_path = os.path.join(ROOT, "paper_1907_04587_amd", "weights", "warm_start_batched.npy")
     if os.path.exists(model_path):
@@ -226,7 +227,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.envs} uneven envs (5-40 boxes, 0-12 revolute joints, 0-3000 "
+        "config": {"workload": f"{args.envs} uneven envs (5-40 boxes, 0-12 revolute joints, 0-{args.tets_max} "
                                f"{'linear co-rotated' if args.tet_model == 'linear' else 'neo-Hookean'} "
                                f"tets), h=1/60, residual mode tol={args.tol}, "
                                f"{'one PCR per island, ' if args.islands else ''}"

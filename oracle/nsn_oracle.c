@@ -468,8 +468,17 @@ void orc_linear_tet(const double *Dminv, const double *x12, double E, double nu,
 /* ------------------------------------------------------------------------- */
 typedef void (*orc_apply_fn)(void *ctx, const double *in, double *out);
 
+static int pcr_solve_ref(int n, orc_apply_fn apply, void *ctx, const double *b, const double *P,
+                         int iters, double *x, double *hist, double rho_ref);
 static int pcr_solve(int n, orc_apply_fn apply, void *ctx, const double *b, const double *P,
                      int iters, double *x, double *hist) {
+  return pcr_solve_ref(n, apply, ctx, b, P, iters, x, hist, -1.0);
+}
+
+/* rho_ref >= 0: the stop level is TAU_CR * rho_ref instead of TAU_CR times the solve's
+ * own start (the island mode: the rounding level of the whole env's system). */
+static int pcr_solve_ref(int n, orc_apply_fn apply, void *ctx, const double *b, const double *P,
+                         int iters, double *x, double *hist, double rho_ref) {
   double *r = calloc(n, sizeof(double)), *z = calloc(n, sizeof(double));
   double *p = calloc(n, sizeof(double)), *q = calloc(n, sizeof(double));
   double *w = calloc(n, sizeof(double)), *s = calloc(n, sizeof(double));
@@ -479,7 +488,7 @@ static int pcr_solve(int n, orc_apply_fn apply, void *ctx, const double *b, cons
     apply(ctx, z, w);
     double rho = 0.0;
     for (int i = 0; i < n; ++i) { q[i] = w[i]; rho += z[i] * w[i]; }
-    const double rho_stop = TAU_CR * rho;
+    const double rho_stop = TAU_CR * (rho_ref >= 0.0 ? rho_ref : rho);
     for (int it = 0; it < iters; ++it) {
       if (!(rho > rho_stop) || !(rho > 0.0)) break;
       double qs = 0.0;
@@ -1848,15 +1857,24 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
     if (p->islands && p->linear == 0) {
       /* READING of Sec. 11's island remedy: one PCR per island.  A is block diagonal
        * over islands, so the PCR of the right-hand side restricted to an island stays
-       * in that island's rows; the solution is the sum of the island solutions. */
+       * in that island's rows; the solution is the sum of the island solutions.
+       * READING of the stop: an island's rounding level is that of the env's whole
+       * system, so each island stops once its <z, A z> falls to TAU_CR of the env's
+       * start <P b, A P b> (= the sum of the islands' starts), the stop of the
+       * whole-env PCR.  Relative to its own start, an ill-conditioned small island in
+       * FP32 never reaches that level and iterates on rounding with its own scalars. */
       for (int r = 0; r < S.nrows; ++r) x[r] = 0.0;
       double *bi = calloc(nr_alloc, sizeof(double)), *xi = calloc(nr_alloc, sizeof(double));
+      double rho_env = 0.0;
+      for (int r = 0; r < S.nrows; ++r) bi[r] = P[r] * b[r];
+      schur_apply(&sc, bi, xi);
+      for (int r = 0; r < S.nrows; ++r) rho_env += bi[r] * xi[r];
       for (int r0 = 0; r0 < S.nrows; ++r0) {
         int isl = row_isl[r0], first = 1;
         for (int r = 0; r < r0; ++r) if (row_isl[r] == isl) { first = 0; break; }
         if (!first) continue;
         for (int r = 0; r < S.nrows; ++r) bi[r] = row_isl[r] == isl ? b[r] : 0.0;
-        int di = pcr_solve(S.nrows, schur_apply, &sc, bi, P, M, xi, NULL);
+        int di = pcr_solve_ref(S.nrows, schur_apply, &sc, bi, P, M, xi, NULL, rho_env);
         if (di > done) done = di;
         for (int r = 0; r < S.nrows; ++r) if (row_isl[r] == isl) x[r] = xi[r];
       }

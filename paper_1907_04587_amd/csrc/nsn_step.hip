@@ -1927,19 +1927,17 @@ __device__ void island_setup(const Ctx &c, int e, int nel, Red<BS> &red) {
 }
 
 // One wave per island: its three dots summed in element order (fixed, deterministic),
-// then its scalars.  first: the start of the PCR (rho = <z,w>, <q,Pq> = <w,Pw>, stop
-// level, beta = 0); else the single-reduction recurrences of an active island.  Then
-// the check at the top of the next iteration (rho above its stop level and positive,
-// <q,Pq> positive) and alpha = rho / <q,Pq>.  Returns 1 on a lane that saw an active
-// island, else 0.
+// then its scalars.  first: the start of the PCR (rho = <z,w>, <q,Pq> = <w,Pw>,
+// beta = 0); returns the thread's part of the env's start sum of rho.  Else the
+// single-reduction recurrences of an active island, followed by island_check.
 template <int BS>
-__device__ float island_reduce(const Ctx &c, int e, bool first) {
+__device__ double island_reduce(const Ctx &c, int e, bool first) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int eb = E.jnt_off + E.tet_off + E.con_off, ib = E.rig_off + E.par_off + 2 * e;
   const int K = S.isl_n[e];
-  float any = 0.f;
+  double rho0 = 0.0;
   for (int i = w; i < K; i += BS / 64) {
     const int k = S.isl_list[ib + i];
     const int o0 = S.isl_off[ib + k], o1 = S.isl_off[ib + k + 1];
@@ -1958,22 +1956,45 @@ __device__ float island_reduce(const Ctx &c, int e, bool first) {
       if (first) {
         I.rho = d0;
         I.qs = d1;
-        I.stop = kTauCR * d0;
         I.beta = 0.f;
         I.active = 1;
+        rho0 += d0;
       } else if (I.active) {
         const double b = d0 / I.rho;
         I.qs = d1 + 2.0 * b * d2 + b * b * I.qs;
         I.beta = (float)b;
         I.rho = d0;
       }
-      if (I.active) I.active = (I.rho > I.stop) && (I.rho > 0.0) && (I.qs > 0.0);
-      if (I.active) {
-        I.alpha = (float)(I.rho / I.qs);
-        any = 1.f;
-      }
       S.isl[ib + k] = I;
     }
+  }
+  return rho0;
+}
+
+// The check at the top of every PCR iteration, per island (its owner lane): rho above
+// the stop level and positive, <q,Pq> positive; then alpha = rho / <q,Pq>.  stop >= 0:
+// first call, sets every island's stop level (READING: TAU_CR times the env's start
+// rho, the rounding level of the whole system, as in the whole-env PCR).  Returns 1 on
+// a lane that saw an active island, else 0.
+template <int BS>
+__device__ float island_check(const Ctx &c, int e, double stop) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ib = E.rig_off + E.par_off + 2 * e;
+  const int K = S.isl_n[e];
+  float any = 0.f;
+  if (lane != 0) return any;
+  for (int i = w; i < K; i += BS / 64) {
+    const int k = S.isl_list[ib + i];
+    IslState I = S.isl[ib + k];
+    if (stop >= 0.0) I.stop = stop;
+    if (I.active) I.active = (I.rho > I.stop) && (I.rho > 0.0) && (I.qs > 0.0);
+    if (I.active) {
+      I.alpha = (float)(I.rho / I.qs);
+      any = 1.f;
+    }
+    S.isl[ib + k] = I;
   }
   return any;
 }
@@ -2292,7 +2313,8 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       double dots[3] = {0.0, 0.0, 0.0};
       matvec_rows<BS, true, EXT>(c, Y, buf, nel, eps, dots, true);
       __syncthreads();
-      float any = block_max<BS>(island_reduce<BS>(c, e, true), red, 1);
+      const double rho_env = block_sum<BS>(island_reduce<BS>(c, e, true), red, 0);
+      float any = block_max<BS>(island_check<BS>(c, e, kTauCR * rho_env), red, 1);
       for (int it = 0; it < A.cr_iters; ++it) {
         if (any == 0.f) break;
         ++done;
@@ -2316,7 +2338,8 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
         __syncthreads();
         matvec_rows<BS, false, EXT>(c, Y, buf, nel, eps, dots, true);
         __syncthreads();
-        any = block_max<BS>(island_reduce<BS>(c, e, false), red, 1);
+        (void)island_reduce<BS>(c, e, false);
+        any = block_max<BS>(island_check<BS>(c, e, -1.0), red, 1);
       }
     } else {
       // Single-reduction form of the same recurrences: the matvec pass also sums
