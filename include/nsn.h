@@ -262,8 +262,21 @@ nsn_status nsn_get_env_order(nsn_scene s, int32_t *order);
  * wavefront per env).  The buckets must tile [0, n_envs) in order. */
 nsn_status nsn_set_schedule(nsn_scene s, int32_t n_buckets, const int32_t *first, const int32_t *count,
                             const int32_t *block);
+
+/* The current buckets: *n receives their number; up to cap entries are written. */
 nsn_status nsn_get_schedule(nsn_scene s, int32_t cap, int32_t *n, int32_t *first, int32_t *count,
                             int32_t *block);
+
+/* Working memory of the Newton kernel (a tuning and testing switch; results are the
+ * same in every mode, bit for bit): 0 keeps the body-space vector in global memory;
+ * 1 puts it in LDS where a bucket's envs fit; 2 (default) also puts the tets'
+ * contributions (J^T v per tet vertex) in LDS in 1024-thread buckets whose envs fit
+ * (n_dof + 12 n_tet floats within the device's LDS per workgroup).  Applies to the
+ * current and later schedules. */
+nsn_status nsn_set_lds_mode(nsn_scene s, int32_t max_mode);
+
+/* The LDS mode each current bucket runs in (0, 1, 2 as above): mode[cap]. */
+nsn_status nsn_get_lds_modes(nsn_scene s, int32_t cap, int32_t *n, int32_t *mode);
 
 /* Copy the per-env accumulators (out[n_envs], host) / reset them to zero. */
 nsn_status nsn_read_accumulators(nsn_scene s, nsn_accum *out);

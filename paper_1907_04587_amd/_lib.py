@@ -84,6 +84,8 @@ def lib():
     L.nsn_set_use_graphs.argtypes = [VP, S]
     L.nsn_get_env_order.argtypes = [VP, I32]
     L.nsn_set_schedule.argtypes = [VP, S, I32, I32, I32]
+    L.nsn_set_lds_mode.argtypes = [VP, C.c_int32]
+    L.nsn_get_lds_modes.argtypes = [VP, C.c_int32, I32, I32]
     L.nsn_get_schedule.argtypes = [VP, S, I32, I32, I32, I32]
     L.nsn_stats_device_ptr.argtypes = [VP, C.POINTER(VP)]
     L.nsn_read_kernel_times.argtypes = [VP, S, I32, D]

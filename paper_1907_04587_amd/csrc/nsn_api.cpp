@@ -199,7 +199,8 @@ struct GraphKey {
 
 struct Bucket {
   int first, count, block;
-  int lds_floats;  // body-space vector in LDS (max DOFs of the bucket), 0 = global memory
+  int lds_floats;  // dynamic LDS floats of a workgroup
+  int lds_mode;    // 0: body-space vector in global memory, 1: in LDS, 2: with the tet contributions
 };
 
 struct nsn_scene_s {
@@ -212,7 +213,7 @@ struct nsn_scene_s {
   std::vector<Bucket> buckets;
   std::map<GraphKey, hipGraphExec_t> graphs;
   bool use_graphs = true;
-  bool y_global = false;  // force the body-space vector into global memory
+  int lds_max = 2;  // the largest LDS mode the buckets may use (nsn_set_lds_mode)
   int want_features = 0;
   // side streams (default priority) for concurrent schedule buckets, and fork/join events
   std::vector<hipStream_t> side;
@@ -224,12 +225,32 @@ struct nsn_scene_s {
   }
 };
 
-// LDS for the body-space vector of each bucket: the largest env DOF count, if it fits
+// LDS of each bucket.  1024-thread buckets (one workgroup per CU) also hold the tets'
+// contributions when every env's fit (mode 2); other buckets keep the body-space vector
+// there (mode 1), which leaves their occupancy to the registers.
 static void set_bucket_lds(nsn_scene s) {
+  int dev = 0, max_bytes = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&max_bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    max_bytes = 0;
+  // room for the kernel's static LDS (the block reductions, < 1 KB)
+  const int max_cl = std::min(kMaxLdsFloatsCl, (max_bytes - 2048) / 4);
   for (Bucket &b : s->buckets) {
-    int mx = 0;
-    for (int i = b.first; i < b.first + b.count; ++i) mx = std::max(mx, s->env[s->order[i]].n_dof);
-    b.lds_floats = (mx > 0 && mx <= kMaxLdsFloats && !s->y_global) ? mx : 0;
+    int mx = 0, mx_cl = 0;
+    for (int i = b.first; i < b.first + b.count; ++i) {
+      const EnvInfo &E = s->env[s->order[i]];
+      mx = std::max(mx, E.n_dof);
+      mx_cl = std::max(mx_cl, ((E.n_dof + 3) & ~3) + 12 * E.n_tet);
+    }
+    b.lds_mode = 0;
+    b.lds_floats = 0;
+    if (s->lds_max >= 2 && b.block == 1024 && mx_cl > 0 && mx_cl <= max_cl) {
+      b.lds_mode = 2;
+      b.lds_floats = mx_cl;
+    } else if (s->lds_max >= 1 && mx > 0 && mx <= kMaxLdsFloats) {
+      b.lds_mode = 1;
+      b.lds_floats = mx;
+    }
   }
 }
 
@@ -538,7 +559,7 @@ static hipError_t enqueue_step(nsn_scene s, const StepArgs &a) {
   const size_t nb = s->buckets.size();
   if (s->stream == nullptr || nb == 1) {
     for (const Bucket &b : s->buckets) {
-      e = launch_newton(s->S, a, b.block, b.first, b.count, b.lds_floats, s->stream);
+      e = launch_newton(s->S, a, b.block, b.first, b.count, b.lds_floats, b.lds_mode, s->stream);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -553,7 +574,8 @@ static hipError_t enqueue_step(nsn_scene s, const StepArgs &a) {
   }
   for (size_t i = 0; i < nb; ++i) {
     const Bucket &b = s->buckets[i];
-    e = launch_newton(s->S, a, b.block, b.first, b.count, b.lds_floats, i == 0 ? s->stream : s->side[i - 1]);
+    e = launch_newton(s->S, a, b.block, b.first, b.count, b.lds_floats, b.lds_mode,
+                      i == 0 ? s->stream : s->side[i - 1]);
     if (e != hipSuccess) return e;
   }
   for (size_t i = 1; i < nb; ++i) {
@@ -816,11 +838,20 @@ nsn_status nsn_set_schedule(nsn_scene s, int32_t n_buckets, const int32_t *first
     if (first[i] != expect || count[i] < 0) return fail(NSN_EINVAL, "schedule buckets must tile the env order");
     const int bl = block[i];
     if (bl != 64 && bl != 128 && bl != 256 && bl != 512 && bl != 1024) return fail(NSN_EINVAL, "block size must be 64..1024 (power of two)");
-    b.push_back(Bucket{first[i], count[i], bl, 0});
+    b.push_back(Bucket{first[i], count[i], bl, 0, 0});
     expect += count[i];
   }
   if (expect != s->S.n_envs) return fail(NSN_EINVAL, "schedule must cover every env");
   s->buckets = b;
+  set_bucket_lds(s);
+  for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+  s->graphs.clear();
+  return NSN_OK;
+}
+
+nsn_status nsn_set_lds_mode(nsn_scene s, int32_t max_mode) {
+  if (!s || max_mode < 0 || max_mode > 2) return fail(NSN_EINVAL, "LDS mode must be 0, 1 or 2");
+  s->lds_max = max_mode;
   set_bucket_lds(s);
   for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
   s->graphs.clear();
@@ -835,6 +866,13 @@ nsn_status nsn_get_schedule(nsn_scene s, int32_t cap, int32_t *n, int32_t *first
     count[i] = s->buckets[i].count;
     block[i] = s->buckets[i].block;
   }
+  return NSN_OK;
+}
+
+nsn_status nsn_get_lds_modes(nsn_scene s, int32_t cap, int32_t *n, int32_t *mode) {
+  if (!s || !n || (cap > 0 && !mode)) return fail(NSN_EINVAL, "bad arguments");
+  *n = (int)s->buckets.size();
+  for (int i = 0; i < std::min<int>(cap, *n); ++i) mode[i] = s->buckets[i].lds_mode;
   return NSN_OK;
 }
 

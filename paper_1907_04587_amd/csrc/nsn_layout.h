@@ -163,14 +163,17 @@ struct StepArgs {
 
 // kernel launchers (nsn_step.hip)
 hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_features, hipStream_t st);
-// envs S.env_order[first .. first+count) with `block` threads per workgroup; the
-// body-space vector lives in `lds_floats` floats of dynamic LDS (0: global memory)
+// envs S.env_order[first .. first+count) with `block` threads per workgroup;
+// lds_mode 0: the body-space vector in global memory; 1: in `lds_floats` floats of
+// dynamic LDS; 2 (block 1024 only): in LDS together with the tets' contributions
+// (align4(n_dof) + 12 n_tet floats per env)
 hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
-                         hipStream_t st);
+                         int lds_mode, hipStream_t st);
 // the same for the extended instantiation (linear tets, islands; nsn_step_ext.hip)
 hipError_t launch_newton_ext(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
-                             hipStream_t st);
+                             int lds_mode, hipStream_t st);
 constexpr int kMaxLdsFloats = 24 * 1024;  // 96 KB of LDS for the body-space vector
+constexpr int kMaxLdsFloatsCl = 39 * 1024;  // 156 KB: body-space vector + tet contributions (mode 2)
 // learned warm start: MLP prediction for every contact of every env (nsn_mlp.hip)
 hipError_t launch_warm_mlp(const DevScene &s, hipStream_t st);
 

@@ -277,6 +277,10 @@ struct Ctx {
   DevScene S;
   EnvInfo E;
   StepArgs A;
+  // LDS mode 2: the tets' J^T v contributions of the env in LDS (three float arrays of
+  // cl_n entries, indexed by particle-list position - cl_base) instead of p_cj
+  float *cl = nullptr;
+  int cl_base = 0, cl_n = 0;
 };
 
 // world position of a body-fixed point (env-local body id; -1 = world / ground)
@@ -863,6 +867,26 @@ __device__ void assemble_joint(const Ctx &c, int jl, double tplus) {
 // vertex j = 1..3: (R_:a (D_m^-1)_jb + R_:b (D_m^-1)_ja) / 2, vertex 0 minus their sum.
 constexpr int kLinA[6] = {0, 1, 2, 1, 0, 0}, kLinB[6] = {0, 1, 2, 2, 2, 1};
 
+// the four vertex contributions of a tet, at their particle-list positions dst
+__device__ __forceinline__ void store_tet_cj(const Ctx &c, int4 dst, V3 a0, V3 a1, V3 a2, V3 a3) {
+  if (c.cl) {
+    float *cx = c.cl, *cy = cx + c.cl_n, *cz = cy + c.cl_n;
+    const int i[4] = {dst.x - c.cl_base, dst.y - c.cl_base, dst.z - c.cl_base, dst.w - c.cl_base};
+    const V3 v[4] = {a0, a1, a2, a3};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      cx[i[m]] = v[m].x;
+      cy[i[m]] = v[m].y;
+      cz[i[m]] = v[m].z;
+    }
+    return;
+  }
+  c.S.p_cj[dst.x] = f4(a0, 0.f);
+  c.S.p_cj[dst.y] = f4(a1, 0.f);
+  c.S.p_cj[dst.z] = f4(a2, 0.f);
+  c.S.p_cj[dst.w] = f4(a3, 0.f);
+}
+
 __device__ __forceinline__ void ltet_load(const DevScene &S, int buf, int tg, float R[9], float B[9]) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) R[k] = tJ(S, buf, k, tg);
@@ -981,11 +1005,7 @@ __device__ __forceinline__ void ltet_contrib(const Ctx &c, int tl, const float z
               M[3] * B[3 * j] + M[4] * B[3 * j + 1] + M[5] * B[3 * j + 2],
               M[6] * B[3 * j] + M[7] * B[3 * j + 1] + M[8] * B[3 * j + 2]);
   const V3 a0 = mk(0.f, 0.f, 0.f) - (a[0] + a[1] + a[2]);
-  const int4 dst = S.t_dst[tg];
-  S.p_cj[dst.x] = f4(a0, 0.f);
-  S.p_cj[dst.y] = f4(a[0], 0.f);
-  S.p_cj[dst.z] = f4(a[1], 0.f);
-  S.p_cj[dst.w] = f4(a[2], 0.f);
+  store_tet_cj(c, S.t_dst[tg], a0, a[0], a[1], a[2]);
 }
 
 // J_i H~^-1 J_i^T of the 6 rows of a linear tet
@@ -1230,11 +1250,7 @@ __device__ __forceinline__ void tet_contrib(const Ctx &c, int tl, const float z[
     a0 = a0 - (w0 + w1 + w2) * zu;
   }
   // straight into the particles' adjacency order (positions fixed at scene creation)
-  const int4 dst = S.t_dst[tg];
-  S.p_cj[dst.x] = f4(a0, 0.f);
-  S.p_cj[dst.y] = f4(a1, 0.f);
-  S.p_cj[dst.z] = f4(a2, 0.f);
-  S.p_cj[dst.w] = f4(a3, 0.f);
+  store_tet_cj(c, S.t_dst[tg], a0, a1, a2, a3);
 }
 
 __device__ __forceinline__ void acc_wrench(float out[6], V3 d, V3 arm, float sgn) {
@@ -1295,6 +1311,13 @@ __device__ __forceinline__ V3 gather_particle(const Ctx &c, int p) {
   V3 acc = mk(0.f, 0.f, 0.f);
   const int k0 = S.p_tadj_ptr[p], k1 = S.p_tadj_ptr[p + 1];
   int k = k0;
+  if (c.cl) {  // the same sums in the same order, from LDS
+    const float *cx = c.cl, *cy = cx + c.cl_n, *cz = cy + c.cl_n;
+    for (; k < k1; ++k) {
+      const int i = k - c.cl_base;
+      acc = acc + mk(cx[i], cy[i], cz[i]);
+    }
+  }
   for (; k + 8 <= k1; k += 8) {
     float4 v[8];
 #pragma unroll
@@ -2002,7 +2025,9 @@ __device__ float island_check(const Ctx &c, int e, double stop) {
 // --------------------------------------------------------------------------
 // Kernel 3: start iterate + Newton loop + write-back.  One workgroup per env.
 // --------------------------------------------------------------------------
-template <int BS, bool YLDS, bool EXT>
+// LM: 0 body-space vector in global memory, 1 in LDS, 2 in LDS together with the tets'
+// contributions (the largest envs at 1024 threads, one workgroup per CU anyway)
+template <int BS, int LM, bool EXT>
 __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first) {
   __shared__ Red<BS> red;
   extern __shared__ float y_lds[];
@@ -2027,7 +2052,12 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
   const int crow0 = row_con(E, 0);
   const double tplus = S.time[e] + (double)h;
   // env-local body-space vector: in LDS when the bucket's envs fit, else in global memory
-  float *Y = YLDS ? y_lds : S.y + E.dof_off;
+  float *Y = LM > 0 ? y_lds : S.y + E.dof_off;
+  if (LM == 2) {
+    c.cl = y_lds + ((E.n_dof + 3) & ~3);
+    c.cl_base = S.p_tadj_ptr[E.par_off];
+    c.cl_n = 4 * E.n_tet;
+  }
 
   // ---- start iterate (Sec. 8.1); READING for warm starts: projected lambda0 for
   //      contacts, the previous multipliers for joints, the start-configuration
@@ -2510,14 +2540,21 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
 // in scratch memory.  The default instantiation keeps the default budget.
 // --------------------------------------------------------------------------
 template <int BS, bool EXT>
-static void launch_bs(const DevScene &s, const StepArgs &a, int first, int count, int lds_floats, hipStream_t st) {
-  if (lds_floats > 16384)
-    (void)hipFuncSetAttribute((const void *)k_newton<BS, true, EXT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)sizeof(float) * lds_floats);
-  if (lds_floats > 0)
-    hipLaunchKernelGGL((k_newton<BS, true, EXT>), dim3(count), dim3(BS), sizeof(float) * lds_floats, st, s, a, first);
-  else
-    hipLaunchKernelGGL((k_newton<BS, false, EXT>), dim3(count), dim3(BS), 0, st, s, a, first);
+static void launch_bs(const DevScene &s, const StepArgs &a, int first, int count, int lds_floats, int lds_mode,
+                      hipStream_t st) {
+  const size_t bytes = sizeof(float) * (size_t)lds_floats;
+  if (lds_mode == 2 && BS == 1024) {
+    (void)hipFuncSetAttribute((const void *)k_newton<1024, 2, EXT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+    hipLaunchKernelGGL((k_newton<1024, 2, EXT>), dim3(count), dim3(1024), bytes, st, s, a, first);
+  } else if (lds_mode >= 1) {
+    if (lds_floats > 16384)
+      (void)hipFuncSetAttribute((const void *)k_newton<BS, 1, EXT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bytes);
+    hipLaunchKernelGGL((k_newton<BS, 1, EXT>), dim3(count), dim3(BS), bytes, st, s, a, first);
+  } else {
+    hipLaunchKernelGGL((k_newton<BS, 0, EXT>), dim3(count), dim3(BS), 0, st, s, a, first);
+  }
 }
 
 #ifdef NSN_STEP_EXT_TU
@@ -2527,13 +2564,13 @@ constexpr bool kExtTU = false;
 #endif
 
 static hipError_t launch_tu(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
-                            hipStream_t st) {
+                            int lds_mode, hipStream_t st) {
   switch (block) {
-    case 64: launch_bs<64, kExtTU>(s, a, first, count, lds_floats, st); break;
-    case 128: launch_bs<128, kExtTU>(s, a, first, count, lds_floats, st); break;
-    case 256: launch_bs<256, kExtTU>(s, a, first, count, lds_floats, st); break;
-    case 512: launch_bs<512, kExtTU>(s, a, first, count, lds_floats, st); break;
-    case 1024: launch_bs<1024, kExtTU>(s, a, first, count, lds_floats, st); break;
+    case 64: launch_bs<64, kExtTU>(s, a, first, count, lds_floats, lds_mode, st); break;
+    case 128: launch_bs<128, kExtTU>(s, a, first, count, lds_floats, lds_mode, st); break;
+    case 256: launch_bs<256, kExtTU>(s, a, first, count, lds_floats, lds_mode, st); break;
+    case 512: launch_bs<512, kExtTU>(s, a, first, count, lds_floats, lds_mode, st); break;
+    case 1024: launch_bs<1024, kExtTU>(s, a, first, count, lds_floats, lds_mode, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -2541,8 +2578,8 @@ static hipError_t launch_tu(const DevScene &s, const StepArgs &a, int block, int
 
 #ifdef NSN_STEP_EXT_TU
 hipError_t launch_newton_ext(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
-                             hipStream_t st) {
-  return launch_tu(s, a, block, first, count, lds_floats, st);
+                             int lds_mode, hipStream_t st) {
+  return launch_tu(s, a, block, first, count, lds_floats, lds_mode, st);
 }
 #else
 hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_features, hipStream_t st) {
@@ -2551,11 +2588,11 @@ hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_feature
 }
 
 hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
-                         hipStream_t st) {
+                         int lds_mode, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   if (s.any_linear || (a.p.islands && a.p.linear == NSN_LINEAR_PCR))
-    return launch_newton_ext(s, a, block, first, count, lds_floats, st);
-  return launch_tu(s, a, block, first, count, lds_floats, st);
+    return launch_newton_ext(s, a, block, first, count, lds_floats, lds_mode, st);
+  return launch_tu(s, a, block, first, count, lds_floats, lds_mode, st);
 }
 #endif
 

@@ -196,6 +196,19 @@ class Scene:
         L.check(self.lib.nsn_set_schedule(self.h, len(buckets), L.iptr(first), L.iptr(count), L.iptr(block)),
                 "nsn_set_schedule")
 
+    def set_lds_mode(self, max_mode):
+        """0: body-space vector in global memory; 1: in LDS; 2: with the tets'
+        contributions in LDS in 1024-thread buckets (default).  Same results."""
+        L.check(self.lib.nsn_set_lds_mode(self.h, int(max_mode)), "nsn_set_lds_mode")
+
+    def lds_modes(self):
+        """LDS mode of every current bucket."""
+        cap = 64
+        n = C.c_int32(0)
+        m = np.zeros(cap, np.int32)
+        L.check(self.lib.nsn_get_lds_modes(self.h, cap, C.byref(n), L.iptr(m)), "nsn_get_lds_modes")
+        return [int(v) for v in m[:n.value]]
+
     def schedule(self):
         cap = 64
         n = C.c_int32(0)

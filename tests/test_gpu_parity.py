@@ -252,3 +252,29 @@ def test_write_read_state_roundtrip_and_resume():
     for k in s1:
         if k != "time":
             assert np.array_equal(sc2.read_state(0)[k], s1[k]), k
+
+
+@pytest.mark.parametrize("ext", [False, True])
+def test_lds_modes_bitwise_equal(ext):
+    """The tets' contributions in LDS (mode 2, 1024-thread buckets), the body-space
+    vector alone in LDS (1) and everything in global memory (0) sum the same terms in
+    the same order: identical states.  ext: linear tets and islands (the extended
+    kernel)."""
+    envs = [si.batched_env(seed=2100 + i, tets_max=600) for i in range(4)]
+    if ext:
+        envs += [si.tet_block_with_boxes(seed=1, cells=3, n_boxes=3, tet_model=si.TET_LINEAR)]
+    p = si.SolverParams(islands=1 if ext else 0)
+    out = []
+    for mode in [2, 1, 0]:
+        sc = _scene(envs, p)
+        sc.set_schedule([(0, len(envs), 1024)])
+        sc.set_lds_mode(mode)
+        assert sc.lds_modes() == [mode], (mode, sc.lds_modes())
+        for _ in range(3):
+            sc.step(H, 6, 30, 0.0)
+        out.append([sc.read_state(e) for e in range(len(envs))])
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            for k in a:
+                if k != "time":
+                    assert np.array_equal(a[k], b[k]), k
