@@ -64,7 +64,7 @@ def oracle_sensitivity(desc, pre, op, h, N, M, tol, trials=3, L_scene=1.0, prev=
 
 
 def lockstep(scene, envs, params, h, N, M, tol=0.0, steps=1, env_ids=None, check_contacts=True,
-             err_tol=1e-4, L_scene=1.0, sens_factor=None, prev_from_gpu=False):
+             err_tol=1e-4, L_scene=1.0, sens_factor=None, prev_from_gpu=False, sens_trials=3):
     """Step the GPU scene `steps` times; before each step copy every checked env's
     state into a fresh oracle env and step it too; compare after each step.
 
@@ -75,6 +75,8 @@ def lockstep(scene, envs, params, h, N, M, tol=0.0, steps=1, env_ids=None, check
     than the problem's own conditioning; elsewhere err_tol applies unchanged.
     prev_from_gpu: from the second step on, the oracle's previous-step multipliers
     (the warm start's input) are the GPU's, so both sides start from the same lambda0.
+    sens_trials: perturbed oracle runs per estimate (more trials, a larger and less
+    state-dependent estimate of the spread).
     Returns the list of per-step dicts {field: (worst error, its env, its tolerance)}."""
     if env_ids is None:
         env_ids = list(range(len(envs)))
@@ -110,7 +112,8 @@ def lockstep(scene, envs, params, h, N, M, tol=0.0, steps=1, env_ids=None, check
             err["stats_orc"] = ost
             tols = {k: err_tol for k in err}
             if sens_factor is not None:
-                sens = oracle_sensitivity(envs[e], pre[e], op, h, N, M, tol, L_scene=L_scene, prev=prev.get(e))
+                sens = oracle_sensitivity(envs[e], pre[e], op, h, N, M, tol, trials=sens_trials, L_scene=L_scene,
+                                          prev=prev.get(e))
                 # by group: a rounding-level branch flip (a kink of the NCP function, a
                 # friction mode) lands in linear or angular velocity depending on geometry
                 for group in [("rigid_v", "rigid_w", "particle_v"), ("rigid_x", "rigid_q", "particle_x")]:
