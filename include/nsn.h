@@ -270,7 +270,8 @@ nsn_status nsn_get_schedule(nsn_scene s, int32_t cap, int32_t *n, int32_t *first
 /* Working memory of the Newton kernel (a tuning and testing switch; results are the
  * same in every mode, bit for bit): 0 keeps the body-space vector in global memory;
  * 1 puts it in LDS where a bucket's envs fit; 2 (default) also puts the tets'
- * contributions (J^T v per tet vertex) in LDS in 1024-thread buckets whose envs fit
+ * contributions (J^T v per tet vertex) in LDS in 512- and 1024-thread buckets (one
+ * workgroup per CU) whose envs fit
  * (n_dof + 12 n_tet floats within the device's LDS per workgroup).  Applies to the
  * current and later schedules. */
 nsn_status nsn_set_lds_mode(nsn_scene s, int32_t max_mode);

@@ -225,9 +225,10 @@ struct nsn_scene_s {
   }
 };
 
-// LDS of each bucket.  1024-thread buckets (one workgroup per CU) also hold the tets'
-// contributions when every env's fit (mode 2); other buckets keep the body-space vector
-// there (mode 1), which leaves their occupancy to the registers.
+// LDS of each bucket.  512- and 1024-thread buckets (one workgroup per CU at the
+// kernel's register use) also hold the tets' contributions when every env's fit
+// (mode 2); smaller buckets keep the body-space vector there (mode 1), which leaves
+// their occupancy to the registers.
 static void set_bucket_lds(nsn_scene s) {
   int dev = 0, max_bytes = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -244,7 +245,7 @@ static void set_bucket_lds(nsn_scene s) {
     }
     b.lds_mode = 0;
     b.lds_floats = 0;
-    if (s->lds_max >= 2 && b.block == 1024 && mx_cl > 0 && mx_cl <= max_cl) {
+    if (s->lds_max >= 2 && b.block >= 512 && mx_cl > 0 && mx_cl <= max_cl) {
       b.lds_mode = 2;
       b.lds_floats = mx_cl;
     } else if (s->lds_max >= 1 && mx > 0 && mx <= kMaxLdsFloats) {
@@ -491,14 +492,15 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
     d.joint_type = d.joint_body = nullptr;
     d.joint_anchor = d.joint_axis = d.joint_ref = d.joint_drive = nullptr;
   }
-  // default schedule.  Large batches: the heavier three quarters of the envs (launch
-  // order is by decreasing work) with 1024 threads each, their tet contributions in LDS,
-  // the lightest quarter with 128 (measured best on the uneven 4096-env batch: 1209 ms
-  // per step against 1221 for halves and 1243 for a single 1024-thread launch).
-  // Otherwise one launch with the block size from the largest env.
+  // default schedule.  Large batches, in launch order (decreasing work): the heaviest
+  // 3/8 of the envs with 1024 threads each, the next 3/8 with 512 (both with their tet
+  // contributions in LDS), the lightest quarter with 128 (measured best on the uneven
+  // 4096-env batch: 1195 ms per step against 1209 for 3/4 at 1024, 1221 for halves and
+  // 1243 for a single 1024-thread launch).  Otherwise one launch with the block size
+  // from the largest env.
   if (n_envs >= 1024) {
-    const int heavy = 3 * (n_envs / 4);
-    s->buckets = {Bucket{0, heavy, 1024, 0}, Bucket{heavy, n_envs - heavy, 128, 0}};
+    const int a1 = 3 * (n_envs / 8), a2 = 3 * (n_envs / 4);
+    s->buckets = {Bucket{0, a1, 1024, 0}, Bucket{a1, a2 - a1, 512, 0}, Bucket{a2, n_envs - a2, 128, 0}};
   } else {
     int max_el = 0;
     for (auto &E : env) max_el = std::max(max_el, E.n_jnt + E.n_tet + E.max_con + E.n_rig + E.n_par);
