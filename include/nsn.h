@@ -270,9 +270,10 @@ nsn_status nsn_get_schedule(nsn_scene s, int32_t cap, int32_t *n, int32_t *first
 /* Working memory of the Newton kernel (a tuning and testing switch; results are the
  * same in every mode, bit for bit): 0 keeps the body-space vector in global memory;
  * 1 puts it in LDS where a bucket's envs fit; 2 (default) also puts the tets'
- * contributions (J^T v per tet vertex) in LDS in 512- and 1024-thread buckets (one
- * workgroup per CU) whose envs fit
- * (n_dof + 12 n_tet floats within the device's LDS per workgroup).  Applies to the
+ * contributions (J^T v per tet vertex) in LDS in buckets whose envs fit: n_dof +
+ * 12 n_tet floats within the LDS share of a workgroup at the kernel's register-limited
+ * occupancy (all of the device's LDS per workgroup at 512 and 1024 threads, half at
+ * 256, a quarter at 128).  Applies to the
  * current and later schedules. */
 nsn_status nsn_set_lds_mode(nsn_scene s, int32_t max_mode);
 

@@ -225,10 +225,10 @@ struct nsn_scene_s {
   }
 };
 
-// LDS of each bucket.  512- and 1024-thread buckets (one workgroup per CU at the
-// kernel's register use) also hold the tets' contributions when every env's fit
-// (mode 2); smaller buckets keep the body-space vector there (mode 1), which leaves
-// their occupancy to the registers.
+// LDS of each bucket: the body-space vector and the tets' contributions (mode 2) when
+// every env's fit in the LDS share that keeps the register-limited occupancy (one
+// workgroup per CU at 512 and 1024 threads, two at 256, four at 128); else the
+// body-space vector alone (mode 1) when it fits.
 static void set_bucket_lds(nsn_scene s) {
   int dev = 0, max_bytes = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -245,7 +245,10 @@ static void set_bucket_lds(nsn_scene s) {
     }
     b.lds_mode = 0;
     b.lds_floats = 0;
-    if (s->lds_max >= 2 && b.block >= 512 && mx_cl > 0 && mx_cl <= max_cl) {
+    // workgroups per CU at the kernel's register use (8 waves per CU): the LDS share
+    // that keeps them resident
+    const int per_cu = std::max(1, 512 / b.block);
+    if (s->lds_max >= 2 && b.block >= 128 && mx_cl > 0 && mx_cl <= max_cl / per_cu) {
       b.lds_mode = 2;
       b.lds_floats = mx_cl;
     } else if (s->lds_max >= 1 && mx > 0 && mx <= kMaxLdsFloats) {
@@ -493,10 +496,9 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
     d.joint_anchor = d.joint_axis = d.joint_ref = d.joint_drive = nullptr;
   }
   // default schedule.  Large batches, in launch order (decreasing work): the heaviest
-  // 3/8 of the envs with 1024 threads each, the next 3/8 with 512 (both with their tet
-  // contributions in LDS), the lightest quarter with 128 (measured best on the uneven
-  // 4096-env batch: 1195 ms per step against 1209 for 3/4 at 1024, 1221 for halves and
-  // 1243 for a single 1024-thread launch).  Otherwise one launch with the block size
+  // 3/8 of the envs with 1024 threads each, the next 3/8 with 512, the lightest quarter
+  // with 128 (measured best on the uneven 4096-env batch: 1185 ms per step against
+  // 1191 with 1/2 at 512 and 1/8 at 128, and 1206 with the light quarter at 256).  Otherwise one launch with the block size
   // from the largest env.
   if (n_envs >= 1024) {
     const int a1 = 3 * (n_envs / 8), a2 = 3 * (n_envs / 4);

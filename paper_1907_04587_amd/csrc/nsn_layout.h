@@ -165,7 +165,7 @@ struct StepArgs {
 hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_features, hipStream_t st);
 // envs S.env_order[first .. first+count) with `block` threads per workgroup;
 // lds_mode 0: the body-space vector in global memory; 1: in `lds_floats` floats of
-// dynamic LDS; 2 (blocks 512 and 1024): in LDS together with the tets' contributions
+// dynamic LDS; 2: in LDS together with the tets' contributions
 // (align4(n_dof) + 12 n_tet floats per env)
 hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
                          int lds_mode, hipStream_t st);

@@ -2026,7 +2026,7 @@ __device__ float island_check(const Ctx &c, int e, double stop) {
 // Kernel 3: start iterate + Newton loop + write-back.  One workgroup per env.
 // --------------------------------------------------------------------------
 // LM: 0 body-space vector in global memory, 1 in LDS, 2 in LDS together with the tets'
-// contributions (512 and 1024 threads: one workgroup per CU anyway)
+// contributions
 template <int BS, int LM, bool EXT>
 __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first) {
   __shared__ Red<BS> red;
@@ -2543,10 +2543,11 @@ template <int BS, bool EXT>
 static void launch_bs(const DevScene &s, const StepArgs &a, int first, int count, int lds_floats, int lds_mode,
                       hipStream_t st) {
   const size_t bytes = sizeof(float) * (size_t)lds_floats;
-  if (lds_mode == 2 && BS >= 512) {
-    constexpr int B2 = BS >= 512 ? BS : 512;  // mode 2 only at 512 and 1024 threads
-    (void)hipFuncSetAttribute((const void *)k_newton<B2, 2, EXT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)bytes);
+  if (lds_mode == 2 && BS >= 128) {
+    constexpr int B2 = BS >= 128 ? BS : 128;  // mode 2 from 128 threads up
+    if (lds_floats > 16384)
+      (void)hipFuncSetAttribute((const void *)k_newton<B2, 2, EXT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bytes);
     hipLaunchKernelGGL((k_newton<B2, 2, EXT>), dim3(count), dim3(B2), bytes, st, s, a, first);
   } else if (lds_mode >= 1) {
     if (lds_floats > 16384)

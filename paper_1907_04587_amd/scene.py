@@ -198,7 +198,7 @@ class Scene:
 
     def set_lds_mode(self, max_mode):
         """0: body-space vector in global memory; 1: in LDS; 2: with the tets'
-        contributions in LDS in 512- and 1024-thread buckets (default).  Same results."""
+        contributions in LDS where they fit (default).  Same results."""
         L.check(self.lib.nsn_set_lds_mode(self.h, int(max_mode)), "nsn_set_lds_mode")
 
     def lds_modes(self):

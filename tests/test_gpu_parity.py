@@ -254,12 +254,12 @@ def test_write_read_state_roundtrip_and_resume():
             assert np.array_equal(sc2.read_state(0)[k], s1[k]), k
 
 
-@pytest.mark.parametrize("block", [1024, 512])
+@pytest.mark.parametrize("block", [1024, 512, 128])
 @pytest.mark.parametrize("ext", [False, True])
 def test_lds_modes_bitwise_equal(ext, block):
-    """The tets' contributions in LDS (mode 2, 512- and 1024-thread buckets), the
-    body-space vector alone in LDS (1) and everything in global memory (0) sum the same
-    terms in the same order: identical states.  ext: linear tets and islands (the
+    """The tets' contributions in LDS (mode 2), the body-space vector alone in LDS (1)
+    and everything in global memory (0) sum the same terms in the same order:
+    identical states.  ext: linear tets and islands (the
     extended kernel)."""
     envs = [si.batched_env(seed=2100 + i, tets_max=600) for i in range(4)]
     if ext:
