@@ -164,9 +164,9 @@ def main():
                          "scaling the HBM byte counters of a profiler")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: environments are independent and each GPU would "
-              "step its own share of the batch with no communication (see DESIGN.md); "
-              "run with --gpus 1.", file=sys.stderr)
+        print("bench.py runs on one GPU only: environments are independent, so each GPU would "
+              "step its own share of the batch in its own workspace with no per-step "
+              "communication; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
