@@ -1563,7 +1563,7 @@ static void uf_union(int *par, int a, int b) {
 }
 static int body_dynamic(const env_t *e, int b) { return b >= 0 && (b >= e->nr || !is_static_rigid(e, b)); }
 
-static void row_islands(const env_t *e, int *row_isl) {
+static void row_islands(const env_t *e, int *row_isl, int *body_isl) {
   int nb = e->nr + e->np;
   int *par = malloc((nb + 1) * sizeof(int));
   for (int i = 0; i <= nb; ++i) par[i] = i;
@@ -1591,6 +1591,7 @@ static void row_islands(const env_t *e, int *row_isl) {
     int isl = uf_find(par, e->nr + e->tid[4 * t]);
     for (int r = 0; r < e->tet_rows; ++r) row_isl[row_tet(e, t) + r] = isl;
   }
+  for (int b = 0; b < nb; ++b) body_isl[b] = body_dynamic(e, b) ? uf_find(par, b) : -1;
   free(par);
 }
 
@@ -1741,7 +1742,9 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
   double *b = calloc(nr_alloc, sizeof(double)), *P = calloc(nr_alloc, sizeof(double));
   double *x = calloc(nr_alloc, sizeof(double)), *du = calloc(nd, sizeof(double));
   int *row_isl = calloc(nr_alloc, sizeof(int));
-  if (p->islands) row_islands(e, row_isl);
+  int *body_isl = calloc(e->nr + e->np + 1, sizeof(int));
+  double *isl_r = calloc(e->nr + e->np + 1, sizeof(double));  /* residual of every island */
+  if (p->islands) row_islands(e, row_isl, body_isl);
 
   int newton_done = 0, cr_total = 0;
   double r_ncp = 0, r_con = 0, merit = 0;
@@ -1819,6 +1822,16 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
     r_con = rc;
     merit = sqrt(m2);
     if (k == 0) st->r_ncp_first = r_ncp;
+    if (p->islands) {
+      /* the same residual per island (its bodies' DOFs and its rows) */
+      for (int i = 0; i <= e->nr + e->np; ++i) isl_r[i] = 0.0;
+      for (int i = 0; i < S.ndof; ++i) {
+        int b = i < 6 * e->nr ? i / 6 : e->nr + (i - 6 * e->nr) / 3;
+        if (body_isl[b] >= 0 && fabs(tmp[i]) > isl_r[body_isl[b]]) isl_r[body_isl[b]] = fabs(tmp[i]);
+      }
+      for (int r = 0; r < S.nrows; ++r)
+        if (fabs(S.err[r]) > isl_r[row_isl[r]]) isl_r[row_isl[r]] = fabs(S.err[r]);
+    }
     int finite_now = r_ncp == r_ncp && !isinf(r_ncp) && merit == merit && !isinf(merit);
     if (p->line_search && k > 0 && ls_t > LS_TMIN && (!finite_now || merit > (1.0 - LS_SIGMA * ls_t) * merit_k)) {
       ls_t *= 0.5;
@@ -1862,7 +1875,11 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
        * system, so each island stops once its <z, A z> falls to TAU_CR of the env's
        * start <P b, A P b> (= the sum of the islands' starts), the stop of the
        * whole-env PCR.  Relative to its own start, an ill-conditioned small island in
-       * FP32 never reaches that level and iterates on rounding with its own scalars. */
+       * FP32 never reaches that level and iterates on rounding with its own scalars.
+       * READING of the early exit: in residual mode (tol > 0) an island whose own
+       * residual is at or below tol is solved already: it skips its PCR and keeps its
+       * multipliers and velocities (Delta lambda = 0, Delta u = 0); the env's iteration
+       * still ends when every island is. */
       for (int r = 0; r < S.nrows; ++r) x[r] = 0.0;
       double *bi = calloc(nr_alloc, sizeof(double)), *xi = calloc(nr_alloc, sizeof(double));
       double rho_env = 0.0;
@@ -1873,6 +1890,7 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
         int isl = row_isl[r0], first = 1;
         for (int r = 0; r < r0; ++r) if (row_isl[r] == isl) { first = 0; break; }
         if (!first) continue;
+        if (tol > 0.0 && isl_r[isl] <= tol) continue;
         for (int r = 0; r < S.nrows; ++r) bi[r] = row_isl[r] == isl ? b[r] : 0.0;
         int di = pcr_solve_ref(S.nrows, schur_apply, &sc, bi, P, M, xi, NULL, rho_env);
         if (di > done) done = di;
@@ -1889,6 +1907,11 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
     for (int r = 0; r < S.nrows; ++r) jrow_scatter(&S.J[r], x[r], f);
     for (int i = 0; i < S.ndof; ++i) tmp2[i] = h * f[i] - g[i];
     apply_Hinv(&S, tmp2, du);
+    if (p->islands && p->linear == 0 && tol > 0.0)  /* a solved island keeps its velocities */
+      for (int i = 0; i < S.ndof; ++i) {
+        int bb = i < 6 * e->nr ? i / 6 : e->nr + (i - 6 * e->nr) / 3;
+        if (body_isl[bb] >= 0 && isl_r[body_isl[bb]] <= tol) du[i] = 0.0;
+      }
     memcpy(S.uprev, S.u, S.ndof * sizeof(double));
     memcpy(S.Jprev, S.J, S.nrows * sizeof(jrow));
     S.have_prev = 1;
@@ -1960,7 +1983,7 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
   free(S.x0); free(S.q0); free(S.px0); free(S.Iw); free(S.Iwinv); free(S.ut); free(S.u); free(S.uprev);
   free(S.Hdiag); free(S.theta_minus); free(S.lam); free(S.J); free(S.Jprev); free(S.err); free(S.Cblk);
   free(S.blk_start); free(S.blk_size); free(S.row_kind);
-  free(g); free(f); free(fhat); free(tmp); free(tmp2); free(b); free(P); free(x); free(du); free(row_isl);
+  free(g); free(f); free(fhat); free(tmp); free(tmp2); free(b); free(P); free(x); free(du); free(row_isl); free(body_isl); free(isl_r);
   return st->nonfinite ? -4 : 0;
 }
 

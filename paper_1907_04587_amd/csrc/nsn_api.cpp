@@ -163,6 +163,7 @@ void layout(const Sizes &z, int n_envs, Arena &a, DevScene &S, EnvInfo *&env, in
   S.el_isl = a.take<int>(nel); S.el_perm = a.take<int>(nel); S.el_dots = a.take<double>(3 * nel);
   S.isl_cnt = a.take<int>(nslot); S.isl_off = a.take<int>(nslot); S.isl_run = a.take<int>(nslot);
   S.isl_list = a.take<int>(nslot); S.isl = a.take<IslState>(nslot); S.isl_n = a.take<int>(n_envs);
+  S.isl_res = a.take<int>(nslot);
   S.n_con = a.take<int>(n_envs); S.overflow = a.take<int>(n_envs); S.time = a.take<double>(n_envs);
   S.stats = a.take<nsn_step_stats>(n_envs);
   S.mlp = a.take<float>(kMlpBlob);

@@ -131,6 +131,7 @@ struct DevScene {
                                                 // placement counter; non-empty islands
   IslState *isl;
   int *isl_n;                      // per env: number of non-empty islands
+  int *isl_res;                    // per island slot: its residual (bits of a float >= 0)
 
   // per env dynamic
   int *n_con, *overflow;

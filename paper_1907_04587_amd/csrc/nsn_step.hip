@@ -1816,6 +1816,11 @@ __device__ __forceinline__ int ld_coherent(const int *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// an island already solved in residual mode (its residual at or below tol)
+__device__ __forceinline__ bool island_solved(const Ctx &c, int ib, int k) {
+  return c.A.tol > 0.f && __int_as_float(ld_coherent(c.S.isl_res + ib + k)) <= c.A.tol;
+}
+
 // rows of element el: first row and count
 __device__ __forceinline__ void el_rows(const EnvInfo &E, int el, int &r0, int &nr) {
   if (el < E.n_jnt) { r0 = row_joint(E, el); nr = 6; }
@@ -2011,7 +2016,10 @@ __device__ float island_check(const Ctx &c, int e, double stop) {
   for (int i = w; i < K; i += BS / 64) {
     const int k = S.isl_list[ib + i];
     IslState I = S.isl[ib + k];
-    if (stop >= 0.0) I.stop = stop;
+    if (stop >= 0.0) {
+      I.stop = stop;
+      if (island_solved(c, ib, k)) I.active = 0;  // READING: early exit of a solved island
+    }
     if (I.active) I.active = (I.rho > I.stop) && (I.rho > 0.0) && (I.qs > 0.0);
     if (I.active) {
       I.alpha = (float)(I.rho / I.qs);
@@ -2020,6 +2028,48 @@ __device__ float island_check(const Ctx &c, int e, double stop) {
     S.isl[ib + k] = I;
   }
   return any;
+}
+
+// Residual of every island (the same max(|M~^-1 g|, |err|) as the env's, over the
+// island's bodies and rows), for the early exit of solved islands in residual mode.
+// Maxima of non-negative floats through integer atomics: independent of the order.
+template <int BS>
+__device__ void island_residuals(const Ctx &c, int e, int nel) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  const int tid = threadIdx.x;
+  const int nb = E.n_rig + E.n_par;
+  const int eb = E.jnt_off + E.tet_off + E.con_off, ib = E.rig_off + E.par_off + 2 * e;
+  const int *lab = S.b_lab + E.rig_off + E.par_off;
+  for (int k = tid; k < nb + 2; k += BS) S.isl_res[ib + k] = 0;
+  __syncthreads();
+  for (int b = tid; b < nb; b += BS) {
+    const int l = ld_coherent(lab + b);
+    if (l < 0) continue;
+    float r = 0.f;
+    if (b < E.n_rig) {
+      const int g = E.rig_off + b;
+      const int d = E.dof_off + 6 * b;
+      const float im = S.r_inertia[g].w;
+      const V3 ia = sym_mul(S.r_Iwinv + 6 * g, mk(S.g[d + 3], S.g[d + 4], S.g[d + 5]));
+      r = fmaxf(fmaxf(fabsf(S.g[d] * im), fabsf(S.g[d + 1] * im)), fabsf(S.g[d + 2] * im));
+      r = fmaxf(r, fmaxf(fmaxf(fabsf(ia.x), fabsf(ia.y)), fabsf(ia.z)));
+    } else {
+      const int p = E.par_off + b - E.n_rig;
+      const int d = E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
+      const float m = S.p_m[p];
+      r = fmaxf(fmaxf(fabsf(S.g[d] / m), fabsf(S.g[d + 1] / m)), fabsf(S.g[d + 2] / m));
+    }
+    atomicMax(S.isl_res + ib + l, __float_as_int(r));
+  }
+  for (int el = tid; el < nel; el += BS) {
+    int r0, nr;
+    el_rows(E, el, r0, nr);
+    float r = 0.f;
+    for (int q = 0; q < nr; ++q) r = fmaxf(r, fabsf(S.row_err[r0 + q]));
+    atomicMax(S.isl_res + ib + S.el_isl[eb + el], __float_as_int(r));
+  }
+  __syncthreads();
 }
 
 // --------------------------------------------------------------------------
@@ -2218,6 +2268,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     merit = sqrt(msum);
     if (k == 0) r_first = rmax;
     const bool finite_now = rmax == rmax && !isinf(rmax) && msum == msum && !isinf(msum);
+    if (EXT && isl_mode && A.tol > 0.f) island_residuals<BS>(c, e, nel);
     if (A.p.line_search && k > 0 && ls_t > kLsTmin &&
         (!finite_now || merit > (1.0 - kLsSigma * (double)ls_t) * merit_k)) {
       ls_t *= 0.5f;
@@ -2425,6 +2476,11 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     }
     contrib_pass<BS, EXT>(c, S.row_x, buf, nel, true);
     __syncthreads();
+    // READING (island mode, residual mode): a solved island keeps its velocities
+    auto frozen = [&](int b) {
+      const int l = ld_coherent(S.b_lab + E.rig_off + E.par_off + b);
+      return A.tol > 0.f && l >= 0 && island_solved(c, E.rig_off + E.par_off + 2 * e, l);
+    };
     for (int b = tid; b < nb; b += BS) {
       if (b < E.n_rig) {
         const int g = E.rig_off + b;
@@ -2433,6 +2489,8 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
         gather_rigid(c, g, v);
         for (int q = 0; q < 6; ++q) v[q] = h * v[q] - S.g[d + q];
         hinv_rigid(c, g, v);
+        if (EXT && isl_mode && frozen(b))
+          for (int q = 0; q < 6; ++q) v[q] = 0.f;
         float *u = S.r_u + 6 * g;
         if (A.p.line_search) {
           for (int q = 0; q < 6; ++q) {
@@ -2448,7 +2506,8 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
         const V3 a = gather_particle(c, p);
         const float4 H = S.p_H[p];
         const float4 u = S.p_u[p];
-        const float dv[3] = {(h * a.x - S.g[d]) / H.x, (h * a.y - S.g[d + 1]) / H.y, (h * a.z - S.g[d + 2]) / H.z};
+        float dv[3] = {(h * a.x - S.g[d]) / H.x, (h * a.y - S.g[d + 1]) / H.y, (h * a.z - S.g[d + 2]) / H.z};
+        if (EXT && isl_mode && frozen(b)) dv[0] = dv[1] = dv[2] = 0.f;
         if (A.p.line_search) {
           S.du[d] = dv[0]; S.du[d + 1] = dv[1]; S.du[d + 2] = dv[2];
         }
