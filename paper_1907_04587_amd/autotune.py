@@ -21,7 +21,8 @@ def _work(envs, order):
     w = []
     for i in order:
         d = envs[i]
-        w.append(6 * d.n_joints + 3 * d.n_tets + 3 * d.max_contacts + 6 * d.n_rigid + 3 * d.n_particles)
+        tet_rows = getattr(d, "tet_rows", 3)
+        w.append(6 * d.n_joints + tet_rows * d.n_tets + 3 * d.max_contacts + 6 * d.n_rigid + 3 * d.n_particles)
     return np.array(w)
 
 
@@ -43,10 +44,16 @@ def _measure(scene, h, newton, cr, tol, steps):
 
 
 def autotune(scene, h, newton, cr, tol, bucket_counts=(1, 2, 4), steps=2, log=None):
+    """The scene's current schedule is the first candidate (the library's default for
+    large batches is itself a measured choice), then equal-count cuts into
+    `bucket_counts` buckets with a coordinate search over each bucket's block size."""
     order = scene.env_order()
     n = len(order)
     work = _work(scene.envs, order)
-    best = None
+    current = scene.schedule()
+    best = (_measure(scene, h, newton, cr, tol, steps), current)
+    if log:
+        log(f"autotune current {current}: {best[0]:.3f} ms/GB")
     for nb in bucket_counts:
         if nb > n:
             continue
@@ -67,7 +74,7 @@ def autotune(scene, h, newton, cr, tol, bucket_counts=(1, 2, 4), steps=2, log=No
                     log(f"autotune nb={nb} bucket {k} block {blk}: {c:.3f} ms/GB (best {cost:.3f})")
                 if c < cost:
                     cost, buckets = c, trial
-        if best is None or cost < best[0]:
+        if cost < best[0]:
             best = (cost, [tuple(b) for b in buckets])
         if log:
             log(f"autotune nb={nb}: {best}")
