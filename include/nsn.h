@@ -14,7 +14,11 @@
  *   - Sec. 8 (damped step t, zero start, Jacobi-preconditioned conjugate residual,
  *     diagonal geometric stiffness, eps regularisation);
  *   - Sec. 9 / App. B (generalised compliance of stable neo-Hookean tets in
- *     principal stretches, particles, rigid bodies with quaternions).
+ *     principal stretches, particles, rigid bodies with quaternions); Sec. 9.2
+ *     (linear Hookean tets on six strains, constant compliance);
+ *   - options around the method: line search on the merit (Sec. 8.1), PCG as the
+ *     comparison solver (Sec. 8.2), one PCR per island of an env (Sec. 11), a
+ *     learned contact warm start.
  *
  * Conventions: SI units; z up; quaternions (w,x,y,z); angular velocities in the
  * world frame; all host arrays are float32 and row-major unless stated.
