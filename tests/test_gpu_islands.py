@@ -98,3 +98,38 @@ def test_per_newton_iteration_islands_warm_start(newton):
     # particle velocities of the tet-block env at one oracle state)
     hist = lockstep(sc, envs, p, H, newton, 40, steps=4, sens_factor=10.0, prev_from_gpu=True, sens_trials=10)
     _print(f"islwarm{newton}", hist)
+
+
+def test_converged_islands_lockstep():
+    """Residual mode with islands, which exercises the early exit of solved islands on
+    both sides: rigid multi-island envs, several steps in lockstep from the
+    previous-step start (3e-4, as for the converged rigid stack)."""
+    envs = [si.batched_env(seed=1005, tets_max=0), si.batched_env(seed=1003, tets_max=0),
+            si.particles_vs_planes_lcp(seed=2)]
+    p = si.SolverParams(islands=1, warm=si.WARM_PREV)
+    sc = _scene(envs, p)
+    hist = lockstep(sc, envs, p, H, 50, 40, tol=1e-4, steps=3, err_tol=3e-4, prev_from_gpu=True)
+    _print("islconv", hist)
+
+
+def test_solved_island_keeps_its_state():
+    """Two particles on the ground are two islands; after a settling step particle B is
+    thrown down, and particle A, solved at the first iterate, keeps its velocity and
+    multipliers exactly while B's island iterates."""
+    d = si.particle_on_plane(mu=0.5)
+    d.particle_x = np.array([[0.1, -0.2, 0.0], [2.0, 0.5, 0.0]])
+    d.particle_rest = d.particle_x.copy()
+    d.particle_v = np.zeros((2, 3))
+    d.particle_mass = np.array([1.0, 1.0])
+    d = d.finalize()
+    sc = _scene([d], si.SolverParams(islands=1, warm=si.WARM_PREV))
+    sc.step(H, 50, 40, 1e-7)
+    S = sc.read_state(0)
+    lam0 = sc.contacts(0)["lam"].copy()
+    S["particle_v"][1] = [0.3, 0.0, -1.0]
+    sc.write_state(0, S)
+    sc.step(H, 50, 40, 1e-4)
+    st = sc.stats()[0]
+    assert st["converged"] and st["newton_iters"] >= 2, st
+    assert np.array_equal(sc.read_state(0)["particle_v"][0], S["particle_v"][0])
+    assert np.array_equal(sc.contacts(0)["lam"][0], lam0[0])

@@ -757,3 +757,37 @@ def test_islands_solve_the_same_system():
                 else:
                     # the rounding-level PCR stop is relative to each island's own start
                     np.testing.assert_allclose(A[k], B[k], atol=1e-6, err_msg=k)
+
+
+def test_islands_early_exit_keeps_solved_island():
+    """Early exit of a solved island (residual mode): two particles resting on the
+    ground are two islands.  After a settling step, particle B is thrown down; from the
+    previous-step start particle A is solved at the first iterate, so it keeps its start
+    velocity and multipliers exactly while B's island iterates to the tolerance.
+    Without islands A takes part in every update."""
+    h, tol = 1 / 60, 1e-5
+    d = si.particle_on_plane(mu=0.5)
+    d.particle_x = np.array([[0.1, -0.2, 0.0], [2.0, 0.5, 0.0]])
+    d.particle_rest = d.particle_x.copy()
+    d.particle_v = np.zeros((2, 3))
+    d.particle_mass = np.array([1.0, 1.0])
+    d = d.finalize()
+    out = {}
+    for isl in (1, 0):
+        env = O.OracleEnv(d)
+        p = O.make_params(si.SolverParams(islands=isl, warm=si.WARM_PREV))
+        # settle far below the step's tolerance, so that A starts the next step solved
+        assert env.step(h, 50, 40, 1e-10, p)["r_ncp"] <= 1e-10
+        S = env.get_state()
+        lam0 = env.contacts()["lam"].copy()
+        S["particle_v"][1] = [0.3, 0.0, -1.0]
+        env.set_state({k: v for k, v in S.items() if k != "time"})
+        st = env.step(h, 50, 40, tol, p)
+        assert st["r_ncp"] <= tol and st["newton_iters"] >= 2, st
+        out[isl] = (S["particle_v"][0].copy(), env.get_state()["particle_v"][0], lam0, env.contacts())
+    v0, v1, lam0, con = out[1]
+    assert np.array_equal(v0, v1)
+    # particle A's contact has the lower key in both steps
+    assert np.array_equal(con["lam"][0], lam0[0])
+    v0n, v1n, _, _ = out[0]
+    assert not np.array_equal(v0n, v1n)
