@@ -279,3 +279,21 @@ def test_lds_modes_bitwise_equal(ext, block):
             for k in a:
                 if k != "time":
                     assert np.array_equal(a[k], b[k]), k
+
+
+def test_lds_mode_falls_back_for_large_envs():
+    """A 5000-tet env does not fit LDS mode 2 (about 156 KB per workgroup): its bucket
+    runs in mode 1, with the same results as in global memory."""
+    envs = [si.tet_block_with_boxes(seed=2, cells=10, n_boxes=4)]
+    assert envs[0].n_tets == 5000
+    out = []
+    for mode in [2, 0]:
+        sc = _scene(envs)
+        sc.set_schedule([(0, 1, 1024)])
+        sc.set_lds_mode(mode)
+        assert sc.lds_modes() == [1 if mode == 2 else 0]
+        sc.step(H, 3, 20, 0.0)
+        out.append(sc.read_state(0))
+    for k in out[0]:
+        if k != "time":
+            assert np.array_equal(out[0][k], out[1][k]), k
