@@ -283,6 +283,26 @@ struct Ctx {
   int cl_base = 0, cl_n = 0;
 };
 
+// The env's descriptor is the same for every lane of a workgroup: read it into scalar
+// registers so that its fields take no vector registers in the Newton kernel.
+__device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float sgpr(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ EnvInfo uniform_env(const EnvInfo &v) {
+  EnvInfo u;
+  u.rig_off = sgpr(v.rig_off); u.n_rig = sgpr(v.n_rig);
+  u.par_off = sgpr(v.par_off); u.n_par = sgpr(v.n_par);
+  u.tet_off = sgpr(v.tet_off); u.n_tet = sgpr(v.n_tet);
+  u.jnt_off = sgpr(v.jnt_off); u.n_jnt = sgpr(v.n_jnt);
+  u.con_off = sgpr(v.con_off); u.max_con = sgpr(v.max_con);
+  u.row_off = sgpr(v.row_off); u.row_cap = sgpr(v.row_cap);
+  u.dof_off = sgpr(v.dof_off); u.n_dof = sgpr(v.n_dof);
+  u.feat_off = sgpr(v.feat_off); u.n_feat = sgpr(v.n_feat);
+  u.n_targets = sgpr(v.n_targets); u.ground = sgpr(v.ground);
+  u.bcon_off = sgpr(v.bcon_off); u.tet_model = sgpr(v.tet_model);
+  u.mu = sgpr(v.mu); u.gx = sgpr(v.gx); u.gy = sgpr(v.gy); u.gz = sgpr(v.gz);
+  return u;
+}
+
 // world position of a body-fixed point (env-local body id; -1 = world / ground)
 __device__ __forceinline__ V3 body_point(const Ctx &c, int body, V3 loc) {
   if (body < 0) return loc;
@@ -2085,13 +2105,13 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
   Ctx c;
   c.S = S;
   const int e = S.env_order[first + blockIdx.x];
-  c.E = S.env[e];
+  c.E = uniform_env(S.env[e]);
   c.A = A;
   const EnvInfo &E = c.E;
   const int tid = threadIdx.x;
   const float h = A.h;
   const float damp = A.p.damping, eps = A.p.eps;
-  const int nc = S.n_con[e];
+  const int nc = sgpr(S.n_con[e]);
   const int nb = E.n_rig + E.n_par;
   const int nel = E.n_jnt + E.n_tet + nc;
   const int nrows = 6 * E.n_jnt + tet_nrows(E) * E.n_tet + 3 * nc;
@@ -2105,7 +2125,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
   float *Y = LM > 0 ? y_lds : S.y + E.dof_off;
   if (LM == 2) {
     c.cl = y_lds + ((E.n_dof + 3) & ~3);
-    c.cl_base = S.p_tadj_ptr[E.par_off];
+    c.cl_base = sgpr(S.p_tadj_ptr[E.par_off]);
     c.cl_n = 4 * E.n_tet;
   }
 
