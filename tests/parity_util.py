@@ -131,3 +131,18 @@ def lockstep(scene, envs, params, h, N, M, tol=0.0, steps=1, env_ids=None, check
             assert not bad, f"step {s} env {e}: (err, tol) {bad}; gpu stats {stats[e]}; oracle {ost}"
         history.append(worst)
     return history
+
+
+def bucket_sample(scene, n_random=12, seed=0):
+    """Envs to check in a full-size batch: a seeded random sample plus the first and
+    the last env of every schedule bucket (each block size the launch uses, and the
+    largest and smallest env of the batch)."""
+    rng = np.random.default_rng(seed)
+    n = scene.n_envs
+    order = scene.env_order()
+    ids = set(int(i) for i in rng.choice(n, size=min(n_random, n), replace=False))
+    for first, count, _ in scene.schedule():
+        if count > 0:
+            ids.add(int(order[first]))
+            ids.add(int(order[first + count - 1]))
+    return sorted(ids)

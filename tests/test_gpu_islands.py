@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import scene_inputs as si
-from tests.parity_util import lockstep
+from tests.parity_util import bucket_sample, lockstep
 
 pytestmark = pytest.mark.gpu
 
@@ -133,3 +133,16 @@ def test_solved_island_keeps_its_state():
     assert st["converged"] and st["newton_iters"] >= 2, st
     assert np.array_equal(sc.read_state(0)["particle_v"][0], S["particle_v"][0])
     assert np.array_equal(sc.contacts(0)["lam"][0], lam0[0])
+
+
+def test_full_size_batch_islands_sampled():
+    """Island mode on the 4096-env uneven batch at full size, default schedule: sampled
+    envs and the ends of every bucket against the oracle's island mode, 2 Newton
+    iterations from the zero start."""
+    envs = si.batched_envs(4096, base_seed=1000)
+    p = si.SolverParams(islands=1)
+    sc = _scene(envs, p)
+    sample = bucket_sample(sc, seed=2)
+    hist = lockstep(sc, envs, p, H, 2, 40, steps=1, env_ids=sample, sens_factor=10.0)
+    _print("islfull", hist)
+    assert not sc.stats()["nonfinite"].any()

@@ -11,7 +11,7 @@ import pytest
 
 import scene_inputs as si
 from oracle import oracle as O
-from tests.parity_util import lockstep
+from tests.parity_util import bucket_sample, lockstep
 
 pytestmark = pytest.mark.gpu
 
@@ -132,3 +132,16 @@ def test_material_extension_volume_gpu():
         oe.step(H, 50, 100, 1e-4, op)
     xo, xg = oe.get_state()["particle_x"], sc.read_state(0)["particle_x"]
     assert np.abs(xo - xg).max() / np.abs(xo).max() < 1e-4
+
+
+def test_full_size_linear_batch_sampled():
+    """The 4096-env uneven batch with linear tet blocks at full size, in the default
+    schedule (the extended instantiation at every block size): sampled envs and the
+    ends of every bucket against the oracle, 2 Newton iterations."""
+    envs = si.batched_envs(4096, base_seed=1000, tet_model=si.TET_LINEAR)
+    p = si.SolverParams()
+    sc = _scene(envs, p)
+    sample = bucket_sample(sc, seed=1)
+    hist = lockstep(sc, envs, p, H, 2, 40, steps=1, env_ids=sample, sens_factor=10.0)
+    _print("linfull", hist)
+    assert not sc.stats()["nonfinite"].any()

@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import scene_inputs as si
-from tests.parity_util import lockstep
+from tests.parity_util import bucket_sample, lockstep
 
 pytestmark = pytest.mark.gpu
 
@@ -168,15 +168,14 @@ def test_converged_rigid_stack():
 
 
 def test_full_size_batch_sampled():
-    """The 4096-env uneven batch at full size, launched as the benchmark launches it:
-    sampled envs are checked one by one against the oracle (2 Newton iterations)."""
+    """The 4096-env uneven batch at full size, launched as the benchmark launches it
+    (default schedule of three block sizes): sampled envs, with the first and last env
+    of every bucket, are checked one by one against the oracle (2 Newton iterations)."""
     envs = si.batched_envs(4096, base_seed=1000)
     p = si.SolverParams()
     sc = _scene(envs, p)
-    rng = np.random.default_rng(0)
-    sample = sorted(rng.choice(len(envs), size=12, replace=False).tolist())
-    order = sc.env_order()
-    sample += [int(order[0]), int(order[-1])]  # the largest and the smallest env
+    assert len(sc.schedule()) == 3
+    sample = bucket_sample(sc)
     hist = lockstep(sc, envs, p, H, 2, 40, steps=1, env_ids=sample, sens_factor=10.0)
     _print("full", hist)
     st = sc.stats()
