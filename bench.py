@@ -7,9 +7,11 @@ per-env Newton kernel (one launch per step, replayed from a hipGraph), h = 1/60 
 residual mode: every env stops when r_ncp <= 1e-4 or after 50 Newton iterations of 40
 PCR iterations.  Inputs are seeded and synthetic and already resident in HBM.
 
-Prints ONE JSON line.  `value` is env-steps/s of the headline arm (the learned warm
-start when a trained model is available, else the stronger plain start); every arm
-is reported under "arms".  `roofline` covers the dominant kernel (the Newton kernel):
+Prints ONE JSON line.  `value` is env-steps/s of the headline arm (the faster of the
+two learned warm starts when the trained model is available: "learned" takes the
+network's multipliers for every contact, "hybrid" keeps the previous step's for
+contacts that persist and takes the network's for new ones; else the stronger plain
+start); every arm is reported under "arms".  `roofline` covers the dominant kernel (the Newton kernel):
 algorithmic bytes of its PCR loop per launch divided by its launch duration, the
 latter read from the GPU wall clock inside the kernel for every timed step.
 `cpu_baseline` times the FP64 oracle on a bounded sample of the same envs on the
@@ -40,7 +42,8 @@ def run_arm(envs, arm, args, model_blob=None):
     import scene_inputs as si
     from paper_1907_04587_amd import Scene
 
-    warm = {"zero": si.WARM_ZERO, "prev": si.WARM_PREV, "learned": si.WARM_LEARNED}[arm]
+    warm = {"zero": si.WARM_ZERO, "prev": si.WARM_PREV, "learned": si.WARM_LEARNED,
+            "hybrid": si.WARM_HYBRID}[arm]
     p = si.SolverParams(warm=si.WARM_ZERO, islands=int(args.islands))
     sc = Scene(envs, p)
     if model_blob is not None:
@@ -150,7 +153,7 @@ def main():
     ap.add_argument("--newton", type=int, default=50)
     ap.add_argument("--cr", type=int, default=40)
     ap.add_argument("--tol", type=float, default=1e-4)
-    ap.add_argument("--arms", default="zero,prev,learned")
+    ap.add_argument("--arms", default="zero,prev,learned,hybrid")
     ap.add_argument("--islands", action="store_true", help="one PCR per island of an env (Sec. 11 option)")
     ap.add_argument("--tets-max", type=int, default=3000, help="largest tet block of an env (0: rigid only)")
     ap.add_argument("--tet-model", choices=["neohookean", "linear"], default="neohookean",
@@ -187,19 +190,20 @@ def main():
     log(f"generating {args.envs} envs")
     tet_model = si.TET_LINEAR if args.tet_model == "linear" else si.TET_NEOHOOKEAN
     envs = si.batched_envs(args.envs, base_seed=1000, tet_model=tet_model, tets_max=args.tets_max)
-    model_blob = None
+    blobs = {}
     model_path = os.path.join(ROOT, "paper_1907_04587_amd", "weights", "warm_start_batched.npy")
     if os.path.exists(model_path):
-        model_blob = np.load(model_path, allow_pickle=False)
-    arms = [a for a in args.arms.split(",") if a and (a != "learned" or model_blob is not None)]
+        blobs["learned"] = blobs["hybrid"] = np.load(model_path, allow_pickle=False)
+    arms = [a for a in args.arms.split(",") if a and (a not in ("learned", "hybrid") or a in blobs)]
     results = {}
     for arm in arms:
         log(f"arm {arm}")
-        results[arm] = run_arm(envs, arm, args, model_blob if arm == "learned" else None)
+        results[arm] = run_arm(envs, arm, args, blobs.get(arm))
         log(f"arm {arm}: {json.dumps(results[arm])}")
     plains = [a for a in results if a in ("zero", "prev")]
     plain = max(plains, key=lambda a: results[a]["env_steps_per_s"]) if plains else None
-    head = "learned" if "learned" in results else plain
+    learned = [a for a in results if a in ("learned", "hybrid")]
+    head = max(learned, key=lambda a: results[a]["env_steps_per_s"]) if learned else plain
     if head is None:
         sys.exit("bench.py: no arm to report (--arms)")
     r = results[head]

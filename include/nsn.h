@@ -85,6 +85,8 @@ typedef int32_t nsn_status;
 #define NSN_WARM_ZERO 0    /* u0 = 0, lambda0 = 0 (Sec. 8.1) */
 #define NSN_WARM_PREV 1    /* previous-step multipliers (contacts matched by key) */
 #define NSN_WARM_LEARNED 2 /* contact multipliers predicted by the warm-start MLP */
+#define NSN_WARM_HYBRID 3  /* previous-step multipliers for contacts whose key existed in the
+                              previous step, the warm-start MLP's prediction for new ones */
 
 /* linear solver of the Newton system (Sec. 8.2) */
 #define NSN_LINEAR_PCR 0 /* preconditioned conjugate residual: the method */
@@ -208,7 +210,8 @@ nsn_status nsn_set_params(nsn_scene s, const nsn_solver_params *p);
  * `cr_iters` PCR iterations each.  tol > 0: an env stops as soon as its residual
  * r_ncp <= tol (checked before each update); tol = 0: fixed iteration counts.
  * The step sequence is captured once into a hipGraph per (h, iterations, tol) and
- * replayed.  Errors: NSN_EINVAL for h <= 0 or negative counts. */
+ * replayed.  Errors: NSN_EINVAL for h <= 0 or negative counts; NSN_ESTATE in a learned
+ * warm-start mode before nsn_set_warm_start_model. */
 nsn_status nsn_step(nsn_scene s, double h, int32_t newton_iters, int32_t cr_iters, double tol);
 
 /* Statistics of the last step for every env: out[n_envs] (host).  Synchronises. */
@@ -239,7 +242,8 @@ nsn_status nsn_read_contacts(nsn_scene s, int32_t env, int32_t cap, int32_t *n, 
  * Synchronises. */
 nsn_status nsn_read_lambda(nsn_scene s, int32_t env, int32_t cap, int32_t *n, float *lam);
 
-/* Warm-start model for NSN_WARM_LEARNED: float32 blob of 9347 MLP parameters
+/* Warm-start model for NSN_WARM_LEARNED and NSN_WARM_HYBRID: float32 blob of 9347 MLP
+ * parameters
  * (12 -> 64 -> 64 -> 64 -> 3, ReLU; W1[64x12] b1 W2[64x64] b2 W3[64x64] b3 W4[3x64] b4)
  * followed by x_mean[12] x_std[12] y_mean[3] y_std[3].  Copied to the device. */
 nsn_status nsn_set_warm_start_model(nsn_scene s, const float *blob, int64_t n);
@@ -249,7 +253,7 @@ nsn_status nsn_set_warm_start_model(nsn_scene s, const float *blob, int64_t n);
 nsn_status nsn_read_features(nsn_scene s, int32_t env, int32_t cap, int32_t *n, float *feat);
 
 /* Compute the 12 warm-start features of every contact in every step (off by default
- * except in NSN_WARM_LEARNED mode); needed by nsn_read_features. */
+ * except in the learned modes); needed by nsn_read_features. */
 nsn_status nsn_enable_features(nsn_scene s, int32_t on);
 
 /* Replay steps from captured hipGraphs (default on when the scene has a non-NULL

@@ -1618,7 +1618,10 @@ static void start_iterate(step_t *S) {
   for (int ci = 0; ci < e->nc; ++ci) {
     contact *c = &e->con[ci];
     double l[3] = {0, 0, 0};
-    if (S->p->warm == 2 && e->mlp) {
+    /* mode 3: the previous-step multipliers where the key existed in the previous
+     * step, the network's prediction for a new contact */
+    const int known = e->have_prev && prev_lookup(e, c->key) >= 0;
+    if ((S->p->warm == 2 || (S->p->warm == 3 && !known)) && e->mlp) {
       double f[MLP_IN];
       contact_features(S, c, f);
       mlp_predict(e, f, l);

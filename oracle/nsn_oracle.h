@@ -62,7 +62,8 @@ typedef struct {
   int32_t geo_stiff;  /* diagonal geometric stiffness on particle DOFs */
   int32_t fem_mode;   /* 0 projected full 3x3 compliance, 1 diagonal */
   double margin;      /* contact creation distance */
-  int32_t warm;       /* 0 zero start, 1 previous-step multipliers, 2 learned */
+  int32_t warm;       /* 0 zero start, 1 previous-step multipliers, 2 learned, 3 previous-step
+                         multipliers for known contact keys and learned for new ones */
   int32_t line_search; /* 1: back-tracking on the L2 merit from t = 1 instead of the constant damping */
   int32_t linear;      /* 0 preconditioned conjugate residual (the method), 1 preconditioned conjugate gradient */
   int32_t islands;     /* 1: one PCR per island of the env (independent CR scalars) */

@@ -280,11 +280,13 @@ nsn_status nsn_query_workspace(const nsn_env_desc *envs, int32_t n_envs, size_t 
   return NSN_OK;
 }
 
+static bool learned_warm(int w) { return w == NSN_WARM_LEARNED || w == NSN_WARM_HYBRID; }
+
 nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_solver_params *p,
                             void *hip_stream, void *workspace, size_t workspace_bytes, nsn_scene *out) {
   if (!envs || n_envs < 1 || !p || !out) return fail(NSN_EINVAL, "nsn_create_scene: bad arguments");
   if (!workspace || ((uintptr_t)workspace & 255)) return fail(NSN_EINVAL, "workspace must be a 256-byte aligned device pointer");
-  if (p->ncp < 0 || p->ncp > 1 || p->rmode < 0 || p->rmode > 2 || p->warm < 0 || p->warm > 2 ||
+  if (p->ncp < 0 || p->ncp > 1 || p->rmode < 0 || p->rmode > 2 || p->warm < 0 || p->warm > 3 ||
       p->fem_mode < 0 || p->fem_mode > 1 || !(p->damping > 0.f) || !(p->eps >= 0.f) || !(p->margin >= 0.f) ||
       p->line_search < 0 || p->line_search > 1 || p->linear < 0 || p->linear > 1 || p->islands < 0 ||
       p->islands > 1)
@@ -525,12 +527,12 @@ nsn_status nsn_destroy_scene(nsn_scene s) {
 
 nsn_status nsn_set_params(nsn_scene s, const nsn_solver_params *p) {
   if (!s || !p) return fail(NSN_EINVAL, "nsn_set_params: bad arguments");
-  if (p->ncp < 0 || p->ncp > 1 || p->rmode < 0 || p->rmode > 2 || p->warm < 0 || p->warm > 2 ||
+  if (p->ncp < 0 || p->ncp > 1 || p->rmode < 0 || p->rmode > 2 || p->warm < 0 || p->warm > 3 ||
       p->fem_mode < 0 || p->fem_mode > 1 || !(p->damping > 0.f) || !(p->eps >= 0.f) || !(p->margin >= 0.f) ||
       p->line_search < 0 || p->line_search > 1 || p->linear < 0 || p->linear > 1 || p->islands < 0 ||
       p->islands > 1)
     return fail(NSN_EINVAL, "bad solver parameters");
-  if (p->warm == NSN_WARM_LEARNED && !s->S.have_mlp) return fail(NSN_ESTATE, "learned warm start needs nsn_set_warm_start_model first");
+  if (learned_warm(p->warm) && !s->S.have_mlp) return fail(NSN_ESTATE, "learned warm start needs nsn_set_warm_start_model first");
   s->p = *p;
   for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
   s->graphs.clear();
@@ -556,10 +558,10 @@ static hipError_t ensure_side_streams(nsn_scene s, size_t nb) {
 }
 
 static hipError_t enqueue_step(nsn_scene s, const StepArgs &a) {
-  hipError_t e = launch_prepare(s->S, a, s->want_features || a.p.warm == NSN_WARM_LEARNED, s->stream);
+  hipError_t e = launch_prepare(s->S, a, s->want_features || learned_warm(a.p.warm), s->stream);
   if (e != hipSuccess) return e;
-  if (a.p.warm == NSN_WARM_LEARNED) {
-    e = launch_warm_mlp(s->S, s->stream);
+  if (learned_warm(a.p.warm)) {
+    e = launch_warm_mlp(s->S, a.p.warm == NSN_WARM_HYBRID, s->stream);
     if (e != hipSuccess) return e;
   }
   const size_t nb = s->buckets.size();
@@ -596,6 +598,7 @@ static hipError_t enqueue_step(nsn_scene s, const StepArgs &a) {
 nsn_status nsn_step(nsn_scene s, double h, int32_t newton_iters, int32_t cr_iters, double tol) {
   if (!s) return fail(NSN_EINVAL, "nsn_step: null scene");
   if (!(h > 0.0) || newton_iters < 0 || cr_iters < 0 || !(tol >= 0.0)) return fail(NSN_EINVAL, "nsn_step: bad h, iteration counts or tol");
+  if (learned_warm(s->p.warm) && !s->S.have_mlp) return fail(NSN_ESTATE, "learned warm start needs nsn_set_warm_start_model first");
   StepArgs a;
   a.h = (float)h;
   a.newton_iters = newton_iters;
@@ -799,7 +802,7 @@ nsn_status nsn_read_features(nsn_scene s, int32_t env, int32_t cap, int32_t *n, 
   nsn_status st = check_env(s, env);
   if (st) return st;
   if (!n || cap < 0) return fail(NSN_EINVAL, "nsn_read_features: bad arguments");
-  if (!s->want_features && s->p.warm != NSN_WARM_LEARNED)
+  if (!s->want_features && !learned_warm(s->p.warm))
     return fail(NSN_ESTATE, "features are only computed after nsn_enable_features(scene, 1) or in learned mode");
   const EnvInfo &E = s->env[env];
   int nc = 0;

@@ -176,6 +176,7 @@ hipError_t launch_newton_ext(const DevScene &s, const StepArgs &a, int block, in
 constexpr int kMaxLdsFloats = 24 * 1024;  // 96 KB of LDS for the body-space vector
 constexpr int kMaxLdsFloatsCl = 39 * 1024;  // 156 KB: body-space vector + tet contributions (mode 2)
 // learned warm start: MLP prediction for every contact of every env (nsn_mlp.hip)
-hipError_t launch_warm_mlp(const DevScene &s, hipStream_t st);
+// hybrid: contacts that existed in the previous step keep their previous-step multipliers
+hipError_t launch_warm_mlp(const DevScene &s, int hybrid, hipStream_t st);
 
 }  // namespace nsn

@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *w, const float
 // learned warm start inside a step: every contact of every env, standardised
 // features in, de-standardised (lambda_n, lambda_t1, lambda_t2) out.  One block per env.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_warm_mlp(DevScene S) {
+__global__ __launch_bounds__(256) void k_warm_mlp(DevScene S, int hybrid) {
   __shared__ MlpLds L;
   __shared__ float xm[kIn], xis[kIn], ym[kOut], ys[kOut];
   const int e = blockIdx.x;
@@ -203,15 +203,18 @@ __global__ __launch_bounds__(256) void k_warm_mlp(DevScene S) {
     Acts a;
     forward_tile(L, load_x(X, nc, 16 * t, lane, xm, xis), lane, a);
     const int s = 16 * t + (lane & 15);
-    if (lane < 16 && s < nc) {
+    // hybrid mode: a contact whose key existed in the previous step (feature 11) keeps
+    // the previous-step multipliers already in c_lam0; only new contacts take the
+    // prediction
+    if (lane < 16 && s < nc && !(hybrid && X[(size_t)s * kIn + 11] != 0.f)) {
       S.c_lam0[E.con_off + s] = make_float4(a.y[0] * ys[0] + ym[0], a.y[1] * ys[1] + ym[1],
                                             a.y[2] * ys[2] + ym[2], 0.f);
     }
   }
 }
 
-hipError_t launch_warm_mlp(const DevScene &s, hipStream_t st) {
-  hipLaunchKernelGGL(k_warm_mlp, dim3(s.n_envs), dim3(256), 0, st, s);
+hipError_t launch_warm_mlp(const DevScene &s, int hybrid, hipStream_t st) {
+  hipLaunchKernelGGL(k_warm_mlp, dim3(s.n_envs), dim3(256), 0, st, s, hybrid);
   return hipGetLastError();
 }
 

@@ -9,7 +9,8 @@
 2. Training: the 12 -> 64 -> 64 -> 64 -> 3 MLP with the library's BF16-MFMA forward /
    backward kernels and its Adam kernel, inputs and targets z-scored.
 3. Evaluation on held-out seeds (disjoint from the training and validation seeds):
-   the ZERO, PREV and LEARNED starts step identical initial states in residual mode
+   the ZERO, PREV, LEARNED and HYBRID (previous-step multipliers for persisting
+   contacts, the network for new ones) starts step identical initial states in residual mode
    (r_ncp <= 1e-4, at most 50 Newton x 40 PCR); reported per arm: mean Newton and PCR
    iterations, converged fraction, start residual, final residual, contact residual.
 
@@ -47,9 +48,10 @@ def evaluate(dist, blob, seeds, steps, warmup, log=print):
     envs = _envs(dist, seeds)
     h = _h(dist)
     out = {}
-    for arm, mode in [("zero", si.WARM_ZERO), ("prev", si.WARM_PREV), ("learned", si.WARM_LEARNED)]:
+    for arm, mode in [("zero", si.WARM_ZERO), ("prev", si.WARM_PREV), ("learned", si.WARM_LEARNED),
+                      ("hybrid", si.WARM_HYBRID)]:
         sc = Scene(envs, si.SolverParams(warm=mode))
-        if mode == si.WARM_LEARNED:
+        if mode in (si.WARM_LEARNED, si.WARM_HYBRID):
             sc.set_warm_start_model(blob)
         for _ in range(warmup):
             sc.step(h, 50, 40, 1e-4)

@@ -10,7 +10,7 @@ from .scenes import (  # noqa: F401
     EnvDesc, SolverParams,
     SHAPE_BOX, SHAPE_CAPSULE, SHAPE_NONE, JOINT_REVOLUTE, JOINT_PRISMATIC,
     NCP_FB, NCP_MIN, RMODE_IDENTITY, RMODE_H2, RMODE_H2_EFFMASS,
-    FEM_FULL_PROJECTED, FEM_DIAGONAL, WARM_ZERO, WARM_PREV, WARM_LEARNED, TET_NEOHOOKEAN, TET_LINEAR,
+    FEM_FULL_PROJECTED, FEM_DIAGONAL, WARM_ZERO, WARM_PREV, WARM_LEARNED, WARM_HYBRID, TET_NEOHOOKEAN, TET_LINEAR,
     box_inertia, capsule_inertia, hex_grid_tets, sphere_tets,
     cube_stack, heavy_stack, stretched_sheet, extension_bar, tet_block_with_boxes, grasp_scene, batched_env, batched_envs,
     particle_on_plane, free_particle, spinning_box, box_on_incline,

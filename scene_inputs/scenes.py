@@ -27,7 +27,7 @@ JOINT_REVOLUTE, JOINT_PRISMATIC = 0, 1
 NCP_FB, NCP_MIN = 0, 1
 RMODE_IDENTITY, RMODE_H2, RMODE_H2_EFFMASS = 0, 1, 2
 FEM_FULL_PROJECTED, FEM_DIAGONAL = 0, 1
-WARM_ZERO, WARM_PREV, WARM_LEARNED = 0, 1, 2
+WARM_ZERO, WARM_PREV, WARM_LEARNED, WARM_HYBRID = 0, 1, 2, 3
 TET_NEOHOOKEAN, TET_LINEAR = 0, 1
 
 
