@@ -498,14 +498,24 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
     d.joint_type = d.joint_body = nullptr;
     d.joint_anchor = d.joint_axis = d.joint_ref = d.joint_drive = nullptr;
   }
-  // default schedule.  Large batches, in launch order (decreasing work): the heaviest
-  // 3/8 of the envs with 1024 threads each, the next 3/8 with 512, the lightest quarter
-  // with 128 (measured best on the uneven 4096-env batch: 1185 ms per step against
-  // 1191 with 1/2 at 512 and 1/8 at 128, and 1206 with the light quarter at 256).  Otherwise one launch with the block size
-  // from the largest env.
-  if (n_envs >= 1024) {
+  // default schedule.  Large batches of heavy envs, in launch order (decreasing work):
+  // the heaviest 3/8 of the envs with 1024 threads each, the next 3/8 with 512, the
+  // lightest quarter with 128 (measured best on the uneven 4096-env batch with tet
+  // blocks: 1185 ms per step against 1191 with 1/2 at 512 and 1/8 at 128, and 1206 with
+  // the light quarter at 256).  "Heavy" counts the rows and DOFs an env always has
+  // (joints, tets, bodies), not its contact capacity, which is mostly unused: when the
+  // env at 3/8 of the order has fewer than 1024 of them, a large batch is one launch of
+  // 128 threads per env (the same batch without tets: 18.7 ms per step against 35.5 ms
+  // with the three buckets, 19.5 at 64 threads, 21.5 at 256).  Small batches: one
+  // launch with the block size from the largest env.
+  auto fixed_rows = [&](const EnvInfo &E) {
+    return 6 * E.n_jnt + (E.tet_model == NSN_TET_LINEAR ? 6 : 3) * E.n_tet + 6 * E.n_rig + 3 * E.n_par;
+  };
+  if (n_envs >= 1024 && fixed_rows(env[order[3 * (n_envs / 8)]]) >= 1024) {
     const int a1 = 3 * (n_envs / 8), a2 = 3 * (n_envs / 4);
     s->buckets = {Bucket{0, a1, 1024, 0}, Bucket{a1, a2 - a1, 512, 0}, Bucket{a2, n_envs - a2, 128, 0}};
+  } else if (n_envs >= 1024) {
+    s->buckets = {Bucket{0, n_envs, 128, 0}};
   } else {
     int max_el = 0;
     for (auto &E : env) max_el = std::max(max_el, E.n_jnt + E.n_tet + E.max_con + E.n_rig + E.n_par);

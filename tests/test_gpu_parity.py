@@ -182,6 +182,20 @@ def test_full_size_batch_sampled():
     assert not st["nonfinite"].any()
 
 
+def test_full_size_rigid_batch_sampled():
+    """The same 4096 envs without tet blocks: no env carries 1024 rows + DOFs besides
+    its contact slots, so the default schedule is one launch of 128 threads per env;
+    sampled envs and the ends of the bucket against the oracle (2 Newton iterations)."""
+    envs = si.batched_envs(4096, base_seed=1000, tets_max=0)
+    p = si.SolverParams()
+    sc = _scene(envs, p)
+    assert sc.schedule() == [(0, 4096, 128)]
+    sample = bucket_sample(sc, seed=3)
+    hist = lockstep(sc, envs, p, H, 2, 40, steps=1, env_ids=sample, sens_factor=10.0)
+    _print("rigidfull", hist)
+    assert not sc.stats()["nonfinite"].any()
+
+
 def test_empty_env_and_overflow():
     """An env with no bodies, and contact overflow (capacity below the contact count)."""
     empty = si.scenes._empty(name="empty").finalize()
