@@ -274,8 +274,9 @@ nsn_status nsn_set_schedule(nsn_scene s, int32_t n_buckets, const int32_t *first
 /* The current buckets: *n receives their number; up to cap entries are written.
  * Default at creation: for 1024 envs or more whose env at 3/8 of the order has at
  * least 1024 rows + DOFs besides its contact slots, three buckets (the heaviest 3/8 at
- * 1024 threads, the next 3/8 at 512, the rest at 128); other batches of 1024 envs or
- * more, one bucket at 128; smaller batches, one bucket sized by the largest env. */
+ * 1024 threads, the next 3/8 at 512, the rest at 128), or two (3/4 at 512, the rest at
+ * 128) when some env has linear tets; other batches of 1024 envs or more, one bucket
+ * at 128; smaller batches, one bucket sized by the largest env. */
 nsn_status nsn_get_schedule(nsn_scene s, int32_t cap, int32_t *n, int32_t *first, int32_t *count,
                             int32_t *block);
 

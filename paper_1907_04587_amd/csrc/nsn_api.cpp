@@ -506,12 +506,18 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
   // (joints, tets, bodies), not its contact capacity, which is mostly unused: when the
   // env at 3/8 of the order has fewer than 1024 of them, a large batch is one launch of
   // 128 threads per env (the same batch without tets: 18.7 ms per step against 35.5 ms
-  // with the three buckets, 19.5 at 64 threads, 21.5 at 256).  Small batches: one
-  // launch with the block size from the largest env.
+  // with the three buckets, 19.5 at 64 threads, 21.5 at 256).  Batches with linear tets
+  // run the extended instantiation, which spills at 1024 threads: three quarters at 512
+  // and a quarter at 128 (the batch with linear tet blocks: 1644 ms per step against
+  // 1863 with the three buckets, 1652 all at 512).  Small batches: one launch with the
+  // block size from the largest env.
   auto fixed_rows = [&](const EnvInfo &E) {
     return 6 * E.n_jnt + (E.tet_model == NSN_TET_LINEAR ? 6 : 3) * E.n_tet + 6 * E.n_rig + 3 * E.n_par;
   };
-  if (n_envs >= 1024 && fixed_rows(env[order[3 * (n_envs / 8)]]) >= 1024) {
+  if (n_envs >= 1024 && fixed_rows(env[order[3 * (n_envs / 8)]]) >= 1024 && z.any_linear) {
+    const int a = 3 * (n_envs / 4);
+    s->buckets = {Bucket{0, a, 512, 0}, Bucket{a, n_envs - a, 128, 0}};
+  } else if (n_envs >= 1024 && fixed_rows(env[order[3 * (n_envs / 8)]]) >= 1024) {
     const int a1 = 3 * (n_envs / 8), a2 = 3 * (n_envs / 4);
     s->buckets = {Bucket{0, a1, 1024, 0}, Bucket{a1, a2 - a1, 512, 0}, Bucket{a2, n_envs - a2, 128, 0}};
   } else if (n_envs >= 1024) {

@@ -136,11 +136,12 @@ def test_material_extension_volume_gpu():
 
 def test_full_size_linear_batch_sampled():
     """The 4096-env uneven batch with linear tet blocks at full size, in the default
-    schedule (the extended instantiation at every block size): sampled envs and the
+    schedule (the extended instantiation, 512 and 128 threads): sampled envs and the
     ends of every bucket against the oracle, 2 Newton iterations."""
     envs = si.batched_envs(4096, base_seed=1000, tet_model=si.TET_LINEAR)
     p = si.SolverParams()
     sc = _scene(envs, p)
+    assert [b[2] for b in sc.schedule()] == [512, 128]  # linear tets: no 1024-thread bucket
     sample = bucket_sample(sc, seed=1)
     hist = lockstep(sc, envs, p, H, 2, 40, steps=1, env_ids=sample, sens_factor=10.0)
     _print("linfull", hist)
