@@ -8,17 +8,20 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "nsn_oracle.c")
+HDR = os.path.join(HERE, "nsn_oracle.h")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose=False):
+def build(verbose=False, src=SRC, out=LIB):
+    """Compile the oracle (or a variant source `src`, e.g. one with a planted mistake,
+    into `out`)."""
     cmd = ["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-Wall", "-fPIC", "-shared",
-           "-o", LIB + ".tmp", SRC, "-lm"]
+           "-I", HERE, "-o", out + ".tmp", src, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -34,6 +34,7 @@
 #define TAU_EIG 1e-6      /* READING: relative size below which Jacobi skips a rotation / treats
                              eigenvalues as tied */
 #define MAX_HIST 256
+#define ORC_REC_NFIELDS 22
 #define MLP_IN 12
 #define MLP_H 64
 #define MLP_OUT 3
@@ -629,6 +630,15 @@ typedef struct {
   /* learned warm start */
   double *mlp;
   int64_t mlp_n;
+  /* per-iteration record (orc_set_record): iteration to record (-1 off), the fields */
+  int rec_k;
+  double *rec[ORC_REC_NFIELDS];
+  int rec_len[ORC_REC_NFIELDS];
+  /* orc_eval_iterate: the iterate put in place of the start iterate (and the previous
+   * one, for the secant) during one step */
+  int inj, inj_nc;
+  const double *inj_lam, *inj_u, *inj_rx, *inj_rq, *inj_px;
+  const double *inj_lam_p, *inj_u_p, *inj_rx_p, *inj_rq_p, *inj_px_p;
 } env_t;
 
 static int is_static_rigid(const env_t *e, int i) { return e->rm[i] <= 0.0; }
@@ -735,6 +745,7 @@ void *orc_create(const orc_desc *d, char *err, int errlen) {
   ALLOC(e->dbg_err, e->maxrows); ALLOC(e->dbg_cdiag, e->maxrows); ALLOC(e->dbg_pdiag, e->maxrows);
   ALLOC(e->lam_last, e->maxrows);
 #undef ALLOC
+  e->rec_k = -1;
   return e;
 }
 
@@ -748,6 +759,7 @@ void orc_destroy(void *p) {
   free(e->con); free(e->prev); free(e->lam_joint_prev); free(e->lam_tet_prev);
   free(e->hist); free(e->mhist); free(e->dbg_err); free(e->dbg_cdiag); free(e->dbg_pdiag); free(e->lam_last);
   free(e->mlp);
+  for (int f = 0; f < ORC_REC_NFIELDS; ++f) free(e->rec[f]);
   free(e);
 }
 
@@ -773,6 +785,8 @@ typedef struct {
   double *Cblk;           /* 9 per row: block entries stored at the block's first row */
   int *blk_start, *blk_size;  /* per row */
   int *row_kind;          /* 0 joint, 1 contact normal, 2 friction, 3 tet */
+  double *c_alpha, *c_rn, *c_rf;  /* per contact: alpha of the normal row, r factors */
+  int *c_act;             /* per contact: friction rows active */
   int have_prev;
   double *theta_minus;    /* joint drive coordinate at q^- */
   double t_plus;
@@ -1437,6 +1451,7 @@ static void assemble(step_t *S) {
      * err_n = phi / h.  READING: the same alpha-scaled rows are used in the momentum
      * balance (literal form). */
     jrow_scale(rn, al);
+    S->c_alpha[ci] = al; S->c_rn[ci] = r_n; S->c_rf[ci] = r_f; S->c_act[ci] = 0;
     for (int k = 0; k < 3; ++k) {
       S->blk_start[r0 + k] = r0 + k; S->blk_size[r0 + k] = 1;
       memset(S->Cblk + 9 * (r0 + k), 0, 9 * sizeof(double));
@@ -1453,6 +1468,7 @@ static void assemble(step_t *S) {
       W = orc_friction_w(p->ncp, vn, lam_n, lfn, e->mu, r_f);
     }
     if (isfinite(W)) {
+      S->c_act[ci] = 1;
       S->Cblk[9 * (r0 + 1)] = W / h;
       S->Cblk[9 * (r0 + 2)] = W / h;
       S->err[r0 + 1] = v1 + W * lf1;
@@ -1672,6 +1688,42 @@ static void start_iterate(step_t *S) {
   update_positions(S);
 }
 
+/* ---- per-iteration record (test support, not part of the method) ---- */
+static void rec_put(env_t *e, int f, const double *v, int n) {
+  e->rec[f] = realloc(e->rec[f], (size_t)(n > 0 ? n : 1) * sizeof(double));
+  if (n > 0) {
+    if (v) memcpy(e->rec[f], v, (size_t)n * sizeof(double));
+    else memset(e->rec[f], 0, (size_t)n * sizeof(double));
+  }
+  e->rec_len[f] = n;
+}
+static void rec_put_int(env_t *e, int f, const int *v, int n) {
+  rec_put(e, f, NULL, n);
+  for (int i = 0; i < n; ++i) e->rec[f][i] = v[i];
+}
+
+/* orc_eval_iterate: the given iterate in place of the start iterate.  The previous
+ * iterate, when given, is assembled first: its Jacobians and velocities are the
+ * secant's J^{k-1} and u^{k-1}. */
+static void inject_iterate(step_t *S) {
+  env_t *e = S->e;
+  const size_t nrow = (size_t)S->nrows, nd = (size_t)S->ndof;
+  if (e->inj_lam_p) {
+    if (nrow) memcpy(S->lam, e->inj_lam_p, nrow * sizeof(double));
+    if (nd) memcpy(S->u, e->inj_u_p, nd * sizeof(double));
+    if (e->nr) { memcpy(e->rx, e->inj_rx_p, 3 * e->nr * sizeof(double)); memcpy(e->rq, e->inj_rq_p, 4 * e->nr * sizeof(double)); }
+    if (e->np) memcpy(e->px, e->inj_px_p, 3 * e->np * sizeof(double));
+    assemble(S);
+    memcpy(S->Jprev, S->J, nrow * sizeof(jrow));
+    if (nd) memcpy(S->uprev, e->inj_u_p, nd * sizeof(double));
+    S->have_prev = 1;
+  }
+  if (nrow) memcpy(S->lam, e->inj_lam, nrow * sizeof(double));
+  if (nd) memcpy(S->u, e->inj_u, nd * sizeof(double));
+  if (e->nr) { memcpy(e->rx, e->inj_rx, 3 * e->nr * sizeof(double)); memcpy(e->rq, e->inj_rq, 4 * e->nr * sizeof(double)); }
+  if (e->np) memcpy(e->px, e->inj_px, 3 * e->np * sizeof(double));
+}
+
 int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol, orc_stats *st) {
   env_t *e = (env_t *)envp;
   memset(st, 0, sizeof *st);
@@ -1730,6 +1782,13 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
 
   /* collision detection once per step (Alg. 1) */
   generate_contacts(&S);
+  if (e->inj && e->nc != e->inj_nc) {  /* orc_eval_iterate: not the caller's contact set */
+    free(S.x0); free(S.q0); free(S.px0); free(S.Iw); free(S.Iwinv); free(S.ut); free(S.u); free(S.uprev);
+    free(S.Hdiag); free(S.theta_minus);
+    return -2;
+  }
+  if (e->rec_k >= 0)
+    for (int f = 0; f < ORC_REC_NFIELDS; ++f) e->rec_len[f] = 0;
   st->n_contacts = e->nc;
   st->overflow = e->overflow;
   S.nrows = 6 * e->nj + 3 * e->nc + e->tet_rows * e->nt;
@@ -1740,6 +1799,9 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
   S.Cblk = calloc(9 * nr_alloc, sizeof(double));
   S.blk_start = calloc(nr_alloc, sizeof(int)); S.blk_size = calloc(nr_alloc, sizeof(int));
   S.row_kind = calloc(nr_alloc, sizeof(int));
+  const int nc_alloc = e->nc > 0 ? e->nc : 1;
+  S.c_alpha = calloc(nc_alloc, sizeof(double)); S.c_rn = calloc(nc_alloc, sizeof(double));
+  S.c_rf = calloc(nc_alloc, sizeof(double)); S.c_act = calloc(nc_alloc, sizeof(int));
   double *g = calloc(nd, sizeof(double)), *f = calloc(nd, sizeof(double)), *fhat = calloc(nd, sizeof(double));
   double *tmp = calloc(nd, sizeof(double)), *tmp2 = calloc(nd, sizeof(double));
   double *b = calloc(nr_alloc, sizeof(double)), *P = calloc(nr_alloc, sizeof(double));
@@ -1775,6 +1837,7 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
     st->fallback = 1;
   }
   start_iterate(&S);
+  if (e->inj && attempt == 0) inject_iterate(&S);
   e->nhist = 0;
   /* READING (Sec. 8.1 names watchdog strategies without using one): the step keeps
    * its lowest-merit iterate; when the merit grows past WATCH_BLOWUP times that best,
@@ -1789,6 +1852,15 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
    * not count as Newton iterations. */
   double ls_t = 1.0, merit_k = INFINITY;
   for (int k = 0; k <= N; ++k) {
+    const int rec = k == e->rec_k;  /* test support: record this iteration */
+    if (rec) {
+      rec_put(e, ORC_REC_LAM, S.lam, S.nrows);
+      rec_put(e, ORC_REC_U, S.u, S.ndof);
+      rec_put(e, ORC_REC_UPREV, S.have_prev ? S.uprev : NULL, S.ndof);
+      rec_put(e, ORC_REC_RX, e->rx, 3 * e->nr);
+      rec_put(e, ORC_REC_RQ, e->rq, 4 * e->nr);
+      rec_put(e, ORC_REC_PX, e->px, 3 * e->np);
+    }
     assemble(&S);
     /* momentum balance g = M~(u - u~) - h J^T lambda (Sec. 6.1) */
     memset(f, 0, nd * sizeof(double));
@@ -1800,8 +1872,8 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
      * between the last two iterates, particle DOFs only; H~_jj = M~_jj - min(0, c_j). */
     for (int pi = 0; pi < e->np; ++pi)
       for (int a = 0; a < 3; ++a) S.Hdiag[3 * pi + a] = e->pm[pi];
-    if (p->geo_stiff && k >= 1 && S.have_prev) {
-      memset(fhat, 0, nd * sizeof(double));
+    memset(fhat, 0, nd * sizeof(double));
+    if (p->geo_stiff && S.have_prev) {
       for (int r = 0; r < S.nrows; ++r) jrow_scatter(&S.Jprev[r], S.lam[r], fhat);
       for (int pi = 0; pi < e->np; ++pi)
         for (int a = 0; a < 3; ++a) {
@@ -1810,6 +1882,23 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
           double cj = h * (f[dd] - fhat[dd]) * dU / (dU * dU + TAU_GS * TAU_GS);
           S.Hdiag[3 * pi + a] = e->pm[pi] - (cj < 0 ? cj : 0.0);
         }
+    }
+    if (rec) {
+      rec_put(e, ORC_REC_ERR, S.err, S.nrows);
+      rec_put(e, ORC_REC_CDIAG, NULL, S.nrows);
+      for (int r = 0; r < S.nrows; ++r) {
+        int b0 = S.blk_start[r], ri = r - b0;
+        e->rec[ORC_REC_CDIAG][r] = S.Cblk[9 * b0 + 3 * ri + ri];
+      }
+      rec_put(e, ORC_REC_CBLK, S.Cblk, 9 * S.nrows);
+      rec_put(e, ORC_REC_ALPHA, S.c_alpha, e->nc);
+      rec_put(e, ORC_REC_RN, S.c_rn, e->nc);
+      rec_put(e, ORC_REC_RF, S.c_rf, e->nc);
+      rec_put_int(e, ORC_REC_ACTIVE, S.c_act, e->nc);
+      rec_put(e, ORC_REC_G, g, S.ndof);
+      rec_put(e, ORC_REC_F, f, S.ndof);
+      rec_put(e, ORC_REC_FHAT, fhat, S.ndof);
+      rec_put(e, ORC_REC_HDIAG, S.Hdiag, 3 * e->np);
     }
     /* READING of "residual": r_ncp = max(|M~^-1 g|_inf, |err|_inf), merit |[g; err]|_2 */
     apply_Minv(&S, g, tmp);
@@ -1835,6 +1924,10 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
       for (int r = 0; r < S.nrows; ++r)
         if (fabs(S.err[r]) > isl_r[row_isl[r]]) isl_r[row_isl[r]] = fabs(S.err[r]);
     }
+    if (rec) {
+      double rs[4] = {r_ncp, r_con, merit, 0.0};
+      rec_put(e, ORC_REC_RESID, rs, 4);
+    }
     int finite_now = r_ncp == r_ncp && !isinf(r_ncp) && merit == merit && !isinf(merit);
     if (p->line_search && k > 0 && ls_t > LS_TMIN && (!finite_now || merit > (1.0 - LS_SIGMA * ls_t) * merit_k)) {
       ls_t *= 0.5;
@@ -1846,7 +1939,7 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
       continue;
     }
     if (e->nhist < MAX_HIST) { e->mhist[e->nhist] = merit; e->hist[e->nhist++] = r_ncp; }
-    if (finite_now && merit < best_merit) {
+    if (S.p->watchdog && finite_now && merit < best_merit) {
       best_merit = merit; best_r = r_ncp; best_rc = r_con; have_best = 1;
       memcpy(best_lam, S.lam, S.nrows * sizeof(double));
       memcpy(best_u, S.u, S.ndof * sizeof(double));
@@ -1855,11 +1948,11 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
       memcpy(best_px, e->px, 3 * e->np * sizeof(double));
     }
     if (!finite_now) {
-      if (S.p->warm != 0 || !have_best) { st->nonfinite = 1; break; }
+      if (!S.p->watchdog || S.p->warm != 0 || !have_best) { st->nonfinite = 1; break; }
       restore = 1;
       break;
     }
-    if (merit > WATCH_BLOWUP * best_merit) { restore = 1; break; }
+    if (S.p->watchdog && merit > WATCH_BLOWUP * best_merit) { restore = 1; break; }
     if (k == N || r_ncp <= tol) break;
     /* Schur right-hand side and Jacobi preconditioner (Sec. 6.2, 8.2, 8.4) */
     apply_Hinv(&S, g, tmp);
@@ -1869,6 +1962,16 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
       P[r] = 1.0 / (row_hdiag(&S, &S.J[r]) + S.Cblk[9 * b0 + 3 * ri + ri] + p->eps);
     }
     schur_ctx sc = {&S, tmp, tmp2};
+    if (rec) {
+      rec_put(e, ORC_REC_B, b, S.nrows);
+      rec_put(e, ORC_REC_P, P, S.nrows);
+      /* one product A z with z = P b (the first product of the PCR) */
+      double *z = calloc(nr_alloc, sizeof(double)), *az = calloc(nr_alloc, sizeof(double));
+      for (int r = 0; r < S.nrows; ++r) z[r] = P[r] * b[r];
+      schur_apply(&sc, z, az);
+      rec_put(e, ORC_REC_AZ, az, S.nrows);
+      free(z); free(az);
+    }
     int done = 0;
     if (p->islands && p->linear == 0) {
       /* READING of Sec. 11's island remedy: one PCR per island.  A is block diagonal
@@ -1905,6 +2008,10 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
                             : pcr_solve(S.nrows, schur_apply, &sc, b, P, M, x, NULL);
     }
     cr_total += done;
+    if (rec) {
+      rec_put(e, ORC_REC_DLAM, x, S.nrows);
+      if (e->rec_len[ORC_REC_RESID] == 4) e->rec[ORC_REC_RESID][3] = done;
+    }
     /* du = H~^-1 (h J^T dlambda - g); damped update (Sec. 6.2, 8.1) */
     memset(f, 0, nd * sizeof(double));
     for (int r = 0; r < S.nrows; ++r) jrow_scatter(&S.J[r], x[r], f);
@@ -1986,6 +2093,7 @@ int orc_step(void *envp, const orc_params *p, double h, int N, int M, double tol
   free(S.x0); free(S.q0); free(S.px0); free(S.Iw); free(S.Iwinv); free(S.ut); free(S.u); free(S.uprev);
   free(S.Hdiag); free(S.theta_minus); free(S.lam); free(S.J); free(S.Jprev); free(S.err); free(S.Cblk);
   free(S.blk_start); free(S.blk_size); free(S.row_kind);
+  free(S.c_alpha); free(S.c_rn); free(S.c_rf); free(S.c_act);
   free(g); free(f); free(fhat); free(tmp); free(tmp2); free(b); free(P); free(x); free(du); free(row_isl); free(body_isl); free(isl_r);
   return st->nonfinite ? -4 : 0;
 }
@@ -2072,6 +2180,62 @@ int orc_get_merit_history(void *p, double *m, int cap) {
   int n = e->nhist < cap ? e->nhist : cap;
   memcpy(m, e->mhist, n * sizeof(double));
   return n;
+}
+
+void orc_set_record(void *p, int k) {
+  env_t *e = (env_t *)p;
+  e->rec_k = k;
+  for (int f = 0; f < ORC_REC_NFIELDS; ++f) e->rec_len[f] = 0;
+}
+
+int orc_get_record(void *p, int field, double *out, int cap) {
+  env_t *e = (env_t *)p;
+  if (field < 0 || field >= ORC_REC_NFIELDS) return -1;
+  int n = e->rec_len[field];
+  if (out && n > 0) memcpy(out, e->rec[field], (size_t)(n < cap ? n : cap) * sizeof(double));
+  return n;
+}
+
+static double *dup_d(const double *a, int n) {
+  double *b = malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  if (n > 0) memcpy(b, a, (size_t)n * sizeof(double));
+  return b;
+}
+
+int orc_eval_iterate(void *p, const orc_params *prm, double h, int M, int n_contacts, const double *lam,
+                     const double *u, const double *rx, const double *rq, const double *px, const double *lam_p,
+                     const double *u_p, const double *rx_p, const double *rq_p, const double *px_p) {
+  env_t *e = (env_t *)p;
+  if (!lam || !u || (e->nr && (!rx || !rq)) || (e->np && !px) || n_contacts < 0) return -1;
+  if (lam_p && (!u_p || (e->nr && (!rx_p || !rq_p)) || (e->np && !px_p))) return -1;
+  /* the state and previous-step bookkeeping the step would change */
+  double *rx0 = dup_d(e->rx, 3 * e->nr), *rq0 = dup_d(e->rq, 4 * e->nr), *rv0 = dup_d(e->rv, 3 * e->nr);
+  double *rw0 = dup_d(e->rw, 3 * e->nr), *px0 = dup_d(e->px, 3 * e->np), *pv0 = dup_d(e->pv, 3 * e->np);
+  double *lj0 = dup_d(e->lam_joint_prev, 6 * e->nj), *lt0 = dup_d(e->lam_tet_prev, e->tet_rows * e->nt);
+  contact *prev0 = malloc((size_t)(e->maxc > 0 ? e->maxc : 1) * sizeof(contact));
+  memcpy(prev0, e->prev, (size_t)e->nprev * sizeof(contact));
+  const int nprev0 = e->nprev, have_prev0 = e->have_prev, rec_k0 = e->rec_k;
+  const double time0 = e->time;
+  e->inj = 1; e->inj_nc = n_contacts;
+  e->inj_lam = lam; e->inj_u = u; e->inj_rx = rx; e->inj_rq = rq; e->inj_px = px;
+  e->inj_lam_p = lam_p; e->inj_u_p = u_p; e->inj_rx_p = rx_p; e->inj_rq_p = rq_p; e->inj_px_p = px_p;
+  e->rec_k = 0;
+  orc_params q = *prm;
+  q.warm = 0;          /* the injected iterate replaces any start iterate */
+  q.line_search = 0;
+  orc_stats st;
+  int rc = orc_step(e, &q, h, 1, M, 0.0, &st);
+  e->inj = 0;
+  e->rec_k = rec_k0;
+  memcpy(e->rx, rx0, 3 * e->nr * sizeof(double)); memcpy(e->rq, rq0, 4 * e->nr * sizeof(double));
+  memcpy(e->rv, rv0, 3 * e->nr * sizeof(double)); memcpy(e->rw, rw0, 3 * e->nr * sizeof(double));
+  memcpy(e->px, px0, 3 * e->np * sizeof(double)); memcpy(e->pv, pv0, 3 * e->np * sizeof(double));
+  memcpy(e->lam_joint_prev, lj0, 6 * e->nj * sizeof(double));
+  memcpy(e->lam_tet_prev, lt0, (size_t)e->tet_rows * e->nt * sizeof(double));
+  memcpy(e->prev, prev0, (size_t)nprev0 * sizeof(contact));
+  e->nprev = nprev0; e->have_prev = have_prev0; e->time = time0;
+  free(rx0); free(rq0); free(rv0); free(rw0); free(px0); free(pv0); free(lj0); free(lt0); free(prev0);
+  return rc;
 }
 
 int orc_get_rows_debug(void *p, double *err, double *cdiag, double *pdiag, int cap) {

@@ -67,6 +67,9 @@ typedef struct {
   int32_t line_search; /* 1: back-tracking on the L2 merit from t = 1 instead of the constant damping */
   int32_t linear;      /* 0 preconditioned conjugate residual (the method), 1 preconditioned conjugate gradient */
   int32_t islands;     /* 1: one PCR per island of the env (independent CR scalars) */
+  int32_t watchdog;    /* 1: keep the step's lowest-merit iterate and return it when the merit
+                          blows up (Sec. 8.1 names such safeguards without using one); 0: the
+                          method as the paper runs it, every iterate accepted */
 } orc_params;
 
 typedef struct {
@@ -108,6 +111,52 @@ int orc_get_merit_history(void *env, double *m, int cap);
 int orc_set_prev(void *env, int n, const int64_t *keys, const double *lam3, const double *lam_joint);
 /* per-row data of the final assembly of the last step */
 int orc_get_rows_debug(void *env, double *err, double *cdiag, double *pdiag, int cap);
+
+/* ---- per-iteration record (test support) ----
+ * orc_set_record(env, k): the following steps record Newton iteration k (-1 = off;
+ * with line search, the accepted point of iteration k): the iterate it starts from
+ * and its assembly, residual, geometric stiffness, Schur system and PCR solution.
+ * orc_get_record(env, field, out, cap) copies one field (ORC_REC_*), returns its length
+ * (0 when iteration k was not reached).  Rows are in the oracle's order: joints
+ * (6 each), contacts (3 each), tets (3 or 6 each). */
+#define ORC_REC_LAM 0     /* [rows] multipliers lambda^k */
+#define ORC_REC_U 1       /* [ndof] velocities u^k (6 per rigid body, then 3 per particle) */
+#define ORC_REC_RX 2      /* [3 n_rigid] positions at iterate k */
+#define ORC_REC_RQ 3      /* [4 n_rigid] */
+#define ORC_REC_PX 4      /* [3 n_particles] */
+#define ORC_REC_ERR 5     /* [rows] constraint error vector */
+#define ORC_REC_CDIAG 6   /* [rows] diagonal of the compliance block C */
+#define ORC_REC_P 7       /* [rows] Jacobi preconditioner 1/(J H~^-1 J^T + C + eps)_ii */
+#define ORC_REC_B 8       /* [rows] Schur right-hand side (J H~^-1 g - err)/h */
+#define ORC_REC_AZ 9      /* [rows] A z for z = P b, A = J H~^-1 J^T + C + eps I */
+#define ORC_REC_DLAM 10   /* [rows] PCR solution Delta lambda */
+#define ORC_REC_G 11      /* [ndof] momentum residual g = M~(u - u~) - h J^T lambda */
+#define ORC_REC_HDIAG 12  /* [3 n_particles] diagonal of H~ on particle DOFs */
+#define ORC_REC_ALPHA 13  /* [n_contacts] alpha of the normal row */
+#define ORC_REC_RN 14     /* [n_contacts] r of the normal row */
+#define ORC_REC_RF 15     /* [n_contacts] r of the friction rows */
+#define ORC_REC_CBLK 16   /* [9 rows] compliance block, 3x3 row-major, at the block's first row */
+#define ORC_REC_F 17      /* [ndof] J^T lambda^k */
+#define ORC_REC_FHAT 18   /* [ndof] (J^{k-1})^T lambda^k, the secant's other force (0 if none) */
+#define ORC_REC_UPREV 19  /* [ndof] u^{k-1} (0 if none) */
+#define ORC_REC_ACTIVE 20 /* [n_contacts] 1 where the friction rows are active */
+#define ORC_REC_RESID 21  /* [4] r_ncp, r_contact, merit, cr iterations of iteration k */
+void orc_set_record(void *env, int k);
+int orc_get_record(void *env, int field, double *out, int cap);
+
+/* Evaluate one Newton iteration at a given iterate (test support).  Runs the step
+ * set-up and collision detection at the env's current state (q^-, u^-), puts the
+ * iterate (lam, u, rx, rq, px) in place of the start iterate, and records iteration 0
+ * of that step (orc_get_record): assembly, residual, Schur system, PCR of M
+ * iterations.  The previous iterate (lam_p, u_p, rx_p, rq_p, px_p), when given, is
+ * assembled first and supplies J^{k-1} and u^{k-1} to the geometric-stiffness secant
+ * (NULL: no previous iterate, no secant).  lam and lam_p hold the rows of the contact
+ * set found at q^- (orc_num_contacts after the call tells its size; -2 if it differs
+ * from n_contacts).  The env's state and previous-step data are left unchanged. */
+int orc_eval_iterate(void *env, const orc_params *p, double h, int M, int n_contacts,
+                     const double *lam, const double *u, const double *rx, const double *rq,
+                     const double *px, const double *lam_p, const double *u_p, const double *rx_p,
+                     const double *rq_p, const double *px_p);
 
 /* ---- primitives exposed for the pins ---- */
 void orc_ncp_fb(double C, double lam, double r, double *phi, double *alpha, double *beta);

@@ -13,6 +13,11 @@ import numpy as np
 from . import build as _build
 
 _LIB = None
+_LIBS = {}
+
+# per-iteration record fields (nsn_oracle.h ORC_REC_*)
+REC_FIELDS = ["lam", "u", "rx", "rq", "px", "err", "cdiag", "P", "b", "Az", "dlam", "g", "hdiag",
+              "alpha", "rn", "rf", "cblk", "f", "fhat", "uprev", "active", "resid"]
 
 D = C.POINTER(C.c_double)
 I32 = C.POINTER(C.c_int32)
@@ -38,7 +43,7 @@ class Params(C.Structure):
     _fields_ = [("ncp", C.c_int32), ("rmode", C.c_int32), ("damping", C.c_double),
                 ("eps", C.c_double), ("geo_stiff", C.c_int32), ("fem_mode", C.c_int32),
                 ("margin", C.c_double), ("warm", C.c_int32), ("line_search", C.c_int32),
-                ("linear", C.c_int32), ("islands", C.c_int32)]
+                ("linear", C.c_int32), ("islands", C.c_int32), ("watchdog", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -53,14 +58,26 @@ class Stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
-def lib():
+def lib(path=None):
+    """The oracle library (built on first use), or the one at `path` (a variant built
+    by a test, e.g. with a planted mistake)."""
     global _LIB
+    if path is not None:
+        if path not in _LIBS:
+            _LIBS[path] = _bind(C.CDLL(path))
+        return _LIBS[path]
     if _LIB is None:
         path = _build.LIB
         src = _build.SRC
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src) or \
+                os.path.getmtime(path) < os.path.getmtime(_build.HDR):
             _build.build()
-        L = C.CDLL(path)
+        _LIB = _bind(C.CDLL(path))
+    return _LIB
+
+
+def _bind(L):
+    if True:
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [C.POINTER(_Desc), C.c_char_p, C.c_int]
         L.orc_destroy.argtypes = [C.c_void_p]
@@ -99,8 +116,10 @@ def lib():
         L.orc_mlp_loss_grad.restype = C.c_double
         L.orc_mlp_loss_grad.argtypes = [D, C.c_int64, D, D, D]
         L.orc_contact_features.argtypes = [C.c_void_p, C.POINTER(Params), C.c_double, D, I64, C.c_int]
-        _LIB = L
-    return _LIB
+        L.orc_set_record.argtypes = [C.c_void_p, C.c_int]
+        L.orc_get_record.argtypes = [C.c_void_p, C.c_int, D, C.c_int]
+        L.orc_eval_iterate.argtypes = [C.c_void_p, C.POINTER(Params), C.c_double, C.c_int, C.c_int] + [D] * 10
+    return L
 
 
 def _d(a):
@@ -114,7 +133,7 @@ def _i32(a):
 def make_params(sp=None, **kw):
     """Oracle parameter struct from a scene_inputs.SolverParams (or keywords)."""
     vals = dict(ncp=0, rmode=2, damping=0.75, eps=1e-6, geo_stiff=1, fem_mode=0,
-                margin=5e-3, warm=0, line_search=0, linear=0, islands=0)
+                margin=5e-3, warm=0, line_search=0, linear=0, islands=0, watchdog=0)
     if sp is not None:
         for k in vals:
             vals[k] = getattr(sp, k)
@@ -123,11 +142,13 @@ def make_params(sp=None, **kw):
 
 
 class OracleEnv:
-    """One environment stepped by the FP64 oracle."""
+    """One environment stepped by the FP64 oracle (lib_path: a variant of the library,
+    for tests that plant a mistake in it)."""
 
-    def __init__(self, desc):
+    def __init__(self, desc, lib_path=None):
         self.desc = desc
-        L = lib()
+        self._lib = lib(lib_path)
+        L = self._lib
         self._keep = {}
 
         def arr(name, dtype):
@@ -161,20 +182,20 @@ class OracleEnv:
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().orc_destroy(self.h)
+            self._lib.orc_destroy(self.h)
             self.h = None
 
     def step(self, h, newton_iters, cr_iters, tol=0.0, params=None):
         p = params if params is not None else make_params()
         st = Stats()
-        lib().orc_step(self.h, C.byref(p), float(h), int(newton_iters), int(cr_iters), float(tol),
+        self._lib.orc_step(self.h, C.byref(p), float(h), int(newton_iters), int(cr_iters), float(tol),
                        C.byref(st))
         return st.as_dict()
 
     def get_state(self):
         rx = np.zeros((self.nr, 3)); rq = np.zeros((self.nr, 4)); rv = np.zeros((self.nr, 3))
         rw = np.zeros((self.nr, 3)); px = np.zeros((self.np_, 3)); pv = np.zeros((self.np_, 3))
-        lib().orc_get_state(self.h, _d(rx), _d(rq), _d(rv), _d(rw), _d(px), _d(pv))
+        self._lib.orc_get_state(self.h, _d(rx), _d(rq), _d(rv), _d(rw), _d(px), _d(pv))
         return dict(rigid_x=rx, rigid_q=rq, rigid_v=rv, rigid_w=rw, particle_x=px, particle_v=pv)
 
     def set_state(self, st):
@@ -182,33 +203,33 @@ class OracleEnv:
         rx, rq, rv, rw = (g("rigid_x", (self.nr, 3)), g("rigid_q", (self.nr, 4)),
                           g("rigid_v", (self.nr, 3)), g("rigid_w", (self.nr, 3)))
         px, pv = g("particle_x", (self.np_, 3)), g("particle_v", (self.np_, 3))
-        lib().orc_set_state(self.h, _d(rx), _d(rq), _d(rv), _d(rw), _d(px), _d(pv))
+        self._lib.orc_set_state(self.h, _d(rx), _d(rq), _d(rv), _d(rw), _d(px), _d(pv))
 
     @property
     def time(self):
-        return lib().orc_get_time(self.h)
+        return self._lib.orc_get_time(self.h)
 
     @time.setter
     def time(self, t):
-        lib().orc_set_time(self.h, float(t))
+        self._lib.orc_set_time(self.h, float(t))
 
     def contacts(self):
-        n = lib().orc_num_contacts(self.h)
+        n = self._lib.orc_num_contacts(self.h)
         key = np.zeros(max(n, 1), np.int64); bodies = np.zeros((max(n, 1), 2), np.int32)
         geom = np.zeros((max(n, 1), 10)); lam = np.zeros((max(n, 1), 3))
-        lib().orc_get_contacts(self.h, key.ctypes.data_as(I64), _i32(bodies), _d(geom), _d(lam), n)
+        self._lib.orc_get_contacts(self.h, key.ctypes.data_as(I64), _i32(bodies), _d(geom), _d(lam), n)
         return dict(key=key[:n], bodies=bodies[:n], normal=geom[:n, 0:3], a_local=geom[:n, 3:6],
                     b_local=geom[:n, 6:9], thickness=geom[:n, 9], lam=lam[:n])
 
     def lambdas(self):
-        n = lib().orc_num_rows(self.h)
+        n = self._lib.orc_num_rows(self.h)
         out = np.zeros(max(n, 1))
-        lib().orc_get_lambda(self.h, _d(out))
+        self._lib.orc_get_lambda(self.h, _d(out))
         return out[:n]
 
     def history(self):
         out = np.zeros(256)
-        n = lib().orc_get_history(self.h, _d(out), 256)
+        n = self._lib.orc_get_history(self.h, _d(out), 256)
         return out[:n]
 
     def set_prev(self, keys, lam3, lam_joint):
@@ -218,34 +239,75 @@ class OracleEnv:
         lj = np.ascontiguousarray(lam_joint, dtype=np.float64).reshape(-1)
         self._keep["prev"] = (k, l3, lj)
         assert lj.size == 6 * self.desc.n_joints
-        st = lib().orc_set_prev(self.h, k.size, k.ctypes.data_as(I64), _d(l3), _d(lj) if lj.size else None)
+        st = self._lib.orc_set_prev(self.h, k.size, k.ctypes.data_as(I64), _d(l3), _d(lj) if lj.size else None)
         if st != 0:
             raise ValueError("orc_set_prev: bad keys or count")
 
     def merit_history(self):
         out = np.zeros(256)
-        n = lib().orc_get_merit_history(self.h, _d(out), 256)
+        n = self._lib.orc_get_merit_history(self.h, _d(out), 256)
         return out[:n]
 
     def rows_debug(self):
-        n = lib().orc_num_rows(self.h)
+        n = self._lib.orc_num_rows(self.h)
         e, c, p = np.zeros(max(n, 1)), np.zeros(max(n, 1)), np.zeros(max(n, 1))
-        lib().orc_get_rows_debug(self.h, _d(e), _d(c), _d(p), n)
+        self._lib.orc_get_rows_debug(self.h, _d(e), _d(c), _d(p), n)
         return e[:n], c[:n], p[:n]
 
     def set_mlp(self, blob):
         if blob is None:
-            lib().orc_set_mlp(self.h, None, 0)
+            self._lib.orc_set_mlp(self.h, None, 0)
             return
         b = np.ascontiguousarray(blob, dtype=np.float64)
         self._keep["mlp"] = b
-        lib().orc_set_mlp(self.h, _d(b), b.size)
+        self._lib.orc_set_mlp(self.h, _d(b), b.size)
+
+    def set_record(self, k):
+        """Record Newton iteration k of the following steps (-1: off)."""
+        self._lib.orc_set_record(self.h, int(k))
+
+    def record(self):
+        """The recorded iteration: {field: array} (oracle row order: joints, contacts,
+        tets); empty arrays for fields the iteration did not reach."""
+        out = {}
+        for i, name in enumerate(REC_FIELDS):
+            n = self._lib.orc_get_record(self.h, i, None, 0)
+            a = np.zeros(max(n, 1))
+            if n > 0:
+                self._lib.orc_get_record(self.h, i, _d(a), n)
+            out[name] = a[:max(n, 0)]
+        return out
+
+    def eval_iterate(self, h, M, n_contacts, it, prev=None, params=None):
+        """One Newton iteration at a given iterate from the env's current state (q^-,
+        u^-): it = dict(lam, u, rx, rq, px) (oracle row order, u = 6 per rigid body then
+        3 per particle); prev: the previous iterate (same keys) for the secant, or None.
+        Returns record() of that iteration."""
+        p = params if params is not None else make_params()
+        f = lambda a: np.ascontiguousarray(a, np.float64).ravel()
+        cur = [f(it[k]) for k in ["lam", "u", "rx", "rq", "px"]]
+        cur = [a if a.size else np.zeros(1) for a in cur]
+        self._keep["inj"] = cur
+        if prev is not None:
+            pv = [f(prev[k]) for k in ["lam", "u", "rx", "rq", "px"]]
+            pv = [a if a.size else np.zeros(1) for a in pv]
+            self._keep["inj_p"] = pv
+            pptr = [_d(a) for a in pv]
+        else:
+            pptr = [None] * 5
+        rc = self._lib.orc_eval_iterate(self.h, C.byref(p), float(h), int(M), int(n_contacts),
+                                        *[_d(a) for a in cur], *pptr)
+        if rc == -2:
+            raise ValueError("orc_eval_iterate: the contact set at q^- differs from the caller's")
+        if rc not in (0, -4):
+            raise ValueError(f"orc_eval_iterate failed ({rc})")
+        return self.record()
 
     def contact_features(self, h, params=None):
         p = params if params is not None else make_params()
         cap = self.desc.max_contacts
         feat = np.zeros((max(cap, 1), 12)); key = np.zeros(max(cap, 1), np.int64)
-        n = lib().orc_contact_features(self.h, C.byref(p), float(h), _d(feat), key.ctypes.data_as(I64), cap)
+        n = self._lib.orc_contact_features(self.h, C.byref(p), float(h), _d(feat), key.ctypes.data_as(I64), cap)
         n = min(n, cap)
         return feat[:n], key[:n]
 

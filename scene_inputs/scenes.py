@@ -48,6 +48,8 @@ class SolverParams:
     line_search: int = 0           # 1: back-tracking on the L2 merit (frictionless scenes)
     linear: int = 0                # 0 PCR (the method), 1 PCG (comparison solver)
     islands: int = 0               # 1: independent PCR scalars per island of an env
+    watchdog: int = 0              # 1: return the step's lowest-merit iterate when the merit
+                                   # blows up (a safeguard Sec. 8.1 names); 0: the paper's method
 
 
 @dataclasses.dataclass
