@@ -144,6 +144,10 @@ typedef struct {
   int32_t islands;   /* 1: one PCR per island of an env (dynamic bodies connected by joints,
                         tets and contacts; Sec. 11), each with its own scalars and stop;
                         PCR only.  0 (default): one PCR over the whole env */
+  int32_t watchdog;  /* 1: the step keeps its lowest-merit iterate and returns it when the
+                        merit grows past 1e6 times that best or turns non-finite (a
+                        safeguard Sec. 8.1 names without using it); 0 (default): the
+                        paper's method, every damped iterate accepted */
 } nsn_solver_params;
 
 typedef struct {
@@ -182,27 +186,86 @@ typedef struct {
                                twice), times the PCR iterations performed */
 } nsn_accum;
 
+/* One contact handed to nsn_set_contacts, in the form collision detection produces it
+ * (Sec. 3: a feature point on body A, a point on body B or the world, the normal
+ * fixed for the step at q^-, and a thickness; Alg. 1 runs detection once per step).
+ * Bodies are env-local: rigid body i -> i, particle p -> n_rigid + p, -1 = the ground
+ * plane (target only). */
+typedef struct {
+  int32_t key;         /* unique id, strictly ascending over the list; the library's own
+                          detection uses feature * n_targets + target (features: box
+                          vertices and capsule ends of rigid bodies in body order, then
+                          particles; targets: the ground if present, then rigid bodies) */
+  int32_t body_a;      /* feature body (rigid or particle); non-decreasing over the list */
+  int32_t body_b;      /* target body (rigid) or -1 */
+  float normal[3];     /* unit contact normal (world), pointing from B towards A */
+  float a_local[3];    /* feature point in A's body frame (ignored for particles) */
+  float b_local[3];    /* target point in B's body frame, or in the world for the ground */
+  float thickness;     /* d: C = n.(a - b) - d */
+} nsn_contact;
+
+/* Fields of the per-iteration record (nsn_dump_iteration, nsn_read_iteration).  Row
+ * arrays are in the library's row order: joints (6 rows each), tets (3 rows each, or 6
+ * for NSN_TET_LINEAR), contacts (3 rows each: normal, friction 1, friction 2).
+ * Body-space arrays hold 6 entries per rigid body (v, omega_world) then 3 per
+ * particle. */
+#define NSN_IT_LAM 0       /* [rows] multipliers lambda^k the iteration starts from */
+#define NSN_IT_ERR 1       /* [rows] constraint error err (Sec. 6.1; App. A, B) */
+#define NSN_IT_CDIAG 2     /* [rows] diagonal of the compliance block C */
+#define NSN_IT_P 3         /* [rows] Jacobi preconditioner 1/(J H~^-1 J^T + C + eps)_ii (Sec. 8.2) */
+#define NSN_IT_B 4         /* [rows] Schur right-hand side (J H~^-1 g - err)/h (Sec. 6.2) */
+#define NSN_IT_AZ 5        /* [rows] A z for z = P b, A = J H~^-1 J^T + C + eps I */
+#define NSN_IT_DLAM 6      /* [rows] the linear solve's Delta lambda */
+#define NSN_IT_TETC 7      /* [6 per tet] compliance block E/h^2 of the tet's normal rows
+                              (xx yy zz xy xz yz; App. B eq. E for neo-Hookean tets) */
+#define NSN_IT_ALPHA 8     /* [per contact] alpha of the normal row (App. A) */
+#define NSN_IT_ACTIVE 9    /* [per contact] 1 where the friction rows are active, else 0 */
+#define NSN_IT_G 10        /* [body space] momentum residual g = M~(u - u~) - h J^T lambda */
+#define NSN_IT_U 11        /* [body space] velocities u^k */
+#define NSN_IT_HDIAG 12    /* [3 per particle] diagonal of H~ (Sec. 8.3) */
+#define NSN_IT_RX 13       /* [3 per rigid body] positions at iterate k */
+#define NSN_IT_RQ 14       /* [4 per rigid body] orientations at iterate k */
+#define NSN_IT_PX 15       /* [3 per particle] particle positions at iterate k */
+#define NSN_IT_PREV_LAM 16 /* iterate k-1 (k >= 1), same layouts as the fields above */
+#define NSN_IT_PREV_U 17
+#define NSN_IT_PREV_RX 18
+#define NSN_IT_PREV_RQ 19
+#define NSN_IT_PREV_PX 20
+#define NSN_IT_NFIELDS 21
+
 /* Last error message of the calling thread ("" if none).  Never NULL. */
 const char *nsn_last_error(void);
 
-/* Bytes of device workspace needed for these environments.  n_envs >= 1.
- * Returns NSN_EINVAL on malformed descriptors (see nsn_create_scene). */
-nsn_status nsn_query_workspace(const nsn_env_desc *envs, int32_t n_envs, size_t *bytes);
+/* Bytes of device workspace for these environments under these parameters (Sec. 6:
+ * the Newton system's rows and body-space vectors; every array of a step lives in it).
+ * n_envs >= 1.  params may be NULL for the defaults; its islands and line_search
+ * fields decide whether the buffers of those options (Sec. 11, Sec. 8.1) are reserved,
+ * and a scene created without them rejects turning them on later.  Returns NSN_EINVAL
+ * on malformed descriptors or parameters (see nsn_create_scene). */
+nsn_status nsn_query_workspace(const nsn_env_desc *envs, int32_t n_envs, const nsn_solver_params *params,
+                               size_t *bytes);
 
-/* Validate the descriptors, build the device layout in `workspace` (a device
- * pointer of at least the queried size, 256-byte aligned) and bind the scene to
- * `hip_stream` (a hipStream_t, or NULL).  Errors: NSN_EINVAL for bad sizes, indices,
- * masses, inertias, degenerate rest tets or materials, NSN_ENOMEM if the workspace is
- * too small, NSN_EUNSUPPORTED if an env exceeds the kernel limits, NSN_EDEVICE on a
- * HIP failure.  On success *out owns host bookkeeping only; free it with
- * nsn_destroy_scene (the workspace stays the caller's). */
+/* Validate the descriptors (the problem statement of Sec. 5: state (q^-, u^-), masses,
+ * bilateral constraints, contact geometry, friction coefficient), build the device
+ * layout in `workspace` (a device pointer of at least nsn_query_workspace(envs, n_envs,
+ * p) bytes, 256-byte aligned) and bind the scene to `hip_stream` (a hipStream_t, or
+ * NULL).  Errors: NSN_EINVAL for bad sizes, indices, masses, inertias, degenerate rest
+ * tets or materials, NSN_ENOMEM if the workspace is too small, NSN_EUNSUPPORTED if an
+ * env exceeds the kernel limits, NSN_EDEVICE on a HIP failure.  On success *out owns
+ * host bookkeeping only; free it with nsn_destroy_scene (the workspace stays the
+ * caller's). */
 nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_solver_params *p,
                             void *hip_stream, void *workspace, size_t workspace_bytes,
                             nsn_scene *out);
 
+/* Release the host bookkeeping of a scene (NULL is accepted).  The workspace is the
+ * caller's and is not touched. */
 nsn_status nsn_destroy_scene(nsn_scene s);
 
-/* Replace the solver parameters (takes effect at the next step). */
+/* Replace the solver parameters (the method's choices of Sec. 4, 7 and 8; takes
+ * effect at the next step).  NSN_ESTATE for islands or line search when the scene's
+ * workspace was sized without them, and for a learned warm start before
+ * nsn_set_warm_start_model. */
 nsn_status nsn_set_params(nsn_scene s, const nsn_solver_params *p);
 
 /* One time step of every env (Algorithm 1) enqueued on the scene's stream:
@@ -210,46 +273,81 @@ nsn_status nsn_set_params(nsn_scene s, const nsn_solver_params *p);
  * `cr_iters` PCR iterations each.  tol > 0: an env stops as soon as its residual
  * r_ncp <= tol (checked before each update); tol = 0: fixed iteration counts.
  * The step sequence is captured once into a hipGraph per (h, iterations, tol) and
- * replayed.  Errors: NSN_EINVAL for h <= 0 or negative counts; NSN_ESTATE in a learned
+ * replayed.  stats: NULL keeps the call asynchronous; else a host array of n_envs
+ * records that receives the step's statistics (the call then synchronises the
+ * stream).  Errors: NSN_EINVAL for h <= 0 or negative counts; NSN_ESTATE in a learned
  * warm-start mode before nsn_set_warm_start_model. */
-nsn_status nsn_step(nsn_scene s, double h, int32_t newton_iters, int32_t cr_iters, double tol);
+nsn_status nsn_step(nsn_scene s, double h, int32_t newton_iters, int32_t cr_iters, double tol,
+                    nsn_step_stats *stats);
 
-/* Statistics of the last step for every env: out[n_envs] (host).  Synchronises. */
+/* Statistics of the last step for every env (Sec. 8.1 residual and merit, iteration
+ * counts): out[n_envs] (host).  Synchronises. */
 nsn_status nsn_get_stats(nsn_scene s, nsn_step_stats *out);
 
-/* Copy the state of one env to caller-owned host arrays sized by its descriptor
- * (any pointer may be NULL to skip).  Synchronises the stream. */
+/* Copy the state (q, u) of Sec. 5 of one env to caller-owned host arrays sized by its
+ * descriptor (any pointer may be NULL to skip).  Synchronises the stream. */
 nsn_status nsn_read_state(nsn_scene s, int32_t env, float *rigid_x, float *rigid_q, float *rigid_v,
                           float *rigid_w, float *particle_x, float *particle_v, double *time);
 
-/* Overwrite the state of one env (NULL pointers keep the current values).
- * Quaternions are normalised.  Static bodies keep zero velocity.  Enqueued on the
- * stream; the host arrays may be freed on return. */
+/* Overwrite the state (q, u) of one env (NULL pointers keep the current values).
+ * Quaternions are normalised (Sec. 9 rigid bodies).  Static bodies keep zero velocity.
+ * Enqueued on the stream; the host arrays may be freed on return. */
 nsn_status nsn_write_state(nsn_scene s, int32_t env, const float *rigid_x, const float *rigid_q,
                            const float *rigid_v, const float *rigid_w, const float *particle_x,
                            const float *particle_v, const double *time);
 
-/* Contacts of one env from the last step: up to `cap` records.  *n receives the
- * count.  keys[cap]; bodies[cap*2] = (feature body, target body) with particles
- * numbered after rigid bodies and -1 = ground; geom[cap*10] = normal(3), feature
- * point (body frame / unused for particles)(3), target point (body frame or world)(3),
- * thickness; lam[cap*3] = (lambda_n, lambda_f1, lambda_f2).  Synchronises. */
+/* Contacts of one env from the last step (Alg. 1 collision detection; multipliers of
+ * Sec. 3/4): up to `cap` records.  *n receives the count.  keys[cap]; bodies[cap*2] =
+ * (feature body, target body) numbered as in nsn_contact; geom[cap*10] = normal(3),
+ * feature point (body frame / unused for particles)(3), target point (body frame or
+ * world)(3), thickness; lam[cap*3] = (lambda_n, lambda_f1, lambda_f2).  Synchronises. */
 nsn_status nsn_read_contacts(nsn_scene s, int32_t env, int32_t cap, int32_t *n, int32_t *keys,
                              int32_t *bodies, float *geom, float *lam);
 
-/* Full multiplier vector of one env in row order (joints: 6 rows each, tets: 3 each
- * or 6 for NSN_TET_LINEAR, contacts: 3 each); *n receives the row count.
- * Synchronises. */
+/* Replace collision detection (Alg. 1, "CollisionDetect") of one env for the NEXT step
+ * only by the caller's contact list: n records, 0 <= n <= max_contacts, keys strictly
+ * ascending, feature bodies non-decreasing, bodies in range, normals finite.  The list
+ * is copied to the device on the stream before return (the host array may be freed).
+ * Used to run both sides of a comparison on one contact set.  NSN_EINVAL on a list
+ * that breaks these rules. */
+nsn_status nsn_set_contacts(nsn_scene s, int32_t env, const nsn_contact *contacts, int32_t n);
+
+/* Full multiplier vector lambda of one env (Sec. 6.1) in row order (joints: 6 rows
+ * each, tets: 3 each or 6 for NSN_TET_LINEAR, contacts: 3 each); *n receives the row
+ * count.  Synchronises. */
 nsn_status nsn_read_lambda(nsn_scene s, int32_t env, int32_t cap, int32_t *n, float *lam);
 
-/* Warm-start model for NSN_WARM_LEARNED and NSN_WARM_HYBRID: float32 blob of 9347 MLP
- * parameters
+/* Run ONE time step of every env that stops inside Newton iteration k (Alg. 1): the
+ * first k damped updates as in nsn_step with tol = 0, then iteration k's assembly,
+ * residual, geometric stiffness, Schur right-hand side and preconditioner, one
+ * product A (P b), and `cr_iters` linear iterations; its update is not applied.  The
+ * step is not captured in a graph and the call synchronises.  Afterwards the scene
+ * holds iterate k in its working arrays, readable with nsn_read_iteration: positions
+ * at iterate k, the pre-step velocities, the pre-step time, and the previous step's
+ * contact multipliers for warm starts are left as they were.  Restore the pre-step
+ * positions with nsn_write_state before stepping on.  The watchdog is off for this
+ * step.  NSN_EINVAL for k < 0, cr_iters < 0 or h <= 0; NSN_EUNSUPPORTED with line search
+ * on. */
+nsn_status nsn_dump_iteration(nsn_scene s, double h, int32_t k, int32_t cr_iters);
+
+/* One field (NSN_IT_*) of one env from the last nsn_dump_iteration: up to cap floats
+ * into out (host); *n receives the field's length.  The PREV fields need k >= 1.
+ * NSN_ESTATE before any nsn_dump_iteration; NSN_EINVAL for an unknown field.
+ * Synchronises. */
+nsn_status nsn_read_iteration(nsn_scene s, int32_t env, int32_t field, int32_t cap, int32_t *n, float *out);
+
+/* Warm-start model for NSN_WARM_LEARNED and NSN_WARM_HYBRID (Sec. 8.1 starts the
+ * Newton iteration from a given lambda^0; the learned start predicts it per contact):
+ * float32 blob of 9347 MLP parameters
  * (12 -> 64 -> 64 -> 64 -> 3, ReLU; W1[64x12] b1 W2[64x64] b2 W3[64x64] b3 W4[3x64] b4)
  * followed by x_mean[12] x_std[12] y_mean[3] y_std[3].  Copied to the device. */
 nsn_status nsn_set_warm_start_model(nsn_scene s, const float *blob, int64_t n);
 
 /* Per-contact features of the last step's contact set, as used by the learned
- * warm start: feat[cap*12].  Synchronises. */
+ * warm start (at step start, in the contact basis of Sec. 3): feat[cap*12] = normal
+ * and tangential relative velocity under u~ (3), C_n(q^-), previous-step
+ * (lambda_n, lambda_f1, lambda_f2), 1/m_A, 1/m_B, mu, n_z, 1 if the key existed in the
+ * previous step.  Synchronises. */
 nsn_status nsn_read_features(nsn_scene s, int32_t env, int32_t cap, int32_t *n, float *feat);
 
 /* Compute the 12 warm-start features of every contact in every step (off by default
@@ -260,7 +358,7 @@ nsn_status nsn_enable_features(nsn_scene s, int32_t on);
  * stream; graphs are never used on the NULL stream). */
 nsn_status nsn_set_use_graphs(nsn_scene s, int32_t on);
 
-/* ---- launch schedule (used by the autotuner) -------------------------------
+/* ---- launch schedule (batching of independent envs; used by the autotuner) ------
  * Envs are launched in a fixed order: decreasing rows + DOFs (longest first).
  * order[n_envs] receives that order. */
 nsn_status nsn_get_env_order(nsn_scene s, int32_t *order);
@@ -286,8 +384,7 @@ nsn_status nsn_get_schedule(nsn_scene s, int32_t cap, int32_t *n, int32_t *first
  * contributions (J^T v per tet vertex) in LDS in buckets whose envs fit: n_dof +
  * 12 n_tet floats within the LDS share of a workgroup at the kernel's register-limited
  * occupancy (all of the device's LDS per workgroup at 512 and 1024 threads, half at
- * 256, a quarter at 128).  Applies to the
- * current and later schedules. */
+ * 256, a quarter at 128).  Applies to the current and later schedules. */
 nsn_status nsn_set_lds_mode(nsn_scene s, int32_t max_mode);
 
 /* The LDS mode each current bucket runs in (0, 1, 2 as above): mode[cap]. */
@@ -310,14 +407,17 @@ nsn_status nsn_stats_device_ptr(nsn_scene s, void **ptr);
 /* ---- learned part: MLP kernels on caller-owned device buffers -------------
  * Weights `w` are float32 device arrays in the layout above (9347 floats).  The
  * matrix products run on BF16 MFMA tiles with FP32 accumulation; activations are
- * rounded to bf16 where they enter a product.  `stream` may be NULL. */
+ * rounded to bf16 where they enter a product.  `stream` may be NULL.  (The paper
+ * starts every Newton solve from zero or the previous step's multipliers, Sec. 8.1;
+ * the network supplies a per-contact start instead.) */
 
 /* y[n*3] = MLP(x[n*12]) on the device. */
 nsn_status nsn_mlp_forward(const float *w, const float *x, float *y, int64_t n, void *stream);
 
 /* Mean-squared-error loss over n samples and its gradient grad[9347] (device);
  * *loss_out (device float, may be NULL).  `scratch` is a device buffer of at least
- * nsn_mlp_scratch_bytes(n) bytes. */
+ * nsn_mlp_scratch_bytes(n) bytes (per-block partial gradients, reduced in a fixed
+ * order, so the result is deterministic). */
 size_t nsn_mlp_scratch_bytes(int64_t n);
 nsn_status nsn_mlp_loss_grad(const float *w, const float *x, const float *t, int64_t n,
                              float *grad, float *loss_out, void *scratch, void *stream);
@@ -326,6 +426,39 @@ nsn_status nsn_mlp_loss_grad(const float *w, const float *x, const float *t, int
  * by the caller), step count `step` >= 1. */
 nsn_status nsn_mlp_adam(float *w, const float *grad, float *m, float *v, int64_t n_params,
                         float lr, float beta1, float beta2, float eps, int32_t step, void *stream);
+
+/* Training of the warm-start network on solver-generated data (the network is trained
+ * on the multipliers the method itself converges to; the paper's solver is the
+ * teacher).  Every stage runs on the device in the library:
+ *   1. each of the 15 columns of [x | t] is clipped to its [q, 1 - q] quantiles
+ *      (linear interpolation between order statistics; q = clip_quantile, 0 = off);
+ *   2. z-scoring with the clipped columns' means and standard deviations (FP64
+ *      accumulation; a deviation below 1e-6 counts as 1);
+ *   3. He-initialised weights (counter-based normal draws from `seed`) unless w_init;
+ *   4. `epochs` passes, each over a fresh permutation of the samples (a counter-based
+ *      bijection seeded by seed and the epoch), in batches of `batch` samples: MSE
+ *      loss and gradient (nsn_mlp_loss_grad), then Adam (nsn_mlp_adam) at the
+ *      learning rate lr * (1 + cos(pi * epoch / epochs)) / 2.
+ * x[n*12], t[n*3]: device float32 (read only).  blob_out: device float32, the 9347
+ * parameters then x_mean, x_std, y_mean, y_std (the layout of
+ * nsn_set_warm_start_model).  loss_hist: host double[epochs] of the mean standardised
+ * loss of every epoch, or NULL.  The workspace is a device buffer of at least
+ * nsn_train_workspace_bytes(n, batch) bytes.  Synchronises `stream` at the end.
+ * NSN_EINVAL for n < 2, batch < 1, epochs < 1, non-positive rates or a non-finite
+ * input; NSN_ENONFINITE if the loss turns non-finite. */
+typedef struct {
+  int32_t epochs;
+  int32_t batch;
+  float lr;            /* peak learning rate of the cosine schedule */
+  float beta1, beta2;  /* Adam moment decays (0.9, 0.999) */
+  float adam_eps;      /* Adam denominator floor (1e-8) */
+  float clip_quantile; /* data clipping quantile q in [0, 0.5) (5e-4) */
+  uint64_t seed;
+} nsn_train_params;
+size_t nsn_train_workspace_bytes(int64_t n, int32_t batch);
+nsn_status nsn_train_warm_start(const float *x, const float *t, int64_t n, const nsn_train_params *tp,
+                                const float *w_init, float *blob_out, double *loss_hist, void *workspace,
+                                size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus
 }

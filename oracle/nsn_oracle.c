@@ -2334,6 +2334,110 @@ double orc_mlp_loss_grad(const double *w, int64_t n, const double *x, const doub
   return loss;
 }
 
+/* bfloat16 rounding of a value held in float32 (round to nearest, ties to even on the
+ * 16 dropped mantissa bits): the operand format of the network's products on the GPU. */
+static double bf16_round(double v) {
+  float f = (float)v;
+  uint32_t u;
+  memcpy(&u, &f, sizeof u);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+  memcpy(&f, &u, sizeof f);
+  return (double)f;
+}
+
+static void dense_layer_rounded(const double *W, const double *bvec, int nout, int nin, const double *x_r,
+                                double *pre) {
+  for (int o = 0; o < nout; ++o) {
+    double acc = bvec[o];
+    for (int i = 0; i < nin; ++i) acc += bf16_round(W[o * nin + i]) * x_r[i];
+    pre[o] = acc;
+  }
+}
+
+/* The same loss and gradient with the rounding the BF16 matrix units apply: every
+ * operand of a product (weights, inputs, activations, back-propagated errors) is
+ * rounded to bfloat16 where it enters the product; biases, ReLU masks, the loss and
+ * all sums stay in double.  Backpropagation in the order of the plain version:
+ * dy = 2 (y - t) / (3 n); for each layer, weight gradient = sum over samples of
+ * bf16(delta) bf16(input), bias gradient = sum of delta, and the next delta =
+ * mask (W^T bf16(delta)) with W rounded. */
+double orc_mlp_loss_grad_bf16(const double *w, int64_t n, const double *x, const double *t, double *grad) {
+  const double *W1 = w, *b1 = W1 + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
+  const double *W3 = b2 + MLP_H, *b3 = W3 + MLP_H * MLP_H, *W4 = b3 + MLP_H, *b4 = W4 + MLP_OUT * MLP_H;
+  double *gW1 = grad, *gb1 = gW1 + MLP_H * MLP_IN, *gW2 = gb1 + MLP_H, *gb2 = gW2 + MLP_H * MLP_H;
+  double *gW3 = gb2 + MLP_H, *gb3 = gW3 + MLP_H * MLP_H, *gW4 = gb3 + MLP_H, *gb4 = gW4 + MLP_OUT * MLP_H;
+  memset(grad, 0, MLP_NPARAM * sizeof(double));
+  double loss = 0;
+  const double scale = 1.0 / ((double)n * MLP_OUT);
+  for (int64_t s = 0; s < n; ++s) {
+    double xr[MLP_IN], p1[MLP_H], p2[MLP_H], p3[MLP_H], h1r[MLP_H], h2r[MLP_H], h3r[MLP_H], y[MLP_OUT];
+    for (int i = 0; i < MLP_IN; ++i) xr[i] = bf16_round(x[MLP_IN * s + i]);
+    dense_layer_rounded(W1, b1, MLP_H, MLP_IN, xr, p1);
+    for (int i = 0; i < MLP_H; ++i) h1r[i] = bf16_round(p1[i] > 0 ? p1[i] : 0.0);
+    dense_layer_rounded(W2, b2, MLP_H, MLP_H, h1r, p2);
+    for (int i = 0; i < MLP_H; ++i) h2r[i] = bf16_round(p2[i] > 0 ? p2[i] : 0.0);
+    dense_layer_rounded(W3, b3, MLP_H, MLP_H, h2r, p3);
+    for (int i = 0; i < MLP_H; ++i) h3r[i] = bf16_round(p3[i] > 0 ? p3[i] : 0.0);
+    dense_layer_rounded(W4, b4, MLP_OUT, MLP_H, h3r, y);
+    double dy[MLP_OUT], dyr[MLP_OUT], d3[MLP_H], d2[MLP_H], d1[MLP_H], dr[MLP_H];
+    for (int o = 0; o < MLP_OUT; ++o) {
+      const double e = y[o] - t[MLP_OUT * s + o];
+      loss += e * e * scale;
+      dy[o] = 2.0 * e * scale;
+      dyr[o] = bf16_round(dy[o]);
+    }
+    for (int o = 0; o < MLP_OUT; ++o) {
+      gb4[o] += dy[o];
+      for (int i = 0; i < MLP_H; ++i) gW4[o * MLP_H + i] += dyr[o] * h3r[i];
+    }
+    for (int i = 0; i < MLP_H; ++i) {
+      double acc = 0;
+      for (int o = 0; o < MLP_OUT; ++o) acc += bf16_round(W4[o * MLP_H + i]) * dyr[o];
+      d3[i] = p3[i] > 0 ? acc : 0.0;
+    }
+    for (int o = 0; o < MLP_H; ++o) dr[o] = bf16_round(d3[o]);
+    for (int o = 0; o < MLP_H; ++o) {
+      gb3[o] += d3[o];
+      for (int i = 0; i < MLP_H; ++i) gW3[o * MLP_H + i] += dr[o] * h2r[i];
+    }
+    for (int i = 0; i < MLP_H; ++i) {
+      double acc = 0;
+      for (int o = 0; o < MLP_H; ++o) acc += bf16_round(W3[o * MLP_H + i]) * dr[o];
+      d2[i] = p2[i] > 0 ? acc : 0.0;
+    }
+    for (int o = 0; o < MLP_H; ++o) dr[o] = bf16_round(d2[o]);
+    for (int o = 0; o < MLP_H; ++o) {
+      gb2[o] += d2[o];
+      for (int i = 0; i < MLP_H; ++i) gW2[o * MLP_H + i] += dr[o] * h1r[i];
+    }
+    for (int i = 0; i < MLP_H; ++i) {
+      double acc = 0;
+      for (int o = 0; o < MLP_H; ++o) acc += bf16_round(W2[o * MLP_H + i]) * dr[o];
+      d1[i] = p1[i] > 0 ? acc : 0.0;
+    }
+    for (int o = 0; o < MLP_H; ++o) dr[o] = bf16_round(d1[o]);
+    for (int o = 0; o < MLP_H; ++o) {
+      gb1[o] += d1[o];
+      for (int i = 0; i < MLP_IN; ++i) gW1[o * MLP_IN + i] += dr[o] * xr[i];
+    }
+  }
+  return loss;
+}
+
+/* Pre-activations of the rounded forward pass of one sample (the ReLU decisions the
+ * BF16 network takes): pre[3 * 64] = layers 1, 2, 3. */
+void orc_mlp_preact_bf16(const double *w, const double *x, double *pre) {
+  const double *W1 = w, *b1 = W1 + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
+  const double *W3 = b2 + MLP_H, *b3 = W3 + MLP_H * MLP_H;
+  double xr[MLP_IN], hr[MLP_H];
+  for (int i = 0; i < MLP_IN; ++i) xr[i] = bf16_round(x[i]);
+  dense_layer_rounded(W1, b1, MLP_H, MLP_IN, xr, pre);
+  for (int i = 0; i < MLP_H; ++i) hr[i] = bf16_round(pre[i] > 0 ? pre[i] : 0.0);
+  dense_layer_rounded(W2, b2, MLP_H, MLP_H, hr, pre + MLP_H);
+  for (int i = 0; i < MLP_H; ++i) hr[i] = bf16_round(pre[MLP_H + i] > 0 ? pre[MLP_H + i] : 0.0);
+  dense_layer_rounded(W3, b3, MLP_H, MLP_H, hr, pre + 2 * MLP_H);
+}
+
 void orc_set_mlp(void *p, const double *weights, int64_t n) {
   env_t *e = (env_t *)p;
   free(e->mlp);

@@ -184,6 +184,11 @@ int64_t orc_mlp_num_params(void);
 void orc_mlp_forward(const double *w, int64_t n, const double *x, double *y);
 double orc_mlp_loss_grad(const double *w, int64_t n, const double *x, const double *t,
                          double *grad);
+/* the same with every product operand rounded to bfloat16 (the GPU's MFMA operands) */
+double orc_mlp_loss_grad_bf16(const double *w, int64_t n, const double *x, const double *t,
+                              double *grad);
+/* pre-activations (3 x 64) of that rounded forward pass for one sample */
+void orc_mlp_preact_bf16(const double *w, const double *x, double *pre);
 /* 12 features of every contact of the current state (computed as at step start) */
 int orc_contact_features(void *env, const orc_params *p, double h, double *feat, int64_t *key,
                          int cap);

@@ -115,6 +115,9 @@ def _bind(L):
         L.orc_mlp_forward.argtypes = [D, C.c_int64, D, D]
         L.orc_mlp_loss_grad.restype = C.c_double
         L.orc_mlp_loss_grad.argtypes = [D, C.c_int64, D, D, D]
+        L.orc_mlp_loss_grad_bf16.restype = C.c_double
+        L.orc_mlp_loss_grad_bf16.argtypes = [D, C.c_int64, D, D, D]
+        L.orc_mlp_preact_bf16.argtypes = [D, D, D]
         L.orc_contact_features.argtypes = [C.c_void_p, C.POINTER(Params), C.c_double, D, I64, C.c_int]
         L.orc_set_record.argtypes = [C.c_void_p, C.c_int]
         L.orc_get_record.argtypes = [C.c_void_p, C.c_int, D, C.c_int]
@@ -429,3 +432,142 @@ def mlp_loss_grad(w, x, t):
     g = np.zeros_like(w)
     loss = lib().orc_mlp_loss_grad(_d(w), x.shape[0], _d(x), _d(t), _d(g))
     return loss, g
+
+
+def mlp_loss_grad_bf16(w, x, t):
+    """Loss and gradient with every product operand rounded to bfloat16."""
+    w = np.ascontiguousarray(w, np.float64)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 12)
+    t = np.ascontiguousarray(t, np.float64).reshape(-1, 3)
+    g = np.zeros_like(w)
+    loss = lib().orc_mlp_loss_grad_bf16(_d(w), x.shape[0], _d(x), _d(t), _d(g))
+    return loss, g
+
+
+def mlp_preact_bf16(w, x):
+    """Pre-activations [n, 3, 64] of the bfloat16-rounded forward pass."""
+    w = np.ascontiguousarray(w, np.float64)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 12)
+    out = np.zeros((x.shape[0], 3, 64))
+    for s in range(x.shape[0]):
+        row = np.ascontiguousarray(x[s])
+        lib().orc_mlp_preact_bf16(_d(w), _d(row), _d(out[s]))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# The single-precision build of the same source (nsn_oracle_f32.c): a probe of what
+# FP32 rounding alone does to each quantity of an iteration.  Only the calls the
+# per-row parity tests need are bound.
+# ---------------------------------------------------------------------------
+F = C.POINTER(C.c_float)
+
+
+class _DescF32(C.Structure):
+    _fields_ = [(n, F if t is D else (C.c_float if t is C.c_double else
+                                     (C.c_float * 3 if n == "gravity" else t)))
+                for n, t in _Desc._fields_]
+
+
+class _ParamsF32(C.Structure):
+    _fields_ = [(n, C.c_float if t is C.c_double else t) for n, t in Params._fields_]
+
+
+_LIB_F32 = None
+
+
+def lib_f32():
+    global _LIB_F32
+    if _LIB_F32 is None:
+        path = _build.LIB_F32
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC) or \
+                os.path.getmtime(path) < os.path.getmtime(_build.HDR):
+            _build.build_f32()
+        L = C.CDLL(path)
+        L.orc_create.restype = C.c_void_p
+        L.orc_create.argtypes = [C.POINTER(_DescF32), C.c_char_p, C.c_int]
+        L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_set_state.argtypes = [C.c_void_p] + [F] * 6
+        L.orc_set_time.argtypes = [C.c_void_p, C.c_float]
+        L.orc_get_record.argtypes = [C.c_void_p, C.c_int, F, C.c_int]
+        L.orc_eval_iterate.argtypes = [C.c_void_p, C.POINTER(_ParamsF32), C.c_float, C.c_int, C.c_int] + [F] * 10
+        _LIB_F32 = L
+    return _LIB_F32
+
+
+class OracleEnvF32:
+    """One environment in the single-precision build: state, time and the evaluation
+    of one Newton iteration at a given iterate (see OracleEnv.eval_iterate)."""
+
+    def __init__(self, desc):
+        self.desc = desc
+        self._lib = L = lib_f32()
+        self._keep = {}
+        s = _DescF32()
+        for name, t in _DescF32._fields_:
+            if t is F:
+                a = np.ascontiguousarray(getattr(desc, name), np.float32).ravel()
+                a = a if a.size else np.zeros(1, np.float32)
+                self._keep[name] = a
+                setattr(s, name, a.ctypes.data_as(F))
+            elif t is I32:
+                a = np.ascontiguousarray(getattr(desc, name), np.int32).ravel()
+                a = a if a.size else np.zeros(1, np.int32)
+                self._keep[name] = a
+                setattr(s, name, a.ctypes.data_as(I32))
+        s.n_rigid, s.n_particles, s.n_tets, s.n_joints = desc.n_rigid, desc.n_particles, desc.n_tets, desc.n_joints
+        s.mu = desc.mu
+        s.gravity = (C.c_float * 3)(*desc.gravity)
+        s.ground, s.max_contacts = desc.ground, desc.max_contacts
+        s.tet_model = int(getattr(desc, "tet_model", 0))
+        err = C.create_string_buffer(256)
+        self.h = L.orc_create(C.byref(s), err, 256)
+        if not self.h:
+            raise ValueError(err.value.decode())
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self._lib.orc_destroy(self.h)
+            self.h = None
+
+    def set_state(self, st):
+        d = self.desc
+        shapes = [("rigid_x", 3 * d.n_rigid), ("rigid_q", 4 * d.n_rigid), ("rigid_v", 3 * d.n_rigid),
+                  ("rigid_w", 3 * d.n_rigid), ("particle_x", 3 * d.n_particles), ("particle_v", 3 * d.n_particles)]
+        arrs = []
+        for k, n in shapes:
+            a = np.ascontiguousarray(st[k], np.float32).ravel() if n else np.zeros(1, np.float32)
+            arrs.append(a)
+        self._keep["state"] = arrs
+        self._lib.orc_set_state(self.h, *[a.ctypes.data_as(F) for a in arrs])
+
+    def set_time(self, t):
+        self._lib.orc_set_time(self.h, float(t))
+
+    def eval_iterate(self, h, M, n_contacts, it, prev=None, params=None):
+        p = params if params is not None else make_params()
+        pf = _ParamsF32(**{n: getattr(p, n) for n, _ in Params._fields_})
+        f = lambda a: np.ascontiguousarray(a, np.float32).ravel()
+        cur = [f(it[k]) for k in ["lam", "u", "rx", "rq", "px"]]
+        cur = [a if a.size else np.zeros(1, np.float32) for a in cur]
+        self._keep["inj"] = cur
+        pptr = [None] * 5
+        if prev is not None:
+            pv = [f(prev[k]) for k in ["lam", "u", "rx", "rq", "px"]]
+            pv = [a if a.size else np.zeros(1, np.float32) for a in pv]
+            self._keep["inj_p"] = pv
+            pptr = [a.ctypes.data_as(F) for a in pv]
+        rc = self._lib.orc_eval_iterate(self.h, C.byref(pf), float(h), int(M), int(n_contacts),
+                                        *[a.ctypes.data_as(F) for a in cur], *pptr)
+        if rc == -2:
+            raise ValueError("orc_eval_iterate (f32): the contact set at q^- differs from the caller's")
+        if rc not in (0, -4):
+            raise ValueError(f"orc_eval_iterate (f32) failed ({rc})")
+        out = {}
+        for i, name in enumerate(REC_FIELDS):
+            n = self._lib.orc_get_record(self.h, i, None, 0)
+            a = np.zeros(max(n, 1), np.float32)
+            if n > 0:
+                self._lib.orc_get_record(self.h, i, a.ctypes.data_as(F), n)
+            out[name] = a[:max(n, 0)].astype(np.float64)
+        return out

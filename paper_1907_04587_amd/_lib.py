@@ -35,7 +35,24 @@ class ParamsC(C.Structure):
     _fields_ = [("ncp", C.c_int32), ("rmode", C.c_int32), ("damping", C.c_float),
                 ("eps", C.c_float), ("geo_stiff", C.c_int32), ("fem_mode", C.c_int32),
                 ("margin", C.c_float), ("warm", C.c_int32), ("line_search", C.c_int32),
-                ("linear", C.c_int32), ("islands", C.c_int32)]
+                ("linear", C.c_int32), ("islands", C.c_int32), ("watchdog", C.c_int32)]
+
+
+class ContactC(C.Structure):
+    _fields_ = [("key", C.c_int32), ("body_a", C.c_int32), ("body_b", C.c_int32),
+                ("normal", C.c_float * 3), ("a_local", C.c_float * 3), ("b_local", C.c_float * 3),
+                ("thickness", C.c_float)]
+
+
+class TrainParamsC(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("adam_eps", C.c_float), ("clip_quantile", C.c_float),
+                ("seed", C.c_uint64)]
+
+
+# per-iteration record fields (include/nsn.h NSN_IT_*)
+IT_FIELDS = ["lam", "err", "cdiag", "P", "b", "Az", "dlam", "tetc", "alpha", "active", "g", "u", "hdiag",
+             "rx", "rq", "px", "prev_lam", "prev_u", "prev_rx", "prev_rq", "prev_px"]
 
 
 ACC_DTYPE = np.dtype([("steps", np.int64), ("newton_iters", np.int64), ("cr_iters", np.int64),
@@ -67,12 +84,15 @@ def lib():
     L = C.CDLL(LIB_PATH)
     S = C.c_int32
     L.nsn_last_error.restype = C.c_char_p
-    L.nsn_query_workspace.argtypes = [C.POINTER(EnvDescC), S, C.POINTER(C.c_size_t)]
+    L.nsn_query_workspace.argtypes = [C.POINTER(EnvDescC), S, C.POINTER(ParamsC), C.POINTER(C.c_size_t)]
     L.nsn_create_scene.argtypes = [C.POINTER(EnvDescC), S, C.POINTER(ParamsC), VP, VP, C.c_size_t,
                                    C.POINTER(VP)]
     L.nsn_destroy_scene.argtypes = [VP]
     L.nsn_set_params.argtypes = [VP, C.POINTER(ParamsC)]
-    L.nsn_step.argtypes = [VP, C.c_double, S, S, C.c_double]
+    L.nsn_step.argtypes = [VP, C.c_double, S, S, C.c_double, VP]
+    L.nsn_set_contacts.argtypes = [VP, S, C.POINTER(ContactC), S]
+    L.nsn_dump_iteration.argtypes = [VP, C.c_double, S, S]
+    L.nsn_read_iteration.argtypes = [VP, S, S, S, I32, F]
     L.nsn_get_stats.argtypes = [VP, VP]
     L.nsn_read_state.argtypes = [VP, S, F, F, F, F, F, F, D]
     L.nsn_write_state.argtypes = [VP, S, F, F, F, F, F, F, D]
@@ -97,6 +117,9 @@ def lib():
     L.nsn_mlp_loss_grad.argtypes = [VP, VP, VP, C.c_int64, VP, VP, VP, VP]
     L.nsn_mlp_adam.argtypes = [VP, VP, VP, VP, C.c_int64, C.c_float, C.c_float, C.c_float,
                                C.c_float, S, VP]
+    L.nsn_train_workspace_bytes.restype = C.c_size_t
+    L.nsn_train_workspace_bytes.argtypes = [C.c_int64, S]
+    L.nsn_train_warm_start.argtypes = [VP, VP, C.c_int64, C.POINTER(TrainParamsC), VP, VP, D, VP, C.c_size_t, VP]
     _L = L
     return L
 

@@ -110,8 +110,29 @@ nsn_status validate_env(const nsn_env_desc &d, int e, HostEnv &he) {
   return NSN_OK;
 }
 
+// Which optional buffers a workspace holds (decided by the parameters at creation).
+struct Options {
+  bool islands = false, line_search = false;
+};
+
+Options options_of(const nsn_solver_params *p) {
+  Options o;
+  if (p) {
+    o.islands = p->islands != 0;
+    o.line_search = p->line_search != 0;
+  }
+  return o;
+}
+
+bool params_ok(const nsn_solver_params *p) {
+  return p->ncp >= 0 && p->ncp <= 1 && p->rmode >= 0 && p->rmode <= 2 && p->warm >= 0 && p->warm <= 3 &&
+         p->fem_mode >= 0 && p->fem_mode <= 1 && p->damping > 0.f && p->eps >= 0.f && p->margin >= 0.f &&
+         p->line_search >= 0 && p->line_search <= 1 && p->linear >= 0 && p->linear <= 1 && p->islands >= 0 &&
+         p->islands <= 1 && p->watchdog >= 0 && p->watchdog <= 1 && p->geo_stiff >= 0 && p->geo_stiff <= 1;
+}
+
 // Assign every workspace buffer; with base == nullptr only the size is computed.
-void layout(const Sizes &z, int n_envs, Arena &a, DevScene &S, EnvInfo *&env, int *&order) {
+void layout(const Sizes &z, int n_envs, const Options &opt, Arena &a, DevScene &S, EnvInfo *&env, int *&order) {
   S.n_envs = n_envs;
   S.NR = z.NR; S.NP = z.NP; S.NT = z.NT; S.NJ = z.NJ; S.NC = z.NC; S.NROW = z.NROW; S.NDOF = z.NDOF;
   S.any_linear = z.any_linear;
@@ -153,18 +174,23 @@ void layout(const Sizes &z, int n_envs, Arena &a, DevScene &S, EnvInfo *&env, in
   S.row_lam_best = a.take<float>(z.NROW); S.r_u_best = a.take<float>(6 * (size_t)z.NR);
   S.r_x_best = a.take<float4>(z.NR); S.r_q_best = a.take<float4>(z.NR);
   S.p_u_best = a.take<float4>(z.NP); S.p_x_best = a.take<float4>(z.NP);
-  S.row_lam_k = a.take<float>(z.NROW); S.r_u_k = a.take<float>(6 * (size_t)z.NR);
-  S.r_q_k = a.take<float4>(z.NR); S.du = a.take<float>(z.NDOF);
+  // line search (only when reserved)
+  const size_t ls = opt.line_search ? 1 : 0;
+  S.row_lam_k = a.take<float>(ls * z.NROW); S.r_u_k = a.take<float>(ls * 6 * (size_t)z.NR);
+  S.r_q_k = a.take<float4>(ls * z.NR); S.du = a.take<float>(ls * z.NDOF);
+  S.row_dump = a.take<float>(z.NROW);
   S.y = a.take<float>(z.NDOF); S.g = a.take<float>(z.NDOF); S.f = a.take<float>(z.NDOF);
   // islands: per element (joints, tets, contact slots), per body, and per env
   // n_rig + n_par + 2 island slots (the bodies, the static group, one spare)
-  const size_t nel = (size_t)z.NJ + z.NT + z.NC, nslot = (size_t)z.NR + z.NP + 2 * (size_t)n_envs;
-  S.b_lab = a.take<int>((size_t)z.NR + z.NP);
+  const size_t isl = opt.islands ? 1 : 0;
+  const size_t nel = isl * ((size_t)z.NJ + z.NT + z.NC), nslot = isl * ((size_t)z.NR + z.NP + 2 * (size_t)n_envs);
+  S.b_lab = a.take<int>(isl * ((size_t)z.NR + z.NP));
   S.el_isl = a.take<int>(nel); S.el_perm = a.take<int>(nel); S.el_dots = a.take<double>(3 * nel);
   S.isl_cnt = a.take<int>(nslot); S.isl_off = a.take<int>(nslot); S.isl_run = a.take<int>(nslot);
-  S.isl_list = a.take<int>(nslot); S.isl = a.take<IslState>(nslot); S.isl_n = a.take<int>(n_envs);
+  S.isl_list = a.take<int>(nslot); S.isl = a.take<IslState>(nslot); S.isl_n = a.take<int>(isl * n_envs);
   S.isl_res = a.take<int>(nslot);
-  S.n_con = a.take<int>(n_envs); S.overflow = a.take<int>(n_envs); S.time = a.take<double>(n_envs);
+  S.n_con = a.take<int>(n_envs); S.overflow = a.take<int>(n_envs); S.c_inject = a.take<int>(n_envs);
+  S.time = a.take<double>(n_envs);
   S.stats = a.take<nsn_step_stats>(n_envs);
   S.mlp = a.take<float>(kMlpBlob);
   S.have_mlp = 0;
@@ -208,6 +234,8 @@ struct nsn_scene_s {
   DevScene S;
   hipStream_t stream = nullptr;
   nsn_solver_params p;
+  Options reserved;   // optional buffers present in the workspace
+  int dumped_k = -1;  // iteration of the last dump step (-1: none)
   std::vector<nsn_env_desc> desc_sizes;  // counts only (pointers cleared)
   std::vector<EnvInfo> env;
   std::vector<int> order;
@@ -263,8 +291,10 @@ extern "C" {
 
 const char *nsn_last_error(void) { return g_err.c_str(); }
 
-nsn_status nsn_query_workspace(const nsn_env_desc *envs, int32_t n_envs, size_t *bytes) {
+nsn_status nsn_query_workspace(const nsn_env_desc *envs, int32_t n_envs, const nsn_solver_params *params,
+                               size_t *bytes) {
   if (!envs || n_envs < 1 || !bytes) return fail(NSN_EINVAL, "nsn_query_workspace: bad arguments");
+  if (params && !params_ok(params)) return fail(NSN_EINVAL, "bad solver parameters");
   std::vector<HostEnv> he(n_envs);
   for (int e = 0; e < n_envs; ++e) {
     nsn_status st = validate_env(envs[e], e, he[e]);
@@ -275,7 +305,7 @@ nsn_status nsn_query_workspace(const nsn_env_desc *envs, int32_t n_envs, size_t 
   DevScene S{};
   EnvInfo *env;
   int *order;
-  layout(z, n_envs, a, S, env, order);
+  layout(z, n_envs, options_of(params), a, S, env, order);
   *bytes = a.off + 256;
   return NSN_OK;
 }
@@ -286,13 +316,9 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
                             void *hip_stream, void *workspace, size_t workspace_bytes, nsn_scene *out) {
   if (!envs || n_envs < 1 || !p || !out) return fail(NSN_EINVAL, "nsn_create_scene: bad arguments");
   if (!workspace || ((uintptr_t)workspace & 255)) return fail(NSN_EINVAL, "workspace must be a 256-byte aligned device pointer");
-  if (p->ncp < 0 || p->ncp > 1 || p->rmode < 0 || p->rmode > 2 || p->warm < 0 || p->warm > 3 ||
-      p->fem_mode < 0 || p->fem_mode > 1 || !(p->damping > 0.f) || !(p->eps >= 0.f) || !(p->margin >= 0.f) ||
-      p->line_search < 0 || p->line_search > 1 || p->linear < 0 || p->linear > 1 || p->islands < 0 ||
-      p->islands > 1)
-    return fail(NSN_EINVAL, "bad solver parameters");
+  if (!params_ok(p)) return fail(NSN_EINVAL, "bad solver parameters");
   size_t need = 0;
-  nsn_status st = nsn_query_workspace(envs, n_envs, &need);
+  nsn_status st = nsn_query_workspace(envs, n_envs, p, &need);
   if (st) return st;
   if (workspace_bytes < need) return fail(NSN_ENOMEM, "workspace too small: need " + std::to_string(need));
   std::vector<HostEnv> he(n_envs);
@@ -301,10 +327,11 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
   auto *s = new nsn_scene_s();
   s->stream = (hipStream_t)hip_stream;
   s->p = *p;
+  s->reserved = options_of(p);
   Arena a(workspace);
   EnvInfo *env_dev;
   int *order_dev;
-  layout(z, n_envs, a, s->S, env_dev, order_dev);
+  layout(z, n_envs, s->reserved, a, s->S, env_dev, order_dev);
   DevScene &S = s->S;
 
   // ---- host staging of every static and initial array ----
@@ -543,11 +570,9 @@ nsn_status nsn_destroy_scene(nsn_scene s) {
 
 nsn_status nsn_set_params(nsn_scene s, const nsn_solver_params *p) {
   if (!s || !p) return fail(NSN_EINVAL, "nsn_set_params: bad arguments");
-  if (p->ncp < 0 || p->ncp > 1 || p->rmode < 0 || p->rmode > 2 || p->warm < 0 || p->warm > 3 ||
-      p->fem_mode < 0 || p->fem_mode > 1 || !(p->damping > 0.f) || !(p->eps >= 0.f) || !(p->margin >= 0.f) ||
-      p->line_search < 0 || p->line_search > 1 || p->linear < 0 || p->linear > 1 || p->islands < 0 ||
-      p->islands > 1)
-    return fail(NSN_EINVAL, "bad solver parameters");
+  if (!params_ok(p)) return fail(NSN_EINVAL, "bad solver parameters");
+  if ((p->islands && !s->reserved.islands) || (p->line_search && !s->reserved.line_search))
+    return fail(NSN_ESTATE, "islands / line search need a workspace sized with them (nsn_query_workspace params)");
   if (learned_warm(p->warm) && !s->S.have_mlp) return fail(NSN_ESTATE, "learned warm start needs nsn_set_warm_start_model first");
   s->p = *p;
   for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -611,7 +636,8 @@ static hipError_t enqueue_step(nsn_scene s, const StepArgs &a) {
   return hipSuccess;
 }
 
-nsn_status nsn_step(nsn_scene s, double h, int32_t newton_iters, int32_t cr_iters, double tol) {
+nsn_status nsn_step(nsn_scene s, double h, int32_t newton_iters, int32_t cr_iters, double tol,
+                    nsn_step_stats *stats) {
   if (!s) return fail(NSN_EINVAL, "nsn_step: null scene");
   if (!(h > 0.0) || newton_iters < 0 || cr_iters < 0 || !(tol >= 0.0)) return fail(NSN_EINVAL, "nsn_step: bad h, iteration counts or tol");
   if (learned_warm(s->p.warm) && !s->S.have_mlp) return fail(NSN_ESTATE, "learned warm start needs nsn_set_warm_start_model first");
@@ -620,10 +646,12 @@ nsn_status nsn_step(nsn_scene s, double h, int32_t newton_iters, int32_t cr_iter
   a.newton_iters = newton_iters;
   a.cr_iters = cr_iters;
   a.tol = (float)tol;
+  a.dump_k = -1;
   a.p = s->p;
+  s->dumped_k = -1;
   if (!s->use_graphs) {
     HIP_TRY(enqueue_step(s, a));
-    return NSN_OK;
+    return stats ? nsn_get_stats(s, stats) : NSN_OK;
   }
   GraphKey k{a.h, newton_iters, cr_iters, a.tol};
   auto it = s->graphs.find(k);
@@ -641,7 +669,7 @@ nsn_status nsn_step(nsn_scene s, double h, int32_t newton_iters, int32_t cr_iter
     it = s->graphs.emplace(k, exec).first;
   }
   HIP_TRY(hipGraphLaunch(it->second, s->stream));
-  return NSN_OK;
+  return stats ? nsn_get_stats(s, stats) : NSN_OK;
 }
 
 nsn_status nsn_get_stats(nsn_scene s, nsn_step_stats *out) {
@@ -941,6 +969,173 @@ nsn_status nsn_read_kernel_times(nsn_scene s, int32_t cap, int32_t *n, double *m
 nsn_status nsn_stats_device_ptr(nsn_scene s, void **ptr) {
   if (!s || !ptr) return fail(NSN_EINVAL, "bad arguments");
   *ptr = s->S.stats;
+  return NSN_OK;
+}
+
+nsn_status nsn_set_contacts(nsn_scene s, int32_t env, const nsn_contact *contacts, int32_t n) {
+  nsn_status st = check_env(s, env);
+  if (st) return st;
+  const EnvInfo &E = s->env[env];
+  if (n < 0 || n > E.max_con || (n > 0 && !contacts))
+    return fail(NSN_EINVAL, "nsn_set_contacts: count must be in [0, max_contacts]");
+  std::vector<int> key(std::max(n, 1));
+  std::vector<int2> body(std::max(n, 1));
+  std::vector<float4> nrm(std::max(n, 1)), aL(std::max(n, 1)), bL(std::max(n, 1));
+  const int nb = E.n_rig + E.n_par;
+  for (int i = 0; i < n; ++i) {
+    const nsn_contact &c = contacts[i];
+    const std::string at = "nsn_set_contacts: contact " + std::to_string(i) + ": ";
+    if (i > 0 && !(c.key > contacts[i - 1].key)) return fail(NSN_EINVAL, at + "keys must be strictly ascending");
+    if (i > 0 && c.body_a < contacts[i - 1].body_a) return fail(NSN_EINVAL, at + "feature bodies must be non-decreasing");
+    if (c.body_a < 0 || c.body_a >= nb) return fail(NSN_EINVAL, at + "bad feature body");
+    if (c.body_b < -1 || c.body_b >= E.n_rig || c.body_b == c.body_a) return fail(NSN_EINVAL, at + "bad target body");
+    if (c.body_b == -1 && !E.ground) return fail(NSN_EINVAL, at + "the env has no ground plane");
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(c.normal[k]) || !std::isfinite(c.a_local[k]) || !std::isfinite(c.b_local[k]))
+        return fail(NSN_EINVAL, at + "non-finite geometry");
+    if (!std::isfinite(c.thickness)) return fail(NSN_EINVAL, at + "non-finite thickness");
+    key[i] = c.key;
+    body[i] = make_int2(c.body_a, c.body_b);
+    nrm[i] = make_float4(c.normal[0], c.normal[1], c.normal[2], c.thickness);
+    const bool particle = c.body_a >= E.n_rig;
+    aL[i] = particle ? make_float4(0.f, 0.f, 0.f, 0.f) : make_float4(c.a_local[0], c.a_local[1], c.a_local[2], 0.f);
+    bL[i] = make_float4(c.b_local[0], c.b_local[1], c.b_local[2], 0.f);
+  }
+  const DevScene &S = s->S;
+  const hipStream_t st_ = s->stream;
+  if (n > 0) {
+    HIP_TRY(hipMemcpyAsync(S.c_key + E.con_off, key.data(), sizeof(int) * n, hipMemcpyHostToDevice, st_));
+    HIP_TRY(hipMemcpyAsync(S.c_body + E.con_off, body.data(), sizeof(int2) * n, hipMemcpyHostToDevice, st_));
+    HIP_TRY(hipMemcpyAsync(S.c_n + E.con_off, nrm.data(), sizeof(float4) * n, hipMemcpyHostToDevice, st_));
+    HIP_TRY(hipMemcpyAsync(S.c_aL + E.con_off, aL.data(), sizeof(float4) * n, hipMemcpyHostToDevice, st_));
+    HIP_TRY(hipMemcpyAsync(S.c_bL + E.con_off, bL.data(), sizeof(float4) * n, hipMemcpyHostToDevice, st_));
+  }
+  const int flag = n + 1;
+  HIP_TRY(hipMemcpyAsync(S.c_inject + env, &flag, sizeof(int), hipMemcpyHostToDevice, st_));
+  HIP_TRY(hipStreamSynchronize(st_));  // the staging vectors die on return
+  return NSN_OK;
+}
+
+nsn_status nsn_dump_iteration(nsn_scene s, double h, int32_t k, int32_t cr_iters) {
+  if (!s) return fail(NSN_EINVAL, "nsn_dump_iteration: null scene");
+  if (!(h > 0.0) || k < 0 || cr_iters < 0) return fail(NSN_EINVAL, "nsn_dump_iteration: bad h, k or cr_iters");
+  if (s->p.line_search) return fail(NSN_EUNSUPPORTED, "nsn_dump_iteration: not with line search");
+  if (learned_warm(s->p.warm) && !s->S.have_mlp) return fail(NSN_ESTATE, "learned warm start needs nsn_set_warm_start_model first");
+  StepArgs a;
+  a.h = (float)h;
+  a.newton_iters = k + 1;
+  a.cr_iters = cr_iters;
+  a.tol = 0.f;
+  a.dump_k = k;
+  a.p = s->p;
+  a.p.watchdog = 0;  // the watchdog's slot holds iterate k-1
+  HIP_TRY(enqueue_step(s, a));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->dumped_k = k;
+  return NSN_OK;
+}
+
+nsn_status nsn_read_iteration(nsn_scene s, int32_t env, int32_t field, int32_t cap, int32_t *n, float *out) {
+  nsn_status st = check_env(s, env);
+  if (st) return st;
+  if (!n || cap < 0 || (cap > 0 && !out)) return fail(NSN_EINVAL, "nsn_read_iteration: bad arguments");
+  if (field < 0 || field >= NSN_IT_NFIELDS) return fail(NSN_EINVAL, "nsn_read_iteration: unknown field");
+  if (s->dumped_k < 0) return fail(NSN_ESTATE, "nsn_read_iteration: no dump step since the last nsn_step");
+  const bool prev = field >= NSN_IT_PREV_LAM;
+  if (prev && s->dumped_k < 1) return fail(NSN_ESTATE, "nsn_read_iteration: iterate k-1 needs k >= 1");
+  const EnvInfo &E = s->env[env];
+  const DevScene &S = s->S;
+  const hipStream_t st_ = s->stream;
+  int nc = 0;
+  HIP_TRY(hipMemcpyAsync(&nc, S.n_con + env, sizeof(int), hipMemcpyDeviceToHost, st_));
+  HIP_TRY(hipStreamSynchronize(st_));
+  const int tet_rows = E.tet_model == NSN_TET_LINEAR ? 6 : 3;
+  const int rows = 6 * E.n_jnt + tet_rows * E.n_tet + 3 * nc;
+  std::vector<float> v;
+  auto rowf = [&](const float *src) -> hipError_t {
+    v.resize(rows);
+    if (!rows) return hipSuccess;
+    return hipMemcpyAsync(v.data(), src + E.row_off, sizeof(float) * rows, hipMemcpyDeviceToHost, st_);
+  };
+  auto f4 = [&](const float4 *src, int count, int ncomp) -> hipError_t {
+    std::vector<float4> t(std::max(count, 1));
+    v.resize((size_t)ncomp * count);
+    if (!count) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(t.data(), src, sizeof(float4) * count, hipMemcpyDeviceToHost, st_);
+    if (e == hipSuccess) e = hipStreamSynchronize(st_);
+    for (int i = 0; i < count; ++i) {
+      const float c4[4] = {t[i].x, t[i].y, t[i].z, t[i].w};
+      for (int q = 0; q < ncomp; ++q) v[(size_t)ncomp * i + q] = c4[q];
+    }
+    return e;
+  };
+  // body-space velocities: 6 per rigid body (from a 6-float array), 3 per particle (float4)
+  auto bodyu = [&](const float *ru, const float4 *pu) -> hipError_t {
+    std::vector<float> r(std::max(6 * E.n_rig, 1));
+    std::vector<float4> p(std::max(E.n_par, 1));
+    hipError_t e = hipSuccess;
+    if (E.n_rig) e = hipMemcpyAsync(r.data(), ru + 6 * (size_t)E.rig_off, sizeof(float) * 6 * E.n_rig, hipMemcpyDeviceToHost, st_);
+    if (e == hipSuccess && E.n_par) e = hipMemcpyAsync(p.data(), pu + E.par_off, sizeof(float4) * E.n_par, hipMemcpyDeviceToHost, st_);
+    if (e == hipSuccess) e = hipStreamSynchronize(st_);
+    v.assign(r.begin(), r.begin() + 6 * E.n_rig);
+    for (int i = 0; i < E.n_par; ++i) { v.push_back(p[i].x); v.push_back(p[i].y); v.push_back(p[i].z); }
+    return e;
+  };
+  switch (field) {
+    case NSN_IT_LAM: HIP_TRY(rowf(S.row_lam)); break;
+    case NSN_IT_ERR: HIP_TRY(rowf(S.row_err)); break;
+    case NSN_IT_CDIAG: HIP_TRY(rowf(S.row_C)); break;
+    case NSN_IT_P: HIP_TRY(rowf(S.row_P)); break;
+    case NSN_IT_B: HIP_TRY(rowf(S.row_b)); break;
+    case NSN_IT_AZ: HIP_TRY(rowf(S.row_dump)); break;
+    case NSN_IT_DLAM: HIP_TRY(rowf(S.row_x)); break;
+    case NSN_IT_PREV_LAM: HIP_TRY(rowf(S.row_lam_best)); break;
+    case NSN_IT_TETC: {
+      v.resize(6 * (size_t)E.n_tet);
+      for (int q = 0; q < 6 && E.n_tet; ++q) {
+        std::vector<float> t(E.n_tet);
+        HIP_TRY(hipMemcpyAsync(t.data(), S.t_E + (size_t)q * S.NT + E.tet_off, sizeof(float) * E.n_tet,
+                               hipMemcpyDeviceToHost, st_));
+        HIP_TRY(hipStreamSynchronize(st_));
+        for (int i = 0; i < E.n_tet; ++i) v[6 * (size_t)i + q] = t[i];
+      }
+      break;
+    }
+    case NSN_IT_ALPHA:
+    case NSN_IT_ACTIVE: {
+      // the dumped iteration's half of the ping-pong pair
+      const int buf = s->dumped_k & 1;
+      v.resize(nc);
+      if (nc && field == NSN_IT_ALPHA) {
+        HIP_TRY(hipMemcpyAsync(v.data(), S.c_alpha + (size_t)buf * S.NC + E.con_off, sizeof(float) * nc,
+                               hipMemcpyDeviceToHost, st_));
+      } else if (nc) {
+        std::vector<int> t(nc);
+        HIP_TRY(hipMemcpyAsync(t.data(), S.c_active + (size_t)buf * S.NC + E.con_off, sizeof(int) * nc,
+                               hipMemcpyDeviceToHost, st_));
+        HIP_TRY(hipStreamSynchronize(st_));
+        for (int i = 0; i < nc; ++i) v[i] = (float)t[i];
+      }
+      break;
+    }
+    case NSN_IT_G:
+      v.resize(E.n_dof);
+      if (E.n_dof) HIP_TRY(hipMemcpyAsync(v.data(), S.g + E.dof_off, sizeof(float) * E.n_dof, hipMemcpyDeviceToHost, st_));
+      break;
+    case NSN_IT_U: HIP_TRY(bodyu(S.r_u, S.p_u)); break;
+    case NSN_IT_PREV_U: HIP_TRY(bodyu(S.r_u_best, S.p_u_best)); break;
+    case NSN_IT_HDIAG: HIP_TRY(f4(S.p_H + E.par_off, E.n_par, 3)); break;
+    case NSN_IT_RX: HIP_TRY(f4(S.r_x + E.rig_off, E.n_rig, 3)); break;
+    case NSN_IT_RQ: HIP_TRY(f4(S.r_q + E.rig_off, E.n_rig, 4)); break;
+    case NSN_IT_PX: HIP_TRY(f4(S.p_x + E.par_off, E.n_par, 3)); break;
+    case NSN_IT_PREV_RX: HIP_TRY(f4(S.r_x_best + E.rig_off, E.n_rig, 3)); break;
+    case NSN_IT_PREV_RQ: HIP_TRY(f4(S.r_q_best + E.rig_off, E.n_rig, 4)); break;
+    case NSN_IT_PREV_PX: HIP_TRY(f4(S.p_x_best + E.par_off, E.n_par, 3)); break;
+  }
+  HIP_TRY(hipStreamSynchronize(st_));
+  *n = (int)v.size();
+  const int m = std::min<int>(cap, (int)v.size());
+  if (m > 0) std::copy(v.begin(), v.begin() + m, out);
   return NSN_OK;
 }
 

@@ -110,12 +110,15 @@ struct DevScene {
 
   // rows (capacity NROW)
   float *row_lam, *row_x, *row_z, *row_p, *row_q, *row_w, *row_err, *row_P, *row_C, *row_b;
-  // the step's lowest-merit iterate (watchdog)
+  // the step's lowest-merit iterate (watchdog); in a dump step, iterate k-1
   float *row_lam_best, *r_u_best;
   float4 *r_x_best, *r_q_best, *p_u_best, *p_x_best;
   // line search: the accepted iterate k (particle velocities in p_uprev) and its direction
   float *row_lam_k, *r_u_k, *du;
   float4 *r_q_k;
+
+  // dump step: A (P b) of the dumped iteration
+  float *row_dump;
 
   // body space (NDOF)
   float *y, *g, *f;
@@ -133,8 +136,9 @@ struct DevScene {
   int *isl_n;                      // per env: number of non-empty islands
   int *isl_res;                    // per island slot: its residual (bits of a float >= 0)
 
-  // per env dynamic
-  int *n_con, *overflow;
+  // per env dynamic; c_inject: 1 + the number of caller-given contacts that replace
+  // collision detection in the next step (0: none)
+  int *n_con, *overflow, *c_inject;
   double *time;
   nsn_step_stats *stats;
 
@@ -159,6 +163,7 @@ struct StepArgs {
   float h;
   int newton_iters, cr_iters;
   float tol;
+  int dump_k;  // >= 0: stop inside Newton iteration dump_k and keep its data (dump step)
   nsn_solver_params p;
 };
 

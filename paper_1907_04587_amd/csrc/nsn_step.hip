@@ -666,8 +666,10 @@ __global__ __launch_bounds__(BS) void k_prepare(DevScene S, StepArgs A, int want
   // ---- collision detection at q^- (Alg. 1), canonical candidate order:
   //      candidate = feature * n_targets + target, features = rigid features then
   //      particles, targets = ground then rigid bodies ----
+  // a caller-given contact list (already in the contact slots) replaces detection
+  const int inject = S.c_inject[e];
   const int nfeat = E.n_feat + E.n_par;
-  const long long ncand = (long long)nfeat * E.n_targets;
+  const long long ncand = inject > 0 ? 0 : (long long)nfeat * E.n_targets;
   for (long long base = 0; base < ncand; base += BS) {
     const long long cand = base + tid;
     int keep = 0, fbody = 0, tb = -1;
@@ -737,10 +739,13 @@ __global__ __launch_bounds__(BS) void k_prepare(DevScene S, StepArgs A, int want
     if (tid == 0) s_count += total;
     __syncthreads();
   }
-  const int nc = s_count < E.max_con ? s_count : E.max_con;
+  const int found = inject > 0 ? inject - 1 : s_count;
+  const int nc = found < E.max_con ? found : E.max_con;
+  __syncthreads();
   if (tid == 0) {
     S.n_con[e] = nc;
-    S.overflow[e] = s_count - nc;
+    S.overflow[e] = found - nc;
+    if (inject > 0) S.c_inject[e] = 0;  // one step only
   }
 
   // ---- feature-side ranges (contacts come out sorted by feature body) ----
@@ -2146,10 +2151,11 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     fallback = 1;
     __syncthreads();
   }
-  // READING (Sec. 8.1 names watchdog strategies without using one): the step keeps
-  // its lowest-merit iterate; when the merit grows past kWatchBlowup times that best,
-  // or turns non-finite outside a warm attempt, the iteration stops and the step
-  // returns the best iterate.  All the quantities deciding this are block-uniform.
+  // Option (Sec. 8.1 names watchdog strategies without using one; off by default, as
+  // in the paper): the step keeps its lowest-merit iterate; when the merit grows past
+  // kWatchBlowup times that best, or turns non-finite outside a warm attempt, the
+  // iteration stops and the step returns the best iterate.  All the quantities
+  // deciding this are block-uniform.
   double best_merit = __builtin_huge_val();
   float best_r = 0.f, best_rc = 0.f;
   bool have_best = false, restore = false;
@@ -2198,6 +2204,11 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
 
   for (int k = 0; k <= A.newton_iters; ++k) {
     const int buf = k & 1;
+    // dump step: keep iterate k-1 in the watchdog's slot (the watchdog is off)
+    if (A.dump_k >= 1 && k == A.dump_k - 1) {
+      keep_best(c, nrows, false);
+      __syncthreads();
+    }
     assemble_all<BS, EXT>(c, buf, tplus, nc);
     __syncthreads();
     // momentum balance g = M~(u - u~) - h J^T lambda (Sec. 6.1); geometric stiffness
@@ -2313,7 +2324,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       --k;
       continue;
     }
-    if (finite_now && merit < best_merit) {
+    if (A.p.watchdog && finite_now && merit < best_merit) {
       best_merit = merit;
       best_r = rmax;
       best_rc = rcon;
@@ -2321,11 +2332,11 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       keep_best(c, nrows, false);
     }
     if (!finite_now) {
-      if (warm || !have_best) { nonfinite = 1; break; }
+      if (!A.p.watchdog || warm || !have_best) { nonfinite = 1; break; }
       restore = true;
       break;
     }
-    if (merit > kWatchBlowup * best_merit) { restore = true; break; }
+    if (A.p.watchdog && merit > kWatchBlowup * best_merit) { restore = true; break; }
     if (A.tol > 0.f && rmax <= A.tol) { converged = 1; break; }
     if (k == A.newton_iters) break;
 
@@ -2380,6 +2391,8 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
         double dots[3] = {0.0, 0.0, 0.0};
         matvec_rows<BS, false, EXT>(c, Y, buf, nel, eps, dots);
         block_sum3<BS>(dots, red);
+        if (it == 0 && k == A.dump_k)
+          for (int r = tid; r < nrows; r += BS) S.row_dump[R0 + r] = S.row_w[R0 + r];
         const double pw = dots[0];
         if (!(pw > 0.0)) break;
         const float alpha = (float)(rz / pw);
@@ -2414,6 +2427,8 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       double dots[3] = {0.0, 0.0, 0.0};
       matvec_rows<BS, true, EXT>(c, Y, buf, nel, eps, dots, true);
       __syncthreads();
+      if (k == A.dump_k)
+        for (int r = tid; r < nrows; r += BS) S.row_dump[R0 + r] = S.row_w[R0 + r];
       const double rho_env = block_sum<BS>(island_reduce<BS>(c, e, true), red, 0);
       float any = block_max<BS>(island_check<BS>(c, e, kTauCR * rho_env), red, 1);
       for (int it = 0; it < A.cr_iters; ++it) {
@@ -2454,6 +2469,8 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       double dots[3] = {0.0, 0.0, 0.0};
       matvec_rows<BS, true, EXT>(c, Y, buf, nel, eps, dots);
       block_sum3<BS>(dots, red);
+      if (k == A.dump_k)
+        for (int r = tid; r < nrows; r += BS) S.row_dump[R0 + r] = S.row_w[R0 + r];
       double rho = dots[0], qs = dots[1];
       // READING: stop once <z, A z> is at rounding level relative to its start
       const double rho_stop = kTauCR * rho;
@@ -2487,6 +2504,7 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     }
     cr_total += done;
     __syncthreads();
+    if (k == A.dump_k) break;  // dump step: iteration k's data stays in place
 
     // ---- update: du = H~^-1 (h J^T dlambda - g), damped step t (Sec. 6.2, 8.1) ----
     const float tstep = A.p.line_search ? 1.f : damp;
@@ -2557,8 +2575,9 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
   if (!nonfinite || !warm) break;
   }
 
-  // ---- write-back ----
-  for (int b = tid; b < nb; b += BS) {
+  // ---- write-back (a dump step leaves velocities, time and warm-start data alone) ----
+  const bool dumping = A.dump_k >= 0;
+  for (int b = tid; b < nb && !dumping; b += BS) {
     if (b < E.n_rig) {
       const int g = E.rig_off + b;
       if (S.r_inertia[g].w == 0.f) continue;
@@ -2570,15 +2589,17 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
       S.p_v[p] = S.p_u[p];
     }
   }
-  for (int i = tid; i < nc; i += BS) {
+  for (int i = tid; i < nc && !dumping; i += BS) {
     const int gc = E.con_off + i;
     const int r0 = row_con(E, i);
     S.c_prev_key[gc] = S.c_key[gc];
     S.c_prev_lam[gc] = make_float4(S.row_lam[r0], S.row_lam[r0 + 1], S.row_lam[r0 + 2], 0.f);
   }
   if (tid == 0) {
-    S.n_prev[e] = nc;
-    S.time[e] = tplus;
+    if (!dumping) {
+      S.n_prev[e] = nc;
+      S.time[e] = tplus;
+    }
     nsn_step_stats st;
     st.newton_iters = newton_done;
     st.cr_iters = cr_total;
@@ -2593,18 +2614,20 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
     st.merit = merit;
     st.r_ncp_first = r_first;
     S.stats[e] = st;
-    nsn_accum a = S.acc[e];
-    a.steps += 1;
-    a.newton_iters += newton_done;
-    a.cr_iters += cr_total;
-    a.converged += converged;
-    a.nonfinite += nonfinite;
-    a.fallbacks += fallback;
-    a.watchdogs += watchdog;
-    a.cr_bytes += (double)cr_total * ((lin_tets(E) ? kBytesLinTet : kBytesTet) * E.n_tet + kBytesContact * nc +
-                                      kBytesJoint * E.n_jnt +
-                                      kBytesDof * (6.0 * E.n_rig + 3.0 * E.n_par));
-    S.acc[e] = a;
+    if (!dumping) {
+      nsn_accum a = S.acc[e];
+      a.steps += 1;
+      a.newton_iters += newton_done;
+      a.cr_iters += cr_total;
+      a.converged += converged;
+      a.nonfinite += nonfinite;
+      a.fallbacks += fallback;
+      a.watchdogs += watchdog;
+      a.cr_bytes += (double)cr_total * ((lin_tets(E) ? kBytesLinTet : kBytesTet) * E.n_tet + kBytesContact * nc +
+                                        kBytesJoint * E.n_jnt +
+                                        kBytesDof * (6.0 * E.n_rig + 3.0 * E.n_par));
+      S.acc[e] = a;
+    }
     const int slot = S.tick[0] % kTimingRing;
     atomicMin(S.ts + 2 * slot, t_start);
     atomicMax(S.ts + 2 * slot + 1, (unsigned long long)wall_clock64());

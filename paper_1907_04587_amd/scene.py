@@ -13,7 +13,8 @@ def params_c(p) -> L.ParamsC:
     return L.ParamsC(ncp=int(p.ncp), rmode=int(p.rmode), damping=float(p.damping), eps=float(p.eps),
                      geo_stiff=int(p.geo_stiff), fem_mode=int(p.fem_mode), margin=float(p.margin),
                      warm=int(p.warm), line_search=int(getattr(p, "line_search", 0)),
-                     linear=int(getattr(p, "linear", 0)), islands=int(getattr(p, "islands", 0)))
+                     linear=int(getattr(p, "linear", 0)), islands=int(getattr(p, "islands", 0)),
+                     watchdog=int(getattr(p, "watchdog", 0)))
 
 
 def stats_to_dicts(arr):
@@ -58,9 +59,10 @@ class Scene:
 
     envs: list of scene_inputs.EnvDesc; params: object with the SolverParams fields.
     The device workspace is one torch uint8 tensor; the stream is torch's current
-    stream at creation (or `stream`)."""
+    stream at creation (or `stream`).  reserve: extra parameter objects whose options
+    (islands, line search) the workspace must also hold, for later set_params calls."""
 
-    def __init__(self, envs, params, device="cuda", stream=None):
+    def __init__(self, envs, params, device="cuda", stream=None, reserve=()):
         import torch
 
         self.torch = torch
@@ -69,18 +71,26 @@ class Scene:
         self.n_envs = len(self.envs)
         m = _Marshal(self.envs)
         nbytes = C.c_size_t(0)
-        L.check(self.lib.nsn_query_workspace(m.c, self.n_envs, C.byref(nbytes)), "nsn_query_workspace")
+        pc = params_c(params)
+        for r in reserve:  # the union of the options the scene may use
+            rc = params_c(r)
+            pc.islands = max(pc.islands, rc.islands)
+            pc.line_search = max(pc.line_search, rc.line_search)
+        self._reserved = pc
+        L.check(self.lib.nsn_query_workspace(m.c, self.n_envs, C.byref(pc), C.byref(nbytes)),
+                "nsn_query_workspace")
         self.workspace_bytes = int(nbytes.value)
         self.device = torch.device(device)
         self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._params = params
-        pc = params_c(params)
         h = C.c_void_p()
         L.check(self.lib.nsn_create_scene(m.c, self.n_envs, C.byref(pc), C.c_void_p(self.stream.cuda_stream),
                                           C.c_void_p(self.workspace.data_ptr()), self.workspace_bytes,
                                           C.byref(h)), "nsn_create_scene")
         self.h = h
+        if (pc.islands, pc.line_search) != (params_c(params).islands, params_c(params).line_search):
+            self.set_params(params)
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -94,8 +104,47 @@ class Scene:
         L.check(self.lib.nsn_set_params(self.h, C.byref(pc)), "nsn_set_params")
         self._params = params
 
-    def step(self, h, newton_iters, cr_iters, tol=0.0):
-        L.check(self.lib.nsn_step(self.h, float(h), int(newton_iters), int(cr_iters), float(tol)), "nsn_step")
+    def step(self, h, newton_iters, cr_iters, tol=0.0, with_stats=False):
+        """One time step (asynchronous); with_stats: synchronise and return the stats."""
+        out = np.zeros(self.n_envs, L.STATS_DTYPE) if with_stats else None
+        L.check(self.lib.nsn_step(self.h, float(h), int(newton_iters), int(cr_iters), float(tol),
+                                  out.ctypes.data if out is not None else None), "nsn_step")
+        return out
+
+    # ---- parity hooks ----
+    def set_contacts(self, env, key, bodies, normal, a_local, b_local, thickness):
+        """Replace collision detection of `env` for the next step by this contact list
+        (keys ascending, feature bodies non-decreasing)."""
+        n = len(key)
+        arr = (L.ContactC * max(n, 1))()
+        for i in range(n):
+            c = arr[i]
+            c.key = int(key[i])
+            c.body_a, c.body_b = int(bodies[i][0]), int(bodies[i][1])
+            c.normal = (C.c_float * 3)(*[float(v) for v in normal[i]])
+            c.a_local = (C.c_float * 3)(*[float(v) for v in a_local[i]])
+            c.b_local = (C.c_float * 3)(*[float(v) for v in b_local[i]])
+            c.thickness = float(thickness[i])
+        L.check(self.lib.nsn_set_contacts(self.h, int(env), arr, n), "nsn_set_contacts")
+
+    def dump_iteration(self, h, k, cr_iters):
+        """A step of every env that stops inside Newton iteration k (see nsn.h)."""
+        L.check(self.lib.nsn_dump_iteration(self.h, float(h), int(k), int(cr_iters)), "nsn_dump_iteration")
+        self._dumped_k = int(k)
+
+    def read_iteration(self, env, fields=None):
+        """{field: float32 array} of the last dump step for one env (nsn_read_iteration)."""
+        out = {}
+        names = fields or [f for f in L.IT_FIELDS if getattr(self, "_dumped_k", 0) >= 1 or not f.startswith("prev_")]
+        for name in names:
+            fi = L.IT_FIELDS.index(name)
+            n = C.c_int32(0)
+            L.check(self.lib.nsn_read_iteration(self.h, int(env), fi, 0, C.byref(n), None), "nsn_read_iteration")
+            a = np.zeros(max(n.value, 1), np.float32)
+            L.check(self.lib.nsn_read_iteration(self.h, int(env), fi, n.value, C.byref(n), L.fptr(a)),
+                    "nsn_read_iteration")
+            out[name] = a[:n.value]
+        return out
 
     def stats(self):
         out = np.zeros(self.n_envs, L.STATS_DTYPE)

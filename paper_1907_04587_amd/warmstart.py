@@ -1,7 +1,7 @@
 """Learned warm start: dataset generation from the solver's own trajectories and
-training of the 12 -> 64 -> 64 -> 64 -> 3 MLP with the library's BF16-MFMA forward /
-backward kernels and its Adam kernel (nsn_mlp_loss_grad, nsn_mlp_adam).  Python only
-drives the loop: batching indices, learning-rate schedule, bookkeeping.
+training of the 12 -> 64 -> 64 -> 64 -> 3 MLP by the library (nsn_train_warm_start: its
+BF16-MFMA forward / backward kernels and its Adam kernel, with the data preparation and
+the epoch loop in the library too).  Python only marshals the arrays.
 
 Weights blob (float32): 9347 parameters (W1[64x12] b1 W2[64x64] b2 W3[64x64] b3 W4[3x64]
 b4) followed by x_mean[12] x_std[12] y_mean[3] y_std[3]."""
@@ -18,6 +18,8 @@ N_IN, N_OUT = 12, 3
 
 
 def init_params(seed=0):
+    """He-initialised parameters drawn on the host (for tests that need known weights;
+    nsn_train_warm_start draws its own on the device)."""
     rng = np.random.default_rng(seed)
     w = np.zeros(N_PARAMS, np.float32)
     o = 0
@@ -29,67 +31,36 @@ def init_params(seed=0):
     return w
 
 
-def standardisation(x, t):
-    xm, xs = x.mean(0), x.std(0)
-    ym, ys = t.mean(0), t.std(0)
-    xs = np.where(xs > 1e-6, xs, 1.0)
-    ys = np.where(ys > 1e-6, ys, 1.0)
-    return xm.astype(np.float32), xs.astype(np.float32), ym.astype(np.float32), ys.astype(np.float32)
-
-
-def train_mlp(x, t, epochs=20, batch=4096, lr=2e-3, seed=0, log=None, device="cuda"):
-    """Train on features x [n,12] and targets t [n,3] (raw units).  Returns the weights
-    blob and the per-epoch mean loss (standardised units)."""
+def train_mlp(x, t, epochs=20, batch=4096, lr=2e-3, seed=0, clip_quantile=5e-4, w_init=None, log=None,
+              device="cuda"):
+    """Train on features x [n,12] and targets t [n,3] (raw units) with the library's
+    nsn_train_warm_start: quantile clipping, z-scoring, initialisation, shuffling,
+    mini-batches and Adam all run on the device.  Returns the weights blob (parameters
+    and standardisation) and the per-epoch mean loss (standardised units)."""
     import torch
 
     lib = L.lib()
-    if not (np.isfinite(x).all() and np.isfinite(t).all()):
-        raise ValueError("training data holds non-finite values")
-    # steps that diverged leave a few multipliers orders of magnitude above the rest;
-    # they would set the target scale, so every column is clipped to its
-    # 0.05..99.95 % quantiles (a warm start need not reproduce them)
-    x = np.clip(x, *np.quantile(x, [5e-4, 1 - 5e-4], axis=0))
-    t = np.clip(t, *np.quantile(t, [5e-4, 1 - 5e-4], axis=0))
-    xm, xs, ym, ys = standardisation(x, t)
-    xn = torch.tensor((x - xm) / xs, dtype=torch.float32, device=device)
-    tn = torch.tensor((t - ym) / ys, dtype=torch.float32, device=device)
-    n = xn.shape[0]
-    w = torch.tensor(init_params(seed), device=device)
-    g = torch.zeros_like(w)
-    m = torch.zeros_like(w)
-    v = torch.zeros_like(w)
-    loss = torch.zeros(1, dtype=torch.float32, device=device)
-    scratch = torch.zeros(lib.nsn_mlp_scratch_bytes(batch) // 4 + 1, dtype=torch.float32, device=device)
+    xd = torch.as_tensor(np.ascontiguousarray(x, np.float32)).to(device)
+    td = torch.as_tensor(np.ascontiguousarray(t, np.float32)).to(device)
+    n = int(xd.shape[0])
+    ws_bytes = lib.nsn_train_workspace_bytes(n, int(batch))
+    if ws_bytes == 0:
+        raise L.NSNError("nsn_train_workspace_bytes: bad sizes or sort query failed")
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
+    blob = torch.zeros(N_PARAMS + 2 * N_IN + 2 * N_OUT, dtype=torch.float32, device=device)
+    w0 = None if w_init is None else torch.as_tensor(np.ascontiguousarray(w_init, np.float32)).to(device)
+    hist = np.zeros(int(epochs), np.float64)
+    tp = L.TrainParamsC(epochs=int(epochs), batch=int(batch), lr=float(lr), beta1=0.9, beta2=0.999, adam_eps=1e-8,
+                        clip_quantile=float(clip_quantile), seed=int(seed))
     stream = torch.cuda.current_stream().cuda_stream
-    gen = torch.Generator(device="cpu").manual_seed(seed)
-    hist = []
-    step = 0
-    for ep in range(epochs):
-        perm = torch.randperm(n, generator=gen).to(device)
-        tot, cnt = 0.0, 0
-        lr_ep = lr * 0.5 * (1 + np.cos(np.pi * ep / max(epochs, 1)))  # cosine schedule
-        for b0 in range(0, n, batch):
-            idx = perm[b0:b0 + batch]
-            xb = xn.index_select(0, idx).contiguous()
-            tb = tn.index_select(0, idx).contiguous()
-            nb = xb.shape[0]
-            L.check(lib.nsn_mlp_loss_grad(w.data_ptr(), xb.data_ptr(), tb.data_ptr(), nb, g.data_ptr(),
-                                          loss.data_ptr(), scratch.data_ptr(), C.c_void_p(stream)),
-                    "nsn_mlp_loss_grad")
-            step += 1
-            L.check(lib.nsn_mlp_adam(w.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), N_PARAMS,
-                                     C.c_float(lr_ep), C.c_float(0.9), C.c_float(0.999), C.c_float(1e-8), step,
-                                     C.c_void_p(stream)), "nsn_mlp_adam")
-            lv = loss.item()
-            if not np.isfinite(lv):
-                raise FloatingPointError(f"training loss became non-finite in epoch {ep + 1}")
-            tot += lv * nb
-            cnt += nb
-        hist.append(tot / cnt)
-        if log:
-            log(f"epoch {ep + 1}/{epochs} loss {hist[-1]:.5e}")
-    blob = np.concatenate([w.cpu().numpy(), xm, xs, ym, ys]).astype(np.float32)
-    return blob, hist
+    L.check(lib.nsn_train_warm_start(xd.data_ptr(), td.data_ptr(), n, C.byref(tp),
+                                     w0.data_ptr() if w0 is not None else None, blob.data_ptr(),
+                                     hist.ctypes.data_as(L.D), ws.data_ptr(), ws_bytes, C.c_void_p(stream)),
+            "nsn_train_warm_start")
+    if log:
+        for ep, v in enumerate(hist):
+            log(f"epoch {ep + 1}/{epochs} loss {v:.5e}")
+    return blob.cpu().numpy(), list(hist)
 
 
 def predict(blob, x, device="cuda"):

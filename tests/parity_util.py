@@ -26,6 +26,26 @@ def state_close(gpu, orc, L_scene=1.0, h=1 / 60, g=9.81, tol=1e-4):
 
 
 FP32_REL = 1.2e-7  # about one FP32 ulp, relative
+STATE_TOL_CAP = 1e-3  # largest conditioning-based state tolerance that is still asserted
+
+
+class History(list):
+    """Per-step worst errors of a lockstep run, with the comparisons whose
+    conditioning-based tolerance exceeded STATE_TOL_CAP (not asserted: capped)."""
+
+    def __init__(self):
+        super().__init__()
+        self.capped = []
+
+
+def skip_if_capped(hist):
+    """Mark a test skipped (after every decidable comparison has passed) when some of
+    its comparisons were above the cap, naming them."""
+    import pytest
+    if hist.capped:
+        cases = "; ".join(f"step {s} env {e} {k}: tol {t:.1e} (err {v:.1e})" for s, e, k, t, v in hist.capped[:8])
+        pytest.skip(f"{len(hist.capped)} comparisons not decidable at the {STATE_TOL_CAP:g} cap "
+                    f"(the FP64 oracle itself moves more under FP32-sized input changes): {cases}")
 
 
 def oracle_sensitivity(desc, pre, op, h, N, M, tol, trials=3, L_scene=1.0, prev=None):
@@ -72,7 +92,9 @@ def lockstep(scene, envs, params, h, N, M, tol=0.0, steps=1, env_ids=None, check
     max(err_tol, sens_factor * oracle_sensitivity(...)): where the unconverged
     iterate amplifies rounding (global Krylov scalars shared by stiff and soft parts,
     the per-DOF secant of the geometric stiffness), FP32 and FP64 cannot agree closer
-    than the problem's own conditioning; elsewhere err_tol applies unchanged.
+    than the problem's own conditioning; elsewhere err_tol applies unchanged.  A
+    tolerance above STATE_TOL_CAP is not asserted: the comparison is recorded in the
+    returned history's `capped` list (see skip_if_capped).
     prev_from_gpu: from the second step on, the oracle's previous-step multipliers
     (the warm start's input) are the GPU's, so both sides start from the same lambda0.
     sens_trials: perturbed oracle runs per estimate (more trials, a larger and less
@@ -82,7 +104,7 @@ def lockstep(scene, envs, params, h, N, M, tol=0.0, steps=1, env_ids=None, check
         env_ids = list(range(len(envs)))
     op = O.make_params(params)
     orcs = {e: O.OracleEnv(envs[e]) for e in env_ids}
-    history = []
+    history = History()
     for s in range(steps):
         pre = {e: scene.read_state(e) for e in env_ids}
         prev = {}
@@ -125,9 +147,13 @@ def lockstep(scene, envs, params, h, N, M, tol=0.0, steps=1, env_ids=None, check
             for k, v in err.items():
                 if k.startswith("stats"):
                     continue
+                if tols[k] > STATE_TOL_CAP:
+                    history.capped.append((s, e, k, tols[k], v))
+                    continue
                 if v > worst.get(k, (-1, None, None))[0]:
                     worst[k] = (v, e, tols[k])
-            bad = {k: (v, tols[k]) for k, v in err.items() if not k.startswith("stats") and v > tols[k]}
+            bad = {k: (v, tols[k]) for k, v in err.items()
+                   if not k.startswith("stats") and tols[k] <= STATE_TOL_CAP and v > tols[k]}
             assert not bad, f"step {s} env {e}: (err, tol) {bad}; gpu stats {stats[e]}; oracle {ost}"
         history.append(worst)
     return history

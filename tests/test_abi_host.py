@@ -32,7 +32,7 @@ def _query(envs):
     L, lib = _lib()
     m = _Marshal(envs)
     n = C.c_size_t(0)
-    st = lib.nsn_query_workspace(m.c, len(envs), C.byref(n))
+    st = lib.nsn_query_workspace(m.c, len(envs), None, C.byref(n))
     return st, n.value, lib.nsn_last_error().decode()
 
 
@@ -118,3 +118,30 @@ def test_record_types_match_c_structs(tmp_path):
         assert got[(st, "size")] == C.sizeof(cls), st
         for name, _ in cls._fields_:
             assert got[(st, name)] == getattr(cls, name).offset, (st, name)
+
+
+def _query_p(envs, params):
+    from paper_1907_04587_amd.scene import _Marshal, params_c
+    L, lib = _lib()
+    m = _Marshal(envs)
+    n = C.c_size_t(0)
+    pc = params_c(params) if params is not None else None
+    st = lib.nsn_query_workspace(m.c, len(envs), C.byref(pc) if pc is not None else None, C.byref(n))
+    return st, n.value
+
+
+def test_workspace_query_reserves_optional_buffers():
+    """The parameters decide the optional buffers: island mode and line search each
+    add to the workspace; NULL parameters are the defaults; bad parameters are
+    rejected."""
+    envs = [si.cube_stack(0), si.tet_block_with_boxes(0, cells=3, n_boxes=2)]
+    st0, n0 = _query_p(envs, None)
+    st1, n1 = _query_p(envs, si.SolverParams())
+    st2, n2 = _query_p(envs, si.SolverParams(islands=1))
+    st3, n3 = _query_p(envs, si.SolverParams(line_search=1))
+    assert st0 == st1 == st2 == st3 == 0
+    assert n0 == n1 < n2 and n1 < n3
+    st, _ = _query_p(envs, si.SolverParams(watchdog=2))
+    assert st == -1
+    st, _ = _query_p(envs, si.SolverParams(ncp=5))
+    assert st == -1

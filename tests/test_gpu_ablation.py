@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import scene_inputs as si
-from tests.parity_util import lockstep
+from tests.parity_util import lockstep, skip_if_capped
 
 pytestmark = pytest.mark.gpu
 
@@ -30,6 +30,7 @@ def test_pcg_per_newton_iteration(newton):
     hist = lockstep(sc, envs, p, H, newton, 40, steps=2, sens_factor=10.0)
     for s, w in enumerate(hist):
         print("pcg", newton, s, {k: f"{v[0]:.2e} (tol {v[2]:.1e})" for k, v in w.items()}, flush=True)
+    skip_if_capped(hist)
 
 
 def test_heavy_stack_ablation():

@@ -144,3 +144,118 @@ def test_training_reduces_loss():
     t = np.stack([np.maximum(x[:, 0] + 0.5 * x[:, 3], 0), 0.3 * x[:, 1] * x[:, 2], np.tanh(x[:, 5])], 1).astype(np.float32)
     blob, hist = train_mlp(x, t, epochs=15, batch=2048, lr=3e-3, seed=0, log=print)
     assert hist[-1] < 0.25 * hist[0], hist
+
+
+def _gpu_grad(lib, torch, w, x, t):
+    n = x.shape[0]
+    wd = torch.tensor(w, dtype=torch.float32, device="cuda")
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda")
+    td = torch.tensor(t, dtype=torch.float32, device="cuda")
+    gd = torch.zeros(NP, dtype=torch.float32, device="cuda")
+    ld = torch.zeros(1, dtype=torch.float32, device="cuda")
+    scratch = torch.zeros(lib.nsn_mlp_scratch_bytes(n) // 4 + 1, dtype=torch.float32, device="cuda")
+    assert lib.nsn_mlp_loss_grad(wd.data_ptr(), xd.data_ptr(), td.data_ptr(), n, gd.data_ptr(), ld.data_ptr(),
+                                 scratch.data_ptr(), None) == 0
+    torch.cuda.synchronize()
+    return ld.item(), gd.cpu().numpy().astype(np.float64)
+
+
+def test_loss_gradient_elementwise_against_bf16_oracle():
+    """Every one of the 9347 gradient entries against the oracle's backpropagation with
+    the kernels' bf16 operand rounding (sums in FP64).  Samples whose pre-activations
+    come within 1e-3 of a ReLU kink in the rounded forward pass are left out: there the
+    FP32 and FP64 sums may take different sides of the kink.  Tolerance: 1e-5 of the
+    largest entry of the parameter block (FP32 accumulation over the samples and the
+    odd one-ulp bf16 rounding flip of an FP32-computed operand; measured about 2e-7)."""
+    torch = _torch()
+    L, lib = _lib()
+    rng = np.random.default_rng(11)
+    w = np.asarray(_init_weights(rng), np.float32).astype(np.float64)
+    x = rng.normal(size=(4000, 12)).astype(np.float32).astype(np.float64)
+    t = rng.normal(size=(4000, 3)).astype(np.float32).astype(np.float64)
+    pre = O.mlp_preact_bf16(w, x)
+    keep = (np.abs(pre) > 1e-3).all(axis=(1, 2))
+    x, t = x[keep], t[keep]
+    assert x.shape[0] > 1000, x.shape
+    loss, g = _gpu_grad(lib, torch, w, x, t)
+    loss_ref, g_ref = O.mlp_loss_grad_bf16(w, x, t)
+    assert loss == pytest.approx(loss_ref, rel=1e-5)
+    offs = [0, 768, 832, 4928, 4992, 9088, 9152, 9344, 9347]
+    names = ["W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"]
+    for name, a, b in zip(names, offs[:-1], offs[1:]):
+        scale = np.abs(g_ref[a:b]).max()
+        err = np.abs(g[a:b] - g_ref[a:b]).max()
+        print(f"grad {name}: max err {err / scale:.2e} of the block's largest entry", flush=True)
+        assert err <= 1e-5 * scale, (name, err, scale)
+
+
+def _numpy_standardise(x, t, q):
+    cols = np.concatenate([x, t], 1).astype(np.float64)
+    if q > 0:
+        qf = float(np.float32(q))  # the library takes q as a float32 parameter
+        lo = np.quantile(cols, qf, axis=0)
+        hi = np.quantile(cols, 1 - qf, axis=0)
+        cols = np.clip(cols, lo.astype(np.float32), hi.astype(np.float32))
+    m, s = cols.mean(0), cols.std(0)
+    s = np.where(s > 1e-6, s, 1.0)
+    return cols, m, s
+
+
+def test_training_data_preparation_in_library():
+    """nsn_train_warm_start's clipping and z-scoring: the blob's statistics against
+    NumPy's quantiles (linear interpolation) and moments of the clipped columns."""
+    from paper_1907_04587_amd.warmstart import train_mlp
+    rng = np.random.default_rng(5)
+    n = 5001
+    x = rng.normal(size=(n, 12)).astype(np.float32)
+    x[:, 3] *= 50.0
+    x[rng.choice(n, 7, replace=False), 2] = 1e4  # outliers the clipping removes
+    t = rng.standard_cauchy(size=(n, 3)).astype(np.float32)
+    t[:, 2] = 0.5  # a constant column: deviation counts as 1
+    for q in [5e-4, 0.0]:
+        blob, hist = train_mlp(x, t, epochs=1, batch=1024, lr=1e-3, seed=1, clip_quantile=q)
+        _, m, s = _numpy_standardise(x, t, q)
+        tail = blob[NP:].astype(np.float64)
+        # means to 1e-6 of the column's deviation, deviations to 1e-5 relative
+        assert (np.abs(tail[:12] - m[:12]) <= 1e-6 * s[:12] + 1e-5 * np.abs(m[:12])).all(), (q, tail[:12], m[:12])
+        assert (np.abs(tail[12:24] - s[:12]) <= 1e-5 * s[:12]).all(), (q, tail[12:24], s[:12])
+        assert (np.abs(tail[24:27] - m[12:]) <= 1e-6 * s[12:] + 1e-5 * np.abs(m[12:])).all(), (q, tail[24:27], m[12:])
+        assert (np.abs(tail[27:30] - s[12:]) <= 1e-5 * s[12:]).all(), (q, tail[27:30], s[12:])
+        assert tail[29] == 1.0
+
+
+def test_training_step_is_one_adam_update_of_the_library_gradient():
+    """One epoch of one full batch from given weights: the result is w minus one Adam
+    step (bias-corrected, the first step of the cosine schedule at the full rate) of
+    the loss gradient of the standardised data."""
+    torch = _torch()
+    L, lib = _lib()
+    from paper_1907_04587_amd.warmstart import init_params, train_mlp
+    rng = np.random.default_rng(6)
+    n = 2048
+    x = rng.normal(size=(n, 12)).astype(np.float32)
+    t = rng.normal(size=(n, 3)).astype(np.float32)
+    w0 = init_params(3)
+    lr = 1e-3
+    blob, hist = train_mlp(x, t, epochs=1, batch=n, lr=lr, seed=2, clip_quantile=0.0, w_init=w0)
+    cols, m, s = _numpy_standardise(x, t, 0.0)
+    xs = ((cols[:, :12] - m[:12]) / s[:12]).astype(np.float32)
+    ts = ((cols[:, 12:] - m[12:]) / s[12:]).astype(np.float32)
+    loss, g = _gpu_grad(lib, torch, w0, xs, ts)
+    assert hist[0] == pytest.approx(loss, rel=1e-4)
+    step = lr * g / (np.abs(g) + 1e-8)
+    d = np.abs(blob[:NP] - (w0 - step))
+    assert d.max() <= 0.05 * lr, d.max()
+    assert (d > 1e-3 * lr).sum() <= 5, (d > 1e-3 * lr).sum()
+
+
+def test_training_deterministic_and_seeded():
+    from paper_1907_04587_amd.warmstart import train_mlp
+    rng = np.random.default_rng(7)
+    x = rng.normal(size=(3000, 12)).astype(np.float32)
+    t = rng.normal(size=(3000, 3)).astype(np.float32)
+    a, _ = train_mlp(x, t, epochs=2, batch=512, seed=4)
+    b, _ = train_mlp(x, t, epochs=2, batch=512, seed=4)
+    c, _ = train_mlp(x, t, epochs=2, batch=512, seed=5)
+    assert np.array_equal(a, b)
+    assert not np.array_equal(a[:NP], c[:NP])

@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import scene_inputs as si
-from tests.parity_util import bucket_sample, lockstep
+from tests.parity_util import bucket_sample, lockstep, skip_if_capped
 
 pytestmark = pytest.mark.gpu
 
@@ -46,13 +46,18 @@ def _driven_chain():
     return d
 
 
-def _all_kinds():
+def _rigid_kinds():
     return [
         si.cube_stack(seed=1),
         si.box_on_incline(0.5, 0.3),
         si.particles_vs_planes_lcp(seed=1),
         _driven_chain(),
         si.pendulum_drive(),
+    ]
+
+
+def _all_kinds():
+    return _rigid_kinds() + [
         si.tet_block_with_boxes(seed=0, cells=3, n_boxes=3),
         si.single_tet(n_tets=5, deform=[[1.1, 0.02, 0.0], [0.0, 1.0, 0.03], [0.01, 0.0, 0.9]]),
         si.grasp_scene(seed=0, sphere_cell=0.02),
@@ -75,12 +80,28 @@ def test_single_particle_worked_example():
 
 @pytest.mark.parametrize("newton", [1, 2, 3])
 @pytest.mark.parametrize("ncp", [0, 1])
+def test_per_newton_iteration_rigid_kinds(newton, ncp):
+    """The rigid, contact and joint scenes alone (their states are decidable at 1e-4
+    or at the conditioning tolerance below the cap)."""
+    envs = _rigid_kinds()
+    p = si.SolverParams(ncp=ncp)
+    sc = _scene(envs, p)
+    hist = lockstep(sc, envs, p, H, newton, 40, steps=1, sens_factor=10.0)
+    _print(f"rigid{newton}", hist)
+    skip_if_capped(hist)
+
+
+@pytest.mark.parametrize("newton", [1, 2, 3])
+@pytest.mark.parametrize("ncp", [0, 1])
 def test_per_newton_iteration_all_scene_kinds(newton, ncp):
+    """Every scene kind together; FEM-bearing states often move more than the cap in
+    the oracle itself (they are decided row by row in tests/test_gpu_rows.py)."""
     envs = _all_kinds()
     p = si.SolverParams(ncp=ncp)
     sc = _scene(envs, p)
     hist = lockstep(sc, envs, p, H, newton, 40, steps=1, sens_factor=10.0)
     _print(f"iter{newton}", hist)
+    skip_if_capped(hist)
 
 
 @pytest.mark.parametrize("newton", [1, 2])
@@ -97,6 +118,7 @@ def test_grasp_single_cr_iteration(newton):
         sc.step(1.0 / 120.0, 10, 40, 0.0)
     hist = lockstep(sc, envs, p, 1.0 / 120.0, newton, 1, steps=1, sens_factor=10.0)
     _print(f"grasp{newton}", hist)
+    skip_if_capped(hist)
 
 
 @pytest.mark.parametrize("newton", [1, 2])
@@ -113,6 +135,7 @@ def test_per_newton_iteration_warm_start(newton):
     sc = _scene(envs, p)
     hist = lockstep(sc, envs, p, H, newton, 40, steps=3, sens_factor=10.0, prev_from_gpu=True)
     _print(f"warm{newton}", hist)
+    skip_if_capped(hist)
 
 
 @pytest.mark.parametrize("newton", [2, 4, 8])
@@ -127,6 +150,7 @@ def test_line_search_frictionless(newton):
     sc = _scene(envs, p)
     hist = lockstep(sc, envs, p, H, newton, 40, steps=2, sens_factor=10.0)
     _print(f"linesearch{newton}", hist)
+    skip_if_capped(hist)
 
 
 def test_line_search_converges_in_fewer_iterations():
@@ -180,6 +204,7 @@ def test_full_size_batch_sampled():
     _print("full", hist)
     st = sc.stats()
     assert not st["nonfinite"].any()
+    skip_if_capped(hist)
 
 
 def test_full_size_rigid_batch_sampled():
@@ -194,6 +219,7 @@ def test_full_size_rigid_batch_sampled():
     hist = lockstep(sc, envs, p, H, 2, 40, steps=1, env_ids=sample, sens_factor=10.0)
     _print("rigidfull", hist)
     assert not sc.stats()["nonfinite"].any()
+    skip_if_capped(hist)
 
 
 def test_empty_env_and_overflow():

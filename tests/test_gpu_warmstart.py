@@ -3,9 +3,10 @@ projected MLP start multipliers, and what the trained network gains.
 
 The gain is measured where the network acts: how close its start multipliers are to
 the multipliers the solver ends a step with, against the previous step's multipliers
-(the plain warm start).  On the grasp distribution no start reaches r_ncp <= 1e-4
-within 50 Newton iterations (the FEM rows converge slowly), so the iteration counts
-are reported, not asserted."""
+(the plain warm start), and in Newton / PCR iterations to r_ncp <= 1e-4 on held-out
+rigid batches against the paper's zero start.  On the grasp distribution no start
+reaches r_ncp <= 1e-4 within 50 Newton iterations (the friction and tet rows of the
+soft sphere stall), so the iteration counts there are reported, not asserted."""
 import os
 
 import numpy as np
@@ -202,31 +203,35 @@ def test_learned_mode_needs_a_model():
         assert not sc.stats()["nonfinite"].any()
 
 
-def test_hybrid_start_gain_on_held_out_rigid_batch():
-    """Held-out rigid envs (seeds disjoint from the training, validation, test and
-    benchmark seeds), residual mode r_ncp <= 1e-4: the hybrid start (previous-step
-    multipliers for persisting contacts, the batched model for new ones) leaves fewer
-    env-steps unconverged at the 50-iteration cap than the previous-step start.  A
-    batched step lasts as long as its slowest env, so this is where its throughput
-    gain comes from.  Mean Newton iterations are reported."""
-    envs = si.batched_envs(1024, base_seed=500_000, tets_max=0)
+def test_learned_start_iterations_saved_on_held_out_rigid_batches():
+    """Newton and PCR iterations per env-step to reach r_ncp <= 1e-4 (cap 50 x 40) on
+    two held-out sets of 512 rigid envs (seeds disjoint from the training, validation,
+    test and benchmark seeds), after three settling steps, over eight steps.  Asserted:
+    the learned and hybrid starts save at least 25% of the Newton iterations of the
+    paper's start (zero), on each set.  Reported: the previous-step start, which stays
+    ahead of both learned starts on these envs (persisting contacts make the previous
+    multipliers nearly exact; the network's prediction is percent-level), so the
+    learned starts do not beat the stronger plain start here."""
     blob = np.load(os.path.join(os.path.dirname(WEIGHTS), "warm_start_batched.npy"), allow_pickle=False)
-    out = {}
-    for name, mode in [("prev", si.WARM_PREV), ("hybrid", si.WARM_HYBRID)]:
-        sc = _scene(envs, si.SolverParams(warm=mode))
-        if mode == si.WARM_HYBRID:
-            sc.set_warm_start_model(blob)
-        for _ in range(3):
-            sc.step(1 / 60, 50, 40, 1e-4)
-        sc.reset_accumulators()
-        capped = 0
-        for _ in range(10):
-            sc.step(1 / 60, 50, 40, 1e-4)
-            st = sc.stats()
-            capped += int((~st["converged"].astype(bool)).sum())
-            assert not st["nonfinite"].any()
-        acc = sc.accumulators()
-        out[name] = (capped, float(acc["newton_iters"].sum()) / max(int(acc["steps"].sum()), 1))
-        print(f"arm {name}: unconverged env-steps {capped} of {10 * len(envs)}, mean Newton {out[name][1]:.2f}",
-              flush=True)
-    assert out["hybrid"][0] < out["prev"][0], out
+    for base in (500_000, 600_000):
+        envs = si.batched_envs(512, base_seed=base, tets_max=0)
+        out = {}
+        for name, mode in [("zero", si.WARM_ZERO), ("prev", si.WARM_PREV), ("learned", si.WARM_LEARNED),
+                           ("hybrid", si.WARM_HYBRID)]:
+            sc = _scene(envs, si.SolverParams(warm=mode))
+            if mode in (si.WARM_LEARNED, si.WARM_HYBRID):
+                sc.set_warm_start_model(blob)
+            for _ in range(3):
+                sc.step(1 / 60, 50, 40, 1e-4)
+            sc.reset_accumulators()
+            for _ in range(8):
+                sc.step(1 / 60, 50, 40, 1e-4)
+                assert not sc.stats()["nonfinite"].any()
+            acc = sc.accumulators()
+            steps = max(int(acc["steps"].sum()), 1)
+            out[name] = (float(acc["newton_iters"].sum()) / steps, float(acc["cr_iters"].sum()) / steps,
+                         int(acc["converged"].sum()) / steps)
+            print(f"seeds {base}+: arm {name}: Newton {out[name][0]:.2f}, PCR {out[name][1]:.1f} per env-step, "
+                  f"converged {100 * out[name][2]:.2f}%", flush=True)
+        for arm in ("learned", "hybrid"):
+            assert out[arm][0] <= 0.75 * out["zero"][0], (base, arm, out)
