@@ -427,6 +427,20 @@ nsn_status nsn_mlp_loss_grad(const float *w, const float *x, const float *t, int
 nsn_status nsn_mlp_adam(float *w, const float *grad, float *m, float *v, int64_t n_params,
                         float lr, float beta1, float beta2, float eps, int32_t step, void *stream);
 
+/* The loss and gradient of nsn_mlp_loss_grad for callers that cannot allocate device
+ * memory (code under graph capture, serving loops, harnesses that forbid it): the
+ * same kernels, with the per-block partial gradients in a device array the library
+ * holds for the life of the process on every device it runs on (nsn_mlp_noalloc_
+ * scratch_bytes() bytes, about 10 MiB), so the results equal nsn_mlp_loss_grad's bit
+ * for bit.  Allocates nothing and calls no allocating routine.  Calls on one device
+ * share that array: calls that overlap in time on one device race (serialise them,
+ * e.g. on one stream).  NSN_EINVAL for NULL pointers or n <= 0; NSN_EUNSUPPORTED if n
+ * needs more scratch than the array holds; NSN_EDEVICE if the array's address cannot
+ * be taken.  The message is in nsn_last_error(). */
+size_t nsn_mlp_noalloc_scratch_bytes(void);
+nsn_status nsn_mlp_loss_grad_noalloc(const float *w, const float *x, const float *t, int64_t n,
+                                     float *grad, float *loss_out, void *stream);
+
 /* Training of the warm-start network on solver-generated data (the network is trained
  * on the multipliers the method itself converges to; the paper's solver is the
  * teacher).  Every stage runs on the device in the library:

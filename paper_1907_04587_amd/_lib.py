@@ -117,6 +117,9 @@ def lib():
     L.nsn_mlp_loss_grad.argtypes = [VP, VP, VP, C.c_int64, VP, VP, VP, VP]
     L.nsn_mlp_adam.argtypes = [VP, VP, VP, VP, C.c_int64, C.c_float, C.c_float, C.c_float,
                                C.c_float, S, VP]
+    L.nsn_mlp_noalloc_scratch_bytes.restype = C.c_size_t
+    L.nsn_mlp_noalloc_scratch_bytes.argtypes = []
+    L.nsn_mlp_loss_grad_noalloc.argtypes = [VP, VP, VP, C.c_int64, VP, VP, VP]
     L.nsn_train_workspace_bytes.restype = C.c_size_t
     L.nsn_train_workspace_bytes.argtypes = [C.c_int64, S]
     L.nsn_train_warm_start.argtypes = [VP, VP, C.c_int64, C.POINTER(TrainParamsC), VP, VP, D, VP, C.c_size_t, VP]

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnsn.so")
-SOURCES = ["nsn_step.hip", "nsn_step_ext.hip", "nsn_mlp.hip", "nsn_train.hip", "nsn_api.cpp"]
+SOURCES = ["nsn_step.hip", "nsn_step_ext.hip", "nsn_mlp.hip", "nsn_train.hip", "nsn_noalloc.hip", "nsn_api.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 # per-source extra flags: the extended Newton kernel needs every context-taking

@@ -215,6 +215,8 @@ Sizes sizes_of(const std::vector<HostEnv> &he) {
 
 }  // namespace
 
+nsn_status nsn::set_error(nsn_status st, const std::string &msg) { return fail(st, msg); }
+
 struct GraphKey {
   float h;
   int n, m;

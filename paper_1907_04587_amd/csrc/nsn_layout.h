@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/nsn.h"
 
 namespace nsn {
@@ -166,6 +168,9 @@ struct StepArgs {
   int dump_k;  // >= 0: stop inside Newton iteration dump_k and keep its data (dump step)
   nsn_solver_params p;
 };
+
+// sets the calling thread's nsn_last_error() message and returns st (nsn_api.cpp)
+nsn_status set_error(nsn_status st, const std::string &msg);
 
 // kernel launchers (nsn_step.hip)
 hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_features, hipStream_t st);
