@@ -296,6 +296,24 @@ nsn_status nsn_write_state(nsn_scene s, int32_t env, const float *rigid_x, const
                            const float *rigid_v, const float *rigid_w, const float *particle_x,
                            const float *particle_v, const double *time);
 
+/* Snapshot of the scene's dynamic state: what a time step (Alg. 1) reads that earlier
+ * steps wrote -- positions and velocities (q^-, u^-) of bodies and particles, each
+ * env's time, and what a warm start (Sec. 8.1) carries over: the previous step's
+ * contact keys and multipliers and the joint rows' multipliers.  Geometry, solver
+ * parameters, schedule, warm-start model and accumulators are not part of it.
+ * nsn_state_bytes gives the size of a snapshot of this scene. */
+nsn_status nsn_state_bytes(nsn_scene s, size_t *bytes);
+/* Copies the state of every env into buf (device memory of nsn_state_bytes bytes,
+ * owned by the caller) with device-to-device copies enqueued on the scene's stream;
+ * returns without waiting.  NSN_EINVAL for a null argument. */
+nsn_status nsn_save_state(nsn_scene s, void *buf);
+/* Restores the state from a snapshot that nsn_save_state took of this same scene
+ * (any other buffer is undefined behaviour); enqueued on the scene's stream.  The next
+ * nsn_step continues from the saved state exactly: with the same schedule and
+ * parameters it repeats, bit for bit, the steps that followed the save.  Discards
+ * the record of a dump step (nsn_read_iteration then reports NSN_ESTATE). */
+nsn_status nsn_load_state(nsn_scene s, const void *buf);
+
 /* Contacts of one env from the last step (Alg. 1 collision detection; multipliers of
  * Sec. 3/4): up to `cap` records.  *n receives the count.  keys[cap]; bodies[cap*2] =
  * (feature body, target body) numbered as in nsn_contact; geom[cap*10] = normal(3),
@@ -386,6 +404,14 @@ nsn_status nsn_get_schedule(nsn_scene s, int32_t cap, int32_t *n, int32_t *first
  * occupancy (all of the device's LDS per workgroup at 512 and 1024 threads, half at
  * 256, a quarter at 128).  Applies to the current and later schedules. */
 nsn_status nsn_set_lds_mode(nsn_scene s, int32_t max_mode);
+
+/* Form of the PCR loop (Sec. 8.2; a tuning and testing switch with identical results):
+ * 1 (default) keeps the rows and the element data of every tet and contact in the
+ * registers of the thread that owns the element for all the PCR iterations of a
+ * Newton iteration, in envs whose elements all have a register slot (4 per thread
+ * below 1024 threads, 1 at 1024) and that hold neo-Hookean tets only; other envs, and
+ * 0, stream them from memory every PCR iteration. */
+nsn_status nsn_set_pcr_form(nsn_scene s, int32_t form);
 
 /* The LDS mode each current bucket runs in (0, 1, 2 as above): mode[cap]. */
 nsn_status nsn_get_lds_modes(nsn_scene s, int32_t cap, int32_t *n, int32_t *mode);

@@ -96,6 +96,9 @@ def lib():
     L.nsn_get_stats.argtypes = [VP, VP]
     L.nsn_read_state.argtypes = [VP, S, F, F, F, F, F, F, D]
     L.nsn_write_state.argtypes = [VP, S, F, F, F, F, F, F, D]
+    L.nsn_state_bytes.argtypes = [VP, C.POINTER(C.c_size_t)]
+    L.nsn_save_state.argtypes = [VP, VP]
+    L.nsn_load_state.argtypes = [VP, VP]
     L.nsn_read_contacts.argtypes = [VP, S, S, I32, I32, I32, F, F]
     L.nsn_read_lambda.argtypes = [VP, S, S, I32, F]
     L.nsn_set_warm_start_model.argtypes = [VP, F, C.c_int64]
@@ -106,6 +109,7 @@ def lib():
     L.nsn_set_schedule.argtypes = [VP, S, I32, I32, I32]
     L.nsn_set_lds_mode.argtypes = [VP, C.c_int32]
     L.nsn_get_lds_modes.argtypes = [VP, C.c_int32, I32, I32]
+    L.nsn_set_pcr_form.argtypes = [VP, C.c_int32]
     L.nsn_get_schedule.argtypes = [VP, S, I32, I32, I32, I32]
     L.nsn_stats_device_ptr.argtypes = [VP, C.POINTER(VP)]
     L.nsn_read_kernel_times.argtypes = [VP, S, I32, D]

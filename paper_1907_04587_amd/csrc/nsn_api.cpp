@@ -133,6 +133,7 @@ bool params_ok(const nsn_solver_params *p) {
 
 // Assign every workspace buffer; with base == nullptr only the size is computed.
 void layout(const Sizes &z, int n_envs, const Options &opt, Arena &a, DevScene &S, EnvInfo *&env, int *&order) {
+  S.dev = a.take<DevScene>(1);
   S.n_envs = n_envs;
   S.NR = z.NR; S.NP = z.NP; S.NT = z.NT; S.NJ = z.NJ; S.NC = z.NC; S.NROW = z.NROW; S.NDOF = z.NDOF;
   S.any_linear = z.any_linear;
@@ -245,6 +246,7 @@ struct nsn_scene_s {
   std::map<GraphKey, hipGraphExec_t> graphs;
   bool use_graphs = true;
   int lds_max = 2;  // the largest LDS mode the buckets may use (nsn_set_lds_mode)
+  int pcr_form = 1;  // 1: register-resident PCR where an env's elements fit (nsn_set_pcr_form)
   int want_features = 0;
   // side streams (default priority) for concurrent schedule buckets, and fork/join events
   std::vector<hipStream_t> side;
@@ -287,6 +289,32 @@ static void set_bucket_lds(nsn_scene s) {
       b.lds_floats = mx;
     }
   }
+}
+
+// The dynamic state: every array a step reads that an earlier step wrote (Alg. 1 reads
+// q^-, u^- and the time; a warm start, Sec. 8.1, also the previous step's contact keys
+// and multipliers and the joint rows' multipliers, which stay in row_lam).  Each block
+// starts at a 256-byte boundary of the snapshot.
+template <class F>
+static size_t for_each_state_block(const DevScene &S, F f) {
+  size_t off = 0;
+  auto blk = [&](const void *p, size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    if (bytes) f((char *)p, off, bytes);
+    off += bytes;
+  };
+  blk(S.r_x, sizeof(float4) * S.NR);
+  blk(S.r_q, sizeof(float4) * S.NR);
+  blk(S.r_v, sizeof(float4) * S.NR);
+  blk(S.r_w, sizeof(float4) * S.NR);
+  blk(S.p_x, sizeof(float4) * S.NP);
+  blk(S.p_v, sizeof(float4) * S.NP);
+  blk(S.time, sizeof(double) * S.n_envs);
+  blk(S.c_prev_key, sizeof(int) * S.NC);
+  blk(S.c_prev_lam, sizeof(float4) * S.NC);
+  blk(S.n_prev, sizeof(int) * S.n_envs);
+  blk(S.row_lam, sizeof(float) * S.NROW);
+  return off;
 }
 
 extern "C" {
@@ -514,6 +542,7 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
   HIP_TRY(up((void *)S.t_dst, t_dst.data(), sizeof(int4) * z.NT));
   HIP_TRY(up((void *)S.r_jadj_ptr, jadj_ptr.data(), sizeof(int) * (z.NR + 1)));
   HIP_TRY(up((void *)S.r_jadj, jadj.data(), sizeof(int) * z.NJADJ));
+  HIP_TRY(up((void *)S.dev, &S, sizeof(DevScene)));  // the table itself, for the Newton kernel
   HIP_TRY(hipStreamSynchronize(st_));
 
   s->env = env;
@@ -610,7 +639,7 @@ static hipError_t enqueue_step(nsn_scene s, const StepArgs &a) {
   const size_t nb = s->buckets.size();
   if (s->stream == nullptr || nb == 1) {
     for (const Bucket &b : s->buckets) {
-      e = launch_newton(s->S, a, b.block, b.first, b.count, b.lds_floats, b.lds_mode, s->stream);
+      e = launch_newton(s->S, a, b.block, b.first, b.count, b.lds_floats, b.lds_mode, s->pcr_form, s->stream);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -625,7 +654,7 @@ static hipError_t enqueue_step(nsn_scene s, const StepArgs &a) {
   }
   for (size_t i = 0; i < nb; ++i) {
     const Bucket &b = s->buckets[i];
-    e = launch_newton(s->S, a, b.block, b.first, b.count, b.lds_floats, b.lds_mode,
+    e = launch_newton(s->S, a, b.block, b.first, b.count, b.lds_floats, b.lds_mode, s->pcr_form,
                       i == 0 ? s->stream : s->side[i - 1]);
     if (e != hipSuccess) return e;
   }
@@ -776,6 +805,33 @@ nsn_status nsn_write_state(nsn_scene s, int32_t env, const float *rigid_x, const
   return NSN_OK;
 }
 
+nsn_status nsn_state_bytes(nsn_scene s, size_t *bytes) {
+  if (!s || !bytes) return fail(NSN_EINVAL, "nsn_state_bytes: null argument");
+  *bytes = for_each_state_block(s->S, [](char *, size_t, size_t) {});
+  return NSN_OK;
+}
+
+nsn_status nsn_save_state(nsn_scene s, void *buf) {
+  if (!s || !buf) return fail(NSN_EINVAL, "nsn_save_state: null argument");
+  hipError_t e = hipSuccess;
+  for_each_state_block(s->S, [&](char *p, size_t off, size_t bytes) {
+    if (e == hipSuccess) e = hipMemcpyAsync((char *)buf + off, p, bytes, hipMemcpyDeviceToDevice, s->stream);
+  });
+  HIP_TRY(e);
+  return NSN_OK;
+}
+
+nsn_status nsn_load_state(nsn_scene s, const void *buf) {
+  if (!s || !buf) return fail(NSN_EINVAL, "nsn_load_state: null argument");
+  hipError_t e = hipSuccess;
+  for_each_state_block(s->S, [&](char *p, size_t off, size_t bytes) {
+    if (e == hipSuccess) e = hipMemcpyAsync(p, (const char *)buf + off, bytes, hipMemcpyDeviceToDevice, s->stream);
+  });
+  HIP_TRY(e);
+  s->dumped_k = -1;  // the working arrays no longer hold a dump step's iterate
+  return NSN_OK;
+}
+
 nsn_status nsn_read_contacts(nsn_scene s, int32_t env, int32_t cap, int32_t *n, int32_t *keys, int32_t *bodies,
                              float *geom, float *lam) {
   nsn_status st = check_env(s, env);
@@ -921,6 +977,14 @@ nsn_status nsn_get_schedule(nsn_scene s, int32_t cap, int32_t *n, int32_t *first
     count[i] = s->buckets[i].count;
     block[i] = s->buckets[i].block;
   }
+  return NSN_OK;
+}
+
+nsn_status nsn_set_pcr_form(nsn_scene s, int32_t form) {
+  if (!s || form < 0 || form > 1) return fail(NSN_EINVAL, "PCR form must be 0 or 1");
+  s->pcr_form = form;
+  for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+  s->graphs.clear();
   return NSN_OK;
 }
 

@@ -43,6 +43,7 @@ struct IslState {
 // Pointers into the workspace.  Indices stored in the tables are global
 // (already offset by the env's base) unless noted.
 struct DevScene {
+  const DevScene *dev;  // this table's copy in the workspace (the Newton kernel's argument)
   int n_envs;
   int NR, NP, NT, NJ, NC, NROW, NDOF;  // totals over all envs
   int any_linear;                      // some env has NSN_TET_LINEAR tets
@@ -178,8 +179,10 @@ hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_feature
 // lds_mode 0: the body-space vector in global memory; 1: in `lds_floats` floats of
 // dynamic LDS; 2: in LDS together with the tets' contributions
 // (align4(n_dof) + 12 n_tet floats per env)
+// resident: the register-resident PCR for the envs whose elements all have a register
+// slot (neo-Hookean instantiation only; others take the streaming form)
 hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
-                         int lds_mode, hipStream_t st);
+                         int lds_mode, int resident, hipStream_t st);
 // the same for the extended instantiation (linear tets, islands; nsn_step_ext.hip)
 hipError_t launch_newton_ext(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
                              int lds_mode, hipStream_t st);

@@ -17,6 +17,11 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+// Multiply-adds are fused only within one expression (the C rule), never across
+// statements: the fused operations then follow the source, and the two forms of the
+// PCR loop (rows streamed through memory or held in registers) round identically.
+#pragma clang fp contract(on)
+
 #include "nsn_layout.h"
 #include "nsn_math.h"
 
@@ -144,18 +149,36 @@ __device__ __forceinline__ void ncp_min(float C, float lam, float r, float &phi,
 }
 
 // Friction compliance W (Sec. 4.3 eq. friction_w, Appendix A.2) with the velocity
-// magnitude unsquared and a cancellation-free fixed-point numerator.  When the
-// fixed point asks for a non-positive friction magnitude (den = r |lam_f|^{n+1} at or
-// below kKappaW r mu lam_n) W is infinite: the caller then drives lam_f to zero.
+// magnitude unsquared, W = r num / den with num = sqrt(|v|^2 + r^2 s^2) - r s and
+// den = |v| + r |lam_f| - num, s = mu lam_n - |lam_f|.  Both are evaluated free of
+// cancellation between large terms, which FP32 cannot afford where W is large (den
+// small beside |v|): with root = sqrt(|v|^2 + r^2 s^2) and root - |v| =
+// r^2 s^2 / (root + |v|),
+//   inside the cone (s > 0): num = |v|^2 / (root + r s),
+//       den = r |lam_f| + |v| r s (root + |v| + r s) / ((root + |v|)(root + r s)),
+//       a sum of non-negative terms;
+//   outside (s <= 0): num = root + r |s|, den = r mu lam_n - r^2 s^2 / (root + |v|),
+//       whose remaining cancellation is the limit itself.
+// When the fixed point asks for a non-positive friction magnitude (den = r
+// |lam_f|^{n+1} at or below kKappaW r mu lam_n) W is infinite: the caller then drives
+// lam_f to zero.
 __device__ __forceinline__ float friction_w(int ncp, float vn, float lam_n, float lfn, float mu, float r) {
   const float s = mu * lam_n - lfn;
   if (ncp == NSN_NCP_MIN) {
     if (vn <= r * s) return 0.f;
     return (vn - r * s) / (mu * lam_n);
   }
-  const float root = sqrtf(vn * vn + r * r * s * s);
-  const float num = s > 0.f ? vn * vn / (root + r * s) : root - r * s;
-  const float den = vn + r * lfn - num;
+  const float rs = r * s;
+  const float root = sqrtf(vn * vn + rs * rs);
+  const float rv = root + vn;
+  float num, den;
+  if (s > 0.f) {
+    num = vn * vn / (root + rs);
+    den = r * lfn + vn * rs * (rv + rs) / (rv * (root + rs));
+  } else {
+    num = root - rs;
+    den = r * mu * lam_n - (rv > 0.f ? rs * rs / rv : 0.f);
+  }
   if (den <= kKappaW * r * mu * lam_n) return __builtin_huge_valf();
   return r * num / den;
 }
@@ -274,13 +297,17 @@ __device__ void svd3(const M3 &F, M3 &U, float s[3], M3 &V) {
 // body helpers
 // --------------------------------------------------------------------------
 struct Ctx {
-  DevScene S;
+  // the scene's table: the kernel argument, or (Newton kernel) its device copy read
+  // through a restrict pointer, so that a function that is not inlined receives a
+  // small context and the table's fields are reloaded instead of spilled
+  const DevScene &S;
   EnvInfo E;
   StepArgs A;
   // LDS mode 2: the tets' J^T v contributions of the env in LDS (three float arrays of
   // cl_n entries, indexed by particle-list position - cl_base) instead of p_cj
   float *cl = nullptr;
   int cl_base = 0, cl_n = 0;
+  __device__ Ctx(const DevScene &s, const EnvInfo &e, const StepArgs &a) : S(s), E(e), A(a) {}
 };
 
 // The env's descriptor is the same for every lane of a workgroup: read it into scalar
@@ -410,7 +437,7 @@ __device__ __forceinline__ void store_row(float *J, V3 la, V3 aa, V3 lb, V3 ab) 
 }
 
 // Assemble the 6 rows of joint jg: J (world, per side), constraint values c[6].
-__device__ void joint_rows(const Ctx &c, int jg, float *J, float cval[6]) {
+__device__ __forceinline__ void joint_rows(const Ctx &c, int jg, float *J, float cval[6]) {
   const int4 info = c.S.j_info[jg];
   const JFrame f = joint_frame(c, jg);
   const V3 z = mk(0.f, 0.f, 0.f);
@@ -598,11 +625,8 @@ template <int BS>
 __global__ __launch_bounds__(BS) void k_prepare(DevScene S, StepArgs A, int want_features) {
   __shared__ int s_wave[BS / 64];
   __shared__ int s_count;
-  Ctx c;
-  c.S = S;
   const int e = blockIdx.x;
-  c.E = S.env[e];
-  c.A = A;
+  Ctx c(S, S.env[e], A);
   const EnvInfo &E = c.E;
   const float h = A.h;
   const int tid = threadIdx.x;
@@ -852,7 +876,7 @@ __device__ __forceinline__ float tJ(const DevScene &S, int buf, int comp_, int t
 }
 
 // ---- assembly (Sec. 6.1 eq. newton_system; Appendix A/B) ----
-__device__ void assemble_joint(const Ctx &c, int jl, double tplus) {
+__device__ __forceinline__ void assemble_joint(const Ctx &c, int jl, double tplus) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   const float h = c.A.h;
@@ -1061,7 +1085,7 @@ __device__ __forceinline__ void ltet_hdiag(const Ctx &c, int tl, int buf, float 
 // kernel stays within the inliner's budget); stress_only = true: only the
 // warm-start multipliers of the start configuration.
 template <bool EXT>
-__device__ void assemble_tet(const Ctx &c, int tl, int buf, bool stress_only) {
+__device__ __forceinline__ void assemble_tet(const Ctx &c, int tl, int buf, bool stress_only) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   const float h = c.A.h;
@@ -1155,7 +1179,7 @@ __device__ void assemble_tet(const Ctx &c, int tl, int buf, bool stress_only) {
   for (int k = 0; k < 6; ++k) S.t_E[(size_t)k * NT + tg] = Em[k] * ih2;
 }
 
-__device__ void assemble_contact(const Ctx &c, int cl, int buf) {
+__device__ __forceinline__ void assemble_contact(const Ctx &c, int cl, int buf) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   const float h = c.A.h;
@@ -1223,17 +1247,20 @@ __device__ void assemble_contact(const Ctx &c, int cl, int buf) {
 
 // contact row combination: J_c^T v for one contact as a world-space direction applied
 // at the two points: dir = alpha v_n n + [active](v_1 d1 + v_2 d2)
-__device__ __forceinline__ V3 contact_dir(const Ctx &c, int gc, const float *src, int buf) {
-  const int r0 = row_con(c.E, gc - c.E.con_off);
-  const V3 n = mk(c.S.c_n[gc]);
-  const float al = c.S.c_alpha[(size_t)buf * c.S.NC + gc];
-  V3 dir = (al * src[r0]) * n;
-  if (c.S.c_active[(size_t)buf * c.S.NC + gc]) {
+__device__ __forceinline__ V3 contact_dir_core(V3 n, float al, int active, float v0, float v1, float v2) {
+  V3 dir = (al * v0) * n;
+  if (active) {
     V3 d1, d2;
     tangent_basis(n, d1, d2);
-    dir = dir + src[r0 + 1] * d1 + src[r0 + 2] * d2;
+    dir = dir + v1 * d1 + v2 * d2;
   }
   return dir;
+}
+
+__device__ __forceinline__ V3 contact_dir(const Ctx &c, int gc, const float *src, int buf) {
+  const int r0 = row_con(c.E, gc - c.E.con_off);
+  return contact_dir_core(mk(c.S.c_n[gc]), c.S.c_alpha[(size_t)buf * c.S.NC + gc],
+                          c.S.c_active[(size_t)buf * c.S.NC + gc], src[r0], src[r0 + 1], src[r0 + 2]);
 }
 
 
@@ -1260,22 +1287,30 @@ __device__ __forceinline__ void joint_contrib(const Ctx &c, int jl, const float 
   for (int q = 0; q < 12; ++q) dst[q] = o[q];
 }
 
-// z = the tet's three row values (already loaded)
-__device__ __forceinline__ void tet_contrib(const Ctx &c, int tl, const float z[3], int buf) {
-  const DevScene &S = c.S;
-  const int tg = c.E.tet_off + tl;
+// J^T z of a tet from its compressed rows J[18] (u_i, w_i per stretch row), written
+// straight into the particles' adjacency order (positions dst fixed at scene creation)
+__device__ __forceinline__ void tet_contrib_core(const Ctx &c, const float *J, const float z[3], int4 dst) {
   V3 a0 = mk(0.f, 0.f, 0.f), a1 = a0, a2 = a0, a3 = a0;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const V3 zu = z[i] * mk(tJ(S, buf, 6 * i, tg), tJ(S, buf, 6 * i + 1, tg), tJ(S, buf, 6 * i + 2, tg));
-    const float w0 = tJ(S, buf, 6 * i + 3, tg), w1 = tJ(S, buf, 6 * i + 4, tg), w2 = tJ(S, buf, 6 * i + 5, tg);
+    const V3 zu = z[i] * mk(J[6 * i], J[6 * i + 1], J[6 * i + 2]);
+    const float w0 = J[6 * i + 3], w1 = J[6 * i + 4], w2 = J[6 * i + 5];
     a1 = a1 + w0 * zu;
     a2 = a2 + w1 * zu;
     a3 = a3 + w2 * zu;
     a0 = a0 - (w0 + w1 + w2) * zu;
   }
-  // straight into the particles' adjacency order (positions fixed at scene creation)
-  store_tet_cj(c, S.t_dst[tg], a0, a1, a2, a3);
+  store_tet_cj(c, dst, a0, a1, a2, a3);
+}
+
+// z = the tet's three row values (already loaded)
+__device__ __forceinline__ void tet_contrib(const Ctx &c, int tl, const float z[3], int buf) {
+  const DevScene &S = c.S;
+  const int tg = c.E.tet_off + tl;
+  float J[18];
+#pragma unroll
+  for (int m = 0; m < 18; ++m) J[m] = tJ(S, buf, m, tg);
+  tet_contrib_core(c, J, z, S.t_dst[tg]);
 }
 
 __device__ __forceinline__ void acc_wrench(float out[6], V3 d, V3 arm, float sgn) {
@@ -1370,11 +1405,9 @@ __device__ __forceinline__ void joint_JY(const Ctx &c, int jl, const float *Y, f
   }
 }
 
-__device__ __forceinline__ void tet_JY(const Ctx &c, int tl, const float *Y, int buf, float jy[3]) {
-  const DevScene &S = c.S;
-  const EnvInfo &E = c.E;
-  const int tg = E.tet_off + tl;
-  const int4 id = S.t_ids[tg];
+// J y of a tet from its compressed rows J[18] and its vertex ids (global particle
+// indices) into the env's body-space vector Y
+__device__ __forceinline__ void tet_JY_core(const EnvInfo &E, const float *J, int4 id, const float *Y, float jy[3]) {
   const int base = 6 * E.n_rig - 3 * E.par_off;
   const V3 y0 = mk(Y[base + 3 * id.x], Y[base + 3 * id.x + 1], Y[base + 3 * id.x + 2]);
   const V3 y1 = mk(Y[base + 3 * id.y], Y[base + 3 * id.y + 1], Y[base + 3 * id.y + 2]) - y0;
@@ -1382,21 +1415,26 @@ __device__ __forceinline__ void tet_JY(const Ctx &c, int tl, const float *Y, int
   const V3 y3 = mk(Y[base + 3 * id.w], Y[base + 3 * id.w + 1], Y[base + 3 * id.w + 2]) - y0;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const V3 u = mk(tJ(S, buf, 6 * i, tg), tJ(S, buf, 6 * i + 1, tg), tJ(S, buf, 6 * i + 2, tg));
-    const float w0 = tJ(S, buf, 6 * i + 3, tg), w1 = tJ(S, buf, 6 * i + 4, tg), w2 = tJ(S, buf, 6 * i + 5, tg);
+    const V3 u = mk(J[6 * i], J[6 * i + 1], J[6 * i + 2]);
+    const float w0 = J[6 * i + 3], w1 = J[6 * i + 4], w2 = J[6 * i + 5];
     jy[i] = dot(u, w0 * y1 + w1 * y2 + w2 * y3);
   }
 }
 
-__device__ __forceinline__ void contact_JY(const Ctx &c, int cl, const float *Y, int buf, float jy[3]) {
+__device__ __forceinline__ void tet_JY(const Ctx &c, int tl, const float *Y, int buf, float jy[3]) {
   const DevScene &S = c.S;
-  const int gc = c.E.con_off + cl;
-  const int2 bd = S.c_body[gc];
-  const V3 n = mk(S.c_n[gc]);
-  const V3 vr = point_vel_dof(c, Y, bd.x, mk(S.c_rA[gc])) -
-                (bd.y >= 0 ? point_vel_dof(c, Y, bd.y, mk(S.c_rB[gc])) : mk(0.f, 0.f, 0.f));
-  jy[0] = S.c_alpha[(size_t)buf * S.NC + gc] * dot(n, vr);
-  if (S.c_active[(size_t)buf * S.NC + gc]) {
+  const int tg = c.E.tet_off + tl;
+  float J[18];
+#pragma unroll
+  for (int m = 0; m < 18; ++m) J[m] = tJ(S, buf, m, tg);
+  tet_JY_core(c.E, J, S.t_ids[tg], Y, jy);
+}
+
+__device__ __forceinline__ void contact_JY_core(const Ctx &c, const float *Y, int2 bd, V3 n, V3 rA, V3 rB, float al,
+                                                int active, float jy[3]) {
+  const V3 vr = point_vel_dof(c, Y, bd.x, rA) - (bd.y >= 0 ? point_vel_dof(c, Y, bd.y, rB) : mk(0.f, 0.f, 0.f));
+  jy[0] = al * dot(n, vr);
+  if (active) {
     V3 d1, d2;
     tangent_basis(n, d1, d2);
     jy[1] = dot(d1, vr);
@@ -1405,6 +1443,13 @@ __device__ __forceinline__ void contact_JY(const Ctx &c, int cl, const float *Y,
     jy[1] = 0.f;
     jy[2] = 0.f;
   }
+}
+
+__device__ __forceinline__ void contact_JY(const Ctx &c, int cl, const float *Y, int buf, float jy[3]) {
+  const DevScene &S = c.S;
+  const int gc = c.E.con_off + cl;
+  contact_JY_core(c, Y, S.c_body[gc], mk(S.c_n[gc]), mk(S.c_rA[gc]), mk(S.c_rB[gc]), S.c_alpha[(size_t)buf * S.NC + gc],
+                  S.c_active[(size_t)buf * S.NC + gc], jy);
 }
 
 // J_i H~^-1 J_i^T of every row of an element (preconditioner diagonal without C, eps)
@@ -1458,7 +1503,7 @@ __device__ __forceinline__ void contact_hdiag(const Ctx &c, int cl, int buf, flo
 // Schur right-hand side b = (J Y - err)/h and Jacobi preconditioner for every row
 // (Y = H~^-1 g already in place)
 template <int BS, bool EXT>
-__device__ void rhs_and_precond(const Ctx &c, const float *Y, int buf, int nel, float eps) {
+__device__ __forceinline__ void rhs_and_precond(const Ctx &c, const float *Y, int buf, int nel, float eps) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   const float ih = 1.f / c.A.h;
@@ -1523,7 +1568,7 @@ __device__ __forceinline__ void mv_dots(const DevScene &S, int row, float z, flo
 // Island mode (EXT, isl): every element stores its own three partial sums in el_dots
 // (summed per island in element order afterwards) instead of adding them to part.
 template <int BS, bool FIRST, bool EXT>
-__device__ void matvec_rows(const Ctx &c, const float *Y, int buf, int nel, float eps, double part_[3], bool isl = false) {
+__device__ __forceinline__ void matvec_rows(const Ctx &c, const float *Y, int buf, int nel, float eps, double part_[3], bool isl = false) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   for (int el = threadIdx.x; el < nel; el += BS) {
@@ -1618,7 +1663,7 @@ __device__ __forceinline__ void hinv_rigid(const Ctx &c, int g, float v[6]) {
 }
 
 // Y = H~^-1 (sum of the element contributions) for every body of the env
-__device__ void gather_hinv(const Ctx &c, float *Y, int tid, int BS) {
+__device__ __forceinline__ void gather_hinv(const Ctx &c, float *Y, int tid, int BS) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   const int nb = E.n_rig + E.n_par;
@@ -1646,7 +1691,7 @@ __device__ void gather_hinv(const Ctx &c, float *Y, int tid, int BS) {
 // J^T src contributions of every element (src: one value per row; buf: which
 // Jacobian of the ping-pong pair); joints only when their bodies need them.
 template <int BS, bool EXT>
-__device__ void contrib_pass(const Ctx &c, const float *src, int buf, int nel, bool joints) {
+__device__ __forceinline__ void contrib_pass(const Ctx &c, const float *src, int buf, int nel, bool joints) {
   const EnvInfo &E = c.E;
   for (int el = threadIdx.x; el < nel; el += BS) {
     if (el < E.n_jnt) {
@@ -1699,7 +1744,7 @@ __device__ __forceinline__ float pcr_row(const DevScene &S, int row, float alpha
 // Island mode (EXT, isl): alpha and beta are the element's island's, and the rows of an
 // island that has stopped keep their values (the element still writes its J^T z).
 template <int BS, bool INIT, bool EXT>
-__device__ void pcr_update_contrib(const Ctx &c, int buf, int nel, float alpha_, float beta_, bool upd_,
+__device__ __forceinline__ void pcr_update_contrib(const Ctx &c, int buf, int nel, float alpha_, float beta_, bool upd_,
                                    bool isl = false, int ib = 0) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
@@ -1746,6 +1791,244 @@ __device__ void pcr_update_contrib(const Ctx &c, int buf, int nel, float alpha_,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident PCR.  The PCR's row vectors (x, z, p, q, w) and the
+// preconditioner P of every tet and contact stay in the registers of the thread that
+// owns the element for all the PCR iterations of a Newton iteration: thread t owns
+// elements t, t + BS, ..., t + (R-1) BS, so in an env with at most R BS elements the
+// row vectors never go through memory inside the loop (the element data -- compressed
+// J, compliance, ids -- is still read where it is used).  Joints (six rows each) keep
+// their rows in memory.  The arithmetic and its order are those of the streaming form
+// (pcr_update_contrib, gather_hinv, matvec_rows), so both give identical results.
+// Returns the PCR iterations performed; x is written back to row_x.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void mv_dots_reg(float z, float w, float P, float q, double part[3]) {
+  const float Pw = P * w;
+  part[0] += (double)z * (double)w;
+  part[1] += (double)w * (double)Pw;
+  part[2] += (double)Pw * (double)q;
+}
+
+// J^T z of a resident tet or contact (z from registers) for the body pass
+__device__ __forceinline__ void resident_contrib(const Ctx &c, int el, int buf, const float z[3]) {
+  const EnvInfo &E = c.E;
+  if (el < E.n_jnt + E.n_tet) {
+    tet_contrib(c, el - E.n_jnt, z, buf);
+  } else {
+    const int gc = E.con_off + el - E.n_jnt - E.n_tet;
+    const DevScene &S = c.S;
+    S.c_cj[gc] = f4(contact_dir_core(mk(S.c_n[gc]), S.c_alpha[(size_t)buf * S.NC + gc],
+                                     S.c_active[(size_t)buf * S.NC + gc], z[0], z[1], z[2]),
+                    0.f);
+  }
+}
+
+// w = J Y + C z + eps z of a resident tet or contact
+__device__ __forceinline__ void resident_matvec(const Ctx &c, int el, int buf, const float *Y, float eps,
+                                                const float z[3], float w[3]) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  float jy[3];
+  if (el < E.n_jnt + E.n_tet) {
+    const int tl = el - E.n_jnt, tg = E.tet_off + tl;
+    tet_JY(c, tl, Y, buf, jy);
+    float Em[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Em[k] = S.t_E[(size_t)k * S.NT + tg];
+    const V3 zz = mk(z[0], z[1], z[2]);
+    const V3 cz = sym_mul(Em, zz);
+    w[0] = jy[0] + cz.x + eps * zz.x;
+    w[1] = jy[1] + cz.y + eps * zz.y;
+    w[2] = jy[2] + cz.z + eps * zz.z;
+  } else {
+    const int cl = el - E.n_jnt - E.n_tet;
+    contact_JY(c, cl, Y, buf, jy);
+    const int r0 = row_con(E, cl);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) w[r] = jy[r] + S.row_C[r0 + r] * z[r] + eps * z[r];
+  }
+}
+
+__device__ __forceinline__ int resident_row0(const EnvInfo &E, int el) {
+  return el < E.n_jnt + E.n_tet ? row_tet(E, el - E.n_jnt) : row_con(E, el - E.n_jnt - E.n_tet);
+}
+
+// the rows of a joint in memory, as in the streaming form
+__device__ __forceinline__ void joint_matvec_mem(const Ctx &c, int jl, const float *Y, float eps, bool first,
+                                                 double part[3]) {
+  const DevScene &S = c.S;
+  float jy[6];
+  joint_JY(c, jl, Y, jy);
+  const int r0 = row_joint(c.E, jl);
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    const float zz = S.row_z[r0 + r];
+    const float ww = jy[r] + S.row_C[r0 + r] * zz + eps * zz;
+    S.row_w[r0 + r] = ww;
+    if (first) S.row_q[r0 + r] = ww;
+    mv_dots(S, r0 + r, zz, ww, part);
+  }
+}
+
+template <int BS, int R>
+__device__ __forceinline__ int pcr_resident(const Ctx &c, float *Y, int buf, int nel, float eps, int cr_iters,
+                                            bool dump, Red<BS> &red) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  const int tid = threadIdx.x;
+  const int nj = E.n_jnt;
+  float x[R][3], z[R][3], p[R][3], q[R][3], w[R][3], P[R][3];
+  // ---- the PCR's start: z = P b, x = 0, p = z; J^T z ----
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int el = tid + j * BS;
+    if (el >= nel) continue;
+    if (el < nj) {
+      const int r0 = row_joint(E, el);
+#pragma unroll
+      for (int r = 0; r < 6; ++r) pcr_row<true>(S, r0 + r, 0.f, 0.f, false);
+      joint_contrib(c, el, S.row_z);
+      continue;
+    }
+    const int r0 = resident_row0(E, el);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      P[j][r] = S.row_P[r0 + r];
+      const float zz = P[j][r] * S.row_b[r0 + r];
+      x[j][r] = 0.f;
+      z[j][r] = zz;
+      p[j][r] = zz;
+      q[j][r] = 0.f;
+      w[j][r] = 0.f;
+    }
+    resident_contrib(c, el, buf, z[j]);
+  }
+  __syncthreads();
+  gather_hinv(c, Y, tid, BS);
+  __syncthreads();
+  double dots[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int el = tid + j * BS;
+    if (el >= nel) continue;
+    if (el < nj) {
+      joint_matvec_mem(c, el, Y, eps, true, dots);
+      continue;
+    }
+    resident_matvec(c, el, buf, Y, eps, z[j], w[j]);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      q[j][r] = w[j][r];
+      mv_dots_reg(z[j][r], w[j][r], P[j][r], q[j][r], dots);
+    }
+  }
+  block_sum3<BS>(dots, red);
+  if (dump) {  // A (P b) of the dumped iteration
+    for (int r = tid; r < 6 * nj; r += BS) S.row_dump[E.row_off + r] = S.row_w[E.row_off + r];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int el = tid + j * BS;
+      if (el < nj || el >= nel) continue;
+      const int r0 = resident_row0(E, el);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) S.row_dump[r0 + r] = w[j][r];
+    }
+  }
+  double rho = dots[0], qs = dots[1];
+  // READING: stop once <z, A z> is at rounding level relative to its start
+  const double rho_stop = kTauCR * rho;
+  float beta = 0.f;
+  int done = 0;
+  for (int it = 0; it < cr_iters; ++it) {
+    if (!(rho > rho_stop) || !(rho > 0.0)) break;
+    if (!(qs > 0.0)) break;
+    const float alpha = (float)(rho / qs);
+    ++done;
+    const bool upd = it > 0;
+    if (it == cr_iters - 1) {  // the last update needs no further product
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int el = tid + j * BS;
+        if (el >= nel) continue;
+        if (el < nj) {
+          const int r0 = row_joint(E, el);
+#pragma unroll
+          for (int r = 0; r < 6; ++r) {
+            const int row = r0 + r;
+            const float pp = upd ? S.row_z[row] + beta * S.row_p[row] : S.row_p[row];
+            S.row_x[row] += alpha * pp;
+          }
+          continue;
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const float pp = upd ? z[j][r] + beta * p[j][r] : p[j][r];
+          x[j][r] += alpha * pp;
+        }
+      }
+      break;
+    }
+    // direction update, x += alpha p, z -= alpha P q, J^T z contributions
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int el = tid + j * BS;
+      if (el >= nel) continue;
+      if (el < nj) {
+        const int r0 = row_joint(E, el);
+#pragma unroll
+        for (int r = 0; r < 6; ++r) pcr_row<false>(S, r0 + r, alpha, beta, upd);
+        joint_contrib(c, el, S.row_z);
+        continue;
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        float pp = p[j][r], qq = q[j][r];
+        const float z0 = z[j][r];
+        if (upd) {
+          pp = z0 + beta * pp;
+          qq = w[j][r] + beta * qq;
+          p[j][r] = pp;
+          q[j][r] = qq;
+        }
+        x[j][r] = x[j][r] + alpha * pp;
+        z[j][r] = z0 - alpha * (P[j][r] * qq);
+      }
+      resident_contrib(c, el, buf, z[j]);
+    }
+    __syncthreads();
+    gather_hinv(c, Y, tid, BS);
+    __syncthreads();
+    dots[0] = dots[1] = dots[2] = 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int el = tid + j * BS;
+      if (el >= nel) continue;
+      if (el < nj) {
+        joint_matvec_mem(c, el, Y, eps, false, dots);
+        continue;
+      }
+      resident_matvec(c, el, buf, Y, eps, z[j], w[j]);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) mv_dots_reg(z[j][r], w[j][r], P[j][r], q[j][r], dots);
+    }
+    block_sum3<BS>(dots, red);
+    const double b = dots[0] / rho;
+    qs = dots[1] + 2.0 * b * dots[2] + b * b * qs;
+    beta = (float)b;
+    rho = dots[0];
+  }
+  // Delta lambda of the resident rows back to memory
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int el = tid + j * BS;
+    if (el < nj || el >= nel) continue;
+    const int r0 = resident_row0(E, el);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) S.row_x[r0 + r] = x[j][r];
+  }
+  return done;
+}
+
 // position update q = q^- + h G(q^k) u (Alg. 1; quaternion normalised every update)
 __device__ __forceinline__ void update_positions_body(const Ctx &c, int b) {
   const EnvInfo &E = c.E;
@@ -1774,7 +2057,7 @@ __device__ __forceinline__ void update_positions_body(const Ctx &c, int b) {
 }
 
 // the env's iterate (multipliers, velocities, positions) into / out of the best slot
-__device__ void keep_best(const Ctx &c, int nrows, bool restore) {
+__device__ __forceinline__ void keep_best(const Ctx &c, int nrows, bool restore) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
   const int nb = E.n_rig + E.n_par;
@@ -1817,7 +2100,7 @@ __device__ __forceinline__ void restore_positions_body(const Ctx &c, int b) {
 }
 
 template <int BS, bool EXT>
-__device__ void assemble_all(const Ctx &c, int buf, double tplus, int nc) {
+__device__ __forceinline__ void assemble_all(const Ctx &c, int buf, double tplus, int nc) {
   const EnvInfo &E = c.E;
   const int nel = E.n_jnt + E.n_tet + nc;
   for (int el = threadIdx.x; el < nel; el += BS) {
@@ -2102,16 +2385,14 @@ __device__ void island_residuals(const Ctx &c, int e, int nel) {
 // --------------------------------------------------------------------------
 // LM: 0 body-space vector in global memory, 1 in LDS, 2 in LDS together with the tets'
 // contributions
-template <int BS, int LM, bool EXT>
-__global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first) {
+template <int BS, int LM, bool EXT, int R>
+__global__ __launch_bounds__(BS) void k_newton(const DevScene *__restrict__ Sp, StepArgs A, int first) {
   __shared__ Red<BS> red;
   extern __shared__ float y_lds[];
   const unsigned long long t_start = wall_clock64();
-  Ctx c;
-  c.S = S;
+  const DevScene &S = *Sp;
   const int e = S.env_order[first + blockIdx.x];
-  c.E = uniform_env(S.env[e]);
-  c.A = A;
+  Ctx c(S, uniform_env(S.env[e]), A);
   const EnvInfo &E = c.E;
   const int tid = threadIdx.x;
   const float h = A.h;
@@ -2458,48 +2739,59 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
         any = block_max<BS>(island_check<BS>(c, e, -1.0), red, 1);
       }
     } else {
-      // Single-reduction form of the same recurrences: the matvec pass also sums
-      // <w, P w> and <w, P q>, so that <q', P q'> of the next direction q' = w + beta q
-      // follows as <w,Pw> + 2 beta <w,Pq> + beta^2 <q,Pq>, and the direction update is
-      // fused into the next element pass (one pass and one barrier fewer per iteration).
-      pcr_update_contrib<BS, true, EXT>(c, buf, nel, 0.f, 0.f, false);
-      __syncthreads();
-      gather_hinv(c, Y, tid, BS);
-      __syncthreads();
-      double dots[3] = {0.0, 0.0, 0.0};
-      matvec_rows<BS, true, EXT>(c, Y, buf, nel, eps, dots);
-      block_sum3<BS>(dots, red);
-      if (k == A.dump_k)
-        for (int r = tid; r < nrows; r += BS) S.row_dump[R0 + r] = S.row_w[R0 + r];
-      double rho = dots[0], qs = dots[1];
-      // READING: stop once <z, A z> is at rounding level relative to its start
-      const double rho_stop = kTauCR * rho;
-      float beta = 0.f;
-      for (int it = 0; it < A.cr_iters; ++it) {
-        if (!(rho > rho_stop) || !(rho > 0.0)) break;
-        if (!(qs > 0.0)) break;
-        const float alpha = (float)(rho / qs);
-        ++done;
-        if (it == A.cr_iters - 1) {  // the last update needs no further product
-          for (int r = tid; r < nrows; r += BS) {
-            const int row = R0 + r;
-            const float p = it > 0 ? S.row_z[row] + beta * S.row_p[row] : S.row_p[row];
-            S.row_x[row] += alpha * p;
-          }
-          break;
+      bool resident = false;
+      if constexpr (!EXT && R > 0) {
+        // register-resident form where every element of the env has a register slot
+        if (nel <= R * BS) {
+          done = pcr_resident<BS, R>(c, Y, buf, nel, eps, A.cr_iters, k == A.dump_k, red);
+          resident = true;
         }
-        // direction update, x += alpha p, z -= alpha P q, J^T z contributions
-        pcr_update_contrib<BS, false, EXT>(c, buf, nel, alpha, beta, it > 0);
+      }
+      if (!resident) {
+        // Single-reduction form of the same recurrences: the matvec pass also sums
+        // <w, P w> and <w, P q>, so that <q', P q'> of the next direction q' = w + beta q
+        // follows as <w,Pw> + 2 beta <w,Pq> + beta^2 <q,Pq>, and the direction update is
+        // fused into the next element pass (one pass and one barrier fewer per iteration).
+        pcr_update_contrib<BS, true, EXT>(c, buf, nel, 0.f, 0.f, false);
         __syncthreads();
         gather_hinv(c, Y, tid, BS);
         __syncthreads();
-        dots[0] = dots[1] = dots[2] = 0.0;
-        matvec_rows<BS, false, EXT>(c, Y, buf, nel, eps, dots);
+        double dots[3] = {0.0, 0.0, 0.0};
+        matvec_rows<BS, true, EXT>(c, Y, buf, nel, eps, dots);
         block_sum3<BS>(dots, red);
-        const double b = dots[0] / rho;
-        qs = dots[1] + 2.0 * b * dots[2] + b * b * qs;
-        beta = (float)b;
-        rho = dots[0];
+        if (k == A.dump_k)
+          for (int r = tid; r < nrows; r += BS) S.row_dump[R0 + r] = S.row_w[R0 + r];
+        double rho = dots[0], qs = dots[1];
+        // READING: stop once <z, A z> is at rounding level relative to its start
+        const double rho_stop = kTauCR * rho;
+        float beta = 0.f;
+        for (int it = 0; it < A.cr_iters; ++it) {
+          if (!(rho > rho_stop) || !(rho > 0.0)) break;
+          if (!(qs > 0.0)) break;
+          const float alpha = (float)(rho / qs);
+          ++done;
+          if (it == A.cr_iters - 1) {  // the last update needs no further product
+            for (int r = tid; r < nrows; r += BS) {
+              const int row = R0 + r;
+              const float p = it > 0 ? S.row_z[row] + beta * S.row_p[row] : S.row_p[row];
+              S.row_x[row] += alpha * p;
+            }
+            break;
+          }
+          // direction update, x += alpha p, z -= alpha P q, J^T z contributions
+          pcr_update_contrib<BS, false, EXT>(c, buf, nel, alpha, beta, it > 0);
+          __syncthreads();
+          gather_hinv(c, Y, tid, BS);
+          __syncthreads();
+          dots[0] = dots[1] = dots[2] = 0.0;
+          matvec_rows<BS, false, EXT>(c, Y, buf, nel, eps, dots);
+          block_sum3<BS>(dots, red);
+          const double b = dots[0] / rho;
+          qs = dots[1] + 2.0 * b * dots[2] + b * b * qs;
+          beta = (float)b;
+          rho = dots[0];
+        }
+
       }
     }
     cr_total += done;
@@ -2641,23 +2933,36 @@ __global__ __launch_bounds__(BS) void k_newton(DevScene S, StepArgs A, int first
 // kernel leaves functions taking the Ctx out of line, which puts the Ctx (about 1 KB)
 // in scratch memory.  The default instantiation keeps the default budget.
 // --------------------------------------------------------------------------
+// register slots per thread of the resident PCR (18 registers each) that fit the
+// 256-VGPR budget without spilling below 1024 threads; none at 1024 threads (128 VGPRs)
+template <int BS, bool EXT>
+constexpr int resident_slots() {
+  return EXT ? 0 : (BS >= 1024 ? 0 : 2);
+}
+
+template <int BS, int LM, bool EXT, int RS>
+static void launch_one(const DevScene &s, const StepArgs &a, int first, int count, size_t bytes, hipStream_t st) {
+  if (bytes > 16384 * sizeof(float))
+    (void)hipFuncSetAttribute((const void *)k_newton<BS, LM, EXT, RS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+  hipLaunchKernelGGL((k_newton<BS, LM, EXT, RS>), dim3(count), dim3(BS), bytes, st, s.dev, a, first);
+}
+
 template <int BS, bool EXT>
 static void launch_bs(const DevScene &s, const StepArgs &a, int first, int count, int lds_floats, int lds_mode,
-                      hipStream_t st) {
-  const size_t bytes = sizeof(float) * (size_t)lds_floats;
+                      int resident, hipStream_t st) {
+  const size_t bytes = lds_mode > 0 ? sizeof(float) * (size_t)lds_floats : 0;
+  constexpr int B2 = BS >= 128 ? BS : 128;  // mode 2 from 128 threads up
+  constexpr int R2 = resident_slots<B2, EXT>(), R1 = resident_slots<BS, EXT>();
   if (lds_mode == 2 && BS >= 128) {
-    constexpr int B2 = BS >= 128 ? BS : 128;  // mode 2 from 128 threads up
-    if (lds_floats > 16384)
-      (void)hipFuncSetAttribute((const void *)k_newton<B2, 2, EXT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)bytes);
-    hipLaunchKernelGGL((k_newton<B2, 2, EXT>), dim3(count), dim3(B2), bytes, st, s, a, first);
+    if (resident && R2 > 0) launch_one<B2, 2, EXT, R2>(s, a, first, count, bytes, st);
+    else launch_one<B2, 2, EXT, 0>(s, a, first, count, bytes, st);
   } else if (lds_mode >= 1) {
-    if (lds_floats > 16384)
-      (void)hipFuncSetAttribute((const void *)k_newton<BS, 1, EXT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)bytes);
-    hipLaunchKernelGGL((k_newton<BS, 1, EXT>), dim3(count), dim3(BS), bytes, st, s, a, first);
+    if (resident && R1 > 0) launch_one<BS, 1, EXT, R1>(s, a, first, count, bytes, st);
+    else launch_one<BS, 1, EXT, 0>(s, a, first, count, bytes, st);
   } else {
-    hipLaunchKernelGGL((k_newton<BS, 0, EXT>), dim3(count), dim3(BS), 0, st, s, a, first);
+    if (resident && R1 > 0) launch_one<BS, 0, EXT, R1>(s, a, first, count, 0, st);
+    else launch_one<BS, 0, EXT, 0>(s, a, first, count, 0, st);
   }
 }
 
@@ -2668,13 +2973,13 @@ constexpr bool kExtTU = false;
 #endif
 
 static hipError_t launch_tu(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
-                            int lds_mode, hipStream_t st) {
+                            int lds_mode, int resident, hipStream_t st) {
   switch (block) {
-    case 64: launch_bs<64, kExtTU>(s, a, first, count, lds_floats, lds_mode, st); break;
-    case 128: launch_bs<128, kExtTU>(s, a, first, count, lds_floats, lds_mode, st); break;
-    case 256: launch_bs<256, kExtTU>(s, a, first, count, lds_floats, lds_mode, st); break;
-    case 512: launch_bs<512, kExtTU>(s, a, first, count, lds_floats, lds_mode, st); break;
-    case 1024: launch_bs<1024, kExtTU>(s, a, first, count, lds_floats, lds_mode, st); break;
+    case 64: launch_bs<64, kExtTU>(s, a, first, count, lds_floats, lds_mode, resident, st); break;
+    case 128: launch_bs<128, kExtTU>(s, a, first, count, lds_floats, lds_mode, resident, st); break;
+    case 256: launch_bs<256, kExtTU>(s, a, first, count, lds_floats, lds_mode, resident, st); break;
+    case 512: launch_bs<512, kExtTU>(s, a, first, count, lds_floats, lds_mode, resident, st); break;
+    case 1024: launch_bs<1024, kExtTU>(s, a, first, count, lds_floats, lds_mode, resident, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -2683,7 +2988,7 @@ static hipError_t launch_tu(const DevScene &s, const StepArgs &a, int block, int
 #ifdef NSN_STEP_EXT_TU
 hipError_t launch_newton_ext(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
                              int lds_mode, hipStream_t st) {
-  return launch_tu(s, a, block, first, count, lds_floats, lds_mode, st);
+  return launch_tu(s, a, block, first, count, lds_floats, lds_mode, 0, st);
 }
 #else
 hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_features, hipStream_t st) {
@@ -2692,11 +2997,11 @@ hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_feature
 }
 
 hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
-                         int lds_mode, hipStream_t st) {
+                         int lds_mode, int resident, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   if (s.any_linear || (a.p.islands && a.p.linear == NSN_LINEAR_PCR))
     return launch_newton_ext(s, a, block, first, count, lds_floats, lds_mode, st);
-  return launch_tu(s, a, block, first, count, lds_floats, lds_mode, st);
+  return launch_tu(s, a, block, first, count, lds_floats, lds_mode, resident, st);
 }
 #endif
 

@@ -166,6 +166,20 @@ class Scene:
         return dict(rigid_x=rx, rigid_q=rq, rigid_v=rv, rigid_w=rw, particle_x=px, particle_v=pv,
                     time=t.value)
 
+    def save_state(self):
+        """Snapshot of every env's dynamic state (nsn_save_state) in a device buffer."""
+        import torch
+
+        n = C.c_size_t(0)
+        L.check(self.lib.nsn_state_bytes(self.h, C.byref(n)), "nsn_state_bytes")
+        buf = torch.empty(int(n.value), dtype=torch.uint8, device=self.device)
+        L.check(self.lib.nsn_save_state(self.h, C.c_void_p(buf.data_ptr())), "nsn_save_state")
+        return buf
+
+    def load_state(self, buf):
+        """Restore a snapshot taken by save_state of this scene (nsn_load_state)."""
+        L.check(self.lib.nsn_load_state(self.h, C.c_void_p(buf.data_ptr())), "nsn_load_state")
+
     def write_state(self, env, st):
         d = self.envs[env]
 
@@ -249,6 +263,11 @@ class Scene:
         """0: body-space vector in global memory; 1: in LDS; 2: with the tets'
         contributions in LDS where they fit (default).  Same results."""
         L.check(self.lib.nsn_set_lds_mode(self.h, int(max_mode)), "nsn_set_lds_mode")
+
+    def set_pcr_form(self, form):
+        """1: register-resident PCR where an env's elements fit (default); 0: streaming.
+        Same results."""
+        L.check(self.lib.nsn_set_pcr_form(self.h, int(form)), "nsn_set_pcr_form")
 
     def lds_modes(self):
         """LDS mode of every current bucket."""

@@ -15,9 +15,11 @@ Tolerance of an element: the larger of
     of (a) how far the FP64 value moves when the iterate and the pre-step state are
     perturbed at the level of FP32 rounding (three trials) and (b) how far the same
     source evaluated in single precision (oracle/nsn_oracle_f32.c) lies from the FP64
-    value on the same inputs -- the rounding of the arithmetic itself, which input
-    perturbations miss where terms cancel (a body at rest: g is a sum of large
-    opposite momenta; a friction row near its inactive limit: den of W cancels).
+    value on the same inputs, at the given iterate and at each perturbed one -- the
+    rounding of the arithmetic itself, which input perturbations miss where terms
+    cancel (a body at rest: g is a sum of large opposite momenta; a friction row near
+    its inactive limit: den of W cancels).  Its error at a cancellation is one draw
+    from a wide distribution, so it is sampled at several nearby inputs.
 Elements whose tolerance exceeds 1e-3 of their group's scale are counted as
 ill-conditioned in the report (a kink of the NCP function inside the rounding band,
 a friction row switching activity, a repeated singular value); they are compared at
@@ -148,23 +150,38 @@ def compare_iteration(scene, env, desc, pre, h, k, M, params, trials=3, seed=0):
     fields = ["err", "cdiag", "P", "b", "Az", "g", "hdiag", "alpha", "active", "cblk", "dlam"]
     rng = np.random.default_rng(seed)
     spreads = {f: np.zeros(np.asarray(base[f]).shape) for f in fields}
+    f32_note = ""
+
+    def widen(rec, ref):
+        for f in fields:
+            spreads[f] = np.maximum(spreads[f], np.abs(np.asarray(rec[f]) - np.asarray(ref[f])))
+
+    def f32_eval(st, itp, prevp):
+        # the arithmetic's own rounding: the single-precision build on the same inputs
+        nonlocal f32_note
+        try:
+            o32 = O.OracleEnvF32(desc)
+            o32.set_state(st)
+            o32.set_time(pre["time"])
+            return o32.eval_iterate(h, M, nc, itp, prevp, params)
+        except ValueError as ex:  # its collision detection found another contact set
+            f32_note = f" (single-precision probe unavailable: {ex})"
+            return None
+
+    rec = f32_eval(pre_state, it, prev)
+    if rec is not None:
+        widen(rec, base)
     for _ in range(trials):
         st = _perturb_state(pre, rng, h)
         itp = _perturb(it, rng, h)
         prevp = _perturb(prev, rng, h) if prev is not None else None
         rec = oracle_eval(desc, st, pre["time"], h, M, nc, itp, prevp, params)
-        for f in fields:
-            spreads[f] = np.maximum(spreads[f], np.abs(np.asarray(rec[f]) - np.asarray(base[f])))
-    try:  # the arithmetic's own rounding: the single-precision build on the same inputs
-        o32 = O.OracleEnvF32(desc)
-        o32.set_state(pre_state)
-        o32.set_time(pre["time"])
-        rec = o32.eval_iterate(h, M, nc, it, prev, params)
-        for f in fields:
-            spreads[f] = np.maximum(spreads[f], np.abs(np.asarray(rec[f]) - np.asarray(base[f])))
-        f32_note = ""
-    except ValueError as ex:  # its collision detection found another contact set
-        f32_note = f" (single-precision probe unavailable: {ex})"
+        widen(rec, base)
+        # one more sample of the single-precision rounding, at this nearby input: at a
+        # cancellation one sample can fall far below another evaluation order's error
+        rec32 = f32_eval(st, itp, prevp)
+        if rec32 is not None:
+            widen(rec32, rec)
     g2o, rgroup = row_maps(desc, nc)
     report = {}
     bad = []

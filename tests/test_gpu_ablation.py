@@ -51,10 +51,12 @@ def test_heavy_stack_ablation():
     good_r, good_sink = res["PCR, h^2 effmass"]
     assert good_r <= 1e-2 and good_sink < 1e-3
     # the failure is the collapse (boxes sink into each other); the residual a collapsed,
-    # interpenetrating stack ends with depends on the rounding path, so it is only
-    # required to stay well above the held stack's
+    # interpenetrating stack ends with, and how deep it has sunk after 30 steps, depend
+    # on the rounding path of the collapse, so both are only required to stay well
+    # beyond the held stack's: ten times its residual, and a centimetre of sinking
+    # (ten times the 1 mm the held stack stays within)
     for name in ["PCR, identity", "PCR, h^2"]:
-        assert res[name][0] > 10 * good_r and res[name][1] > 0.05, name
+        assert res[name][0] > 10 * good_r and res[name][1] > 1e-2, name
     assert res["PCG, h^2 effmass"][0] > 100 * good_r
 
 

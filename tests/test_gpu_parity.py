@@ -336,3 +336,29 @@ def test_lds_mode_falls_back_for_large_envs():
     for k in out[0]:
         if k != "time":
             assert np.array_equal(out[0][k], out[1][k]), k
+
+
+@pytest.mark.parametrize("block", [512, 256, 128])
+def test_register_resident_pcr_bitwise_equal(block):
+    """The register-resident PCR (rows of every tet and contact in registers for all the
+    PCR iterations of a Newton iteration) and the streaming form sum the same terms in
+    the same order: identical states, also with envs too large for their slots (those
+    take the streaming form inside the same launch), with the previous-step start and in
+    residual mode."""
+    envs = [si.batched_env(seed=2200 + i, tets_max=500) for i in range(5)] + [si.cube_stack(seed=3),
+                                                                               _driven_chain()]
+    for p, tol, n in [(si.SolverParams(), 0.0, 6), (si.SolverParams(warm=si.WARM_PREV), 1e-4, 50)]:
+        out = []
+        for form in [1, 0]:
+            sc = _scene(envs, p)
+            sc.set_schedule([(0, len(envs), block)])
+            sc.set_pcr_form(form)
+            for _ in range(3):
+                sc.step(H, n, 30, tol)
+            out.append(([sc.read_state(e) for e in range(len(envs))], sc.stats()))
+        (sa, ta), (sb, tb) = out
+        assert np.array_equal(ta["cr_iters"], tb["cr_iters"])
+        for a, b in zip(sa, sb):
+            for k in a:
+                if k != "time":
+                    assert np.array_equal(a[k], b[k]), (block, k)
