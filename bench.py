@@ -7,15 +7,22 @@ per-env Newton kernel (one launch per step, replayed from a hipGraph), h = 1/60 
 residual mode: every env stops when r_ncp <= 1e-4 or after 50 Newton iterations of 40
 PCR iterations.  Inputs are seeded and synthetic and already resident in HBM.
 
-Prints ONE JSON line.  `value` is env-steps/s of the headline arm (the faster of the
-two learned warm starts when the trained model is available: "learned" takes the
-network's multipliers for every contact, "hybrid" keeps the previous step's for
-contacts that persist and takes the network's for new ones; else the stronger plain
-start); every arm is reported under "arms".  `roofline` covers the dominant kernel (the Newton kernel):
-algorithmic bytes of its PCR loop per launch divided by its launch duration, the
-latter read from the GPU wall clock inside the kernel for every timed step.
-`cpu_baseline` times the FP64 oracle on a bounded sample of the same envs on the
-host cores.
+Before the timed steps the autotuner picks the launch schedule by env-steps/s,
+replaying the same steps from one state snapshot per candidate (--no-tune keeps the
+library's default); every arm then runs under that schedule.
+
+Prints ONE JSON line.  `value` is env-steps/s of the headline arm: of the two learned
+warm starts ("learned" takes the network's multipliers for every contact, "hybrid"
+keeps the previous step's for contacts that persist and takes the network's for new
+ones), the one with more env-steps/s reaching the residual, when the trained model is
+available; else the stronger plain start.  Each arm reports its env-steps/s, the
+env-steps/s that reached the residual, and the distribution of the last step's exit
+residuals; `learned_vs_plain` compares the headline arm with each plain arm.
+`roofline` covers the dominant kernel (the Newton kernel): algorithmic bytes of its
+PCR loop per launch divided by its launch duration, the latter read from the GPU wall
+clock inside the kernel for every timed step, with a plain device copy's bandwidth
+beside it.  `cpu_baseline` times the FP64 oracle in the headline arm and step window
+on a bounded sample of the same envs on the host cores.
 """
 import argparse
 import json
@@ -35,7 +42,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_arm(envs, arm, args, model_blob=None):
+def run_arm(envs, arm, args, model_blob=None, schedule=None):
+    """One arm: warm-up steps, then (first arm only, schedule None and tuning on) the
+    autotuner from the post-warm-up state, then the timed steps from that same state.
+    Returns (results, schedule used, tuner report or None)."""
     import numpy as np
     import torch
 
@@ -44,21 +54,26 @@ def run_arm(envs, arm, args, model_blob=None):
 
     warm = {"zero": si.WARM_ZERO, "prev": si.WARM_PREV, "learned": si.WARM_LEARNED,
             "hybrid": si.WARM_HYBRID}[arm]
-    p = si.SolverParams(warm=si.WARM_ZERO, islands=int(args.islands))
+    p = si.SolverParams(warm=si.WARM_ZERO, islands=int(args.islands), watchdog=int(args.watchdog))
     sc = Scene(envs, p)
     if model_blob is not None:
         sc.set_warm_start_model(model_blob)
-    if args.schedule:
-        from paper_1907_04587_amd.autotune import autotune
-        sched = autotune(sc, H, args.newton, args.cr, args.tol, log=log)
-        log(f"[{arm}] schedule {sched}")
+    if schedule is not None:
+        sc.set_schedule(schedule)
     p.warm = warm
     sc.set_params(p)
+    sc.set_pcr_form(args.pcr_form)
     for i in range(args.warmup):
         sc.step(H, args.newton, args.cr, args.tol)
         if i == 0 or (i + 1) % 10 == 0:
             sc.synchronize()
             log(f"[{arm}] warmup {i + 1}/{args.warmup}")
+    report = None
+    if schedule is None and not args.no_tune:
+        from paper_1907_04587_amd.autotune import autotune
+        schedule, report = autotune(sc, H, args.newton, args.cr, args.tol, steps=args.tune_steps, log=log)
+        log(f"[{arm}] tuned schedule {schedule}")
+    schedule = [tuple(b) for b in sc.schedule()]
     sc.reset_accumulators()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -71,12 +86,15 @@ def run_arm(envs, arm, args, model_blob=None):
     wall = t1 - t0
     acc = sc.accumulators()
     kt = sc.kernel_times_ms(cap=args.steps)
+    st = sc.stats()  # the last timed step's per-env exit record
     n = len(envs)
     steps_total = int(acc["steps"].sum())
+    conv_total = int(acc["converged"].sum())
     res = {
         "env_steps_per_s": steps_total / wall,
+        "converged_env_steps_per_s": conv_total / wall,
         "ms_per_step": 1e3 * wall / args.steps,
-        "converged_frac": float(acc["converged"].sum()) / max(steps_total, 1),
+        "converged_frac": conv_total / max(steps_total, 1),
         "mean_newton_iters": float(acc["newton_iters"].sum()) / max(steps_total, 1),
         "mean_cr_iters": float(acc["cr_iters"].sum()) / max(steps_total, 1),
         "env_cr_iters_per_s": float(acc["cr_iters"].sum()) / wall,
@@ -87,14 +105,48 @@ def run_arm(envs, arm, args, model_blob=None):
     }
     if res["newton_kernel_ms"]:
         res["achieved_gbs"] = res["cr_bytes_per_launch"] / (res["newton_kernel_ms"] * 1e-3) / 1e9
+    res["residual_last_step"] = residual_distribution(envs, st, args.tol)
     del sc
     torch.cuda.empty_cache()
-    return res
+    return res, schedule, report
 
 
-def cpu_baseline(envs, args):
-    """FP64 oracle, as it stands, on a bounded sample of the same envs (a few steps of
-    residual mode each, one env per thread)."""
+def residual_distribution(envs, st, tol):
+    """Exit residuals r_ncp of one step over the batch: quantiles, the fraction at or
+    below tol, and the same for the envs with and without a tet block."""
+    import numpy as np
+
+    r = np.asarray(st["r_ncp"], np.float64)
+    fem = np.array([d.n_tets > 0 for d in envs])
+
+    def summ(m):
+        if not m.any():
+            return None
+        q = np.quantile(r[m], [0.1, 0.5, 0.9, 0.99])
+        return {"n": int(m.sum()), "p10": float(q[0]), "p50": float(q[1]), "p90": float(q[2]),
+                "p99": float(q[3]), "max": float(r[m].max()), "frac_at_tol": float((r[m] <= tol).mean())}
+
+    return {"all": summ(np.ones(len(r), bool)), "with_tets": summ(fem), "rigid_only": summ(~fem)}
+
+
+WARM_OF_ARM = {"zero": 0, "prev": 1, "learned": 2, "hybrid": 3}
+
+
+def host_cores():
+    """Cores this process may use, bounded by the host's share per GPU (16)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(envs, args, arm, blob):
+    """FP64 oracle, as it stands, on a bounded sample of the same batch, in the headline's
+    arm (same warm start, same weights) and step window (args.warmup untimed steps from
+    the initial state, then the timed steps), one env per thread on every usable core.
+    The sample is stratified over the launch order of work (evenly spaced ranks of
+    rows + DOFs), so its mean work per env follows the batch's."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -102,25 +154,61 @@ def cpu_baseline(envs, args):
     from oracle import oracle as O
     import scene_inputs as si
 
-    cores = min(16, os.cpu_count() or 1)
-    rng = np.random.default_rng(123)
-    idx = rng.choice(len(envs), size=min(args.cpu_envs, len(envs)), replace=False)
-    params = O.make_params(si.SolverParams(warm=si.WARM_PREV))
+    cores = host_cores()
+    work = np.array([6 * d.n_joints + 3 * d.n_tets + 6 * d.n_rigid + 3 * d.n_particles for d in envs])
+    order = np.argsort(-work, kind="stable")
+    m = min(args.cpu_envs, len(envs))
+    idx = order[np.linspace(0, len(envs) - 1, m).round().astype(int)]
+    params = O.make_params(si.SolverParams(warm=WARM_OF_ARM[arm]))
+    oes = {}
 
-    def work(i):
+    def warm_up(i):
         e = O.OracleEnv(envs[i])
+        if blob is not None:
+            e.set_mlp(blob)
+        for _ in range(args.warmup):
+            e.step(H, args.newton, args.cr, args.tol, params)
+        oes[i] = e
+
+    def timed(i):
+        e = oes[i]
         for _ in range(args.cpu_steps):
             e.step(H, args.newton, args.cr, args.tol, params)
         return args.cpu_steps
 
-    t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=cores) as ex:
-        done = sum(ex.map(work, idx))
-    wall = time.perf_counter() - t0
-    return {"value": done / wall, "unit": "env-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(idx)} randomly chosen envs of the same 4096-env batch x {args.cpu_steps} steps "
-                      f"from their initial state, residual mode (tol {args.tol}, <= {args.newton} Newton x "
-                      f"{args.cr} PCR), previous-step warm start, one env per thread, {wall:.1f} s"}
+        list(ex.map(warm_up, idx))
+        t0 = time.perf_counter()
+        done = sum(ex.map(timed, idx))
+        wall = time.perf_counter() - t0
+    return {"value": done / wall, "unit": "env-steps/s", "cores": cores, "nproc": os.cpu_count(),
+            "kind": "oracle",
+            "sample": f"{m} envs of the same {len(envs)}-env batch at evenly spaced ranks of work, arm {arm}, "
+                      f"{args.warmup} untimed steps from the initial state then {args.cpu_steps} timed steps "
+                      f"(steps {args.warmup + 1}-{args.warmup + args.cpu_steps} of the window the GPU times), "
+                      f"residual mode (tol {args.tol}, <= {args.newton} Newton x {args.cr} PCR), one env per "
+                      f"thread on {cores} threads, {wall:.1f} s timed"}
+
+
+def copy_gbs(mib=2048, reps=10):
+    """Bandwidth of a plain device copy (read + write bytes over time, HIP events): what
+    a pure streaming kernel reaches on this GPU, next to the roofline's peak."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * 4 * n / (ms * 1e-3) / 1e9
 
 
 def traffic_from_profile(tet_model):
@@ -158,9 +246,16 @@ def main():
     ap.add_argument("--tets-max", type=int, default=3000, help="largest tet block of an env (0: rigid only)")
     ap.add_argument("--tet-model", choices=["neohookean", "linear"], default="neohookean",
                     help="material of the envs' tet blocks (linear: six co-rotated strain rows per tet)")
-    ap.add_argument("--schedule", action="store_true", help="autotune the launch schedule first")
-    ap.add_argument("--cpu-envs", type=int, default=256)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--watchdog", type=int, default=0, choices=[0, 1],
+                    help="1: a diverging step returns its lowest-merit iterate (not in the paper); "
+                         "0: the paper's iteration (default)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the library's default schedule (no autotuning before the timed steps)")
+    ap.add_argument("--tune-steps", type=int, default=1, help="replayed steps per autotuner candidate")
+    ap.add_argument("--pcr-form", type=int, default=1, choices=[0, 1],
+                    help="1: register-resident PCR where an env's elements fit (default); 0: streaming")
+    ap.add_argument("--cpu-envs", type=int, default=48, help="envs of the oracle's sample")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="timed oracle steps per sampled env")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 launches): the reference for "
@@ -196,14 +291,18 @@ def main():
         blobs["learned"] = blobs["hybrid"] = np.load(model_path, allow_pickle=False)
     arms = [a for a in args.arms.split(",") if a and (a not in ("learned", "hybrid") or a in blobs)]
     results = {}
+    schedule, tune_report = None, None
     for arm in arms:
         log(f"arm {arm}")
-        results[arm] = run_arm(envs, arm, args, blobs.get(arm))
+        results[arm], schedule, rep = run_arm(envs, arm, args, blobs.get(arm), schedule)
+        tune_report = tune_report or rep
         log(f"arm {arm}: {json.dumps(results[arm])}")
+    # arms ranked by env-steps/s that reach the residual, then by all env-steps/s
+    rank = lambda a: (results[a]["converged_env_steps_per_s"], results[a]["env_steps_per_s"])  # noqa: E731
     plains = [a for a in results if a in ("zero", "prev")]
-    plain = max(plains, key=lambda a: results[a]["env_steps_per_s"]) if plains else None
+    plain = max(plains, key=rank) if plains else None
     learned = [a for a in results if a in ("learned", "hybrid")]
-    head = max(learned, key=lambda a: results[a]["env_steps_per_s"]) if learned else plain
+    head = max(learned, key=rank) if learned else plain
     if head is None:
         sys.exit("bench.py: no arm to report (--arms)")
     r = results[head]
@@ -213,11 +312,27 @@ def main():
         roof = {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "nsn::k_newton", "kernel_ms": round(r["newton_kernel_ms"], 3),
-                "algorithmic_bytes_per_launch": r["cr_bytes_per_launch"]}
+                "algorithmic_bytes_per_launch": r["cr_bytes_per_launch"],
+                "copy_kernel_gbs": round(copy_gbs(), 1)}
+    verdict = None
+    if plain is not None and head != plain:
+        def versus(rp):
+            ratio = r["env_steps_per_s"] / rp["env_steps_per_s"]
+            cratio = (r["converged_env_steps_per_s"] / rp["converged_env_steps_per_s"]
+                      if rp["converged_env_steps_per_s"] > 0 else None)
+            return {"env_steps_ratio": round(ratio, 4),
+                    "converged_env_steps_ratio": round(cratio, 4) if cratio is not None else None,
+                    "newton_iters_ratio": round(r["mean_newton_iters"] / max(rp["mean_newton_iters"], 1e-30), 4),
+                    # beats: more env-steps/s reach the residual, by more than a 1% margin
+                    # over the run-to-run spread, at no loss of env-steps/s overall
+                    "beats": bool(cratio is not None and cratio > 1.01 and ratio > 0.99)}
+        verdict = {"learned_arm": head, "plain_arm": plain, **versus(results[plain]),
+                   "per_plain_arm": {a: versus(results[a]) for a in plains}}
+        verdict["beats_plain"] = verdict.pop("beats")
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(envs, args)
+        cpu = cpu_baseline(envs, args, head, blobs.get(head))
     out = {
         "metric": "env-steps/s at NCP residual 1e-4 (plain vs learned warm start); CR iters/s",
         "value": round(r["env_steps_per_s"], 2),
@@ -235,11 +350,21 @@ def main():
                                f"{'linear co-rotated' if args.tet_model == 'linear' else 'neo-Hookean'} "
                                f"tets), h=1/60, residual mode tol={args.tol}, "
                                f"{'one PCR per island, ' if args.islands else ''}"
+                               f"{'watchdog on, ' if args.watchdog else ''}"
                                f"<= {args.newton} Newton x {args.cr} PCR",
-                   "n_envs": args.envs, "arm": head, "plain_arm": plain},
+                   "n_envs": args.envs, "arm": head, "plain_arm": plain,
+                   "schedule": [list(b) for b in schedule]},
         "cr_iters_per_s": round(r["env_cr_iters_per_s"], 1),
+        "converged_env_steps_per_s": round(r["converged_env_steps_per_s"], 2),
+        "learned_vs_plain": verdict,
         "arms": {a: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in results[a].items()}
                  for a in results},
+        "autotune": None if tune_report is None else {
+            "objective": "env-steps/s over replayed steps from one state snapshot",
+            "default_env_steps_per_s": round(tune_report[0]["env_steps_per_s"], 2),
+            "best_env_steps_per_s": round(max(c["env_steps_per_s"] for c in tune_report), 2),
+            "candidates": [[c["family"], [list(b) for b in c["schedule"]], round(c["env_steps_per_s"], 2)]
+                           for c in tune_report]},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -1,82 +1,112 @@
 """Autotuner of the batched launch schedule.
 
 Environments are launched in decreasing order of work (rows + DOFs).  A schedule cuts
-that order into consecutive buckets; each bucket is one grid with its own workgroup
-size: 64 threads = one wavefront per env (no cross-wave barrier, many envs per CU),
-up to 1024 threads = a 16-wave workgroup per env (large envs).  Buckets run
-concurrently on forked streams.
+that order into consecutive buckets; each bucket is one grid, launched concurrently
+with the others on forked streams, in one of two families:
 
-The tuner measures candidates on live steps of the scene (they double as warm-up
-steps) and scores each by Newton-kernel time per algorithmic byte of the PCR loop,
-which normalises away the step-to-step change of work while the simulation evolves.
+  tile:                one workgroup of 128 to 1024 threads (2 to 16 wavefronts) per
+                       env, cooperating over the env's rows through LDS and barriers;
+  wavefront per env:   one 64-thread workgroup per env, the whole env in a single
+                       wavefront (no cross-wave barrier or LDS reduction); the CU holds
+                       as many of them side by side as registers allow, so several
+                       small envs share a CU without waiting on one another.
+
+Objective: env-steps/s.  Every candidate replays the same steps from one snapshot of
+the scene's state (nsn_save_state / nsn_load_state), so candidates see identical work;
+the scene is left at the snapshot with the best schedule set.
 """
 from __future__ import annotations
 
-import numpy as np
+import time
 
 BLOCKS = (64, 128, 256, 512, 1024)
 
 
-def _work(envs, order):
-    w = []
-    for i in order:
-        d = envs[i]
-        tet_rows = getattr(d, "tet_rows", 3)
-        w.append(6 * d.n_joints + tet_rows * d.n_tets + 3 * d.max_contacts + 6 * d.n_rigid + 3 * d.n_particles)
-    return np.array(w)
+def _valid(buckets, n):
+    at = 0
+    for first, count, block in buckets:
+        if first != at or count <= 0 or block not in BLOCKS:
+            return False
+        at += count
+    return at == n
 
 
-def _start_block(elements):
-    b = 64
-    while b < 1024 and b * 4 < elements:
-        b *= 2
-    return b
-
-
-def _measure(scene, h, newton, cr, tol, steps):
-    scene.reset_accumulators()
+def _score(scene, snap, sched, h, newton, cr, tol, steps):
+    """env-steps/s of `steps` steps from the snapshot under `sched`."""
+    scene.set_schedule([tuple(b) for b in sched])
+    scene.load_state(snap)
+    scene.synchronize()
+    t0 = time.perf_counter()
     for _ in range(steps):
         scene.step(h, newton, cr, tol)
-    kt = scene.kernel_times_ms(cap=steps)
-    acc = scene.accumulators()
-    by = float(acc["cr_bytes"].sum())
-    return float(np.sum(kt)) / max(by, 1.0) * 1e9  # ms per GB
+    scene.synchronize()
+    return scene.n_envs * steps / (time.perf_counter() - t0)
 
 
-def autotune(scene, h, newton, cr, tol, bucket_counts=(1, 2, 4), steps=2, log=None):
-    """The scene's current schedule is the first candidate (the library's default for
-    large batches is itself a measured choice), then equal-count cuts into
-    `bucket_counts` buckets with a coordinate search over each bucket's block size."""
-    order = scene.env_order()
-    n = len(order)
-    work = _work(scene.envs, order)
-    current = scene.schedule()
-    best = (_measure(scene, h, newton, cr, tol, steps), current)
+def candidates(current, n):
+    """The schedules tried after `current`: each bucket's block size moved to its
+    neighbours (coordinate search of the tile family, 64 threads included for the
+    lightest bucket), then the wavefront-per-env family on the light tail of the
+    order (the last 1/8 or 1/4 of the envs at 64 threads, split off the last bucket)."""
+    out = []
+    for k, (_, _, blk) in enumerate(current):
+        i = BLOCKS.index(blk)
+        for j in (i - 1, i + 1):
+            if 0 <= j < len(BLOCKS) and (BLOCKS[j] != 64 or k == len(current) - 1):
+                trial = [list(b) for b in current]
+                trial[k][2] = BLOCKS[j]
+                out.append(("tile" if BLOCKS[j] != 64 else "wavefront", trial))
+    last_first, last_count, last_blk = current[-1]
+    for frac in (1 / 8, 1 / 4):
+        tail = int(round(frac * n))
+        if last_blk != 64 and 0 < tail < last_count:
+            trial = [list(b) for b in current[:-1]]
+            trial.append([last_first, last_count - tail, last_blk])
+            trial.append([last_first + last_count - tail, tail, 64])
+            out.append(("wavefront", trial))
+    return [(fam, t) for fam, t in out if _valid(t, n)]
+
+
+def autotune(scene, h, newton, cr, tol, steps=2, rounds=2, log=None):
+    """Tune the scene's schedule by env-steps/s over `steps` replayed steps per candidate.
+    Starts from the scene's current schedule (the library's default) and repeats the
+    neighbourhood search `rounds` times from the best so far.  Returns (schedule,
+    report) where report lists every candidate's family, schedule and env-steps/s."""
+    n = scene.n_envs
+    snap = scene.save_state()
+    current = [list(b) for b in scene.schedule()]
+    best = _score(scene, snap, current, h, newton, cr, tol, steps)
+    report = [{"family": "default", "schedule": [tuple(b) for b in current], "env_steps_per_s": best}]
     if log:
-        log(f"autotune current {current}: {best[0]:.3f} ms/GB")
-    for nb in bucket_counts:
-        if nb > n:
-            continue
-        cuts = [int(round(k * n / nb)) for k in range(nb + 1)]
-        buckets = [[cuts[k], cuts[k + 1] - cuts[k], _start_block(int(work[cuts[k]] // 3 + 1))]
-                   for k in range(nb) if cuts[k + 1] > cuts[k]]
-        scene.set_schedule([tuple(b) for b in buckets])
-        cost = _measure(scene, h, newton, cr, tol, steps)
-        for k in range(len(buckets)):
-            for blk in BLOCKS:
-                if blk == buckets[k][2]:
-                    continue
-                trial = [list(b) for b in buckets]
-                trial[k][2] = blk
-                scene.set_schedule([tuple(b) for b in trial])
-                c = _measure(scene, h, newton, cr, tol, steps)
-                if log:
-                    log(f"autotune nb={nb} bucket {k} block {blk}: {c:.3f} ms/GB (best {cost:.3f})")
-                if c < cost:
-                    cost, buckets = c, trial
-        if cost < best[0]:
-            best = (cost, [tuple(b) for b in buckets])
-        if log:
-            log(f"autotune nb={nb}: {best}")
-    scene.set_schedule(best[1])
-    return best[1]
+        log(f"autotune default {current}: {best:.1f} env-steps/s")
+    seen = {tuple(map(tuple, current))}
+    for _ in range(rounds):
+        improved = False
+        for fam, trial in candidates(current, n):
+            key = tuple(map(tuple, trial))
+            if key in seen:
+                continue
+            seen.add(key)
+            v = _score(scene, snap, trial, h, newton, cr, tol, steps)
+            report.append({"family": fam, "schedule": [tuple(b) for b in trial], "env_steps_per_s": v})
+            if log:
+                log(f"autotune {fam} {trial}: {v:.1f} env-steps/s (best {best:.1f})")
+            if v > best * 1.01:  # a candidate must beat the timing noise to replace the best
+                best, current, improved = v, trial, True
+        if not improved:
+            break
+    scene.set_schedule([tuple(b) for b in current])
+    scene.load_state(snap)
+    scene.synchronize()
+    return [tuple(b) for b in current], report
+
+
+def default_vs(scene, snap, sched, h, newton, cr, tol, steps, default):
+    """(env-steps/s of `default`, of `sched`) replayed from the same snapshot."""
+    a = _score(scene, snap, default, h, newton, cr, tol, steps)
+    b = _score(scene, snap, sched, h, newton, cr, tol, steps)
+    scene.load_state(snap)
+    return a, b
+
+
+__all__ = ["autotune", "candidates", "default_vs", "BLOCKS"]
