@@ -7,9 +7,9 @@ per-env Newton kernel (one launch per step, replayed from a hipGraph), h = 1/60 
 residual mode: every env stops when r_ncp <= 1e-4 or after 50 Newton iterations of 40
 PCR iterations.  Inputs are seeded and synthetic and already resident in HBM.
 
-Before the timed steps the autotuner picks the launch schedule by env-steps/s,
-replaying the same steps from one state snapshot per candidate (--no-tune keeps the
-library's default); every arm then runs under that schedule.
+Before the timed steps the autotuner picks the launch schedule and the form of the
+PCR loop by env-steps/s, replaying the same steps from one state snapshot per
+candidate (--no-tune keeps the library's defaults); every arm then runs under them.
 
 Prints ONE JSON line.  `value` is env-steps/s of the headline arm: of the two learned
 warm starts ("learned" takes the network's multipliers for every contact, "hybrid"
@@ -42,10 +42,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_arm(envs, arm, args, model_blob=None, schedule=None):
-    """One arm: warm-up steps, then (first arm only, schedule None and tuning on) the
+def run_arm(envs, arm, args, model_blob=None, tuned=None):
+    """One arm: warm-up steps, then (first arm only: tuned None and tuning on) the
     autotuner from the post-warm-up state, then the timed steps from that same state.
-    Returns (results, schedule used, tuner report or None)."""
+    tuned: (schedule, PCR form) to run under.  Returns (results, (schedule, PCR form)
+    used, tuner report or None)."""
     import numpy as np
     import torch
 
@@ -55,25 +56,32 @@ def run_arm(envs, arm, args, model_blob=None, schedule=None):
     warm = {"zero": si.WARM_ZERO, "prev": si.WARM_PREV, "learned": si.WARM_LEARNED,
             "hybrid": si.WARM_HYBRID}[arm]
     p = si.SolverParams(warm=si.WARM_ZERO, islands=int(args.islands), watchdog=int(args.watchdog))
-    sc = Scene(envs, p)
+    sc = Scene(envs, p, stream=None if args.stream == "private" else torch.cuda.current_stream())
     if model_blob is not None:
         sc.set_warm_start_model(model_blob)
-    if schedule is not None:
-        sc.set_schedule(schedule)
+    if args.graphs >= 0:
+        sc.set_use_graphs(bool(args.graphs))
+    if tuned is not None:
+        if tuned[0] is not None:
+            sc.set_schedule(tuned[0])
+        if tuned[1] is not None:
+            sc.set_pcr_form(tuned[1])
     p.warm = warm
     sc.set_params(p)
-    sc.set_pcr_form(args.pcr_form)
+    if args.pcr_form >= 0:
+        sc.set_pcr_form(args.pcr_form)
     for i in range(args.warmup):
         sc.step(H, args.newton, args.cr, args.tol)
         if i == 0 or (i + 1) % 10 == 0:
             sc.synchronize()
             log(f"[{arm}] warmup {i + 1}/{args.warmup}")
     report = None
-    if schedule is None and not args.no_tune:
+    if tuned is None and not args.no_tune:
         from paper_1907_04587_amd.autotune import autotune
-        schedule, report = autotune(sc, H, args.newton, args.cr, args.tol, steps=args.tune_steps, log=log)
-        log(f"[{arm}] tuned schedule {schedule}")
-    schedule = [tuple(b) for b in sc.schedule()]
+        sched, form, report = autotune(sc, H, args.newton, args.cr, args.tol, steps=args.tune_steps,
+                                       forms=(0, 1, 2) if args.pcr_form < 0 else (), log=log)
+        log(f"[{arm}] tuned schedule {sched}, PCR form {form}")
+    used = ([tuple(b) for b in sc.schedule()], sc.pcr_form)
     sc.reset_accumulators()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -108,7 +116,7 @@ def run_arm(envs, arm, args, model_blob=None, schedule=None):
     res["residual_last_step"] = residual_distribution(envs, st, args.tol)
     del sc
     torch.cuda.empty_cache()
-    return res, schedule, report
+    return res, used, report
 
 
 def residual_distribution(envs, st, tol):
@@ -249,11 +257,19 @@ def main():
     ap.add_argument("--watchdog", type=int, default=0, choices=[0, 1],
                     help="1: a diverging step returns its lowest-merit iterate (not in the paper); "
                          "0: the paper's iteration (default)")
+    ap.add_argument("--stream", choices=["private", "current"], default="private",
+                    help="the scene's stream: its own (graph replay, buckets on forked streams; default) or "
+                         "torch's current one")
+    ap.add_argument("--graphs", type=int, default=-1, choices=[-1, 0, 1],
+                    help="1: replay each step from a hipGraph; 0: launch directly; -1: the library's default")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the library's default schedule (no autotuning before the timed steps)")
     ap.add_argument("--tune-steps", type=int, default=1, help="replayed steps per autotuner candidate")
-    ap.add_argument("--pcr-form", type=int, default=1, choices=[0, 1],
-                    help="1: register-resident PCR where an env's elements fit (default); 0: streaming")
+    ap.add_argument("--schedule", default=None, metavar="FIRST:COUNT:BLOCK,...",
+                    help="launch every arm under this schedule (buckets of the launch order) instead of tuning")
+    ap.add_argument("--pcr-form", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="0: streaming two-pass PCR; 1: register-resident where an env's elements fit; "
+                         "2: one-pass; -1: the library's default, or the tuner's choice")
     ap.add_argument("--cpu-envs", type=int, default=48, help="envs of the oracle's sample")
     ap.add_argument("--cpu-steps", type=int, default=2, help="timed oracle steps per sampled env")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -277,10 +293,15 @@ def main():
         n = args.copy_calibration * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
         for _ in range(5):
             dst.copy_(src)
+        b.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 5}))
+        ms = a.elapsed_time(b) / 5
+        print(json.dumps({"copy_calibration_bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 5,
+                          "ms_per_launch": ms, "copy_gbs": 2 * 4 * n / (ms * 1e-3) / 1e9}))
         return
     log(f"generating {args.envs} envs")
     tet_model = si.TET_LINEAR if args.tet_model == "linear" else si.TET_NEOHOOKEAN
@@ -291,10 +312,12 @@ def main():
         blobs["learned"] = blobs["hybrid"] = np.load(model_path, allow_pickle=False)
     arms = [a for a in args.arms.split(",") if a and (a not in ("learned", "hybrid") or a in blobs)]
     results = {}
-    schedule, tune_report = None, None
+    tuned, tune_report = None, None
+    if args.schedule:
+        tuned = ([tuple(int(v) for v in b.split(":")) for b in args.schedule.split(",")], None)
     for arm in arms:
         log(f"arm {arm}")
-        results[arm], schedule, rep = run_arm(envs, arm, args, blobs.get(arm), schedule)
+        results[arm], tuned, rep = run_arm(envs, arm, args, blobs.get(arm), tuned)
         tune_report = tune_report or rep
         log(f"arm {arm}: {json.dumps(results[arm])}")
     # arms ranked by env-steps/s that reach the residual, then by all env-steps/s
@@ -353,7 +376,7 @@ def main():
                                f"{'watchdog on, ' if args.watchdog else ''}"
                                f"<= {args.newton} Newton x {args.cr} PCR",
                    "n_envs": args.envs, "arm": head, "plain_arm": plain,
-                   "schedule": [list(b) for b in schedule]},
+                   "schedule": [list(b) for b in tuned[0]], "pcr_form": tuned[1]},
         "cr_iters_per_s": round(r["env_cr_iters_per_s"], 1),
         "converged_env_steps_per_s": round(r["converged_env_steps_per_s"], 2),
         "learned_vs_plain": verdict,
@@ -363,7 +386,8 @@ def main():
             "objective": "env-steps/s over replayed steps from one state snapshot",
             "default_env_steps_per_s": round(tune_report[0]["env_steps_per_s"], 2),
             "best_env_steps_per_s": round(max(c["env_steps_per_s"] for c in tune_report), 2),
-            "candidates": [[c["family"], [list(b) for b in c["schedule"]], round(c["env_steps_per_s"], 2)]
+            "candidates": [[c["family"], [list(b) for b in c["schedule"]], c["pcr_form"],
+                            round(c["env_steps_per_s"], 2)]
                            for c in tune_report]},
         "roofline": roof,
         "cpu_baseline": cpu,

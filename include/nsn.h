@@ -405,12 +405,17 @@ nsn_status nsn_get_schedule(nsn_scene s, int32_t cap, int32_t *n, int32_t *first
  * 256, a quarter at 128).  Applies to the current and later schedules. */
 nsn_status nsn_set_lds_mode(nsn_scene s, int32_t max_mode);
 
-/* Form of the PCR loop (Sec. 8.2; a tuning and testing switch with identical results):
- * 1 (default) keeps the rows and the element data of every tet and contact in the
- * registers of the thread that owns the element for all the PCR iterations of a
- * Newton iteration, in envs whose elements all have a register slot (4 per thread
- * below 1024 threads, 1 at 1024) and that hold neo-Hookean tets only; other envs, and
- * 0, stream them from memory every PCR iteration. */
+/* Form of the PCR loop (Sec. 8.2; a tuning switch).  0: every PCR iteration streams
+ * the rows and the element data from memory in two element passes, one forming
+ * J^T z and one forming J (H~^-1 J^T z).  1: the same arithmetic with the
+ * rows of every tet and contact held in the registers of the thread that owns the
+ * element for all the PCR iterations of a Newton iteration, in envs whose elements
+ * all have a slot (2 per thread below 1024 threads, none at 1024); results identical
+ * to 0.  2 (default): one element pass per PCR iteration -- J^T z and J^T (P q) are carried in
+ * body space by their own recurrences (linear images of the row updates), so each
+ * element's Jacobian is read once per iteration; the same iterates in exact
+ * arithmetic, with different rounding.  Envs with linear tets, and island mode, use
+ * 0 whatever the setting.  NSN_EINVAL for another value. */
 nsn_status nsn_set_pcr_form(nsn_scene s, int32_t form);
 
 /* The LDS mode each current bucket runs in (0, 1, 2 as above): mode[cap]. */

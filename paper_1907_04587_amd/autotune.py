@@ -13,7 +13,9 @@ with the others on forked streams, in one of two families:
 
 Objective: env-steps/s.  Every candidate replays the same steps from one snapshot of
 the scene's state (nsn_save_state / nsn_load_state), so candidates see identical work;
-the scene is left at the snapshot with the best schedule set.
+the scene is left at the snapshot with the best schedule set.  Candidates run as direct
+launches (a capture per candidate would only be thrown away); the scene's graph
+setting is restored afterwards.
 """
 from __future__ import annotations
 
@@ -67,16 +69,29 @@ def candidates(current, n):
     return [(fam, t) for fam, t in out if _valid(t, n)]
 
 
-def autotune(scene, h, newton, cr, tol, steps=2, rounds=2, log=None):
+def autotune(scene, h, newton, cr, tol, steps=2, rounds=2, forms=(), log=None):
     """Tune the scene's schedule by env-steps/s over `steps` replayed steps per candidate.
     Starts from the scene's current schedule (the library's default) and repeats the
-    neighbourhood search `rounds` times from the best so far.  Returns (schedule,
-    report) where report lists every candidate's family, schedule and env-steps/s."""
+    neighbourhood search `rounds` times from the best so far; then, under the best
+    schedule, tries each PCR form in `forms` (nsn_set_pcr_form).  Returns (schedule,
+    PCR form, report) where report lists every candidate's family, schedule, form and
+    env-steps/s."""
     n = scene.n_envs
+    graphs = scene.use_graphs
+    scene.set_use_graphs(False)
+    try:
+        return _search(scene, n, h, newton, cr, tol, steps, rounds, forms, log)
+    finally:
+        scene.set_use_graphs(graphs)
+
+
+def _search(scene, n, h, newton, cr, tol, steps, rounds, forms, log):
     snap = scene.save_state()
     current = [list(b) for b in scene.schedule()]
+    form = scene.pcr_form
     best = _score(scene, snap, current, h, newton, cr, tol, steps)
-    report = [{"family": "default", "schedule": [tuple(b) for b in current], "env_steps_per_s": best}]
+    report = [{"family": "default", "schedule": [tuple(b) for b in current], "pcr_form": form,
+               "env_steps_per_s": best}]
     if log:
         log(f"autotune default {current}: {best:.1f} env-steps/s")
     seen = {tuple(map(tuple, current))}
@@ -88,22 +103,38 @@ def autotune(scene, h, newton, cr, tol, steps=2, rounds=2, log=None):
                 continue
             seen.add(key)
             v = _score(scene, snap, trial, h, newton, cr, tol, steps)
-            report.append({"family": fam, "schedule": [tuple(b) for b in trial], "env_steps_per_s": v})
+            report.append({"family": fam, "schedule": [tuple(b) for b in trial], "pcr_form": form,
+                           "env_steps_per_s": v})
             if log:
                 log(f"autotune {fam} {trial}: {v:.1f} env-steps/s (best {best:.1f})")
             if v > best * 1.01:  # a candidate must beat the timing noise to replace the best
                 best, current, improved = v, trial, True
         if not improved:
             break
+    for f in forms:
+        if f == form:
+            continue
+        scene.set_pcr_form(f)
+        v = _score(scene, snap, current, h, newton, cr, tol, steps)
+        report.append({"family": f"pcr form {f}", "schedule": [tuple(b) for b in current], "pcr_form": f,
+                       "env_steps_per_s": v})
+        if log:
+            log(f"autotune PCR form {f}: {v:.1f} env-steps/s (best {best:.1f})")
+        if v > best * 1.01:
+            best, form = v, f
+    scene.set_pcr_form(form)
     scene.set_schedule([tuple(b) for b in current])
     scene.load_state(snap)
     scene.synchronize()
-    return [tuple(b) for b in current], report
+    return [tuple(b) for b in current], form, report
 
 
-def default_vs(scene, snap, sched, h, newton, cr, tol, steps, default):
-    """(env-steps/s of `default`, of `sched`) replayed from the same snapshot."""
+def default_vs(scene, snap, sched, form, h, newton, cr, tol, steps, default, default_form):
+    """(env-steps/s of `default` with PCR form `default_form`, of `sched` with `form`)
+    replayed from the same snapshot; the scene is left at the snapshot under `sched`."""
+    scene.set_pcr_form(default_form)
     a = _score(scene, snap, default, h, newton, cr, tol, steps)
+    scene.set_pcr_form(form)
     b = _score(scene, snap, sched, h, newton, cr, tol, steps)
     scene.load_state(snap)
     return a, b

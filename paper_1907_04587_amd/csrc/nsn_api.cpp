@@ -181,6 +181,7 @@ void layout(const Sizes &z, int n_envs, const Options &opt, Arena &a, DevScene &
   S.r_q_k = a.take<float4>(ls * z.NR); S.du = a.take<float>(ls * z.NDOF);
   S.row_dump = a.take<float>(z.NROW);
   S.y = a.take<float>(z.NDOF); S.g = a.take<float>(z.NDOF); S.f = a.take<float>(z.NDOF);
+  S.bz = a.take<float>(z.NDOF); S.bq = a.take<float>(z.NDOF);
   // islands: per element (joints, tets, contact slots), per body, and per env
   // n_rig + n_par + 2 island slots (the bodies, the static group, one spare)
   const size_t isl = opt.islands ? 1 : 0;
@@ -246,7 +247,7 @@ struct nsn_scene_s {
   std::map<GraphKey, hipGraphExec_t> graphs;
   bool use_graphs = true;
   int lds_max = 2;  // the largest LDS mode the buckets may use (nsn_set_lds_mode)
-  int pcr_form = 1;  // 1: register-resident PCR where an env's elements fit (nsn_set_pcr_form)
+  int pcr_form = 2;  // the PCR loop's form (nsn_set_pcr_form): one-pass by default
   int want_features = 0;
   // side streams (default priority) for concurrent schedule buckets, and fork/join events
   std::vector<hipStream_t> side;
@@ -629,7 +630,26 @@ static hipError_t ensure_side_streams(nsn_scene s, size_t nb) {
   return hipSuccess;
 }
 
-static hipError_t enqueue_step(nsn_scene s, const StepArgs &a) {
+// Everything a step's launches need that is not a stream operation -- the side streams
+// and events of the buckets, the dynamic-LDS limit of each bucket's kernel -- set up
+// before a capture begins (such calls are not allowed inside one).
+static hipError_t prime_step(nsn_scene s, const StepArgs &a) {
+  if (s->stream != nullptr && s->buckets.size() > 1) {
+    hipError_t e = ensure_side_streams(s, s->buckets.size());
+    if (e != hipSuccess) return e;
+  }
+  for (const Bucket &b : s->buckets) {
+    hipError_t e = launch_newton(s->S, a, b.block, b.first, b.count, b.lds_floats, b.lds_mode, s->pcr_form, s->stream,
+                                 kLaunchAttr);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Enqueues one step; with `capturing` set only stream operations are issued (prime_step
+// has run first).
+static hipError_t enqueue_step(nsn_scene s, const StepArgs &a, bool capturing = false) {
+  const int what = capturing ? kLaunchRun : (kLaunchAttr | kLaunchRun);
   hipError_t e = launch_prepare(s->S, a, s->want_features || learned_warm(a.p.warm), s->stream);
   if (e != hipSuccess) return e;
   if (learned_warm(a.p.warm)) {
@@ -639,13 +659,16 @@ static hipError_t enqueue_step(nsn_scene s, const StepArgs &a) {
   const size_t nb = s->buckets.size();
   if (s->stream == nullptr || nb == 1) {
     for (const Bucket &b : s->buckets) {
-      e = launch_newton(s->S, a, b.block, b.first, b.count, b.lds_floats, b.lds_mode, s->pcr_form, s->stream);
+      e = launch_newton(s->S, a, b.block, b.first, b.count, b.lds_floats, b.lds_mode, s->pcr_form, s->stream, what);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   }
-  e = ensure_side_streams(s, nb);
-  if (e != hipSuccess) return e;
+  if (s->side.size() + 1 < nb || s->ev.size() < 2 * nb) {
+    if (capturing) return hipErrorStreamCaptureUnsupported;  // prime_step creates them
+    e = ensure_side_streams(s, nb);
+    if (e != hipSuccess) return e;
+  }
   e = hipEventRecord(s->ev[0], s->stream);
   if (e != hipSuccess) return e;
   for (size_t i = 1; i < nb; ++i) {
@@ -655,7 +678,7 @@ static hipError_t enqueue_step(nsn_scene s, const StepArgs &a) {
   for (size_t i = 0; i < nb; ++i) {
     const Bucket &b = s->buckets[i];
     e = launch_newton(s->S, a, b.block, b.first, b.count, b.lds_floats, b.lds_mode, s->pcr_form,
-                      i == 0 ? s->stream : s->side[i - 1]);
+                      i == 0 ? s->stream : s->side[i - 1], what);
     if (e != hipSuccess) return e;
   }
   for (size_t i = 1; i < nb; ++i) {
@@ -688,8 +711,9 @@ nsn_status nsn_step(nsn_scene s, double h, int32_t newton_iters, int32_t cr_iter
   auto it = s->graphs.find(k);
   if (it == s->graphs.end()) {
     hipGraph_t graph;
+    HIP_TRY(prime_step(s, a));
     HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t le = enqueue_step(s, a);
+    hipError_t le = enqueue_step(s, a, true);
     hipError_t ce = hipStreamEndCapture(s->stream, &graph);
     if (le != hipSuccess) return fail(NSN_EDEVICE, std::string("capture: ") + hipGetErrorString(le));
     if (ce != hipSuccess) return fail(NSN_EDEVICE, std::string("end capture: ") + hipGetErrorString(ce));
@@ -981,7 +1005,7 @@ nsn_status nsn_get_schedule(nsn_scene s, int32_t cap, int32_t *n, int32_t *first
 }
 
 nsn_status nsn_set_pcr_form(nsn_scene s, int32_t form) {
-  if (!s || form < 0 || form > 1) return fail(NSN_EINVAL, "PCR form must be 0 or 1");
+  if (!s || form < 0 || form > 2) return fail(NSN_EINVAL, "PCR form must be 0, 1 or 2");
   s->pcr_form = form;
   for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
   s->graphs.clear();

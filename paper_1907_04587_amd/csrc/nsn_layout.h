@@ -125,6 +125,7 @@ struct DevScene {
 
   // body space (NDOF)
   float *y, *g, *f;
+  float *bz, *bq;  // one-pass PCR: J^T z and J^T (P q) in body space (NDOF each)
 
   // islands (rebuilt every step in island mode).  Element index space of an env:
   // [joints | tets | contact slots] from jnt_off + tet_off + con_off; island slots of
@@ -181,11 +182,14 @@ hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_feature
 // (align4(n_dof) + 12 n_tet floats per env)
 // resident: the register-resident PCR for the envs whose elements all have a register
 // slot (neo-Hookean instantiation only; others take the streaming form)
+// what: kLaunchAttr sets the chosen kernel's dynamic-LDS limit (not allowed inside a
+// stream capture), kLaunchRun enqueues it
+constexpr int kLaunchAttr = 1, kLaunchRun = 2;
 hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
-                         int lds_mode, int resident, hipStream_t st);
+                         int lds_mode, int resident, hipStream_t st, int what = kLaunchAttr | kLaunchRun);
 // the same for the extended instantiation (linear tets, islands; nsn_step_ext.hip)
 hipError_t launch_newton_ext(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
-                             int lds_mode, hipStream_t st);
+                             int lds_mode, hipStream_t st, int what);
 constexpr int kMaxLdsFloats = 24 * 1024;  // 96 KB of LDS for the body-space vector
 constexpr int kMaxLdsFloatsCl = 39 * 1024;  // 156 KB: body-space vector + tet contributions (mode 2)
 // learned warm start: MLP prediction for every contact of every env (nsn_mlp.hip)

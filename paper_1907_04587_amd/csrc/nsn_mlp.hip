@@ -1,13 +1,19 @@
 // Learned warm start: MLP 12 -> 64 -> 64 -> 64 -> 3 with ReLU on the hidden layers,
-// forward and backward on gfx950 BF16 MFMA tiles (v_mfma_f32_16x16x16_bf16) with FP32
+// forward and backward on gfx950 BF16 MFMA tiles (v_mfma_f32_16x16x32_bf16) with FP32
 // accumulation.
 //
 // Layout: every product is computed transposed, Z^T = W H^T, with the weight tile as
 // the A operand (rows = output features) and the activations as the B operand
-// (rows = input features, columns = 16 samples).  The accumulator layout of one layer
-// (lane l holds rows 4*(l/16)..+3 of column l%16) is then exactly the B-operand layout
-// the next layer needs, so activations stay in registers between layers; only the
-// weight-gradient products (sum over samples) go through an LDS transpose.
+// (rows = input features, columns = 16 samples).  One 16x16 accumulator tile leaves
+// lane l with rows 4*(l/16)..+3 of column l%16.  A K=32 operand gives lane l eight
+// slots; the contraction pairs slot i of lane group g = l/16 in A with the same slot of
+// the same group in B, so any assignment of the 32 summed indices to (group, slot)
+// serves, as long as both operands use it.  Here slots 0..3 of group g carry index
+// 4g + 0..3 and slots 4..7 carry 16 + 4g + 0..3: the two accumulator tiles of one
+// layer (features 0..15 and 16..31 of a 32-chunk) are then, as they stand, the B
+// operand of the next layer, and activations stay in registers between layers.  The
+// weight-gradient products (sums over 32 samples, two 16-sample tiles) go through an
+// LDS transpose.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,7 +22,8 @@
 
 namespace nsn {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kIn = kMlpIn, kH = kMlpHidden, kOut = kMlpOut;
@@ -32,14 +39,30 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
-__device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
-  bf16x4 r;
-  r[0] = (short)f2bf(a); r[1] = (short)f2bf(b); r[2] = (short)f2bf(c); r[3] = (short)f2bf(d);
+// slots 0..3 from lo, 4..7 from hi (the summed indices 4g+v and 16+4g+v)
+__device__ __forceinline__ s16x8 pack8(f32x4 lo, f32x4 hi) {
+  s16x8 r;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    r[v] = (short)f2bf(lo[v]);
+    r[4 + v] = (short)f2bf(hi[v]);
+  }
+  return r;
+}
+// slots 0..3 from lo, 4..7 zero (a 16-wide contraction on the 32-wide instruction)
+__device__ __forceinline__ s16x8 pack8_lo(f32x4 lo) {
+  s16x8 r;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    r[v] = (short)f2bf(lo[v]);
+    r[4 + v] = 0;
+  }
   return r;
 }
 
-__device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+__device__ __forceinline__ f32x4 mfma(s16x8 a, s16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                 0, 0);
 }
 
 // Weights staged in LDS as bf16, row-major [out][in] with the input dimension of W1
@@ -73,19 +96,30 @@ __device__ void stage_weights(MlpLds &L, const float *w) {
   for (int i = threadIdx.x; i < 16; i += blockDim.x) L.b4[i] = i < kOut ? w[oB4 + i] : 0.f;
 }
 
-// A fragment of a row-major bf16 matrix with `ld` columns: rows r0..r0+15, cols k0..k0+15
-__device__ __forceinline__ bf16x4 afrag(const unsigned short *W, int ld, int r0, int k0, int lane) {
+// A fragment of a row-major bf16 matrix with `ld` columns: rows r0..r0+15, summed
+// columns k0 + (4g + 0..3, 16 + 4g + 0..3) in the slot order above; lo: only the first
+// 16 columns exist (slots 4..7 zero)
+template <bool LO = false>
+__device__ __forceinline__ s16x8 afrag(const unsigned short *W, int ld, int r0, int k0, int lane) {
   const unsigned short *p = W + (r0 + (lane & 15)) * ld + k0 + 4 * (lane >> 4);
-  bf16x4 r;
-  r[0] = (short)p[0]; r[1] = (short)p[1]; r[2] = (short)p[2]; r[3] = (short)p[3];
+  s16x8 r;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    r[v] = (short)p[v];
+    r[4 + v] = LO ? (short)0 : (short)p[16 + v];
+  }
   return r;
 }
-// A fragment of the TRANSPOSE of a row-major matrix W [rows x ld]: A[i][k] = W[k][i]
-__device__ __forceinline__ bf16x4 afragT(const unsigned short *W, int ld, int i0, int k0, int lane) {
+// the same for the TRANSPOSE of a row-major matrix W [rows x ld]: A[i][k] = W[k][i]
+template <bool LO = false>
+__device__ __forceinline__ s16x8 afragT(const unsigned short *W, int ld, int i0, int k0, int lane) {
   const int i = i0 + (lane & 15), k = k0 + 4 * (lane >> 4);
-  bf16x4 r;
-  r[0] = (short)W[(k + 0) * ld + i]; r[1] = (short)W[(k + 1) * ld + i];
-  r[2] = (short)W[(k + 2) * ld + i]; r[3] = (short)W[(k + 3) * ld + i];
+  s16x8 r;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    r[v] = (short)W[(k + v) * ld + i];
+    r[4 + v] = LO ? (short)0 : (short)W[(k + 16 + v) * ld + i];
+  }
   return r;
 }
 
@@ -94,56 +128,58 @@ struct Acts {
   f32x4 y;                    // outputs (rows 0..2 valid in lanes 0..15)
 };
 
-// forward of one 16-sample tile; x: the B fragment of the inputs (features 4*(l/16)..+3
-// of sample l%16, zero padded to 16)
-__device__ __forceinline__ void forward_tile(const MlpLds &L, bf16x4 x, int lane, Acts &a) {
+// forward of one 16-sample tile; x: the B fragment of the inputs (slots 0..3: features
+// 4*(l/16)..+3 of sample l%16, zero padded to 16; slots 4..7 zero)
+__device__ __forceinline__ void forward_tile(const MlpLds &L, s16x8 x, int lane, Acts &a) {
   const int rb = 4 * (lane >> 4);
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    acc = mfma(afrag(L.W1, 16, 16 * t, 0, lane), x, acc);
+    acc = mfma(afrag<true>(L.W1, 16, 16 * t, 0, lane), x, acc);
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[v] = fmaxf(acc[v] + L.b1[16 * t + rb + v], 0.f);
     a.h1[t] = acc;
   }
-  bf16x4 hb[4];
+  s16x8 hb[2];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) hb[t] = pack4(a.h1[t][0], a.h1[t][1], a.h1[t][2], a.h1[t][3]);
+  for (int j = 0; j < 2; ++j) hb[j] = pack8(a.h1[2 * j], a.h1[2 * j + 1]);
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) acc = mfma(afrag(L.W2, kH, 16 * t, 16 * ks, lane), hb[ks], acc);
+    for (int j = 0; j < 2; ++j) acc = mfma(afrag(L.W2, kH, 16 * t, 32 * j, lane), hb[j], acc);
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[v] = fmaxf(acc[v] + L.b2[16 * t + rb + v], 0.f);
     a.h2[t] = acc;
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t) hb[t] = pack4(a.h2[t][0], a.h2[t][1], a.h2[t][2], a.h2[t][3]);
+  for (int j = 0; j < 2; ++j) hb[j] = pack8(a.h2[2 * j], a.h2[2 * j + 1]);
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) acc = mfma(afrag(L.W3, kH, 16 * t, 16 * ks, lane), hb[ks], acc);
+    for (int j = 0; j < 2; ++j) acc = mfma(afrag(L.W3, kH, 16 * t, 32 * j, lane), hb[j], acc);
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[v] = fmaxf(acc[v] + L.b3[16 * t + rb + v], 0.f);
     a.h3[t] = acc;
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t) hb[t] = pack4(a.h3[t][0], a.h3[t][1], a.h3[t][2], a.h3[t][3]);
+  for (int j = 0; j < 2; ++j) hb[j] = pack8(a.h3[2 * j], a.h3[2 * j + 1]);
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks) acc = mfma(afrag(L.W4, kH, 0, 16 * ks, lane), hb[ks], acc);
+  for (int j = 0; j < 2; ++j) acc = mfma(afrag(L.W4, kH, 0, 32 * j, lane), hb[j], acc);
 #pragma unroll
   for (int v = 0; v < 4; ++v) acc[v] += L.b4[rb + v];
   a.y = acc;
 }
 
-__device__ __forceinline__ bf16x4 load_x(const float *X, long long n, long long s0, int lane,
-                                         const float *mean, const float *inv_std) {
+// the raw (unpacked) input features of one tile in accumulator layout (features
+// 4*(l/16)+v of sample l%16), standardised when mean is given
+__device__ __forceinline__ f32x4 load_xf(const float *X, long long n, long long s0, int lane, const float *mean,
+                                         const float *inv_std) {
   const long long s = s0 + (lane & 15);
   const int k = 4 * (lane >> 4);
-  float v[4] = {0.f, 0.f, 0.f, 0.f};
+  f32x4 v = {0.f, 0.f, 0.f, 0.f};
   if (s < n && k < kIn) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -152,7 +188,12 @@ __device__ __forceinline__ bf16x4 load_x(const float *X, long long n, long long 
       v[j] = xv;
     }
   }
-  return pack4(v[0], v[1], v[2], v[3]);
+  return v;
+}
+
+__device__ __forceinline__ s16x8 load_x(const float *X, long long n, long long s0, int lane, const float *mean,
+                                        const float *inv_std) {
+  return pack8_lo(load_xf(X, n, s0, lane, mean, inv_std));
 }
 
 // ---------------------------------------------------------------------------
@@ -225,42 +266,65 @@ hipError_t launch_warm_mlp(const DevScene &s, int hybrid, hipStream_t st) {
 // ---------------------------------------------------------------------------
 constexpr int kGradBlocks = 256;
 
-struct GradLds {
-  MlpLds L;
-  float zt[4][16 * kH];  // per-wave transposed dZ tile [sample][feature]
-  float ht[4][16 * kH];  // per-wave transposed activation tile [sample][feature]
+// Per-wave LDS of the gradient kernel: for each layer, the transposes of dZ and of the
+// layer's input over a 32-sample pair of tiles, bf16 [sample][feature] (layer 4: dY 16
+// (3 valid) and h3 64; layer 3: dZ3 and h2; layer 2: dZ2 and h1; layer 1: dZ1 64 and x
+// 16 (12 valid)), filled by the backward of both tiles before the weight-gradient
+// products run.
+constexpr int kPairS = 32;
+constexpr int kWaveStage = kPairS * (16 + kH + kH + kH + kH + kH + kH + 16);  // bf16 elements
+struct WaveStage {
+  unsigned short *z4, *h3, *z3, *h2, *z2, *h1, *z1, *x;
+  __device__ explicit WaveStage(unsigned short *b)
+      : z4(b), h3(z4 + kPairS * 16), z3(h3 + kPairS * kH), h2(z3 + kPairS * kH), z2(h2 + kPairS * kH),
+        h1(z2 + kPairS * kH), z1(h1 + kPairS * kH), x(z1 + kPairS * kH) {}
 };
+constexpr size_t kGradLdsBytes = sizeof(MlpLds) + 4 * sizeof(unsigned short) * (size_t)kWaveStage;
+static_assert(kGradLdsBytes <= 160 * 1024, "gradient kernel LDS");
 
-// dW[o][i] += sum_s dz[o][s] h[i][s] over one tile, with dz and h given in accumulator
-// layout (tile t holds features 16t + 4*(l/16) + v of sample l%16); the products run
-// on MFMA after an LDS transpose.  acc: [no/16][ni/16] accumulator tiles.
+// write one tile's accumulator-layout values (tile t: features 16t + 4*(l/16) + v of
+// sample l%16) as bf16 into rows q*16 + sample of a [32][NF] transpose
+template <int NF>
+__device__ __forceinline__ void stage_t(const f32x4 *v, unsigned short *dst, int q, int lane) {
+  const int s = 16 * q + (lane & 15), rb = 4 * (lane >> 4);
+#pragma unroll
+  for (int t = 0; t < NF / 16; ++t)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dst[s * NF + 16 * t + rb + k] = f2bf(v[t][k]);
+}
+
+// dW[o][i] += sum over the 32 staged samples of dz[o][s] h[i][s], on MFMA with the
+// samples in the slot order of the header (slots 0..3 of group g: samples 4g + 0..3 of
+// the pair's first tile; slots 4..7: the same samples of its second tile).
+// acc: [no/16][ni/16] accumulator tiles.
 template <int NO, int NI>
-__device__ __forceinline__ void accum_wgrad(const f32x4 *dz, const f32x4 *h, float *zt, float *ht, int lane,
-                                            f32x4 (&acc)[NO / 16][NI / 16]) {
-  const int s = lane & 15, rb = 4 * (lane >> 4);
-#pragma unroll
-  for (int t = 0; t < NO / 16; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) zt[s * kH + 16 * t + rb + v] = dz[t][v];
-#pragma unroll
-  for (int t = 0; t < NI / 16; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) ht[s * kH + 16 * t + rb + v] = h[t][v];
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  // A[o][s] = dz[o][s]: lane holds o = 16mt + l%16, s = 4*(l/16)+j
-  // B[s][i] = h[i][s]: lane holds s = 4*(l/16)+j, i = 16nt + l%16
+__device__ __forceinline__ void wgrad_mfma(const unsigned short *zt, const unsigned short *ht, int lane,
+                                           f32x4 (&acc)[NO / 16][NI / 16]) {
+  const int rb = 4 * (lane >> 4);
 #pragma unroll
   for (int mt = 0; mt < NO / 16; ++mt) {
     const int o = 16 * mt + (lane & 15);
-    const bf16x4 a = pack4(zt[(rb + 0) * kH + o], zt[(rb + 1) * kH + o], zt[(rb + 2) * kH + o], zt[(rb + 3) * kH + o]);
+    s16x8 a;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      a[v] = (short)zt[(rb + v) * NO + o];
+      a[4 + v] = (short)zt[(16 + rb + v) * NO + o];
+    }
 #pragma unroll
     for (int nt = 0; nt < NI / 16; ++nt) {
       const int i = 16 * nt + (lane & 15);
-      const bf16x4 b = pack4(ht[(rb + 0) * kH + i], ht[(rb + 1) * kH + i], ht[(rb + 2) * kH + i], ht[(rb + 3) * kH + i]);
+      s16x8 b;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        b[v] = (short)ht[(rb + v) * NI + i];
+        b[4 + v] = (short)ht[(16 + rb + v) * NI + i];
+      }
       acc[mt][nt] = mfma(a, b, acc[mt][nt]);
     }
   }
+}
+
+__device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
@@ -289,15 +353,34 @@ __device__ __forceinline__ void store_acc(const f32x4 (&acc)[NO / 16][NI / 16], 
       }
 }
 
+// dH of a hidden layer from the next layer's dZ (two accumulator tiles per 32-chunk),
+// masked by the ReLU of its pre-activation: dz_out[t] = (W^T dz_in)[tile t] * (h > 0)
+__device__ __forceinline__ void back_hidden(const unsigned short *W, const f32x4 *dz_in, const f32x4 *h, int lane,
+                                            f32x4 *dz_out) {
+  s16x8 zb[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) zb[j] = pack8(dz_in[2 * j], dz_in[2 * j + 1]);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc = mfma(afragT(W, kH, 16 * t, 32 * j, lane), zb[j], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = h[t][v] > 0.f ? acc[v] : 0.f;
+    dz_out[t] = acc;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_mlp_grad(const float *w, const float *X, const float *T, long long n,
                                                   float *partial, float *loss_part) {
-  __shared__ GradLds G;
-  stage_weights(G.L, w);
+  extern __shared__ __align__(16) unsigned char g_lds[];
+  MlpLds &L = *reinterpret_cast<MlpLds *>(g_lds);
+  unsigned short *stage_base = reinterpret_cast<unsigned short *>(g_lds + sizeof(MlpLds));
+  stage_weights(L, w);
   __syncthreads();
-  const MlpLds &L = G.L;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int rb = 4 * (lane >> 4);
-  float *zt = G.zt[wv], *ht = G.ht[wv];
+  const WaveStage ws(stage_base + (size_t)wv * kWaveStage);
   f32x4 gW1[kH / 16][1], gW2[kH / 16][kH / 16], gW3[kH / 16][kH / 16], gW4[1][kH / 16];
   zero_acc<kH, 16>(gW1);
   zero_acc<kH, kH>(gW2);
@@ -309,92 +392,75 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *w, const float *X
   for (int v = 0; v < 4; ++v) gb4[v] = 0.f;
   float loss = 0.f;
   const float scale = 2.f / (float)(n * kOut);
-  const long long ntiles = (n + 15) / 16;
-  for (long long tile = (long long)blockIdx.x * 4 + wv; tile < ntiles; tile += (long long)gridDim.x * 4) {
-    const bf16x4 x = load_x(X, n, 16 * tile, lane, nullptr, nullptr);
-    Acts a;
-    forward_tile(L, x, lane, a);
-    const long long s = 16 * tile + (lane & 15);
-    const bool valid = s < n;
-    // dY (rows 0..2 live in lanes 0..15)
-    f32x4 dy = {0.f, 0.f, 0.f, 0.f};
+  const long long ntiles = (n + 15) / 16, npairs = (ntiles + 1) / 2;
+  // each wave takes pairs of 16-sample tiles; samples beyond n have dY = 0, so every
+  // gradient term they touch is zero
+  for (long long pr = (long long)blockIdx.x * 4 + wv; pr < npairs; pr += (long long)gridDim.x * 4) {
+    for (int q = 0; q < 2; ++q) {
+      const long long tile = 2 * pr + q;
+      f32x4 xa[1] = {load_xf(X, n, 16 * tile, lane, nullptr, nullptr)};
+      Acts a;
+      forward_tile(L, pack8_lo(xa[0]), lane, a);
+      const long long s = 16 * tile + (lane & 15);
+      const bool valid = s < n;
+      f32x4 dy[1] = {{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int o = rb + v;
-      if (o < kOut && valid) {
-        const float e = a.y[v] - T[s * kOut + o];
-        loss += e * e;
-        dy[v] = scale * e;
+      for (int v = 0; v < 4; ++v) {
+        const int o = rb + v;
+        if (o < kOut && valid) {
+          const float e = a.y[v] - T[s * kOut + o];
+          loss += e * e;
+          dy[0][v] = scale * e;
+        }
       }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) gb4[v] += dy[0][v];
+      stage_t<16>(dy, ws.z4, q, lane);
+      stage_t<kH>(a.h3, ws.h3, q, lane);
+      // dH3 = W4^T dY (a 16-wide contraction: W4 has 16 padded rows), masked by ReLU
+      f32x4 dz3[4];
+      const s16x8 dyb = pack8_lo(dy[0]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma(afragT<true>(L.W4, kH, 16 * t, 0, lane), dyb, acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = a.h3[t][v] > 0.f ? acc[v] : 0.f;
+        dz3[t] = acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gb3[t][v] += acc[v];
+      }
+      stage_t<kH>(dz3, ws.z3, q, lane);
+      stage_t<kH>(a.h2, ws.h2, q, lane);
+      f32x4 dz2[4];
+      back_hidden(L.W3, dz3, a.h2, lane, dz2);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gb2[t][v] += dz2[t][v];
+      stage_t<kH>(dz2, ws.z2, q, lane);
+      stage_t<kH>(a.h1, ws.h1, q, lane);
+      f32x4 dz1[4];
+      back_hidden(L.W2, dz2, a.h1, lane, dz1);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gb1[t][v] += dz1[t][v];
+      stage_t<kH>(dz1, ws.z1, q, lane);
+      stage_t<16>(xa, ws.x, q, lane);
     }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) gb4[v] += dy[v];
-    // gradient of W4: dy [16(3) x s] times h3^T
-    {
-      f32x4 dz4[1] = {dy};
-      accum_wgrad<16, kH>(dz4, a.h3, zt, ht, lane, gW4);
-    }
-    // dH3 = W4^T dY, masked by ReLU
-    const bf16x4 dyb = pack4(dy[0], dy[1], dy[2], dy[3]);
-    f32x4 dz3[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      acc = mfma(afragT(L.W4, kH, 16 * t, 0, lane), dyb, acc);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[v] = a.h3[t][v] > 0.f ? acc[v] : 0.f;
-      dz3[t] = acc;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) gb3[t][v] += acc[v];
-    }
-    accum_wgrad<kH, kH>(dz3, a.h2, zt, ht, lane, gW3);
-    bf16x4 zb[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) zb[t] = pack4(dz3[t][0], dz3[t][1], dz3[t][2], dz3[t][3]);
-    f32x4 dz2[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) acc = mfma(afragT(L.W3, kH, 16 * t, 16 * ks, lane), zb[ks], acc);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[v] = a.h2[t][v] > 0.f ? acc[v] : 0.f;
-      dz2[t] = acc;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) gb2[t][v] += acc[v];
-    }
-    accum_wgrad<kH, kH>(dz2, a.h1, zt, ht, lane, gW2);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) zb[t] = pack4(dz2[t][0], dz2[t][1], dz2[t][2], dz2[t][3]);
-    f32x4 dz1[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) acc = mfma(afragT(L.W2, kH, 16 * t, 16 * ks, lane), zb[ks], acc);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[v] = a.h1[t][v] > 0.f ? acc[v] : 0.f;
-      dz1[t] = acc;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) gb1[t][v] += acc[v];
-    }
-    // gradient of W1: dz1 [64 x s] times x^T (x in accumulator layout: features 4*(l/16)+v)
-    f32x4 xa[1];
-    {
-      const long long ss = 16 * tile + (lane & 15);
-      const int k = 4 * (lane >> 4);
-      f32x4 xv = {0.f, 0.f, 0.f, 0.f};
-      if (ss < n && k < kIn)
-        for (int j = 0; j < 4; ++j) xv[j] = X[ss * kIn + k + j];
-      xa[0] = xv;
-    }
-    accum_wgrad<kH, 16>(dz1, xa, zt, ht, lane, gW1);
+    wave_sync();
+    wgrad_mfma<16, kH>(ws.z4, ws.h3, lane, gW4);
+    wgrad_mfma<kH, kH>(ws.z3, ws.h2, lane, gW3);
+    wgrad_mfma<kH, kH>(ws.z2, ws.h1, lane, gW2);
+    wgrad_mfma<kH, 16>(ws.z1, ws.x, lane, gW1);
+    wave_sync();  // the next pair overwrites the stage
   }
   // ---- per-block reduction of the four waves (fixed order) into `partial` ----
   float *out = partial + (size_t)blockIdx.x * kMlpParams;
   // each wave writes its part to LDS scratch sequentially: reuse zt/ht as staging
   __syncthreads();
-  float *stage = &G.zt[0][0];  // 4 * 16 * 64 floats = 4096 >= one 64x64 matrix
+  float *stage = reinterpret_cast<float *>(stage_base);  // >= 4096 floats: one 64x64 matrix
   for (int w = 0; w < 4; ++w) {
     // W2 and W3 (64 x 64) through the stage, one matrix at a time
     for (int m = 0; m < 4; ++m) {
@@ -413,7 +479,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *w, const float *X
   }
   // biases: lanes hold features 16t + 4*(l/16) + v summed over their own sample column;
   // sum over the 16 sample lanes of each row group and over waves in a fixed order
-  float *bst = &G.ht[0][0];
+  float *bst = reinterpret_cast<float *>(stage_base) + 4096;  // 1024 floats after the matrix stage
   for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) bst[i] = 0.f;
   __syncthreads();
   for (int w = 0; w < 4; ++w) {
@@ -484,6 +550,20 @@ __global__ void k_adam(float *w, const float *g, float *m, float *v, long long n
 
 using namespace nsn;
 
+// the gradient kernel's LDS (above the 64 KB default) is enabled once per device
+static bool grad_lds_ready() {
+  static bool done[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+  if (!done[dev]) {
+    if (hipFuncSetAttribute((const void *)k_mlp_grad, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kGradLdsBytes) != hipSuccess)
+      return false;
+    done[dev] = true;
+  }
+  return true;
+}
+
 extern "C" {
 
 nsn_status nsn_mlp_forward(const float *w, const float *x, float *y, int64_t n, void *stream) {
@@ -505,10 +585,12 @@ nsn_status nsn_mlp_loss_grad(const float *w, const float *x, const float *t, int
   if (!w || !x || !t || !grad || !scratch || n <= 0) return NSN_EINVAL;
   float *partial = (float *)scratch;
   float *loss_part = partial + (size_t)kGradBlocks * kMlpParams;
-  const long long tiles = (n + 15) / 16;
-  const int blocks = (int)std::min<long long>((tiles + 3) / 4, kGradBlocks);
+  const long long pairs = ((n + 15) / 16 + 1) / 2;
+  const int blocks = (int)std::min<long long>((pairs + 3) / 4, kGradBlocks);
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(256), 0, st, w, x, t, (long long)n, partial, loss_part);
+  if (!grad_lds_ready()) return NSN_EDEVICE;
+  hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(256), kGradLdsBytes, st, w, x, t, (long long)n, partial,
+                     loss_part);
   if (hipGetLastError() != hipSuccess) return NSN_EDEVICE;
   hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, partial, loss_part, blocks, grad,
                      loss_out, 1.f / (float)(n * kOut));

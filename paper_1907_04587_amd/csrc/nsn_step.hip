@@ -1269,22 +1269,29 @@ __device__ __forceinline__ V3 contact_dir(const Ctx &c, int gc, const float *src
 // ---- J^T v in two passes: every element writes its contribution once (coalesced,
 // element-parallel), then every body sums the contributions of its elements in a
 // fixed order (deterministic, no atomics) ----
-__device__ __forceinline__ void joint_contrib(const Ctx &c, int jl, const float *src) {
+// v: the joint's six row values
+__device__ __forceinline__ void joint_contrib_vals(const Ctx &c, int jl, const float v[6]) {
   const int jg = c.E.jnt_off + jl;
-  const int r0 = row_joint(c.E, jl);
   const float *J = c.S.j_J + (size_t)72 * jg;
   float o[12];
 #pragma unroll
   for (int q = 0; q < 12; ++q) o[q] = 0.f;
 #pragma unroll
   for (int r = 0; r < 6; ++r) {
-    const float v = src[r0 + r];
 #pragma unroll
-    for (int q = 0; q < 12; ++q) o[q] += v * J[12 * r + q];
+    for (int q = 0; q < 12; ++q) o[q] += v[r] * J[12 * r + q];
   }
   float *dst = c.S.j_cj + (size_t)12 * jg;
 #pragma unroll
   for (int q = 0; q < 12; ++q) dst[q] = o[q];
+}
+
+__device__ __forceinline__ void joint_contrib(const Ctx &c, int jl, const float *src) {
+  const int r0 = row_joint(c.E, jl);
+  float v[6];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) v[r] = src[r0 + r];
+  joint_contrib_vals(c, jl, v);
 }
 
 // J^T z of a tet from its compressed rows J[18] (u_i, w_i per stretch row), written
@@ -2030,6 +2037,180 @@ __device__ __forceinline__ int pcr_resident(const Ctx &c, float *Y, int buf, int
 }
 
 // position update q = q^- + h G(q^k) u (Alg. 1; quaternion normalised every update)
+// ---------------------------------------------------------------------------
+// One-pass PCR.  The recurrences are those of the single-reduction form above, but
+// J^T z is carried in body space instead of being formed from z each iteration: with
+// Bz = J^T z and Bq = J^T (P q), the updates q' = w + beta q and z' = z - alpha P q'
+// give, by linearity,
+//     Bq' = J^T (P w) + beta Bq,      Bz' = Bz - alpha Bq',
+// so one element visit per iteration suffices: it applies the deferred row updates of
+// the last reduction, forms w = J H~^-1 Bz + C' z at the new z, and writes its
+// J^T (P w) contribution in the same visit, reading the element's Jacobian once per
+// iteration instead of twice.  The body pass sums those contributions, advances Bq and
+// Bz and applies H~^-1.  Bz starts as J^T z0 from an ordinary contribution pass, so
+// the first product (the record a dump step keeps) is the streaming form's.
+// ---------------------------------------------------------------------------
+// iterations between two re-formations of Bz from the rows (residual replacement)
+constexpr int kOnePassRefresh = 8;
+
+// Deferred row update: MODE 0 keeps the rows as the initialisation set them; 1 applies
+// x += alpha p, z -= alpha P q with the starting p and q; 2 first advances
+// p = z + beta p, q = w + beta q.  Returns z, q and P of the row.
+template <int MODE>
+__device__ __forceinline__ void fused_row(const DevScene &S, int row, float alpha, float beta, float &z, float &q,
+                                          float &P) {
+  P = S.row_P[row];
+  if (MODE == 0) {
+    z = S.row_z[row];
+    q = 0.f;
+    return;
+  }
+  float p = S.row_p[row];
+  q = S.row_q[row];
+  const float z0 = S.row_z[row], x = S.row_x[row];
+  if (MODE == 2) {
+    p = z0 + beta * p;
+    q = S.row_w[row] + beta * q;
+    S.row_p[row] = p;
+    S.row_q[row] = q;
+  }
+  S.row_x[row] = x + alpha * p;
+  z = z0 - alpha * (P * q);
+  S.row_z[row] = z;
+}
+
+// the product's row value w is stored (and, in the first visit, taken as q = A p0);
+// returns P w, the value the element's contribution carries
+template <int MODE>
+__device__ __forceinline__ float fused_finish(const DevScene &S, int row, float z, float w, float P, float &q,
+                                              double part[3]) {
+  S.row_w[row] = w;
+  if (MODE == 0) {
+    S.row_q[row] = w;
+    q = w;
+  }
+  mv_dots_reg(z, w, P, q, part);
+  return P * w;
+}
+
+template <int BS, int MODE>
+__device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int buf, int nel, float eps, float alpha,
+                                            float beta, double part[3]) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  for (int el = threadIdx.x; el < nel; el += BS) {
+    if (el < E.n_jnt) {
+      const int r0 = row_joint(E, el);
+      float z[6], q[6], P[6], jy[6], pw[6];
+#pragma unroll
+      for (int r = 0; r < 6; ++r) fused_row<MODE>(S, r0 + r, alpha, beta, z[r], q[r], P[r]);
+      joint_JY(c, el, Y, jy);
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        const float w = jy[r] + S.row_C[r0 + r] * z[r] + eps * z[r];
+        pw[r] = fused_finish<MODE>(S, r0 + r, z[r], w, P[r], q[r], part);
+      }
+      joint_contrib_vals(c, el, pw);
+    } else if (el < E.n_jnt + E.n_tet) {
+      const int tl = el - E.n_jnt, tg = E.tet_off + tl;
+      const int r0 = row_tet(E, tl);
+      float z[3], q[3], P[3], jy[3], pw[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) fused_row<MODE>(S, r0 + r, alpha, beta, z[r], q[r], P[r]);
+      float J[18];
+#pragma unroll
+      for (int m = 0; m < 18; ++m) J[m] = tJ(S, buf, m, tg);
+      tet_JY_core(E, J, S.t_ids[tg], Y, jy);
+      float Em[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) Em[k] = S.t_E[(size_t)k * S.NT + tg];
+      const V3 zz = mk(z[0], z[1], z[2]);
+      const V3 cz = sym_mul(Em, zz);
+      const float w0 = jy[0] + cz.x + eps * zz.x, w1 = jy[1] + cz.y + eps * zz.y, w2 = jy[2] + cz.z + eps * zz.z;
+      pw[0] = fused_finish<MODE>(S, r0, z[0], w0, P[0], q[0], part);
+      pw[1] = fused_finish<MODE>(S, r0 + 1, z[1], w1, P[1], q[1], part);
+      pw[2] = fused_finish<MODE>(S, r0 + 2, z[2], w2, P[2], q[2], part);
+      tet_contrib_core(c, J, pw, S.t_dst[tg]);
+    } else {
+      const int cl = el - E.n_jnt - E.n_tet, gc = E.con_off + cl;
+      const int r0 = row_con(E, cl);
+      float z[3], q[3], P[3], jy[3], pw[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) fused_row<MODE>(S, r0 + r, alpha, beta, z[r], q[r], P[r]);
+      const V3 n = mk(S.c_n[gc]);
+      const float al = S.c_alpha[(size_t)buf * S.NC + gc];
+      const int act = S.c_active[(size_t)buf * S.NC + gc];
+      contact_JY_core(c, Y, S.c_body[gc], n, mk(S.c_rA[gc]), mk(S.c_rB[gc]), al, act, jy);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const float w = jy[r] + S.row_C[r0 + r] * z[r] + eps * z[r];
+        pw[r] = fused_finish<MODE>(S, r0 + r, z[r], w, P[r], q[r], part);
+      }
+      S.c_cj[gc] = f4(contact_dir_core(n, al, act, pw[0], pw[1], pw[2]), 0.f);
+    }
+  }
+}
+
+// Body pass of the one-pass PCR: G = the summed contributions of the last visit.
+// MODE 0: Bz = G (= J^T z0); 1: Bq = G, Bz -= alpha Bq; 2: Bq = G + beta Bq,
+// Bz -= alpha Bq.  Then Y = H~^-1 Bz.  Residual replacement (every kOnePassRefresh
+// iterations): MODE 3 advances Bq only; after a contribution pass of the current z,
+// MODE 4 re-forms Bz = G - alpha Bq from it (G = J^T z) and applies H~^-1, so the
+// rounding gap between the carried Bz and J^T z cannot grow past that many updates.
+template <int MODE>
+__device__ __forceinline__ void fused_body(const Ctx &c, float *Y, float alpha, float beta, int tid, int BS) {
+  const EnvInfo &E = c.E;
+  const DevScene &S = c.S;
+  const int nb = E.n_rig + E.n_par;
+  for (int b = tid; b < nb; b += BS) {
+    if (b < E.n_rig) {
+      const int g = E.rig_off + b;
+      float v[6];
+      gather_rigid(c, g, v);
+      const int d = E.dof_off + 6 * b;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        if (MODE == 4) {
+          v[k] = v[k] - alpha * S.bq[d + k];
+        } else if (MODE > 0) {
+          const float bq = MODE == 1 ? v[k] : v[k] + beta * S.bq[d + k];
+          S.bq[d + k] = bq;
+          if (MODE == 3) continue;
+          v[k] = S.bz[d + k] - alpha * bq;
+        }
+        S.bz[d + k] = v[k];
+      }
+      if (MODE == 3) continue;
+      hinv_rigid(c, g, v);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) Y[6 * b + k] = v[k];
+    } else {
+      const int p = E.par_off + b - E.n_rig;
+      const V3 a = gather_particle(c, p);
+      float v[3] = {a.x, a.y, a.z};
+      const int d = E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (MODE == 4) {
+          v[k] = v[k] - alpha * S.bq[d + k];
+        } else if (MODE > 0) {
+          const float bq = MODE == 1 ? v[k] : v[k] + beta * S.bq[d + k];
+          S.bq[d + k] = bq;
+          if (MODE == 3) continue;
+          v[k] = S.bz[d + k] - alpha * bq;
+        }
+        S.bz[d + k] = v[k];
+      }
+      if (MODE == 3) continue;
+      const float4 H = S.p_H[p];
+      const int y = 6 * E.n_rig + 3 * (b - E.n_rig);
+      Y[y] = v[0] / H.x;
+      Y[y + 1] = v[1] / H.y;
+      Y[y + 2] = v[2] / H.z;
+    }
+  }
+}
+
 __device__ __forceinline__ void update_positions_body(const Ctx &c, int b) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
@@ -2747,6 +2928,56 @@ __global__ __launch_bounds__(BS) void k_newton(const DevScene *__restrict__ Sp, 
           resident = true;
         }
       }
+      if constexpr (!EXT && R < 0) {
+        // one-pass form (fused_visit / fused_body)
+        pcr_update_contrib<BS, true, EXT>(c, buf, nel, 0.f, 0.f, false);  // z0 = P b, x = 0, p = z0; J^T z0
+        __syncthreads();
+        fused_body<0>(c, Y, 0.f, 0.f, tid, BS);
+        __syncthreads();
+        double dots[3] = {0.0, 0.0, 0.0};
+        fused_visit<BS, 0>(c, Y, buf, nel, eps, 0.f, 0.f, dots);
+        block_sum3<BS>(dots, red);
+        if (k == A.dump_k)
+          for (int r = tid; r < nrows; r += BS) S.row_dump[R0 + r] = S.row_w[R0 + r];
+        double rho = dots[0], qs = dots[1];
+        const double rho_stop = kTauCR * rho;
+        float beta = 0.f;
+        for (int it = 0; it < A.cr_iters; ++it) {
+          if (!(rho > rho_stop) || !(rho > 0.0)) break;
+          if (!(qs > 0.0)) break;
+          const float alpha = (float)(rho / qs);
+          ++done;
+          if (it == A.cr_iters - 1) {  // the last update needs no further product
+            for (int r = tid; r < nrows; r += BS) {
+              const int row = R0 + r;
+              const float p = it > 0 ? S.row_z[row] + beta * S.row_p[row] : S.row_p[row];
+              S.row_x[row] += alpha * p;
+            }
+            break;
+          }
+          if (it == 0) {
+            fused_body<1>(c, Y, alpha, beta, tid, BS);
+          } else if (it % kOnePassRefresh == 0) {  // residual replacement of Bz
+            fused_body<3>(c, Y, alpha, beta, tid, BS);
+            __syncthreads();
+            contrib_pass<BS, EXT>(c, S.row_z, buf, nel, true);  // J^T z of the current z
+            __syncthreads();
+            fused_body<4>(c, Y, alpha, beta, tid, BS);
+          } else {
+            fused_body<2>(c, Y, alpha, beta, tid, BS);
+          }
+          __syncthreads();
+          dots[0] = dots[1] = dots[2] = 0.0;
+          if (it == 0) fused_visit<BS, 1>(c, Y, buf, nel, eps, alpha, beta, dots);
+          else fused_visit<BS, 2>(c, Y, buf, nel, eps, alpha, beta, dots);
+          block_sum3<BS>(dots, red);
+          const double b = dots[0] / rho;
+          qs = dots[1] + 2.0 * b * dots[2] + b * b * qs;
+          beta = (float)b;
+          rho = dots[0];
+        }
+        resident = true;
+      }
       if (!resident) {
         // Single-reduction form of the same recurrences: the matvec pass also sums
         // <w, P w> and <w, P q>, so that <q', P q'> of the next direction q' = w + beta q
@@ -2939,30 +3170,42 @@ template <int BS, bool EXT>
 constexpr int resident_slots() {
   return EXT ? 0 : (BS >= 1024 ? 0 : 2);
 }
+// PCR form of a launch: 0 streaming, 1 register-resident where the env fits, 2 one-pass
+constexpr int kFormStream = 0, kFormResident = 1, kFormOnePass = 2;
 
+// what: kLaunchAttr sets the kernel's dynamic-LDS limit (a call that must stay outside
+// a stream capture), kLaunchRun enqueues the launch; both by default.
 template <int BS, int LM, bool EXT, int RS>
-static void launch_one(const DevScene &s, const StepArgs &a, int first, int count, size_t bytes, hipStream_t st) {
-  if (bytes > 16384 * sizeof(float))
+static void launch_one(const DevScene &s, const StepArgs &a, int first, int count, size_t bytes, hipStream_t st,
+                       int what) {
+  if ((what & kLaunchAttr) && bytes > 16384 * sizeof(float))
     (void)hipFuncSetAttribute((const void *)k_newton<BS, LM, EXT, RS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)bytes);
-  hipLaunchKernelGGL((k_newton<BS, LM, EXT, RS>), dim3(count), dim3(BS), bytes, st, s.dev, a, first);
+  if (what & kLaunchRun)
+    hipLaunchKernelGGL((k_newton<BS, LM, EXT, RS>), dim3(count), dim3(BS), bytes, st, s.dev, a, first);
 }
 
 template <int BS, bool EXT>
 static void launch_bs(const DevScene &s, const StepArgs &a, int first, int count, int lds_floats, int lds_mode,
-                      int resident, hipStream_t st) {
+                      int resident, hipStream_t st, int what) {
   const size_t bytes = lds_mode > 0 ? sizeof(float) * (size_t)lds_floats : 0;
   constexpr int B2 = BS >= 128 ? BS : 128;  // mode 2 from 128 threads up
   constexpr int R2 = resident_slots<B2, EXT>(), R1 = resident_slots<BS, EXT>();
   if (lds_mode == 2 && BS >= 128) {
-    if (resident && R2 > 0) launch_one<B2, 2, EXT, R2>(s, a, first, count, bytes, st);
-    else launch_one<B2, 2, EXT, 0>(s, a, first, count, bytes, st);
+    if constexpr (!EXT)
+      if (resident == kFormOnePass) return launch_one<B2, 2, EXT, -1>(s, a, first, count, bytes, st, what);
+    if (resident == kFormResident && R2 > 0) launch_one<B2, 2, EXT, R2>(s, a, first, count, bytes, st, what);
+    else launch_one<B2, 2, EXT, 0>(s, a, first, count, bytes, st, what);
   } else if (lds_mode >= 1) {
-    if (resident && R1 > 0) launch_one<BS, 1, EXT, R1>(s, a, first, count, bytes, st);
-    else launch_one<BS, 1, EXT, 0>(s, a, first, count, bytes, st);
+    if constexpr (!EXT)
+      if (resident == kFormOnePass) return launch_one<BS, 1, EXT, -1>(s, a, first, count, bytes, st, what);
+    if (resident == kFormResident && R1 > 0) launch_one<BS, 1, EXT, R1>(s, a, first, count, bytes, st, what);
+    else launch_one<BS, 1, EXT, 0>(s, a, first, count, bytes, st, what);
   } else {
-    if (resident && R1 > 0) launch_one<BS, 0, EXT, R1>(s, a, first, count, 0, st);
-    else launch_one<BS, 0, EXT, 0>(s, a, first, count, 0, st);
+    if constexpr (!EXT)
+      if (resident == kFormOnePass) return launch_one<BS, 0, EXT, -1>(s, a, first, count, 0, st, what);
+    if (resident == kFormResident && R1 > 0) launch_one<BS, 0, EXT, R1>(s, a, first, count, 0, st, what);
+    else launch_one<BS, 0, EXT, 0>(s, a, first, count, 0, st, what);
   }
 }
 
@@ -2973,13 +3216,13 @@ constexpr bool kExtTU = false;
 #endif
 
 static hipError_t launch_tu(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
-                            int lds_mode, int resident, hipStream_t st) {
+                            int lds_mode, int resident, hipStream_t st, int what) {
   switch (block) {
-    case 64: launch_bs<64, kExtTU>(s, a, first, count, lds_floats, lds_mode, resident, st); break;
-    case 128: launch_bs<128, kExtTU>(s, a, first, count, lds_floats, lds_mode, resident, st); break;
-    case 256: launch_bs<256, kExtTU>(s, a, first, count, lds_floats, lds_mode, resident, st); break;
-    case 512: launch_bs<512, kExtTU>(s, a, first, count, lds_floats, lds_mode, resident, st); break;
-    case 1024: launch_bs<1024, kExtTU>(s, a, first, count, lds_floats, lds_mode, resident, st); break;
+    case 64: launch_bs<64, kExtTU>(s, a, first, count, lds_floats, lds_mode, resident, st, what); break;
+    case 128: launch_bs<128, kExtTU>(s, a, first, count, lds_floats, lds_mode, resident, st, what); break;
+    case 256: launch_bs<256, kExtTU>(s, a, first, count, lds_floats, lds_mode, resident, st, what); break;
+    case 512: launch_bs<512, kExtTU>(s, a, first, count, lds_floats, lds_mode, resident, st, what); break;
+    case 1024: launch_bs<1024, kExtTU>(s, a, first, count, lds_floats, lds_mode, resident, st, what); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -2987,8 +3230,8 @@ static hipError_t launch_tu(const DevScene &s, const StepArgs &a, int block, int
 
 #ifdef NSN_STEP_EXT_TU
 hipError_t launch_newton_ext(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
-                             int lds_mode, hipStream_t st) {
-  return launch_tu(s, a, block, first, count, lds_floats, lds_mode, 0, st);
+                             int lds_mode, hipStream_t st, int what) {
+  return launch_tu(s, a, block, first, count, lds_floats, lds_mode, 0, st, what);
 }
 #else
 hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_features, hipStream_t st) {
@@ -2997,11 +3240,11 @@ hipError_t launch_prepare(const DevScene &s, const StepArgs &a, int want_feature
 }
 
 hipError_t launch_newton(const DevScene &s, const StepArgs &a, int block, int first, int count, int lds_floats,
-                         int lds_mode, int resident, hipStream_t st) {
+                         int lds_mode, int resident, hipStream_t st, int what) {
   if (count <= 0) return hipSuccess;
   if (s.any_linear || (a.p.islands && a.p.linear == NSN_LINEAR_PCR))
-    return launch_newton_ext(s, a, block, first, count, lds_floats, lds_mode, st);
-  return launch_tu(s, a, block, first, count, lds_floats, lds_mode, resident, st);
+    return launch_newton_ext(s, a, block, first, count, lds_floats, lds_mode, st, what);
+  return launch_tu(s, a, block, first, count, lds_floats, lds_mode, resident, st, what);
 }
 #endif
 

@@ -58,9 +58,13 @@ class Scene:
     """A batch of environments on one GPU.
 
     envs: list of scene_inputs.EnvDesc; params: object with the SolverParams fields.
-    The device workspace is one torch uint8 tensor; the stream is torch's current
-    stream at creation (or `stream`).  reserve: extra parameter objects whose options
-    (islands, line search) the workspace must also hold, for later set_params calls."""
+    The device workspace is one torch uint8 tensor.  The scene runs on its own stream
+    (default priority) unless `stream` is given: steps are then captured once and
+    replayed from a hipGraph, and the launch buckets of a step run on streams forked
+    from it (the library launches directly, in order, on the null stream).  Calls that
+    return data synchronise that stream; torch work that reads scene memory must wait
+    for it.  reserve: extra parameter objects whose options (islands, line search) the
+    workspace must also hold, for later set_params calls."""
 
     def __init__(self, envs, params, device="cuda", stream=None, reserve=()):
         import torch
@@ -82,13 +86,15 @@ class Scene:
         self.workspace_bytes = int(nbytes.value)
         self.device = torch.device(device)
         self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.workspace.record_stream(self.stream)
         self._params = params
         h = C.c_void_p()
         L.check(self.lib.nsn_create_scene(m.c, self.n_envs, C.byref(pc), C.c_void_p(self.stream.cuda_stream),
                                           C.c_void_p(self.workspace.data_ptr()), self.workspace_bytes,
                                           C.byref(h)), "nsn_create_scene")
         self.h = h
+        self.use_graphs = self.stream.cuda_stream != 0
         if (pc.islands, pc.line_search) != (params_c(params).islands, params_c(params).line_search):
             self.set_params(params)
 
@@ -173,6 +179,7 @@ class Scene:
         n = C.c_size_t(0)
         L.check(self.lib.nsn_state_bytes(self.h, C.byref(n)), "nsn_state_bytes")
         buf = torch.empty(int(n.value), dtype=torch.uint8, device=self.device)
+        buf.record_stream(self.stream)
         L.check(self.lib.nsn_save_state(self.h, C.c_void_p(buf.data_ptr())), "nsn_save_state")
         return buf
 
@@ -229,6 +236,9 @@ class Scene:
 
     def set_use_graphs(self, on):
         L.check(self.lib.nsn_set_use_graphs(self.h, int(bool(on))), "nsn_set_use_graphs")
+        self.use_graphs = bool(on) and self.stream.cuda_stream != 0
+
+    use_graphs = True  # the library's default for a scene with its own stream
 
     def accumulators(self):
         out = np.zeros(self.n_envs, L.ACC_DTYPE)
@@ -264,10 +274,13 @@ class Scene:
         contributions in LDS where they fit (default).  Same results."""
         L.check(self.lib.nsn_set_lds_mode(self.h, int(max_mode)), "nsn_set_lds_mode")
 
+    pcr_form = 2  # the library's default
+
     def set_pcr_form(self, form):
-        """1: register-resident PCR where an env's elements fit (default); 0: streaming.
-        Same results."""
+        """0: streaming two-pass PCR; 1: register-resident where an env's elements fit
+        (results identical to 0); 2: one-pass (default) (nsn_set_pcr_form)."""
         L.check(self.lib.nsn_set_pcr_form(self.h, int(form)), "nsn_set_pcr_form")
+        self.pcr_form = int(form)
 
     def lds_modes(self):
         """LDS mode of every current bucket."""

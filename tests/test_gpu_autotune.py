@@ -61,8 +61,9 @@ def test_autotune_bench_batch_valid_not_slower_with_row_parity():
     sc = Scene(envs, p)
     for _ in range(2):
         sc.step(H, 50, 40, 1e-4)
-    default = [tuple(b) for b in sc.schedule()]
-    sched, report = autotune(sc, H, 50, 40, 1e-4, steps=1, rounds=1, log=print)
+    default, default_form = [tuple(b) for b in sc.schedule()], sc.pcr_form
+    sched, form, report = autotune(sc, H, 50, 40, 1e-4, steps=1, rounds=1, forms=(0, 1, 2), log=print)
+    assert form in (0, 1, 2) and sc.pcr_form == form
     # valid: consecutive buckets covering the launch order once, known block sizes
     at = 0
     for first, count, block in sched:
@@ -70,11 +71,12 @@ def test_autotune_bench_batch_valid_not_slower_with_row_parity():
         at += count
     assert at == len(envs)
     assert [tuple(b) for b in sc.schedule()] == [tuple(b) for b in sched]
-    assert {c["family"] for c in report} >= {"default", "tile", "wavefront"}
+    assert {c["family"] for c in report} >= {"default", "tile", "wavefront"} | {
+        f"pcr form {f}" for f in (0, 1, 2) if f != default_form}
     # not slower than the default on the same replayed steps (a timing-noise margin)
     snap = sc.save_state()
-    d, t = default_vs(sc, snap, sched, H, 50, 40, 1e-4, 2, default)
-    print(f"default {default}: {d:.1f} env-steps/s; tuned {sched}: {t:.1f} env-steps/s")
+    d, t = default_vs(sc, snap, sched, form, H, 50, 40, 1e-4, 2, default, default_form)
+    print(f"default {default} form {default_form}: {d:.1f} env-steps/s; tuned {sched} form {form}: {t:.1f}")
     assert t >= 0.97 * d
     # row parity on sampled envs of every bucket of the tuned schedule
     sc.set_schedule(sched)
