@@ -346,9 +346,10 @@ def main():
             return {"env_steps_ratio": round(ratio, 4),
                     "converged_env_steps_ratio": round(cratio, 4) if cratio is not None else None,
                     "newton_iters_ratio": round(r["mean_newton_iters"] / max(rp["mean_newton_iters"], 1e-30), 4),
-                    # beats: more env-steps/s reach the residual, by more than a 1% margin
-                    # over the run-to-run spread, at no loss of env-steps/s overall
-                    "beats": bool(cratio is not None and cratio > 1.01 and ratio > 0.99)}
+                    # beats: more env-steps/s reach the residual, by a 5% margin (the
+                    # converged counts of one arm move by about 3% between runs), at no
+                    # loss of env-steps/s overall (1%)
+                    "beats": bool(cratio is not None and cratio > 1.05 and ratio > 0.99)}
         verdict = {"learned_arm": head, "plain_arm": plain, **versus(results[plain]),
                    "per_plain_arm": {a: versus(results[a]) for a in plains}}
         verdict["beats_plain"] = verdict.pop("beats")

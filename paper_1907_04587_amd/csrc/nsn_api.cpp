@@ -152,7 +152,7 @@ void layout(const Sizes &z, int n_envs, const Options &opt, Arena &a, DevScene &
   S.feat = a.take<int2>(z.NF);
   S.t_ids = a.take<int4>(z.NT); S.t_Dminv = a.take<float>(9 * (size_t)z.NT); S.t_mat = a.take<float4>(z.NT);
   S.t_J = a.take<float>(2 * 18 * (size_t)z.NT); S.t_E = a.take<float>(6 * (size_t)z.NT);
-  S.t_dst = a.take<int4>(z.NT); S.p_cj = a.take<float4>(z.NTADJ);
+  S.t_dst = a.take<int4>(z.NT); S.p_cj = a.take<float4>(z.NTADJ); S.t_loc = a.take<uint4>(z.NT);
   S.j_info = a.take<int4>(z.NJ); S.j_frame = a.take<float4>(6 * (size_t)z.NJ);
   S.j_drive = a.take<float4>(2 * (size_t)z.NJ); S.j_theta0 = a.take<float>(z.NJ);
   S.j_J = a.take<float>(72 * (size_t)z.NJ);
@@ -541,6 +541,26 @@ nsn_status nsn_create_scene(const nsn_env_desc *envs, int32_t n_envs, const nsn_
   HIP_TRY(up((void *)S.p_tadj_ptr, tadj_ptr.data(), sizeof(int) * (z.NP + 1)));
   HIP_TRY(up((void *)S.p_tadj, tadj.data(), sizeof(int) * z.NTADJ));
   HIP_TRY(up((void *)S.t_dst, t_dst.data(), sizeof(int4) * z.NT));
+  {  // the same indices packed to 16 bits per field, env-local, for the one-pass PCR
+    std::vector<uint4> t_loc(std::max(z.NT, 1));
+    S.tet_loc = 1;
+    for (int e = 0; e < n_envs && S.tet_loc; ++e) {
+      const EnvInfo &E = env[e];
+      const int abase = tadj_ptr[E.par_off];
+      for (int t = E.tet_off; t < E.tet_off + E.n_tet; ++t) {
+        const int id[4] = {t_ids[t].x, t_ids[t].y, t_ids[t].z, t_ids[t].w};
+        const int ds[4] = {t_dst[t].x, t_dst[t].y, t_dst[t].z, t_dst[t].w};
+        unsigned w[4];
+        for (int k = 0; k < 4; ++k) {
+          const int l = id[k] - E.par_off, d = ds[k] - abase;
+          if (l < 0 || l > 0xffff || d < 0 || d > 0xffff) S.tet_loc = 0;
+          w[k] = (unsigned)(l & 0xffff) | ((unsigned)(d & 0xffff) << 16);
+        }
+        t_loc[t] = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    }
+    HIP_TRY(up((void *)S.t_loc, t_loc.data(), sizeof(uint4) * z.NT));
+  }
   HIP_TRY(up((void *)S.r_jadj_ptr, jadj_ptr.data(), sizeof(int) * (z.NR + 1)));
   HIP_TRY(up((void *)S.r_jadj, jadj.data(), sizeof(int) * z.NJADJ));
   HIP_TRY(up((void *)S.dev, &S, sizeof(DevScene)));  // the table itself, for the Newton kernel

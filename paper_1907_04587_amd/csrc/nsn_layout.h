@@ -75,6 +75,9 @@ struct DevScene {
                                    // linear tets: the rotation R (9, row-major)
   float *t_E;                      // 6 x NT : E / h^2 (xx yy zz xy xz yz); linear tets: normal block
   const int4 *t_dst;               // per tet: positions of its 4 slots in the particle lists
+  const uint4 *t_loc;              // per tet, vertex k: (env-local particle id) | (slot position
+                                   // from the env's first particle list entry) << 16
+  int tet_loc;                     // 1 if every env's ids and slot positions fit 16 bits
   float4 *p_cj;                    // NTADJ : J^T v of the tets, in particle-list order
 
   // joints

@@ -2050,8 +2050,11 @@ __device__ __forceinline__ int pcr_resident(const Ctx &c, float *Y, int buf, int
 // Bz and applies H~^-1.  Bz starts as J^T z0 from an ordinary contribution pass, so
 // the first product (the record a dump step keeps) is the streaming form's.
 // ---------------------------------------------------------------------------
-// iterations between two re-formations of Bz from the rows (residual replacement)
-constexpr int kOnePassRefresh = 8;
+// Bz is re-formed from the rows (residual replacement) once rho = <z, A z> has fallen
+// by this factor since Bz was last formed: the carried Bz's rounding gap grows with the
+// updates' size, the size of Bz (~ |z|) with the residual, so the gap relative to Bz
+// stays below about (updates since) x eps x 10.
+constexpr double kOnePassRefreshDrop = 1e-2;
 
 // Deferred row update: MODE 0 keeps the rows as the initialisation set them; 1 applies
 // x += alpha p, z -= alpha P q with the starting p and q; 2 first advances
@@ -2120,7 +2123,18 @@ __device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int bu
       float J[18];
 #pragma unroll
       for (int m = 0; m < 18; ++m) J[m] = tJ(S, buf, m, tg);
-      tet_JY_core(E, J, S.t_ids[tg], Y, jy);
+      int4 ids, dst;
+      if (S.tet_loc) {  // ids and slots from one 16-byte record (env-local, 16 bits each)
+        const uint4 L = S.t_loc[tg];
+        const int po = E.par_off, ab = c.cl_base;
+        ids = make_int4(po + (int)(L.x & 0xffffu), po + (int)(L.y & 0xffffu), po + (int)(L.z & 0xffffu),
+                        po + (int)(L.w & 0xffffu));
+        dst = make_int4(ab + (int)(L.x >> 16), ab + (int)(L.y >> 16), ab + (int)(L.z >> 16), ab + (int)(L.w >> 16));
+      } else {
+        ids = S.t_ids[tg];
+        dst = S.t_dst[tg];
+      }
+      tet_JY_core(E, J, ids, Y, jy);
       float Em[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) Em[k] = S.t_E[(size_t)k * S.NT + tg];
@@ -2130,7 +2144,7 @@ __device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int bu
       pw[0] = fused_finish<MODE>(S, r0, z[0], w0, P[0], q[0], part);
       pw[1] = fused_finish<MODE>(S, r0 + 1, z[1], w1, P[1], q[1], part);
       pw[2] = fused_finish<MODE>(S, r0 + 2, z[2], w2, P[2], q[2], part);
-      tet_contrib_core(c, J, pw, S.t_dst[tg]);
+      tet_contrib_core(c, J, pw, dst);
     } else {
       const int cl = el - E.n_jnt - E.n_tet, gc = E.con_off + cl;
       const int r0 = row_con(E, cl);
@@ -2153,10 +2167,9 @@ __device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int bu
 
 // Body pass of the one-pass PCR: G = the summed contributions of the last visit.
 // MODE 0: Bz = G (= J^T z0); 1: Bq = G, Bz -= alpha Bq; 2: Bq = G + beta Bq,
-// Bz -= alpha Bq.  Then Y = H~^-1 Bz.  Residual replacement (every kOnePassRefresh
-// iterations): MODE 3 advances Bq only; after a contribution pass of the current z,
-// MODE 4 re-forms Bz = G - alpha Bq from it (G = J^T z) and applies H~^-1, so the
-// rounding gap between the carried Bz and J^T z cannot grow past that many updates.
+// Bz -= alpha Bq.  Then Y = H~^-1 Bz.  Residual replacement (kOnePassRefreshDrop):
+// MODE 3 advances Bq only; after a contribution pass of the current z, MODE 4 re-forms
+// Bz = G - alpha Bq from it (G = J^T z) and applies H~^-1.
 template <int MODE>
 __device__ __forceinline__ void fused_body(const Ctx &c, float *Y, float alpha, float beta, int tid, int BS) {
   const EnvInfo &E = c.E;
@@ -2590,9 +2603,9 @@ __global__ __launch_bounds__(BS) void k_newton(const DevScene *__restrict__ Sp, 
   const double tplus = S.time[e] + (double)h;
   // env-local body-space vector: in LDS when the bucket's envs fit, else in global memory
   float *Y = LM > 0 ? y_lds : S.y + E.dof_off;
+  c.cl_base = sgpr(S.p_tadj_ptr[E.par_off]);  // the env's first particle-list entry
   if (LM == 2) {
     c.cl = y_lds + ((E.n_dof + 3) & ~3);
-    c.cl_base = sgpr(S.p_tadj_ptr[E.par_off]);
     c.cl_n = 4 * E.n_tet;
   }
 
@@ -2941,6 +2954,7 @@ __global__ __launch_bounds__(BS) void k_newton(const DevScene *__restrict__ Sp, 
           for (int r = tid; r < nrows; r += BS) S.row_dump[R0 + r] = S.row_w[R0 + r];
         double rho = dots[0], qs = dots[1];
         const double rho_stop = kTauCR * rho;
+        double rho_ref = rho;  // rho when Bz was last formed from the rows
         float beta = 0.f;
         for (int it = 0; it < A.cr_iters; ++it) {
           if (!(rho > rho_stop) || !(rho > 0.0)) break;
@@ -2957,7 +2971,8 @@ __global__ __launch_bounds__(BS) void k_newton(const DevScene *__restrict__ Sp, 
           }
           if (it == 0) {
             fused_body<1>(c, Y, alpha, beta, tid, BS);
-          } else if (it % kOnePassRefresh == 0) {  // residual replacement of Bz
+          } else if (rho <= kOnePassRefreshDrop * rho_ref) {  // residual replacement of Bz
+            rho_ref = rho;
             fused_body<3>(c, Y, alpha, beta, tid, BS);
             __syncthreads();
             contrib_pass<BS, EXT>(c, S.row_z, buf, nel, true);  // J^T z of the current z
