@@ -68,4 +68,37 @@ __device__ __forceinline__ float det3(const M3 &A) {
          A.m[2] * (A.m[3] * A.m[7] - A.m[4] * A.m[6]);
 }
 
+// ---- global-memory access through address-space-1 pointers ----
+// The scene's arrays are reached through pointers read from memory, which the compiler
+// cannot prove global: a plain access through them is a FLAT instruction, and a FLAT
+// load counts against the counter of LDS and scalar loads as well, so every wait for an
+// LDS read or a pointer reload also waits for the memory loads in flight.  gld / gst
+// issue GLOBAL instructions instead (same address, same data).
+#define NSN_GLOBAL __attribute__((address_space(1)))
+typedef float nsn_f4 __attribute__((ext_vector_type(4)));
+typedef int nsn_i4 __attribute__((ext_vector_type(4)));
+typedef unsigned nsn_u4 __attribute__((ext_vector_type(4)));
+typedef int nsn_i2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float gld(const float *p) { return *(const NSN_GLOBAL float *)p; }
+__device__ __forceinline__ int gld(const int *p) { return *(const NSN_GLOBAL int *)p; }
+__device__ __forceinline__ float4 gld(const float4 *p) {
+  const nsn_f4 v = *(const NSN_GLOBAL nsn_f4 *)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ int4 gld(const int4 *p) {
+  const nsn_i4 v = *(const NSN_GLOBAL nsn_i4 *)p;
+  return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint4 gld(const uint4 *p) {
+  const nsn_u4 v = *(const NSN_GLOBAL nsn_u4 *)p;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ int2 gld(const int2 *p) {
+  const nsn_i2 v = *(const NSN_GLOBAL nsn_i2 *)p;
+  return make_int2(v.x, v.y);
+}
+__device__ __forceinline__ void gst(float *p, float v) { *(NSN_GLOBAL float *)p = v; }
+__device__ __forceinline__ void gst(float4 *p, float4 v) { *(NSN_GLOBAL nsn_f4 *)p = nsn_f4{v.x, v.y, v.z, v.w}; }
+
 }  // namespace nsn

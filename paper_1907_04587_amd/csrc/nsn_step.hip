@@ -491,6 +491,14 @@ __device__ __forceinline__ void joint_rows(const Ctx &c, int jg, float *J, float
       for (int k = 6; k < 12; ++k) J[12 * r + k] = 0.f;
 }
 
+// symmetric 3x3 (xx yy zz xy xz yz) read from global memory, times v
+__device__ __forceinline__ V3 sym_mul_g(const float *s, V3 v) {
+  float m[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) m[k] = gld(s + k);
+  return sym_mul(m, v);
+}
+
 __device__ __forceinline__ float row_dot_rigid(const float *J6, const float *Y, int d) {
   return J6[0] * Y[d] + J6[1] * Y[d + 1] + J6[2] * Y[d + 2] + J6[3] * Y[d + 3] + J6[4] * Y[d + 4] +
          J6[5] * Y[d + 5];
@@ -872,7 +880,7 @@ __global__ __launch_bounds__(BS) void k_prepare(DevScene S, StepArgs A, int want
 // Newton kernel pieces
 // --------------------------------------------------------------------------
 __device__ __forceinline__ float tJ(const DevScene &S, int buf, int comp_, int tg) {
-  return S.t_J[((size_t)buf * 18 + comp_) * S.NT + tg];
+  return gld(S.t_J + ((size_t)buf * 18 + comp_) * S.NT + tg);
 }
 
 // ---- assembly (Sec. 6.1 eq. newton_system; Appendix A/B) ----
@@ -930,10 +938,10 @@ __device__ __forceinline__ void store_tet_cj(const Ctx &c, int4 dst, V3 a0, V3 a
     }
     return;
   }
-  c.S.p_cj[dst.x] = f4(a0, 0.f);
-  c.S.p_cj[dst.y] = f4(a1, 0.f);
-  c.S.p_cj[dst.z] = f4(a2, 0.f);
-  c.S.p_cj[dst.w] = f4(a3, 0.f);
+  gst(c.S.p_cj + dst.x, f4(a0, 0.f));
+  gst(c.S.p_cj + dst.y, f4(a1, 0.f));
+  gst(c.S.p_cj + dst.z, f4(a2, 0.f));
+  gst(c.S.p_cj + dst.w, f4(a3, 0.f));
 }
 
 __device__ __forceinline__ void ltet_load(const DevScene &S, int buf, int tg, float R[9], float B[9]) {
@@ -1259,8 +1267,9 @@ __device__ __forceinline__ V3 contact_dir_core(V3 n, float al, int active, float
 
 __device__ __forceinline__ V3 contact_dir(const Ctx &c, int gc, const float *src, int buf) {
   const int r0 = row_con(c.E, gc - c.E.con_off);
-  return contact_dir_core(mk(c.S.c_n[gc]), c.S.c_alpha[(size_t)buf * c.S.NC + gc],
-                          c.S.c_active[(size_t)buf * c.S.NC + gc], src[r0], src[r0 + 1], src[r0 + 2]);
+  return contact_dir_core(mk(gld(c.S.c_n + gc)), gld(c.S.c_alpha + (size_t)buf * c.S.NC + gc),
+                          gld(c.S.c_active + (size_t)buf * c.S.NC + gc), gld(src + r0), gld(src + r0 + 1),
+                          gld(src + r0 + 2));
 }
 
 
@@ -1279,18 +1288,18 @@ __device__ __forceinline__ void joint_contrib_vals(const Ctx &c, int jl, const f
 #pragma unroll
   for (int r = 0; r < 6; ++r) {
 #pragma unroll
-    for (int q = 0; q < 12; ++q) o[q] += v[r] * J[12 * r + q];
+    for (int q = 0; q < 12; ++q) o[q] += v[r] * gld(J + 12 * r + q);
   }
   float *dst = c.S.j_cj + (size_t)12 * jg;
 #pragma unroll
-  for (int q = 0; q < 12; ++q) dst[q] = o[q];
+  for (int q = 0; q < 12; ++q) gst(dst + q, o[q]);
 }
 
 __device__ __forceinline__ void joint_contrib(const Ctx &c, int jl, const float *src) {
   const int r0 = row_joint(c.E, jl);
   float v[6];
 #pragma unroll
-  for (int r = 0; r < 6; ++r) v[r] = src[r0 + r];
+  for (int r = 0; r < 6; ++r) v[r] = gld(src + r0 + r);
   joint_contrib_vals(c, jl, v);
 }
 
@@ -1317,7 +1326,7 @@ __device__ __forceinline__ void tet_contrib(const Ctx &c, int tl, const float z[
   float J[18];
 #pragma unroll
   for (int m = 0; m < 18; ++m) J[m] = tJ(S, buf, m, tg);
-  tet_contrib_core(c, J, z, S.t_dst[tg]);
+  tet_contrib_core(c, J, z, gld(S.t_dst + tg));
 }
 
 __device__ __forceinline__ void acc_wrench(float out[6], V3 d, V3 arm, float sgn) {
@@ -1331,43 +1340,44 @@ __device__ __forceinline__ void acc_wrench(float out[6], V3 d, V3 arm, float sgn
 __device__ __forceinline__ void gather_rigid(const Ctx &c, int g, float out[6]) {
   const DevScene &S = c.S;
   for (int k = 0; k < 6; ++k) out[k] = 0.f;
-  for (int k = S.r_jadj_ptr[g]; k < S.r_jadj_ptr[g + 1]; ++k) {
-    const int ent = S.r_jadj[k];
+  const int j1 = gld(S.r_jadj_ptr + g + 1);
+  for (int k = gld(S.r_jadj_ptr + g); k < j1; ++k) {
+    const int ent = gld(S.r_jadj + k);
     const float *o = S.j_cj + (size_t)12 * (ent >> 1) + 6 * (ent & 1);
 #pragma unroll
-    for (int q = 0; q < 6; ++q) out[q] += o[q];
+    for (int q = 0; q < 6; ++q) out[q] += gld(o + q);
   }
-  const int a1 = S.r_acon_end[g];
-  int gc = S.r_acon_beg[g];
+  const int a1 = gld(S.r_acon_end + g);
+  int gc = gld(S.r_acon_beg + g);
   for (; gc + 4 <= a1; gc += 4) {
     float4 d[4], r[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      d[m] = S.c_cj[gc + m];
-      r[m] = S.c_rA[gc + m];
+      d[m] = gld(S.c_cj + gc + m);
+      r[m] = gld(S.c_rA + gc + m);
     }
 #pragma unroll
     for (int m = 0; m < 4; ++m) acc_wrench(out, mk(d[m]), mk(r[m]), 1.f);
   }
-  for (; gc < a1; ++gc) acc_wrench(out, mk(S.c_cj[gc]), mk(S.c_rA[gc]), 1.f);
-  const int b0 = S.r_bcon_beg[g], bn = S.r_bcon_cnt[g];
+  for (; gc < a1; ++gc) acc_wrench(out, mk(gld(S.c_cj + gc)), mk(gld(S.c_rA + gc)), 1.f);
+  const int b0 = gld(S.r_bcon_beg + g), bn = gld(S.r_bcon_cnt + g);
   int k = 0;
   for (; k + 4 <= bn; k += 4) {
     int id[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) id[m] = S.bcon_list[b0 + k + m];
+    for (int m = 0; m < 4; ++m) id[m] = gld(S.bcon_list + b0 + k + m);
     float4 d[4], r[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      d[m] = S.c_cj[id[m]];
-      r[m] = S.c_rB[id[m]];
+      d[m] = gld(S.c_cj + id[m]);
+      r[m] = gld(S.c_rB + id[m]);
     }
 #pragma unroll
     for (int m = 0; m < 4; ++m) acc_wrench(out, mk(d[m]), mk(r[m]), -1.f);
   }
   for (; k < bn; ++k) {
-    const int id = S.bcon_list[b0 + k];
-    acc_wrench(out, mk(S.c_cj[id]), mk(S.c_rB[id]), -1.f);
+    const int id = gld(S.bcon_list + b0 + k);
+    acc_wrench(out, mk(gld(S.c_cj + id)), mk(gld(S.c_rB + id)), -1.f);
   }
 }
 
@@ -1376,7 +1386,7 @@ __device__ __forceinline__ void gather_rigid(const Ctx &c, int g, float out[6]) 
 __device__ __forceinline__ V3 gather_particle(const Ctx &c, int p) {
   const DevScene &S = c.S;
   V3 acc = mk(0.f, 0.f, 0.f);
-  const int k0 = S.p_tadj_ptr[p], k1 = S.p_tadj_ptr[p + 1];
+  const int k0 = gld(S.p_tadj_ptr + p), k1 = gld(S.p_tadj_ptr + p + 1);
   int k = k0;
   if (c.cl) {  // the same sums in the same order, from LDS
     const float *cx = c.cl, *cy = cx + c.cl_n, *cz = cy + c.cl_n;
@@ -1388,26 +1398,30 @@ __device__ __forceinline__ V3 gather_particle(const Ctx &c, int p) {
   for (; k + 8 <= k1; k += 8) {
     float4 v[8];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) v[m] = S.p_cj[k + m];
+    for (int m = 0; m < 8; ++m) v[m] = gld(S.p_cj + k + m);
 #pragma unroll
     for (int m = 0; m < 8; ++m) acc = acc + mk(v[m]);
   }
-  for (; k < k1; ++k) acc = acc + mk(S.p_cj[k]);
-  for (int gc = S.p_acon_beg[p]; gc < S.p_acon_end[p]; ++gc) acc = acc + mk(S.c_cj[gc]);
+  for (; k < k1; ++k) acc = acc + mk(gld(S.p_cj + k));
+  const int c1 = gld(S.p_acon_end + p);
+  for (int gc = gld(S.p_acon_beg + p); gc < c1; ++gc) acc = acc + mk(gld(S.c_cj + gc));
   return acc;
 }
 
 __device__ __forceinline__ void joint_JY(const Ctx &c, int jl, const float *Y, float jy[6]) {
   const EnvInfo &E = c.E;
   const int jg = E.jnt_off + jl;
-  const int4 info = c.S.j_info[jg];
+  const int4 info = gld(c.S.j_info + jg);
   const float *J = c.S.j_J + (size_t)72 * jg;
   const int dB = ldof(E, info.z - E.rig_off);
   const int dA = info.y >= 0 ? ldof(E, info.y - E.rig_off) : -1;
 #pragma unroll
   for (int r = 0; r < 6; ++r) {
-    float acc = row_dot_rigid(J + 12 * r + 6, Y, dB);
-    if (dA >= 0) acc += row_dot_rigid(J + 12 * r, Y, dA);
+    float Jr[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) Jr[q] = gld(J + 12 * r + q);
+    float acc = row_dot_rigid(Jr + 6, Y, dB);
+    if (dA >= 0) acc += row_dot_rigid(Jr, Y, dA);
     jy[r] = acc;
   }
 }
@@ -1434,7 +1448,7 @@ __device__ __forceinline__ void tet_JY(const Ctx &c, int tl, const float *Y, int
   float J[18];
 #pragma unroll
   for (int m = 0; m < 18; ++m) J[m] = tJ(S, buf, m, tg);
-  tet_JY_core(c.E, J, S.t_ids[tg], Y, jy);
+  tet_JY_core(c.E, J, gld(S.t_ids + tg), Y, jy);
 }
 
 __device__ __forceinline__ void contact_JY_core(const Ctx &c, const float *Y, int2 bd, V3 n, V3 rA, V3 rB, float al,
@@ -1455,8 +1469,8 @@ __device__ __forceinline__ void contact_JY_core(const Ctx &c, const float *Y, in
 __device__ __forceinline__ void contact_JY(const Ctx &c, int cl, const float *Y, int buf, float jy[3]) {
   const DevScene &S = c.S;
   const int gc = c.E.con_off + cl;
-  contact_JY_core(c, Y, S.c_body[gc], mk(S.c_n[gc]), mk(S.c_rA[gc]), mk(S.c_rB[gc]), S.c_alpha[(size_t)buf * S.NC + gc],
-                  S.c_active[(size_t)buf * S.NC + gc], jy);
+  contact_JY_core(c, Y, gld(S.c_body + gc), mk(gld(S.c_n + gc)), mk(gld(S.c_rA + gc)), mk(gld(S.c_rB + gc)),
+                  gld(S.c_alpha + (size_t)buf * S.NC + gc), gld(S.c_active + (size_t)buf * S.NC + gc), jy);
 }
 
 // J_i H~^-1 J_i^T of every row of an element (preconditioner diagonal without C, eps)
@@ -1566,10 +1580,10 @@ __device__ __forceinline__ void rhs_and_precond(const Ctx &c, const float *Y, in
 // thread's parts of <z, w>, <w, P w> and <w, P q> to part[0..2].  FIRST: also q = w
 // (initialisation of the PCR).
 __device__ __forceinline__ void mv_dots(const DevScene &S, int row, float z, float w, double part[3]) {
-  const float Pw = S.row_P[row] * w;
+  const float Pw = gld(S.row_P + row) * w;
   part[0] += (double)z * (double)w;
   part[1] += (double)w * (double)Pw;
-  part[2] += (double)Pw * (double)S.row_q[row];
+  part[2] += (double)Pw * (double)gld(S.row_q + row);
 }
 
 // Island mode (EXT, isl): every element stores its own three partial sums in el_dots
@@ -1587,10 +1601,10 @@ __device__ __forceinline__ void matvec_rows(const Ctx &c, const float *Y, int bu
       const int r0 = row_joint(E, el);
 #pragma unroll
       for (int r = 0; r < 6; ++r) {
-        const float z = S.row_z[r0 + r];
-        const float w = jy[r] + S.row_C[r0 + r] * z + eps * z;
-        S.row_w[r0 + r] = w;
-        if (FIRST) S.row_q[r0 + r] = w;
+        const float z = gld(S.row_z + r0 + r);
+        const float w = jy[r] + gld(S.row_C + r0 + r) * z + eps * z;
+        gst(S.row_w + r0 + r, w);
+        if (FIRST) gst(S.row_q + r0 + r, w);
         mv_dots(S, r0 + r, z, w, part);
       }
     } else if (EXT && el < E.n_jnt + E.n_tet && lin_tets(E)) {
@@ -1602,21 +1616,21 @@ __device__ __forceinline__ void matvec_rows(const Ctx &c, const float *Y, int bu
       const int r0 = row_tet(E, tl);
       float Em[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) Em[k] = S.t_E[(size_t)k * S.NT + tg];
-      const V3 z = mk(S.row_z[r0], S.row_z[r0 + 1], S.row_z[r0 + 2]);
+      for (int k = 0; k < 6; ++k) Em[k] = gld(S.t_E + (size_t)k * S.NT + tg);
+      const V3 z = mk(gld(S.row_z + r0), gld(S.row_z + r0 + 1), gld(S.row_z + r0 + 2));
       const V3 cz = sym_mul(Em, z);
       const float w0 = jy[0] + cz.x + eps * z.x, w1 = jy[1] + cz.y + eps * z.y, w2 = jy[2] + cz.z + eps * z.z;
-      S.row_w[r0] = w0; S.row_w[r0 + 1] = w1; S.row_w[r0 + 2] = w2;
-      if (FIRST) { S.row_q[r0] = w0; S.row_q[r0 + 1] = w1; S.row_q[r0 + 2] = w2; }
+      gst(S.row_w + r0, w0); gst(S.row_w + r0 + 1, w1); gst(S.row_w + r0 + 2, w2);
+      if (FIRST) { gst(S.row_q + r0, w0); gst(S.row_q + r0 + 1, w1); gst(S.row_q + r0 + 2, w2); }
       mv_dots(S, r0, z.x, w0, part);
       mv_dots(S, r0 + 1, z.y, w1, part);
       mv_dots(S, r0 + 2, z.z, w2, part);
 #pragma unroll
       for (int r = 3; r < 6; ++r) {
-        const float zr = S.row_z[r0 + r];
-        const float w = jy[r] + S.row_C[r0 + r] * zr + eps * zr;
-        S.row_w[r0 + r] = w;
-        if (FIRST) S.row_q[r0 + r] = w;
+        const float zr = gld(S.row_z + r0 + r);
+        const float w = jy[r] + gld(S.row_C + r0 + r) * zr + eps * zr;
+        gst(S.row_w + r0 + r, w);
+        if (FIRST) gst(S.row_q + r0 + r, w);
         mv_dots(S, r0 + r, zr, w, part);
       }
     } else if (el < E.n_jnt + E.n_tet) {
@@ -1627,12 +1641,12 @@ __device__ __forceinline__ void matvec_rows(const Ctx &c, const float *Y, int bu
       const int r0 = row_tet(E, tl);
       float Em[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) Em[k] = S.t_E[(size_t)k * S.NT + tg];
-      const V3 z = mk(S.row_z[r0], S.row_z[r0 + 1], S.row_z[r0 + 2]);
+      for (int k = 0; k < 6; ++k) Em[k] = gld(S.t_E + (size_t)k * S.NT + tg);
+      const V3 z = mk(gld(S.row_z + r0), gld(S.row_z + r0 + 1), gld(S.row_z + r0 + 2));
       const V3 cz = sym_mul(Em, z);
       const float w0 = jy[0] + cz.x + eps * z.x, w1 = jy[1] + cz.y + eps * z.y, w2 = jy[2] + cz.z + eps * z.z;
-      S.row_w[r0] = w0; S.row_w[r0 + 1] = w1; S.row_w[r0 + 2] = w2;
-      if (FIRST) { S.row_q[r0] = w0; S.row_q[r0 + 1] = w1; S.row_q[r0 + 2] = w2; }
+      gst(S.row_w + r0, w0); gst(S.row_w + r0 + 1, w1); gst(S.row_w + r0 + 2, w2);
+      if (FIRST) { gst(S.row_q + r0, w0); gst(S.row_q + r0 + 1, w1); gst(S.row_q + r0 + 2, w2); }
       mv_dots(S, r0, z.x, w0, part);
       mv_dots(S, r0 + 1, z.y, w1, part);
       mv_dots(S, r0 + 2, z.z, w2, part);
@@ -1643,10 +1657,10 @@ __device__ __forceinline__ void matvec_rows(const Ctx &c, const float *Y, int bu
       const int r0 = row_con(E, cl);
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
-        const float z = S.row_z[r0 + r];
-        const float w = jy[r] + S.row_C[r0 + r] * z + eps * z;
-        S.row_w[r0 + r] = w;
-        if (FIRST) S.row_q[r0 + r] = w;
+        const float z = gld(S.row_z + r0 + r);
+        const float w = jy[r] + gld(S.row_C + r0 + r) * z + eps * z;
+        gst(S.row_w + r0 + r, w);
+        if (FIRST) gst(S.row_q + r0 + r, w);
         mv_dots(S, r0 + r, z, w, part);
       }
     }
@@ -1659,12 +1673,12 @@ __device__ __forceinline__ void matvec_rows(const Ctx &c, const float *Y, int bu
 
 // H~^-1 applied to a rigid 6-vector (in place)
 __device__ __forceinline__ void hinv_rigid(const Ctx &c, int g, float v[6]) {
-  const float im = c.S.r_inertia[g].w;
+  const float im = gld(c.S.r_inertia + g).w;
   if (im == 0.f) {
     for (int k = 0; k < 6; ++k) v[k] = 0.f;
     return;
   }
-  const V3 a = sym_mul(c.S.r_Iwinv + 6 * g, mk(v[3], v[4], v[5]));
+  const V3 a = sym_mul_g(c.S.r_Iwinv + 6 * g, mk(v[3], v[4], v[5]));
   v[0] *= im; v[1] *= im; v[2] *= im;
   v[3] = a.x; v[4] = a.y; v[5] = a.z;
 }
@@ -1686,7 +1700,7 @@ __device__ __forceinline__ void gather_hinv(const Ctx &c, float *Y, int tid, int
     } else {
       const int p = E.par_off + b - E.n_rig;
       const V3 a = gather_particle(c, p);
-      const float4 H = S.p_H[p];
+      const float4 H = gld(S.p_H + p);
       const int d = 6 * E.n_rig + 3 * (b - E.n_rig);
       Y[d] = a.x / H.x;
       Y[d + 1] = a.y / H.y;
@@ -1706,16 +1720,18 @@ __device__ __forceinline__ void contrib_pass(const Ctx &c, const float *src, int
     } else if (EXT && el < E.n_jnt + E.n_tet && lin_tets(E)) {
       const int tl = el - E.n_jnt;
       const int r0 = row_tet(E, tl);
-      const float z[6] = {src[r0], src[r0 + 1], src[r0 + 2], src[r0 + 3], src[r0 + 4], src[r0 + 5]};
+      float z[6];
+#pragma unroll
+      for (int r = 0; r < 6; ++r) z[r] = gld(src + r0 + r);
       ltet_contrib(c, tl, z, buf);
     } else if (el < E.n_jnt + E.n_tet) {
       const int tl = el - E.n_jnt;
       const int r0 = row_tet(E, tl);
-      const float z[3] = {src[r0], src[r0 + 1], src[r0 + 2]};
+      const float z[3] = {gld(src + r0), gld(src + r0 + 1), gld(src + r0 + 2)};
       tet_contrib(c, tl, z, buf);
     } else {
       const int gc = E.con_off + el - E.n_jnt - E.n_tet;
-      c.S.c_cj[gc] = f4(contact_dir(c, gc, src, buf), 0.f);
+      gst(c.S.c_cj + gc, f4(contact_dir(c, gc, src, buf), 0.f));
     }
   }
 }
@@ -1726,23 +1742,23 @@ __device__ __forceinline__ void contrib_pass(const Ctx &c, const float *src, int
 template <bool INIT>
 __device__ __forceinline__ float pcr_row(const DevScene &S, int row, float alpha, float beta, bool upd) {
   if (INIT) {
-    const float z = S.row_P[row] * S.row_b[row];
-    S.row_x[row] = 0.f;
-    S.row_z[row] = z;
-    S.row_p[row] = z;
+    const float z = gld(S.row_P + row) * gld(S.row_b + row);
+    gst(S.row_x + row, 0.f);
+    gst(S.row_z + row, z);
+    gst(S.row_p + row, z);
     return z;
   }
-  float p = S.row_p[row], q = S.row_q[row];
-  const float z0 = S.row_z[row], P = S.row_P[row], x = S.row_x[row];
+  float p = gld(S.row_p + row), q = gld(S.row_q + row);
+  const float z0 = gld(S.row_z + row), P = gld(S.row_P + row), x = gld(S.row_x + row);
   if (upd) {
     p = z0 + beta * p;
-    q = S.row_w[row] + beta * q;
-    S.row_p[row] = p;
-    S.row_q[row] = q;
+    q = gld(S.row_w + row) + beta * q;
+    gst(S.row_p + row, p);
+    gst(S.row_q + row, q);
   }
-  S.row_x[row] = x + alpha * p;
+  gst(S.row_x + row, x + alpha * p);
   const float z = z0 - alpha * (P * q);
-  S.row_z[row] = z;
+  gst(S.row_z + row, z);
   return z;
 }
 
@@ -1776,14 +1792,14 @@ __device__ __forceinline__ void pcr_update_contrib(const Ctx &c, int buf, int ne
       const int r0 = row_tet(E, tl);
       float z[6];
 #pragma unroll
-      for (int r = 0; r < 6; ++r) z[r] = act ? pcr_row<INIT>(S, r0 + r, alpha, beta, upd) : S.row_z[r0 + r];
+      for (int r = 0; r < 6; ++r) z[r] = act ? pcr_row<INIT>(S, r0 + r, alpha, beta, upd) : gld(S.row_z + r0 + r);
       ltet_contrib(c, tl, z, buf);
     } else if (el < E.n_jnt + E.n_tet) {
       const int tl = el - E.n_jnt;
       const int r0 = row_tet(E, tl);
       float z[3];
 #pragma unroll
-      for (int r = 0; r < 3; ++r) z[r] = act ? pcr_row<INIT>(S, r0 + r, alpha, beta, upd) : S.row_z[r0 + r];
+      for (int r = 0; r < 3; ++r) z[r] = act ? pcr_row<INIT>(S, r0 + r, alpha, beta, upd) : gld(S.row_z + r0 + r);
       tet_contrib(c, tl, z, buf);
     } else {
       const int cl = el - E.n_jnt - E.n_tet;
@@ -1793,7 +1809,7 @@ __device__ __forceinline__ void pcr_update_contrib(const Ctx &c, int buf, int ne
         for (int r = 0; r < 3; ++r) pcr_row<INIT>(S, r0 + r, alpha, beta, upd);
       }
       const int gc = E.con_off + cl;
-      S.c_cj[gc] = f4(contact_dir(c, gc, S.row_z, buf), 0.f);
+      gst(S.c_cj + gc, f4(contact_dir(c, gc, S.row_z, buf), 0.f));
     }
   }
 }
@@ -1824,9 +1840,9 @@ __device__ __forceinline__ void resident_contrib(const Ctx &c, int el, int buf, 
   } else {
     const int gc = E.con_off + el - E.n_jnt - E.n_tet;
     const DevScene &S = c.S;
-    S.c_cj[gc] = f4(contact_dir_core(mk(S.c_n[gc]), S.c_alpha[(size_t)buf * S.NC + gc],
-                                     S.c_active[(size_t)buf * S.NC + gc], z[0], z[1], z[2]),
-                    0.f);
+    gst(S.c_cj + gc, f4(contact_dir_core(mk(gld(S.c_n + gc)), gld(S.c_alpha + (size_t)buf * S.NC + gc),
+                                         gld(S.c_active + (size_t)buf * S.NC + gc), z[0], z[1], z[2]),
+                        0.f));
   }
 }
 
@@ -1841,7 +1857,7 @@ __device__ __forceinline__ void resident_matvec(const Ctx &c, int el, int buf, c
     tet_JY(c, tl, Y, buf, jy);
     float Em[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) Em[k] = S.t_E[(size_t)k * S.NT + tg];
+    for (int k = 0; k < 6; ++k) Em[k] = gld(S.t_E + (size_t)k * S.NT + tg);
     const V3 zz = mk(z[0], z[1], z[2]);
     const V3 cz = sym_mul(Em, zz);
     w[0] = jy[0] + cz.x + eps * zz.x;
@@ -1852,7 +1868,7 @@ __device__ __forceinline__ void resident_matvec(const Ctx &c, int el, int buf, c
     contact_JY(c, cl, Y, buf, jy);
     const int r0 = row_con(E, cl);
 #pragma unroll
-    for (int r = 0; r < 3; ++r) w[r] = jy[r] + S.row_C[r0 + r] * z[r] + eps * z[r];
+    for (int r = 0; r < 3; ++r) w[r] = jy[r] + gld(S.row_C + r0 + r) * z[r] + eps * z[r];
   }
 }
 
@@ -1869,10 +1885,10 @@ __device__ __forceinline__ void joint_matvec_mem(const Ctx &c, int jl, const flo
   const int r0 = row_joint(c.E, jl);
 #pragma unroll
   for (int r = 0; r < 6; ++r) {
-    const float zz = S.row_z[r0 + r];
-    const float ww = jy[r] + S.row_C[r0 + r] * zz + eps * zz;
-    S.row_w[r0 + r] = ww;
-    if (first) S.row_q[r0 + r] = ww;
+    const float zz = gld(S.row_z + r0 + r);
+    const float ww = jy[r] + gld(S.row_C + r0 + r) * zz + eps * zz;
+    gst(S.row_w + r0 + r, ww);
+    if (first) gst(S.row_q + r0 + r, ww);
     mv_dots(S, r0 + r, zz, ww, part);
   }
 }
@@ -2062,24 +2078,24 @@ constexpr double kOnePassRefreshDrop = 1e-2;
 template <int MODE>
 __device__ __forceinline__ void fused_row(const DevScene &S, int row, float alpha, float beta, float &z, float &q,
                                           float &P) {
-  P = S.row_P[row];
+  P = gld(S.row_P + row);
   if (MODE == 0) {
-    z = S.row_z[row];
+    z = gld(S.row_z + row);
     q = 0.f;
     return;
   }
-  float p = S.row_p[row];
-  q = S.row_q[row];
-  const float z0 = S.row_z[row], x = S.row_x[row];
+  float p = gld(S.row_p + row);
+  q = gld(S.row_q + row);
+  const float z0 = gld(S.row_z + row), x = gld(S.row_x + row);
   if (MODE == 2) {
     p = z0 + beta * p;
-    q = S.row_w[row] + beta * q;
-    S.row_p[row] = p;
-    S.row_q[row] = q;
+    q = gld(S.row_w + row) + beta * q;
+    gst(S.row_p + row, p);
+    gst(S.row_q + row, q);
   }
-  S.row_x[row] = x + alpha * p;
+  gst(S.row_x + row, x + alpha * p);
   z = z0 - alpha * (P * q);
-  S.row_z[row] = z;
+  gst(S.row_z + row, z);
 }
 
 // the product's row value w is stored (and, in the first visit, taken as q = A p0);
@@ -2087,9 +2103,9 @@ __device__ __forceinline__ void fused_row(const DevScene &S, int row, float alph
 template <int MODE>
 __device__ __forceinline__ float fused_finish(const DevScene &S, int row, float z, float w, float P, float &q,
                                               double part[3]) {
-  S.row_w[row] = w;
+  gst(S.row_w + row, w);
   if (MODE == 0) {
-    S.row_q[row] = w;
+    gst(S.row_q + row, w);
     q = w;
   }
   mv_dots_reg(z, w, P, q, part);
@@ -2110,7 +2126,7 @@ __device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int bu
       joint_JY(c, el, Y, jy);
 #pragma unroll
       for (int r = 0; r < 6; ++r) {
-        const float w = jy[r] + S.row_C[r0 + r] * z[r] + eps * z[r];
+        const float w = jy[r] + gld(S.row_C + r0 + r) * z[r] + eps * z[r];
         pw[r] = fused_finish<MODE>(S, r0 + r, z[r], w, P[r], q[r], part);
       }
       joint_contrib_vals(c, el, pw);
@@ -2125,19 +2141,19 @@ __device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int bu
       for (int m = 0; m < 18; ++m) J[m] = tJ(S, buf, m, tg);
       int4 ids, dst;
       if (S.tet_loc) {  // ids and slots from one 16-byte record (env-local, 16 bits each)
-        const uint4 L = S.t_loc[tg];
+        const uint4 L = gld(S.t_loc + tg);
         const int po = E.par_off, ab = c.cl_base;
         ids = make_int4(po + (int)(L.x & 0xffffu), po + (int)(L.y & 0xffffu), po + (int)(L.z & 0xffffu),
                         po + (int)(L.w & 0xffffu));
         dst = make_int4(ab + (int)(L.x >> 16), ab + (int)(L.y >> 16), ab + (int)(L.z >> 16), ab + (int)(L.w >> 16));
       } else {
-        ids = S.t_ids[tg];
-        dst = S.t_dst[tg];
+        ids = gld(S.t_ids + tg);
+        dst = gld(S.t_dst + tg);
       }
       tet_JY_core(E, J, ids, Y, jy);
       float Em[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) Em[k] = S.t_E[(size_t)k * S.NT + tg];
+      for (int k = 0; k < 6; ++k) Em[k] = gld(S.t_E + (size_t)k * S.NT + tg);
       const V3 zz = mk(z[0], z[1], z[2]);
       const V3 cz = sym_mul(Em, zz);
       const float w0 = jy[0] + cz.x + eps * zz.x, w1 = jy[1] + cz.y + eps * zz.y, w2 = jy[2] + cz.z + eps * zz.z;
@@ -2151,16 +2167,16 @@ __device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int bu
       float z[3], q[3], P[3], jy[3], pw[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) fused_row<MODE>(S, r0 + r, alpha, beta, z[r], q[r], P[r]);
-      const V3 n = mk(S.c_n[gc]);
-      const float al = S.c_alpha[(size_t)buf * S.NC + gc];
-      const int act = S.c_active[(size_t)buf * S.NC + gc];
-      contact_JY_core(c, Y, S.c_body[gc], n, mk(S.c_rA[gc]), mk(S.c_rB[gc]), al, act, jy);
+      const V3 n = mk(gld(S.c_n + gc));
+      const float al = gld(S.c_alpha + (size_t)buf * S.NC + gc);
+      const int act = gld(S.c_active + (size_t)buf * S.NC + gc);
+      contact_JY_core(c, Y, gld(S.c_body + gc), n, mk(gld(S.c_rA + gc)), mk(gld(S.c_rB + gc)), al, act, jy);
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
-        const float w = jy[r] + S.row_C[r0 + r] * z[r] + eps * z[r];
+        const float w = jy[r] + gld(S.row_C + r0 + r) * z[r] + eps * z[r];
         pw[r] = fused_finish<MODE>(S, r0 + r, z[r], w, P[r], q[r], part);
       }
-      S.c_cj[gc] = f4(contact_dir_core(n, al, act, pw[0], pw[1], pw[2]), 0.f);
+      gst(S.c_cj + gc, f4(contact_dir_core(n, al, act, pw[0], pw[1], pw[2]), 0.f));
     }
   }
 }
@@ -2184,14 +2200,14 @@ __device__ __forceinline__ void fused_body(const Ctx &c, float *Y, float alpha, 
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         if (MODE == 4) {
-          v[k] = v[k] - alpha * S.bq[d + k];
+          v[k] = v[k] - alpha * gld(S.bq + d + k);
         } else if (MODE > 0) {
-          const float bq = MODE == 1 ? v[k] : v[k] + beta * S.bq[d + k];
-          S.bq[d + k] = bq;
+          const float bq = MODE == 1 ? v[k] : v[k] + beta * gld(S.bq + d + k);
+          gst(S.bq + d + k, bq);
           if (MODE == 3) continue;
-          v[k] = S.bz[d + k] - alpha * bq;
+          v[k] = gld(S.bz + d + k) - alpha * bq;
         }
-        S.bz[d + k] = v[k];
+        gst(S.bz + d + k, v[k]);
       }
       if (MODE == 3) continue;
       hinv_rigid(c, g, v);
@@ -2205,17 +2221,17 @@ __device__ __forceinline__ void fused_body(const Ctx &c, float *Y, float alpha, 
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         if (MODE == 4) {
-          v[k] = v[k] - alpha * S.bq[d + k];
+          v[k] = v[k] - alpha * gld(S.bq + d + k);
         } else if (MODE > 0) {
-          const float bq = MODE == 1 ? v[k] : v[k] + beta * S.bq[d + k];
-          S.bq[d + k] = bq;
+          const float bq = MODE == 1 ? v[k] : v[k] + beta * gld(S.bq + d + k);
+          gst(S.bq + d + k, bq);
           if (MODE == 3) continue;
-          v[k] = S.bz[d + k] - alpha * bq;
+          v[k] = gld(S.bz + d + k) - alpha * bq;
         }
-        S.bz[d + k] = v[k];
+        gst(S.bz + d + k, v[k]);
       }
       if (MODE == 3) continue;
-      const float4 H = S.p_H[p];
+      const float4 H = gld(S.p_H + p);
       const int y = 6 * E.n_rig + 3 * (b - E.n_rig);
       Y[y] = v[0] / H.x;
       Y[y + 1] = v[1] / H.y;
@@ -2964,8 +2980,8 @@ __global__ __launch_bounds__(BS) void k_newton(const DevScene *__restrict__ Sp, 
           if (it == A.cr_iters - 1) {  // the last update needs no further product
             for (int r = tid; r < nrows; r += BS) {
               const int row = R0 + r;
-              const float p = it > 0 ? S.row_z[row] + beta * S.row_p[row] : S.row_p[row];
-              S.row_x[row] += alpha * p;
+              const float p = it > 0 ? gld(S.row_z + row) + beta * gld(S.row_p + row) : gld(S.row_p + row);
+              gst(S.row_x + row, gld(S.row_x + row) + alpha * p);
             }
             break;
           }
@@ -3019,8 +3035,8 @@ __global__ __launch_bounds__(BS) void k_newton(const DevScene *__restrict__ Sp, 
           if (it == A.cr_iters - 1) {  // the last update needs no further product
             for (int r = tid; r < nrows; r += BS) {
               const int row = R0 + r;
-              const float p = it > 0 ? S.row_z[row] + beta * S.row_p[row] : S.row_p[row];
-              S.row_x[row] += alpha * p;
+              const float p = it > 0 ? gld(S.row_z + row) + beta * gld(S.row_p + row) : gld(S.row_p + row);
+              gst(S.row_x + row, gld(S.row_x + row) + alpha * p);
             }
             break;
           }
