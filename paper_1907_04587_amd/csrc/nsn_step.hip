@@ -1671,6 +1671,17 @@ __device__ __forceinline__ void matvec_rows(const Ctx &c, const float *Y, int bu
   }
 }
 
+// H~^-1 applied to a rigid 6-vector (in place), given 1/m and the world inverse inertia
+__device__ __forceinline__ void hinv_rigid_vals(float im, const float Iwinv[6], float v[6]) {
+  if (im == 0.f) {
+    for (int k = 0; k < 6; ++k) v[k] = 0.f;
+    return;
+  }
+  const V3 a = sym_mul(Iwinv, mk(v[3], v[4], v[5]));
+  v[0] *= im; v[1] *= im; v[2] *= im;
+  v[3] = a.x; v[4] = a.y; v[5] = a.z;
+}
+
 // H~^-1 applied to a rigid 6-vector (in place)
 __device__ __forceinline__ void hinv_rigid(const Ctx &c, int g, float v[6]) {
   const float im = gld(c.S.r_inertia + g).w;
@@ -2074,26 +2085,45 @@ constexpr double kOnePassRefreshDrop = 1e-2;
 
 // Deferred row update: MODE 0 keeps the rows as the initialisation set them; 1 applies
 // x += alpha p, z -= alpha P q with the starting p and q; 2 first advances
-// p = z + beta p, q = w + beta q.  Returns z, q and P of the row.
+// p = z + beta p, q = w + beta q.  An element visit reads all its rows (and its
+// element data) before it writes any: the row arrays are reached through pointers the
+// compiler cannot separate, so a load placed after a store waits for it, and a visit
+// that interleaved them would pay one memory round trip per row.
+struct RowIn {
+  float P, z, p, q, x, w;
+};
+
 template <int MODE>
-__device__ __forceinline__ void fused_row(const DevScene &S, int row, float alpha, float beta, float &z, float &q,
-                                          float &P) {
-  P = gld(S.row_P + row);
+__device__ __forceinline__ void fused_row_load(const DevScene &S, int row, RowIn &v) {
+  v.P = gld(S.row_P + row);
+  v.z = gld(S.row_z + row);
+  if (MODE == 0) return;
+  v.p = gld(S.row_p + row);
+  v.q = gld(S.row_q + row);
+  v.x = gld(S.row_x + row);
+  if (MODE == 2) v.w = gld(S.row_w + row);
+}
+
+// applies the update to the loaded values and stores them; returns z, q and P
+template <int MODE>
+__device__ __forceinline__ void fused_row(const DevScene &S, int row, const RowIn &v, float alpha, float beta,
+                                          float &z, float &q, float &P) {
+  P = v.P;
   if (MODE == 0) {
-    z = gld(S.row_z + row);
+    z = v.z;
     q = 0.f;
     return;
   }
-  float p = gld(S.row_p + row);
-  q = gld(S.row_q + row);
-  const float z0 = gld(S.row_z + row), x = gld(S.row_x + row);
+  float p = v.p;
+  q = v.q;
+  const float z0 = v.z;
   if (MODE == 2) {
     p = z0 + beta * p;
-    q = gld(S.row_w + row) + beta * q;
+    q = v.w + beta * q;
     gst(S.row_p + row, p);
     gst(S.row_q + row, q);
   }
-  gst(S.row_x + row, x + alpha * p);
+  gst(S.row_x + row, v.x + alpha * p);
   z = z0 - alpha * (P * q);
   gst(S.row_z + row, z);
 }
@@ -2120,13 +2150,19 @@ __device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int bu
   for (int el = threadIdx.x; el < nel; el += BS) {
     if (el < E.n_jnt) {
       const int r0 = row_joint(E, el);
-      float z[6], q[6], P[6], jy[6], pw[6];
+      float z[6], q[6], P[6], jy[6], pw[6], C[6];
+      RowIn v[6];
 #pragma unroll
-      for (int r = 0; r < 6; ++r) fused_row<MODE>(S, r0 + r, alpha, beta, z[r], q[r], P[r]);
+      for (int r = 0; r < 6; ++r) {
+        fused_row_load<MODE>(S, r0 + r, v[r]);
+        C[r] = gld(S.row_C + r0 + r);
+      }
+#pragma unroll
+      for (int r = 0; r < 6; ++r) fused_row<MODE>(S, r0 + r, v[r], alpha, beta, z[r], q[r], P[r]);
       joint_JY(c, el, Y, jy);
 #pragma unroll
       for (int r = 0; r < 6; ++r) {
-        const float w = jy[r] + gld(S.row_C + r0 + r) * z[r] + eps * z[r];
+        const float w = jy[r] + C[r] * z[r] + eps * z[r];
         pw[r] = fused_finish<MODE>(S, r0 + r, z[r], w, P[r], q[r], part);
       }
       joint_contrib_vals(c, el, pw);
@@ -2134,8 +2170,9 @@ __device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int bu
       const int tl = el - E.n_jnt, tg = E.tet_off + tl;
       const int r0 = row_tet(E, tl);
       float z[3], q[3], P[3], jy[3], pw[3];
+      RowIn v[3];
 #pragma unroll
-      for (int r = 0; r < 3; ++r) fused_row<MODE>(S, r0 + r, alpha, beta, z[r], q[r], P[r]);
+      for (int r = 0; r < 3; ++r) fused_row_load<MODE>(S, r0 + r, v[r]);
       float J[18];
 #pragma unroll
       for (int m = 0; m < 18; ++m) J[m] = tJ(S, buf, m, tg);
@@ -2150,10 +2187,12 @@ __device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int bu
         ids = gld(S.t_ids + tg);
         dst = gld(S.t_dst + tg);
       }
-      tet_JY_core(E, J, ids, Y, jy);
       float Em[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) Em[k] = gld(S.t_E + (size_t)k * S.NT + tg);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) fused_row<MODE>(S, r0 + r, v[r], alpha, beta, z[r], q[r], P[r]);
+      tet_JY_core(E, J, ids, Y, jy);
       const V3 zz = mk(z[0], z[1], z[2]);
       const V3 cz = sym_mul(Em, zz);
       const float w0 = jy[0] + cz.x + eps * zz.x, w1 = jy[1] + cz.y + eps * zz.y, w2 = jy[2] + cz.z + eps * zz.z;
@@ -2164,16 +2203,24 @@ __device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int bu
     } else {
       const int cl = el - E.n_jnt - E.n_tet, gc = E.con_off + cl;
       const int r0 = row_con(E, cl);
-      float z[3], q[3], P[3], jy[3], pw[3];
+      float z[3], q[3], P[3], jy[3], pw[3], C[3];
+      RowIn v[3];
 #pragma unroll
-      for (int r = 0; r < 3; ++r) fused_row<MODE>(S, r0 + r, alpha, beta, z[r], q[r], P[r]);
+      for (int r = 0; r < 3; ++r) {
+        fused_row_load<MODE>(S, r0 + r, v[r]);
+        C[r] = gld(S.row_C + r0 + r);
+      }
       const V3 n = mk(gld(S.c_n + gc));
       const float al = gld(S.c_alpha + (size_t)buf * S.NC + gc);
       const int act = gld(S.c_active + (size_t)buf * S.NC + gc);
-      contact_JY_core(c, Y, gld(S.c_body + gc), n, mk(gld(S.c_rA + gc)), mk(gld(S.c_rB + gc)), al, act, jy);
+      const int2 bd = gld(S.c_body + gc);
+      const V3 rA = mk(gld(S.c_rA + gc)), rB = mk(gld(S.c_rB + gc));
+#pragma unroll
+      for (int r = 0; r < 3; ++r) fused_row<MODE>(S, r0 + r, v[r], alpha, beta, z[r], q[r], P[r]);
+      contact_JY_core(c, Y, bd, n, rA, rB, al, act, jy);
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
-        const float w = jy[r] + gld(S.row_C + r0 + r) * z[r] + eps * z[r];
+        const float w = jy[r] + C[r] * z[r] + eps * z[r];
         pw[r] = fused_finish<MODE>(S, r0 + r, z[r], w, P[r], q[r], part);
       }
       gst(S.c_cj + gc, f4(contact_dir_core(n, al, act, pw[0], pw[1], pw[2]), 0.f));
@@ -2194,44 +2241,57 @@ __device__ __forceinline__ void fused_body(const Ctx &c, float *Y, float alpha, 
   for (int b = tid; b < nb; b += BS) {
     if (b < E.n_rig) {
       const int g = E.rig_off + b;
-      float v[6];
+      float v[6], oq[6], oz[6], Iw[6];
       gather_rigid(c, g, v);
       const int d = E.dof_off + 6 * b;
+      // every load before the first store (see fused_row_load)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        oq[k] = MODE >= 2 ? gld(S.bq + d + k) : 0.f;
+        oz[k] = MODE == 1 || MODE == 2 ? gld(S.bz + d + k) : 0.f;
+        Iw[k] = MODE == 3 ? 0.f : gld(S.r_Iwinv + 6 * g + k);
+      }
+      const float im = MODE == 3 ? 0.f : gld(S.r_inertia + g).w;
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         if (MODE == 4) {
-          v[k] = v[k] - alpha * gld(S.bq + d + k);
+          v[k] = v[k] - alpha * oq[k];
         } else if (MODE > 0) {
-          const float bq = MODE == 1 ? v[k] : v[k] + beta * gld(S.bq + d + k);
+          const float bq = MODE == 1 ? v[k] : v[k] + beta * oq[k];
           gst(S.bq + d + k, bq);
           if (MODE == 3) continue;
-          v[k] = gld(S.bz + d + k) - alpha * bq;
+          v[k] = oz[k] - alpha * bq;
         }
         gst(S.bz + d + k, v[k]);
       }
       if (MODE == 3) continue;
-      hinv_rigid(c, g, v);
+      hinv_rigid_vals(im, Iw, v);
 #pragma unroll
       for (int k = 0; k < 6; ++k) Y[6 * b + k] = v[k];
     } else {
       const int p = E.par_off + b - E.n_rig;
       const V3 a = gather_particle(c, p);
-      float v[3] = {a.x, a.y, a.z};
+      float v[3] = {a.x, a.y, a.z}, oq[3], oz[3];
       const int d = E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
+        oq[k] = MODE >= 2 ? gld(S.bq + d + k) : 0.f;
+        oz[k] = MODE == 1 || MODE == 2 ? gld(S.bz + d + k) : 0.f;
+      }
+      const float4 H = MODE == 3 ? make_float4(1.f, 1.f, 1.f, 0.f) : gld(S.p_H + p);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
         if (MODE == 4) {
-          v[k] = v[k] - alpha * gld(S.bq + d + k);
+          v[k] = v[k] - alpha * oq[k];
         } else if (MODE > 0) {
-          const float bq = MODE == 1 ? v[k] : v[k] + beta * gld(S.bq + d + k);
+          const float bq = MODE == 1 ? v[k] : v[k] + beta * oq[k];
           gst(S.bq + d + k, bq);
           if (MODE == 3) continue;
-          v[k] = gld(S.bz + d + k) - alpha * bq;
+          v[k] = oz[k] - alpha * bq;
         }
         gst(S.bz + d + k, v[k]);
       }
       if (MODE == 3) continue;
-      const float4 H = gld(S.p_H + p);
       const int y = 6 * E.n_rig + 3 * (b - E.n_rig);
       Y[y] = v[0] / H.x;
       Y[y + 1] = v[1] / H.y;
