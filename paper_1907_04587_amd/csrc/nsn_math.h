@@ -99,6 +99,16 @@ __device__ __forceinline__ int2 gld(const int2 *p) {
   return make_int2(v.x, v.y);
 }
 __device__ __forceinline__ void gst(float *p, float v) { *(NSN_GLOBAL float *)p = v; }
+__device__ __forceinline__ void gst(int *p, int v) { *(NSN_GLOBAL int *)p = v; }
 __device__ __forceinline__ void gst(float4 *p, float4 v) { *(NSN_GLOBAL nsn_f4 *)p = nsn_f4{v.x, v.y, v.z, v.w}; }
+
+
+// symmetric 3x3 (xx yy zz xy xz yz) read from global memory, times v
+__device__ __forceinline__ V3 sym_mul_g(const float *s, V3 v) {
+  float m[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) m[k] = gld(s + k);
+  return sym_mul(m, v);
+}
 
 }  // namespace nsn

@@ -335,14 +335,14 @@ __device__ __forceinline__ V3 body_point(const Ctx &c, int body, V3 loc) {
   if (body < 0) return loc;
   if (body < c.E.n_rig) {
     const int g = c.E.rig_off + body;
-    return mk(c.S.r_x[g]) + mul(quat_mat(c.S.r_q[g]), loc);
+    return mk(gld(c.S.r_x + g)) + mul(quat_mat(gld(c.S.r_q + g)), loc);
   }
-  return mk(c.S.p_x[c.E.par_off + body - c.E.n_rig]);
+  return mk(gld(c.S.p_x + c.E.par_off + body - c.E.n_rig));
 }
 
 __device__ __forceinline__ V3 body_arm(const Ctx &c, int body, V3 loc) {
   if (body < 0 || body >= c.E.n_rig) return mk(0.f, 0.f, 0.f);
-  return mul(quat_mat(c.S.r_q[c.E.rig_off + body]), loc);
+  return mul(quat_mat(gld(c.S.r_q + c.E.rig_off + body)), loc);
 }
 
 __device__ __forceinline__ bool rigid_static(const Ctx &c, int body) {
@@ -356,9 +356,9 @@ __device__ __forceinline__ V3 point_vel(const Ctx &c, const float *rvec, const f
   if (body < c.E.n_rig) {
     const int g = c.E.rig_off + body;
     const float *u = rvec + 6 * g;
-    return mk(u[0], u[1], u[2]) + cross(mk(u[3], u[4], u[5]), arm);
+    return mk(gld(u), gld(u + 1), gld(u + 2)) + cross(mk(gld(u + 3), gld(u + 4), gld(u + 5)), arm);
   }
-  return mk(pvec[c.E.par_off + body - c.E.n_rig]);
+  return mk(gld(pvec + c.E.par_off + body - c.E.n_rig));
 }
 
 // env-local dof index of an env-local body (body-space vectors Y are per env)
@@ -379,17 +379,17 @@ __device__ __forceinline__ float effmass_dir(const Ctx &c, int body, V3 arm, V3 
   if (body < 0) return 0.f;
   if (body < c.E.n_rig) {
     const int g = c.E.rig_off + body;
-    const float im = c.S.r_inertia[g].w;
+    const float im = gld(c.S.r_inertia + g).w;
     if (im == 0.f) return 0.f;
     const V3 ad = cross(arm, dir);
-    return im * dot(dir, dir) + dot(ad, sym_mul(c.S.r_Iwinv + 6 * g, ad));
+    return im * dot(dir, dir) + dot(ad, sym_mul_g(c.S.r_Iwinv + 6 * g, ad));
   }
   const int p = c.E.par_off + body - c.E.n_rig;
   if (use_H) {
-    const float4 H = c.S.p_H[p];
+    const float4 H = gld(c.S.p_H + p);
     return dir.x * dir.x / H.x + dir.y * dir.y / H.y + dir.z * dir.z / H.z;
   }
-  return dot(dir, dir) / c.S.p_m[p];
+  return dot(dir, dir) / gld(c.S.p_m + p);
 }
 
 // --------------------------------------------------------------------------
@@ -491,24 +491,16 @@ __device__ __forceinline__ void joint_rows(const Ctx &c, int jg, float *J, float
       for (int k = 6; k < 12; ++k) J[12 * r + k] = 0.f;
 }
 
-// symmetric 3x3 (xx yy zz xy xz yz) read from global memory, times v
-__device__ __forceinline__ V3 sym_mul_g(const float *s, V3 v) {
-  float m[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) m[k] = gld(s + k);
-  return sym_mul(m, v);
-}
-
 __device__ __forceinline__ float row_dot_rigid(const float *J6, const float *Y, int d) {
   return J6[0] * Y[d] + J6[1] * Y[d + 1] + J6[2] * Y[d + 2] + J6[3] * Y[d + 3] + J6[4] * Y[d + 4] +
          J6[5] * Y[d + 5];
 }
 
 __device__ __forceinline__ float rigid_quad(const Ctx &c, int g, const float *J6) {
-  const float im = c.S.r_inertia[g].w;
+  const float im = gld(c.S.r_inertia + g).w;
   if (im == 0.f) return 0.f;
   const V3 l = mk(J6[0], J6[1], J6[2]), a = mk(J6[3], J6[4], J6[5]);
-  return im * dot(l, l) + dot(a, sym_mul(c.S.r_Iwinv + 6 * g, a));
+  return im * dot(l, l) + dot(a, sym_mul_g(c.S.r_Iwinv + 6 * g, a));
 }
 
 // --------------------------------------------------------------------------
@@ -1099,12 +1091,22 @@ __device__ __forceinline__ void assemble_tet(const Ctx &c, int tl, int buf, bool
   const float h = c.A.h;
   const int NT = S.NT;
   const int tg = E.tet_off + tl;
-  const int4 id = S.t_ids[tg];
+  const int4 id = gld(S.t_ids + tg);
   M3 Dmi;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) Dmi.m[k] = S.t_Dminv[(size_t)k * NT + tg];
-  const V3 x0 = mk(S.p_x[id.x]);
-  const V3 e1 = mk(S.p_x[id.y]) - x0, e2 = mk(S.p_x[id.z]) - x0, e3 = mk(S.p_x[id.w]) - x0;
+  for (int k = 0; k < 9; ++k) Dmi.m[k] = gld(S.t_Dminv + (size_t)k * NT + tg);
+  const V3 x0 = mk(gld(S.p_x + id.x));
+  const V3 e1 = mk(gld(S.p_x + id.y)) - x0, e2 = mk(gld(S.p_x + id.z)) - x0, e3 = mk(gld(S.p_x + id.w)) - x0;
+  // the tet's remaining inputs, read before its first store (see RowIn)
+  const int r0 = row_tet(E, tl);
+  float4 mt = make_float4(0.f, 0.f, 0.f, 0.f);
+  float lam0[3] = {0.f, 0.f, 0.f};
+  if (!(EXT && lin_tets(E))) {
+    mt = gld(S.t_mat + tg);  // (Ve, C1, D1, alpha)
+    if (!stress_only)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) lam0[r] = gld(S.row_lam + r0 + r);
+  }
   M3 Ds = {{e1.x, e2.x, e3.x, e1.y, e2.y, e3.y, e1.z, e2.z, e3.z}};
   M3 F;
 #pragma unroll
@@ -1124,14 +1126,13 @@ __device__ __forceinline__ void assemble_tet(const Ctx &c, int tl, int buf, bool
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const V3 u = col(U, i), w = mul(Dmi, col(V, i));
-    Jb[(size_t)(6 * i + 0) * NT + tg] = u.x;
-    Jb[(size_t)(6 * i + 1) * NT + tg] = u.y;
-    Jb[(size_t)(6 * i + 2) * NT + tg] = u.z;
-    Jb[(size_t)(6 * i + 3) * NT + tg] = w.x;
-    Jb[(size_t)(6 * i + 4) * NT + tg] = w.y;
-    Jb[(size_t)(6 * i + 5) * NT + tg] = w.z;
+    gst(Jb + (size_t)(6 * i + 0) * NT + tg, u.x);
+    gst(Jb + (size_t)(6 * i + 1) * NT + tg, u.y);
+    gst(Jb + (size_t)(6 * i + 2) * NT + tg, u.z);
+    gst(Jb + (size_t)(6 * i + 3) * NT + tg, w.x);
+    gst(Jb + (size_t)(6 * i + 4) * NT + tg, w.y);
+    gst(Jb + (size_t)(6 * i + 5) * NT + tg, w.z);
   }
-  const float4 mt = S.t_mat[tg];  // (Ve, C1, D1, alpha)
   const float Ve = mt.x, C1 = mt.y, D1 = mt.z, al = mt.w;
   // stable neo-Hookean (Appendix B) in principal stretches
   const float J = s[0] * s[1] * s[2];
@@ -1141,10 +1142,9 @@ __device__ __forceinline__ void assemble_tet(const Ctx &c, int tl, int buf, bool
   if (stress_only) {
     // warm start: the stress of the start configuration in its own principal basis,
     // lambda0 = -V_e dPsi/ds (multipliers of the previous step live in another basis)
-    const int r0 = row_tet(E, tl);
-    S.row_lam[r0] = -Ve * gr[0];
-    S.row_lam[r0 + 1] = -Ve * gr[1];
-    S.row_lam[r0 + 2] = -Ve * gr[2];
+    gst(S.row_lam + r0, -Ve * gr[0]);
+    gst(S.row_lam + r0 + 1, -Ve * gr[1]);
+    gst(S.row_lam + r0 + 2, -Ve * gr[2]);
     return;
   }
   const float k0 = 2.f * J - al;
@@ -1173,18 +1173,17 @@ __device__ __forceinline__ void assemble_tet(const Ctx &c, int tl, int buf, bool
       Em[k] = Q.m[3 * ia[k]] * Q.m[3 * ib[k]] * iw0 + Q.m[3 * ia[k] + 1] * Q.m[3 * ib[k] + 1] * iw1 +
               Q.m[3 * ia[k] + 2] * Q.m[3 * ib[k] + 2] * iw2;
   }
-  const int r0 = row_tet(E, tl);
-  const V3 cl = mk(Ve * gr[0] + S.row_lam[r0], Ve * gr[1] + S.row_lam[r0 + 1], Ve * gr[2] + S.row_lam[r0 + 2]);
+  const V3 cl = mk(Ve * gr[0] + lam0[0], Ve * gr[1] + lam0[1], Ve * gr[2] + lam0[2]);
   const V3 Ecl = sym_mul(Em, cl);
   const float ih = 1.f / h, ih2 = 1.f / (h * h);
-  S.row_err[r0] = Ecl.x * ih;
-  S.row_err[r0 + 1] = Ecl.y * ih;
-  S.row_err[r0 + 2] = Ecl.z * ih;
-  S.row_C[r0] = Em[0] * ih2;
-  S.row_C[r0 + 1] = Em[1] * ih2;
-  S.row_C[r0 + 2] = Em[2] * ih2;
+  gst(S.row_err + r0, Ecl.x * ih);
+  gst(S.row_err + r0 + 1, Ecl.y * ih);
+  gst(S.row_err + r0 + 2, Ecl.z * ih);
+  gst(S.row_C + r0, Em[0] * ih2);
+  gst(S.row_C + r0 + 1, Em[1] * ih2);
+  gst(S.row_C + r0 + 2, Em[2] * ih2);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) S.t_E[(size_t)k * NT + tg] = Em[k] * ih2;
+  for (int k = 0; k < 6; ++k) gst(S.t_E + (size_t)k * NT + tg, Em[k] * ih2);
 }
 
 __device__ __forceinline__ void assemble_contact(const Ctx &c, int cl, int buf) {
@@ -1192,14 +1191,12 @@ __device__ __forceinline__ void assemble_contact(const Ctx &c, int cl, int buf) 
   const DevScene &S = c.S;
   const float h = c.A.h;
   const int gc = E.con_off + cl;
-  const int2 bd = S.c_body[gc];
-  const float4 n4 = S.c_n[gc];
+  const int2 bd = gld(S.c_body + gc);
+  const float4 n4 = gld(S.c_n + gc);
   const V3 n = mk(n4);
-  const V3 aL = mk(S.c_aL[gc]), bL = mk(S.c_bL[gc]);
+  const V3 aL = mk(gld(S.c_aL + gc)), bL = mk(gld(S.c_bL + gc));
   const V3 armA = body_arm(c, bd.x, aL);
   const V3 armB = bd.y >= 0 ? body_arm(c, bd.y, bL) : mk(0.f, 0.f, 0.f);
-  S.c_rA[gc] = f4(armA, 0.f);
-  S.c_rB[gc] = f4(armB, 0.f);
   const V3 pa = body_point(c, bd.x, aL);
   const V3 pb = bd.y >= 0 ? body_point(c, bd.y, bL) : bL;
   const float Cn = dot(n, pa - pb) - n4.w;
@@ -1219,13 +1216,10 @@ __device__ __forceinline__ void assemble_contact(const Ctx &c, int cl, int buf) 
     r_f = h * 0.5f * (A1 + A2);
   }
   const int r0 = row_con(E, cl);
-  const float lam_n = S.row_lam[r0], lf1 = S.row_lam[r0 + 1], lf2 = S.row_lam[r0 + 2];
+  const float lam_n = gld(S.row_lam + r0), lf1 = gld(S.row_lam + r0 + 1), lf2 = gld(S.row_lam + r0 + 2);
   float phi, al, be;
   if (c.A.p.ncp == NSN_NCP_MIN) ncp_min(Cn, lam_n, r_n, phi, al, be);
   else ncp_fb(Cn, lam_n, r_n, phi, al, be);
-  S.c_alpha[(size_t)buf * S.NC + gc] = al;
-  S.row_C[r0] = be * r_n / (h * h);
-  S.row_err[r0] = phi / h;
   float v1 = 0.f, v2 = 0.f, W = __builtin_huge_valf();
   if (E.mu * lam_n > 0.f) {
     const V3 vr = point_vel(c, S.r_u, S.p_u, bd.x, armA) -
@@ -1237,19 +1231,25 @@ __device__ __forceinline__ void assemble_contact(const Ctx &c, int cl, int buf) 
     W = friction_w(c.A.p.ncp, vn, lam_n, lfn, E.mu, r_f);
   }
   const bool active = W < __builtin_huge_valf();
-  S.c_active[(size_t)buf * S.NC + gc] = active ? 1 : 0;
+  // every input is read: the stores follow (see RowIn)
+  gst(S.c_rA + gc, f4(armA, 0.f));
+  gst(S.c_rB + gc, f4(armB, 0.f));
+  gst(S.c_alpha + (size_t)buf * S.NC + gc, al);
+  gst(S.row_C + r0, be * r_n / (h * h));
+  gst(S.row_err + r0, phi / h);
+  gst(S.c_active + (size_t)buf * S.NC + gc, active ? 1 : 0);
   if (active) {
-    S.row_C[r0 + 1] = W / h;
-    S.row_C[r0 + 2] = W / h;
-    S.row_err[r0 + 1] = v1 + W * lf1;
-    S.row_err[r0 + 2] = v2 + W * lf2;
+    gst(S.row_C + r0 + 1, W / h);
+    gst(S.row_C + r0 + 2, W / h);
+    gst(S.row_err + r0 + 1, v1 + W * lf1);
+    gst(S.row_err + r0 + 2, v2 + W * lf2);
   } else {
     // READING: inactive friction rows (mu lam_n <= 0, or W infinite) are removed
     // (zero J); compliance r_f/h and error r_f lambda_f drive their multipliers to zero
-    S.row_C[r0 + 1] = r_f / h;
-    S.row_C[r0 + 2] = r_f / h;
-    S.row_err[r0 + 1] = r_f * lf1;
-    S.row_err[r0 + 2] = r_f * lf2;
+    gst(S.row_C + r0 + 1, r_f / h);
+    gst(S.row_C + r0 + 2, r_f / h);
+    gst(S.row_err + r0 + 1, r_f * lf1);
+    gst(S.row_err + r0 + 2, r_f * lf2);
   }
 }
 
@@ -1476,12 +1476,15 @@ __device__ __forceinline__ void contact_JY(const Ctx &c, int cl, const float *Y,
 // J_i H~^-1 J_i^T of every row of an element (preconditioner diagonal without C, eps)
 __device__ __forceinline__ void joint_hdiag(const Ctx &c, int jl, float dg[6]) {
   const int jg = c.E.jnt_off + jl;
-  const int4 info = c.S.j_info[jg];
+  const int4 info = gld(c.S.j_info + jg);
   const float *J = c.S.j_J + (size_t)72 * jg;
 #pragma unroll
   for (int r = 0; r < 6; ++r) {
-    float acc = rigid_quad(c, info.z, J + 12 * r + 6);
-    if (info.y >= 0) acc += rigid_quad(c, info.y, J + 12 * r);
+    float Jr[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) Jr[q] = gld(J + 12 * r + q);
+    float acc = rigid_quad(c, info.z, Jr + 6);
+    if (info.y >= 0) acc += rigid_quad(c, info.y, Jr);
     dg[r] = acc;
   }
 }
@@ -1489,8 +1492,8 @@ __device__ __forceinline__ void joint_hdiag(const Ctx &c, int jl, float dg[6]) {
 __device__ __forceinline__ void tet_hdiag(const Ctx &c, int tl, int buf, float dg[3]) {
   const DevScene &S = c.S;
   const int tg = c.E.tet_off + tl;
-  const int4 id = S.t_ids[tg];
-  const float4 H0 = S.p_H[id.x], H1 = S.p_H[id.y], H2 = S.p_H[id.z], H3 = S.p_H[id.w];
+  const int4 id = gld(S.t_ids + tg);
+  const float4 H0 = gld(S.p_H + id.x), H1 = gld(S.p_H + id.y), H2 = gld(S.p_H + id.z), H3 = gld(S.p_H + id.w);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const V3 u = mk(tJ(S, buf, 6 * i, tg), tJ(S, buf, 6 * i + 1, tg), tJ(S, buf, 6 * i + 2, tg));
@@ -1505,12 +1508,12 @@ __device__ __forceinline__ void tet_hdiag(const Ctx &c, int tl, int buf, float d
 __device__ __forceinline__ void contact_hdiag(const Ctx &c, int cl, int buf, float dg[3]) {
   const DevScene &S = c.S;
   const int gc = c.E.con_off + cl;
-  const int2 bd = S.c_body[gc];
-  const V3 n = mk(S.c_n[gc]);
-  const V3 rA = mk(S.c_rA[gc]), rB = mk(S.c_rB[gc]);
-  const float al = S.c_alpha[(size_t)buf * S.NC + gc];
+  const int2 bd = gld(S.c_body + gc);
+  const V3 n = mk(gld(S.c_n + gc));
+  const V3 rA = mk(gld(S.c_rA + gc)), rB = mk(gld(S.c_rB + gc));
+  const float al = gld(S.c_alpha + (size_t)buf * S.NC + gc);
   dg[0] = al * al * (effmass_dir(c, bd.x, rA, n, true) + effmass_dir(c, bd.y, rB, n, true));
-  if (S.c_active[(size_t)buf * S.NC + gc]) {
+  if (gld(S.c_active + (size_t)buf * S.NC + gc)) {
     V3 d1, d2;
     tangent_basis(n, d1, d2);
     dg[1] = effmass_dir(c, bd.x, rA, d1, true) + effmass_dir(c, bd.y, rB, d1, true);
@@ -1518,6 +1521,24 @@ __device__ __forceinline__ void contact_hdiag(const Ctx &c, int cl, int buf, flo
   } else {
     dg[1] = 0.f;
     dg[2] = 0.f;
+  }
+}
+
+// b and P of an element's N rows from its J Y and Jacobi diagonal (err and C read
+// before the first store, see RowIn)
+template <int N>
+__device__ __forceinline__ void rhs_rows(const DevScene &S, int r0, const float jy[N], const float dg[N], float ih,
+                                         float eps) {
+  float err[N], C[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    err[r] = gld(S.row_err + r0 + r);
+    C[r] = gld(S.row_C + r0 + r);
+  }
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    gst(S.row_b + r0 + r, (jy[r] - err[r]) * ih);
+    gst(S.row_P + r0 + r, 1.f / (dg[r] + C[r] + eps));
   }
 }
 
@@ -1534,46 +1555,35 @@ __device__ __forceinline__ void rhs_and_precond(const Ctx &c, const float *Y, in
       joint_JY(c, el, Y, jy);
       joint_hdiag(c, el, dg);
       const int r0 = row_joint(E, el);
-#pragma unroll
-      for (int r = 0; r < 6; ++r) {
-        S.row_b[r0 + r] = (jy[r] - S.row_err[r0 + r]) * ih;
-        S.row_P[r0 + r] = 1.f / (dg[r] + S.row_C[r0 + r] + eps);
-      }
+      rhs_rows<6>(S, r0, jy, dg, ih, eps);
     } else if (EXT && el < E.n_jnt + E.n_tet && lin_tets(E)) {
       float jy[6], dg[6];
       const int tl = el - E.n_jnt;
       ltet_JY(c, tl, Y, buf, jy);
       ltet_hdiag(c, tl, buf, dg);
-      const int r0 = row_tet(E, tl);
-#pragma unroll
-      for (int r = 0; r < 6; ++r) {
-        S.row_b[r0 + r] = (jy[r] - S.row_err[r0 + r]) * ih;
-        S.row_P[r0 + r] = 1.f / (dg[r] + S.row_C[r0 + r] + eps);
-      }
+      rhs_rows<6>(S, row_tet(E, tl), jy, dg, ih, eps);
     } else if (el < E.n_jnt + E.n_tet) {
       float jy[3], dg[3];
       const int tl = el - E.n_jnt;
       tet_JY(c, tl, Y, buf, jy);
       tet_hdiag(c, tl, buf, dg);
-      const int r0 = row_tet(E, tl);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        S.row_b[r0 + r] = (jy[r] - S.row_err[r0 + r]) * ih;
-        S.row_P[r0 + r] = 1.f / (dg[r] + S.row_C[r0 + r] + eps);
-      }
+      rhs_rows<3>(S, row_tet(E, tl), jy, dg, ih, eps);
     } else {
       float jy[3], dg[3];
       const int cl = el - E.n_jnt - E.n_tet;
       contact_JY(c, cl, Y, buf, jy);
       contact_hdiag(c, cl, buf, dg);
-      const int r0 = row_con(E, cl);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        S.row_b[r0 + r] = (jy[r] - S.row_err[r0 + r]) * ih;
-        S.row_P[r0 + r] = 1.f / (dg[r] + S.row_C[r0 + r] + eps);
-      }
+      rhs_rows<3>(S, row_con(E, cl), jy, dg, ih, eps);
     }
   }
+}
+
+// a row's parts of <z, w>, <w, P w> and <w, P q>, added to part[0..2]
+__device__ __forceinline__ void mv_dots_reg(float z, float w, float P, float q, double part[3]) {
+  const float Pw = P * w;
+  part[0] += (double)z * (double)w;
+  part[1] += (double)w * (double)Pw;
+  part[2] += (double)Pw * (double)q;
 }
 
 // w = A z = J Y + C z + eps z for every row (Y = H~^-1 J^T z in place); adds the
@@ -1592,76 +1602,101 @@ template <int BS, bool FIRST, bool EXT>
 __device__ __forceinline__ void matvec_rows(const Ctx &c, const float *Y, int buf, int nel, float eps, double part_[3], bool isl = false) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
+  // every row of an element is read before its first store (see RowIn); q of the dots
+  // is the stored w itself in the first pass
   for (int el = threadIdx.x; el < nel; el += BS) {
     double el3[3] = {0.0, 0.0, 0.0};
     double *part = (EXT && isl) ? el3 : part_;
     if (el < E.n_jnt) {
-      float jy[6];
-      joint_JY(c, el, Y, jy);
       const int r0 = row_joint(E, el);
+      float z[6], C[6], P[6], q[6], jy[6];
 #pragma unroll
       for (int r = 0; r < 6; ++r) {
-        const float z = gld(S.row_z + r0 + r);
-        const float w = jy[r] + gld(S.row_C + r0 + r) * z + eps * z;
+        z[r] = gld(S.row_z + r0 + r);
+        C[r] = gld(S.row_C + r0 + r);
+        P[r] = gld(S.row_P + r0 + r);
+        q[r] = FIRST ? 0.f : gld(S.row_q + r0 + r);
+      }
+      joint_JY(c, el, Y, jy);
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        const float w = jy[r] + C[r] * z[r] + eps * z[r];
         gst(S.row_w + r0 + r, w);
         if (FIRST) gst(S.row_q + r0 + r, w);
-        mv_dots(S, r0 + r, z, w, part);
+        mv_dots_reg(z[r], w, P[r], FIRST ? w : q[r], part);
       }
     } else if (EXT && el < E.n_jnt + E.n_tet && lin_tets(E)) {
       // linear tet: normal rows with the 3x3 compliance block, shear rows diagonal
       float jy[6];
       const int tl = el - E.n_jnt;
-      ltet_JY(c, tl, Y, buf, jy);
       const int tg = E.tet_off + tl;
       const int r0 = row_tet(E, tl);
-      float Em[6];
+      float Em[6], zr[6], C[6], P[6], q[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) Em[k] = gld(S.t_E + (size_t)k * S.NT + tg);
-      const V3 z = mk(gld(S.row_z + r0), gld(S.row_z + r0 + 1), gld(S.row_z + r0 + 2));
+      for (int k = 0; k < 6; ++k) {
+        Em[k] = gld(S.t_E + (size_t)k * S.NT + tg);
+        zr[k] = gld(S.row_z + r0 + k);
+        C[k] = k < 3 ? 0.f : gld(S.row_C + r0 + k);
+        P[k] = gld(S.row_P + r0 + k);
+        q[k] = FIRST ? 0.f : gld(S.row_q + r0 + k);
+      }
+      ltet_JY(c, tl, Y, buf, jy);
+      const V3 z = mk(zr[0], zr[1], zr[2]);
       const V3 cz = sym_mul(Em, z);
-      const float w0 = jy[0] + cz.x + eps * z.x, w1 = jy[1] + cz.y + eps * z.y, w2 = jy[2] + cz.z + eps * z.z;
-      gst(S.row_w + r0, w0); gst(S.row_w + r0 + 1, w1); gst(S.row_w + r0 + 2, w2);
-      if (FIRST) { gst(S.row_q + r0, w0); gst(S.row_q + r0 + 1, w1); gst(S.row_q + r0 + 2, w2); }
-      mv_dots(S, r0, z.x, w0, part);
-      mv_dots(S, r0 + 1, z.y, w1, part);
-      mv_dots(S, r0 + 2, z.z, w2, part);
+      float w[6];
+      w[0] = jy[0] + cz.x + eps * z.x; w[1] = jy[1] + cz.y + eps * z.y; w[2] = jy[2] + cz.z + eps * z.z;
 #pragma unroll
-      for (int r = 3; r < 6; ++r) {
-        const float zr = gld(S.row_z + r0 + r);
-        const float w = jy[r] + gld(S.row_C + r0 + r) * zr + eps * zr;
-        gst(S.row_w + r0 + r, w);
-        if (FIRST) gst(S.row_q + r0 + r, w);
-        mv_dots(S, r0 + r, zr, w, part);
+      for (int r = 3; r < 6; ++r) w[r] = jy[r] + C[r] * zr[r] + eps * zr[r];
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        gst(S.row_w + r0 + r, w[r]);
+        if (FIRST) gst(S.row_q + r0 + r, w[r]);
+        mv_dots_reg(zr[r], w[r], P[r], FIRST ? w[r] : q[r], part);
       }
     } else if (el < E.n_jnt + E.n_tet) {
-      float jy[3];
       const int tl = el - E.n_jnt;
-      tet_JY(c, tl, Y, buf, jy);
       const int tg = E.tet_off + tl;
       const int r0 = row_tet(E, tl);
-      float Em[6];
+      float J[18], Em[6], zr[3], P[3], q[3], jy[3];
+#pragma unroll
+      for (int m = 0; m < 18; ++m) J[m] = tJ(S, buf, m, tg);
+      const int4 ids = gld(S.t_ids + tg);
 #pragma unroll
       for (int k = 0; k < 6; ++k) Em[k] = gld(S.t_E + (size_t)k * S.NT + tg);
-      const V3 z = mk(gld(S.row_z + r0), gld(S.row_z + r0 + 1), gld(S.row_z + r0 + 2));
-      const V3 cz = sym_mul(Em, z);
-      const float w0 = jy[0] + cz.x + eps * z.x, w1 = jy[1] + cz.y + eps * z.y, w2 = jy[2] + cz.z + eps * z.z;
-      gst(S.row_w + r0, w0); gst(S.row_w + r0 + 1, w1); gst(S.row_w + r0 + 2, w2);
-      if (FIRST) { gst(S.row_q + r0, w0); gst(S.row_q + r0 + 1, w1); gst(S.row_q + r0 + 2, w2); }
-      mv_dots(S, r0, z.x, w0, part);
-      mv_dots(S, r0 + 1, z.y, w1, part);
-      mv_dots(S, r0 + 2, z.z, w2, part);
-    } else {
-      float jy[3];
-      const int cl = el - E.n_jnt - E.n_tet;
-      contact_JY(c, cl, Y, buf, jy);
-      const int r0 = row_con(E, cl);
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
-        const float z = gld(S.row_z + r0 + r);
-        const float w = jy[r] + gld(S.row_C + r0 + r) * z + eps * z;
+        zr[r] = gld(S.row_z + r0 + r);
+        P[r] = gld(S.row_P + r0 + r);
+        q[r] = FIRST ? 0.f : gld(S.row_q + r0 + r);
+      }
+      tet_JY_core(E, J, ids, Y, jy);
+      const V3 z = mk(zr[0], zr[1], zr[2]);
+      const V3 cz = sym_mul(Em, z);
+      const float w[3] = {jy[0] + cz.x + eps * z.x, jy[1] + cz.y + eps * z.y, jy[2] + cz.z + eps * z.z};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        gst(S.row_w + r0 + r, w[r]);
+        if (FIRST) gst(S.row_q + r0 + r, w[r]);
+        mv_dots_reg(zr[r], w[r], P[r], FIRST ? w[r] : q[r], part);
+      }
+    } else {
+      const int cl = el - E.n_jnt - E.n_tet;
+      const int r0 = row_con(E, cl);
+      float z[3], C[3], P[3], q[3], jy[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        z[r] = gld(S.row_z + r0 + r);
+        C[r] = gld(S.row_C + r0 + r);
+        P[r] = gld(S.row_P + r0 + r);
+        q[r] = FIRST ? 0.f : gld(S.row_q + r0 + r);
+      }
+      contact_JY(c, cl, Y, buf, jy);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const float w = jy[r] + C[r] * z[r] + eps * z[r];
         gst(S.row_w + r0 + r, w);
         if (FIRST) gst(S.row_q + r0 + r, w);
-        mv_dots(S, r0 + r, z, w, part);
+        mv_dots_reg(z[r], w, P[r], FIRST ? w : q[r], part);
       }
     }
     if (EXT && isl) {
@@ -1747,23 +1782,48 @@ __device__ __forceinline__ void contrib_pass(const Ctx &c, const float *src, int
   }
 }
 
+// The values of one row that a PCR pass reads.  An element pass reads all the rows
+// (and the element data) of an element before it writes any of them: the row arrays
+// are reached through pointers the compiler cannot tell apart, so a load placed after
+// a store waits for it, and an element that interleaved them would pay one memory
+// round trip per row.
+struct RowIn {
+  float P, z, p, q, x, w;
+};
+
 // One PCR row.  INIT: z = P b, x = 0, p = z.  Else the direction update of the
 // previous iteration (upd: p = z + beta p, q = w + beta q) followed by this
-// iteration's x += alpha p, z -= alpha P q.
+// iteration's x += alpha p, z -= alpha P q.  pcr_row_load reads the row (INIT: P and b,
+// the latter in the z slot), pcr_row_apply updates and stores it.
 template <bool INIT>
-__device__ __forceinline__ float pcr_row(const DevScene &S, int row, float alpha, float beta, bool upd) {
+__device__ __forceinline__ void pcr_row_load(const DevScene &S, int row, bool upd, RowIn &v) {
+  v.P = gld(S.row_P + row);
   if (INIT) {
-    const float z = gld(S.row_P + row) * gld(S.row_b + row);
+    v.z = gld(S.row_b + row);
+    return;
+  }
+  v.p = gld(S.row_p + row);
+  v.q = gld(S.row_q + row);
+  v.z = gld(S.row_z + row);
+  v.x = gld(S.row_x + row);
+  v.w = upd ? gld(S.row_w + row) : 0.f;
+}
+
+template <bool INIT>
+__device__ __forceinline__ float pcr_row_apply(const DevScene &S, int row, const RowIn &v, float alpha, float beta,
+                                               bool upd) {
+  if (INIT) {
+    const float z = v.P * v.z;
     gst(S.row_x + row, 0.f);
     gst(S.row_z + row, z);
     gst(S.row_p + row, z);
     return z;
   }
-  float p = gld(S.row_p + row), q = gld(S.row_q + row);
-  const float z0 = gld(S.row_z + row), P = gld(S.row_P + row), x = gld(S.row_x + row);
+  float p = v.p, q = v.q;
+  const float z0 = v.z, P = v.P, x = v.x;
   if (upd) {
     p = z0 + beta * p;
-    q = gld(S.row_w + row) + beta * q;
+    q = v.w + beta * q;
     gst(S.row_p + row, p);
     gst(S.row_q + row, q);
   }
@@ -1771,6 +1831,13 @@ __device__ __forceinline__ float pcr_row(const DevScene &S, int row, float alpha
   const float z = z0 - alpha * (P * q);
   gst(S.row_z + row, z);
   return z;
+}
+
+template <bool INIT>
+__device__ __forceinline__ float pcr_row(const DevScene &S, int row, float alpha, float beta, bool upd) {
+  RowIn v;
+  pcr_row_load<INIT>(S, row, upd, v);
+  return pcr_row_apply<INIT>(S, row, v, alpha, beta, upd);
 }
 
 // Element pass of the PCR: the rows of every element are updated (pcr_row) and the
@@ -1791,36 +1858,65 @@ __device__ __forceinline__ void pcr_update_contrib(const Ctx &c, int buf, int ne
       beta = I.beta;
       act = I.active != 0;
     }
+    // an element's rows and data are all read before its first store (see RowIn);
+    // a row of a stopped island keeps its z
     if (el < E.n_jnt) {
       const int r0 = row_joint(E, el);
-      if (act) {
+      RowIn v[6];
+      float z[6];
 #pragma unroll
-        for (int r = 0; r < 6; ++r) pcr_row<INIT>(S, r0 + r, alpha, beta, upd);
+      for (int r = 0; r < 6; ++r) {
+        if (act) pcr_row_load<INIT>(S, r0 + r, upd, v[r]);
+        else v[r].z = gld(S.row_z + r0 + r);
       }
-      joint_contrib(c, el, S.row_z);
+#pragma unroll
+      for (int r = 0; r < 6; ++r) z[r] = act ? pcr_row_apply<INIT>(S, r0 + r, v[r], alpha, beta, upd) : v[r].z;
+      joint_contrib_vals(c, el, z);
     } else if (EXT && el < E.n_jnt + E.n_tet && lin_tets(E)) {
       const int tl = el - E.n_jnt;
       const int r0 = row_tet(E, tl);
+      RowIn v[6];
       float z[6];
 #pragma unroll
-      for (int r = 0; r < 6; ++r) z[r] = act ? pcr_row<INIT>(S, r0 + r, alpha, beta, upd) : gld(S.row_z + r0 + r);
+      for (int r = 0; r < 6; ++r) {
+        if (act) pcr_row_load<INIT>(S, r0 + r, upd, v[r]);
+        else v[r].z = gld(S.row_z + r0 + r);
+      }
+#pragma unroll
+      for (int r = 0; r < 6; ++r) z[r] = act ? pcr_row_apply<INIT>(S, r0 + r, v[r], alpha, beta, upd) : v[r].z;
       ltet_contrib(c, tl, z, buf);
     } else if (el < E.n_jnt + E.n_tet) {
-      const int tl = el - E.n_jnt;
+      const int tl = el - E.n_jnt, tg = E.tet_off + tl;
       const int r0 = row_tet(E, tl);
+      RowIn v[3];
+      float z[3], J[18];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        if (act) pcr_row_load<INIT>(S, r0 + r, upd, v[r]);
+        else v[r].z = gld(S.row_z + r0 + r);
+      }
+#pragma unroll
+      for (int m = 0; m < 18; ++m) J[m] = tJ(S, buf, m, tg);
+      const int4 dst = gld(S.t_dst + tg);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) z[r] = act ? pcr_row_apply<INIT>(S, r0 + r, v[r], alpha, beta, upd) : v[r].z;
+      tet_contrib_core(c, J, z, dst);
+    } else {
+      const int cl = el - E.n_jnt - E.n_tet, gc = E.con_off + cl;
+      const int r0 = row_con(E, cl);
+      RowIn v[3];
       float z[3];
 #pragma unroll
-      for (int r = 0; r < 3; ++r) z[r] = act ? pcr_row<INIT>(S, r0 + r, alpha, beta, upd) : gld(S.row_z + r0 + r);
-      tet_contrib(c, tl, z, buf);
-    } else {
-      const int cl = el - E.n_jnt - E.n_tet;
-      const int r0 = row_con(E, cl);
-      if (act) {
-#pragma unroll
-        for (int r = 0; r < 3; ++r) pcr_row<INIT>(S, r0 + r, alpha, beta, upd);
+      for (int r = 0; r < 3; ++r) {
+        if (act) pcr_row_load<INIT>(S, r0 + r, upd, v[r]);
+        else v[r].z = gld(S.row_z + r0 + r);
       }
-      const int gc = E.con_off + cl;
-      gst(S.c_cj + gc, f4(contact_dir(c, gc, S.row_z, buf), 0.f));
+      const V3 n = mk(gld(S.c_n + gc));
+      const float al = gld(S.c_alpha + (size_t)buf * S.NC + gc);
+      const int active = gld(S.c_active + (size_t)buf * S.NC + gc);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) z[r] = act ? pcr_row_apply<INIT>(S, r0 + r, v[r], alpha, beta, upd) : v[r].z;
+      gst(S.c_cj + gc, f4(contact_dir_core(n, al, active, z[0], z[1], z[2]), 0.f));
     }
   }
 }
@@ -1836,12 +1932,6 @@ __device__ __forceinline__ void pcr_update_contrib(const Ctx &c, int buf, int ne
 // (pcr_update_contrib, gather_hinv, matvec_rows), so both give identical results.
 // Returns the PCR iterations performed; x is written back to row_x.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void mv_dots_reg(float z, float w, float P, float q, double part[3]) {
-  const float Pw = P * w;
-  part[0] += (double)z * (double)w;
-  part[1] += (double)w * (double)Pw;
-  part[2] += (double)Pw * (double)q;
-}
 
 // J^T z of a resident tet or contact (z from registers) for the body pass
 __device__ __forceinline__ void resident_contrib(const Ctx &c, int el, int buf, const float z[3]) {
@@ -2083,15 +2173,34 @@ __device__ __forceinline__ int pcr_resident(const Ctx &c, float *Y, int buf, int
 // stays below about (updates since) x eps x 10.
 constexpr double kOnePassRefreshDrop = 1e-2;
 
+// The last PCR iteration's x += alpha p (upd: p = z + beta p first) over the env's rows,
+// four rows of the thread at a time with their loads before their stores (see RowIn)
+template <int BS>
+__device__ __forceinline__ void last_x_update(const DevScene &S, int R0, int nrows, int tid, bool upd, float alpha,
+                                              float beta) {
+  for (int r = tid; r < nrows; r += 4 * BS) {
+    float z[4], p[4], x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = R0 + r + j * BS;
+      const bool in = r + j * BS < nrows;
+      z[j] = in && upd ? gld(S.row_z + row) : 0.f;
+      p[j] = in ? gld(S.row_p + row) : 0.f;
+      x[j] = in ? gld(S.row_x + row) : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (r + j * BS >= nrows) continue;
+      const float pp = upd ? z[j] + beta * p[j] : p[j];
+      gst(S.row_x + R0 + r + j * BS, x[j] + alpha * pp);
+    }
+  }
+}
+
 // Deferred row update: MODE 0 keeps the rows as the initialisation set them; 1 applies
 // x += alpha p, z -= alpha P q with the starting p and q; 2 first advances
-// p = z + beta p, q = w + beta q.  An element visit reads all its rows (and its
-// element data) before it writes any: the row arrays are reached through pointers the
-// compiler cannot separate, so a load placed after a store waits for it, and a visit
-// that interleaved them would pay one memory round trip per row.
-struct RowIn {
-  float P, z, p, q, x, w;
-};
+// p = z + beta p, q = w + beta q.  The element visit reads all its rows and element
+// data before it writes any (see RowIn).
 
 template <int MODE>
 __device__ __forceinline__ void fused_row_load(const DevScene &S, int row, RowIn &v) {
@@ -3038,11 +3147,7 @@ __global__ __launch_bounds__(BS) void k_newton(const DevScene *__restrict__ Sp, 
           const float alpha = (float)(rho / qs);
           ++done;
           if (it == A.cr_iters - 1) {  // the last update needs no further product
-            for (int r = tid; r < nrows; r += BS) {
-              const int row = R0 + r;
-              const float p = it > 0 ? gld(S.row_z + row) + beta * gld(S.row_p + row) : gld(S.row_p + row);
-              gst(S.row_x + row, gld(S.row_x + row) + alpha * p);
-            }
+            last_x_update<BS>(S, R0, nrows, tid, it > 0, alpha, beta);
             break;
           }
           if (it == 0) {
@@ -3093,11 +3198,7 @@ __global__ __launch_bounds__(BS) void k_newton(const DevScene *__restrict__ Sp, 
           const float alpha = (float)(rho / qs);
           ++done;
           if (it == A.cr_iters - 1) {  // the last update needs no further product
-            for (int r = tid; r < nrows; r += BS) {
-              const int row = R0 + r;
-              const float p = it > 0 ? gld(S.row_z + row) + beta * gld(S.row_p + row) : gld(S.row_p + row);
-              gst(S.row_x + row, gld(S.row_x + row) + alpha * p);
-            }
+            last_x_update<BS>(S, R0, nrows, tid, it > 0, alpha, beta);
             break;
           }
           // direction update, x += alpha p, z -= alpha P q, J^T z contributions
@@ -3168,10 +3269,26 @@ __global__ __launch_bounds__(BS) void k_newton(const DevScene *__restrict__ Sp, 
       }
     }
     __syncthreads();
-    for (int r = tid; r < nrows; r += BS) {
-      const int row = R0 + r;
-      if (A.p.line_search) S.row_lam_k[row] = S.row_lam[row];
-      S.row_lam[row] += tstep * S.row_x[row];
+    if (A.p.line_search) {
+      for (int r = tid; r < nrows; r += BS) {
+        const int row = R0 + r;
+        S.row_lam_k[row] = S.row_lam[row];
+        S.row_lam[row] += tstep * S.row_x[row];
+      }
+    } else {
+      // four rows of the thread at a time, loads before stores (see RowIn)
+      for (int r = tid; r < nrows; r += 4 * BS) {
+        float l[4], x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int rr = r + j * BS;
+          l[j] = rr < nrows ? gld(S.row_lam + R0 + rr) : 0.f;
+          x[j] = rr < nrows ? gld(S.row_x + R0 + rr) : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (r + j * BS < nrows) gst(S.row_lam + R0 + r + j * BS, l[j] + tstep * x[j]);
+      }
     }
     for (int b = tid; b < nb; b += BS) update_positions_body(c, b);
     __syncthreads();
