@@ -2279,26 +2279,32 @@ __device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int bu
       const int tl = el - E.n_jnt, tg = E.tet_off + tl;
       const int r0 = row_tet(E, tl);
       float z[3], q[3], P[3], jy[3], pw[3];
-      RowIn v[3];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) fused_row_load<MODE>(S, r0 + r, v[r]);
-      float J[18];
-#pragma unroll
-      for (int m = 0; m < 18; ++m) J[m] = tJ(S, buf, m, tg);
-      int4 ids, dst;
-      if (S.tet_loc) {  // ids and slots from one 16-byte record (env-local, 16 bits each)
-        const uint4 L = gld(S.t_loc + tg);
-        const int po = E.par_off, ab = c.cl_base;
-        ids = make_int4(po + (int)(L.x & 0xffffu), po + (int)(L.y & 0xffffu), po + (int)(L.z & 0xffffu),
-                        po + (int)(L.w & 0xffffu));
-        dst = make_int4(ab + (int)(L.x >> 16), ab + (int)(L.y >> 16), ab + (int)(L.z >> 16), ab + (int)(L.w >> 16));
+      // ids and slots first (the Y reads wait for them), decoded after the other loads
+      // are issued: from one 16-byte record of env-local 16-bit fields where the
+      // scene's envs fit them, else from the two global index tables
+      const bool packed = S.tet_loc != 0;
+      uint4 L = make_uint4(0u, 0u, 0u, 0u);
+      int4 ids = make_int4(0, 0, 0, 0), dst = ids;
+      if (packed) {
+        L = gld(S.t_loc + tg);
       } else {
         ids = gld(S.t_ids + tg);
         dst = gld(S.t_dst + tg);
       }
-      float Em[6];
+      RowIn v[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) fused_row_load<MODE>(S, r0 + r, v[r]);
+      float J[18], Em[6];
+#pragma unroll
+      for (int m = 0; m < 18; ++m) J[m] = tJ(S, buf, m, tg);
 #pragma unroll
       for (int k = 0; k < 6; ++k) Em[k] = gld(S.t_E + (size_t)k * S.NT + tg);
+      if (packed) {
+        const int po = E.par_off, ab = c.cl_base;
+        ids = make_int4(po + (int)(L.x & 0xffffu), po + (int)(L.y & 0xffffu), po + (int)(L.z & 0xffffu),
+                        po + (int)(L.w & 0xffffu));
+        dst = make_int4(ab + (int)(L.x >> 16), ab + (int)(L.y >> 16), ab + (int)(L.z >> 16), ab + (int)(L.w >> 16));
+      }
 #pragma unroll
       for (int r = 0; r < 3; ++r) fused_row<MODE>(S, r0 + r, v[r], alpha, beta, z[r], q[r], P[r]);
       tet_JY_core(E, J, ids, Y, jy);
@@ -2313,6 +2319,7 @@ __device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int bu
       const int cl = el - E.n_jnt - E.n_tet, gc = E.con_off + cl;
       const int r0 = row_con(E, cl);
       float z[3], q[3], P[3], jy[3], pw[3], C[3];
+      const int2 bd = gld(S.c_body + gc);  // first: the Y reads wait for it
       RowIn v[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
@@ -2322,7 +2329,6 @@ __device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int bu
       const V3 n = mk(gld(S.c_n + gc));
       const float al = gld(S.c_alpha + (size_t)buf * S.NC + gc);
       const int act = gld(S.c_active + (size_t)buf * S.NC + gc);
-      const int2 bd = gld(S.c_body + gc);
       const V3 rA = mk(gld(S.c_rA + gc)), rB = mk(gld(S.c_rB + gc));
 #pragma unroll
       for (int r = 0; r < 3; ++r) fused_row<MODE>(S, r0 + r, v[r], alpha, beta, z[r], q[r], P[r]);
