@@ -49,10 +49,31 @@ struct Red {
   float f[2][NW > 0 ? NW : 1];
 };
 
+// One lane-permutation step of a wave reduction on a double: each 32-bit half moves
+// with the same DPP control (quad_perm, row_half_mirror, row_mirror).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes in a fixed order, returned to every lane: pairs, quads, half
+// rows and rows of 16 through DPP moves (no LDS traffic), then the four row sums
+// read out and added in row order.
 __device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  double r[4];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  for (int k = 0; k < 4; ++k) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 16 * k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 16 * k);
+    r[k] = __hiloint2double(hi, lo);
+  }
+  return (r[0] + r[1]) + (r[2] + r[3]);
 }
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
