@@ -81,16 +81,30 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
+// Sum of the NW (<= 16) per-wave partials p[0..NW-1]: lane i of every wave reads p[i]
+// and the same DPP steps add them in a fixed order, so every wave of the block gets
+// the identical value from one LDS read per lane.
+template <int NW>
+__device__ __forceinline__ double partials_sum(const double *p) {
+  static_assert(NW <= 16, "one DPP row holds the partials");
+  const int lane = threadIdx.x & 63;
+  double v = lane < NW ? p[lane] : 0.0;
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 0);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 0);
+  return __hiloint2double(hi, lo);
+}
+
 template <int BS>
 __device__ __forceinline__ double block_sum(double v, Red<BS> &r, int slot) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) r.d[slot][w] = v;
   __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int i = 0; i < Red<BS>::NW; ++i) s += r.d[slot][i];
-  return s;
+  return partials_sum<Red<BS>::NW>(r.d[slot]);
 }
 
 // three sums in one barrier
@@ -104,12 +118,7 @@ __device__ __forceinline__ void block_sum3(double v[3], Red<BS> &r) {
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < Red<BS>::NW; ++i) s += r.d3[k][i];
-    v[k] = s;
-  }
+  for (int k = 0; k < 3; ++k) v[k] = partials_sum<Red<BS>::NW>(r.d3[k]);
 }
 
 template <int BS>
