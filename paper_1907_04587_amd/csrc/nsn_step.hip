@@ -1417,9 +1417,22 @@ __device__ __forceinline__ V3 gather_particle(const Ctx &c, int p) {
   const DevScene &S = c.S;
   V3 acc = mk(0.f, 0.f, 0.f);
   const int k0 = gld(S.p_tadj_ptr + p), k1 = gld(S.p_tadj_ptr + p + 1);
+  const int c0 = gld(S.p_acon_beg + p), c1 = gld(S.p_acon_end + p);
   int k = k0;
-  if (c.cl) {  // the same sums in the same order, from LDS
+  if (c.cl) {  // the same sums in the same order, from LDS, four entries' reads at a time
     const float *cx = c.cl, *cy = cx + c.cl_n, *cz = cy + c.cl_n;
+    for (; k + 4 <= k1; k += 4) {
+      float vx[4], vy[4], vz[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int i = k + m - c.cl_base;
+        vx[m] = cx[i];
+        vy[m] = cy[i];
+        vz[m] = cz[i];
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc = acc + mk(vx[m], vy[m], vz[m]);
+    }
     for (; k < k1; ++k) {
       const int i = k - c.cl_base;
       acc = acc + mk(cx[i], cy[i], cz[i]);
@@ -1433,8 +1446,7 @@ __device__ __forceinline__ V3 gather_particle(const Ctx &c, int p) {
     for (int m = 0; m < 8; ++m) acc = acc + mk(v[m]);
   }
   for (; k < k1; ++k) acc = acc + mk(gld(S.p_cj + k));
-  const int c1 = gld(S.p_acon_end + p);
-  for (int gc = gld(S.p_acon_beg + p); gc < c1; ++gc) acc = acc + mk(gld(S.c_cj + gc));
+  for (int gc = c0; gc < c1; ++gc) acc = acc + mk(gld(S.c_cj + gc));
   return acc;
 }
 
