@@ -2399,9 +2399,9 @@ __device__ __forceinline__ void fused_body(const Ctx &c, float *Y, float alpha, 
     if (b < E.n_rig) {
       const int g = E.rig_off + b;
       float v[6], oq[6], oz[6], Iw[6];
-      gather_rigid(c, g, v);
       const int d = E.dof_off + 6 * b;
-      // every load before the first store (see fused_row_load)
+      // every load before the first store (see fused_row_load), the body's own values
+      // ahead of the gather's chains
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         oq[k] = MODE >= 2 ? gld(S.bq + d + k) : 0.f;
@@ -2409,6 +2409,7 @@ __device__ __forceinline__ void fused_body(const Ctx &c, float *Y, float alpha, 
         Iw[k] = MODE == 3 ? 0.f : gld(S.r_Iwinv + 6 * g + k);
       }
       const float im = MODE == 3 ? 0.f : gld(S.r_inertia + g).w;
+      gather_rigid(c, g, v);
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         if (MODE == 4) {
@@ -2427,8 +2428,7 @@ __device__ __forceinline__ void fused_body(const Ctx &c, float *Y, float alpha, 
       for (int k = 0; k < 6; ++k) Y[6 * b + k] = v[k];
     } else {
       const int p = E.par_off + b - E.n_rig;
-      const V3 a = gather_particle(c, p);
-      float v[3] = {a.x, a.y, a.z}, oq[3], oz[3];
+      float oq[3], oz[3];
       const int d = E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -2436,6 +2436,8 @@ __device__ __forceinline__ void fused_body(const Ctx &c, float *Y, float alpha, 
         oz[k] = MODE == 1 || MODE == 2 ? gld(S.bz + d + k) : 0.f;
       }
       const float4 H = MODE == 3 ? make_float4(1.f, 1.f, 1.f, 0.f) : gld(S.p_H + p);
+      const V3 a = gather_particle(c, p);
+      float v[3] = {a.x, a.y, a.z};
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         if (MODE == 4) {
