@@ -156,7 +156,7 @@ void layout(const Sizes &z, int n_envs, const Options &opt, Arena &a, DevScene &
   S.j_info = a.take<int4>(z.NJ); S.j_frame = a.take<float4>(6 * (size_t)z.NJ);
   S.j_drive = a.take<float4>(2 * (size_t)z.NJ); S.j_theta0 = a.take<float>(z.NJ);
   S.j_J = a.take<float>(72 * (size_t)z.NJ);
-  S.j_cj = a.take<float>(12 * (size_t)z.NJ);
+  S.j_slot = a.take<int2>(z.NJ);
   S.c_key = a.take<int>(z.NC); S.c_body = a.take<int2>(z.NC); S.c_n = a.take<float4>(z.NC);
   S.c_aL = a.take<float4>(z.NC); S.c_bL = a.take<float4>(z.NC); S.c_rA = a.take<float4>(z.NC);
   S.c_rB = a.take<float4>(z.NC); S.c_cj = a.take<float4>(z.NC); S.c_alpha = a.take<float>(2 * (size_t)z.NC);
@@ -166,6 +166,8 @@ void layout(const Sizes &z, int n_envs, const Options &opt, Arena &a, DevScene &
   S.r_acon_beg = a.take<int>(z.NR); S.r_acon_end = a.take<int>(z.NR);
   S.p_acon_beg = a.take<int>(z.NP); S.p_acon_end = a.take<int>(z.NP);
   S.r_bcon_beg = a.take<int>(z.NR); S.r_bcon_cnt = a.take<int>(z.NR); S.bcon_list = a.take<int>(z.NC);
+  S.r_cj = a.take<float4>(2 * (2 * (size_t)z.NJ + 2 * (size_t)z.NC)); S.r_slot = a.take<int2>(z.NR);
+  S.c_slot = a.take<int2>(z.NC);
   S.p_tadj_ptr = a.take<int>(z.NP + 1); S.p_tadj = a.take<int>(z.NTADJ);
   S.r_jadj_ptr = a.take<int>(z.NR + 1); S.r_jadj = a.take<int>(z.NJADJ);
   S.row_lam = a.take<float>(z.NROW); S.row_x = a.take<float>(z.NROW); S.row_z = a.take<float>(z.NROW);

@@ -86,7 +86,7 @@ struct DevScene {
   const float4 *j_drive;           // 2 per joint: (kp, kd, amp, freq), (phase, offset, -, -)
   float *j_theta0;                 // drive coordinate at q^-
   float *j_J;                      // NJ x 6 rows x 12 (J_A, J_B)
-  float *j_cj;                     // NJ x 12 : J^T v of a joint for its bodies A and B
+  int2 *j_slot;                    // NJ : (side A, side B) contribution slot, -1 for the world
 
   // contacts (capacity NC)
   int *c_key;
@@ -95,7 +95,8 @@ struct DevScene {
   float4 *c_n;                     // normal, thickness
   float4 *c_aL, *c_bL;             // feature / target points (body frame or world)
   float4 *c_rA, *c_rB;             // world arms at the current iterate
-  float4 *c_cj;                    // world direction of a contact's J^T v
+  float4 *c_cj;                    // world direction of a contact's J^T v (particle feature bodies)
+  int2 *c_slot;                    // (feature side, target side) contribution slot, -1 if not rigid
   float *c_alpha;                  // 2 x NC ping-pong (normal row scale alpha)
   int *c_active;                   // 2 x NC ping-pong (friction rows active)
   float4 *c_lam0;                  // warm-start multipliers
@@ -109,6 +110,12 @@ struct DevScene {
   int *p_acon_beg, *p_acon_end;    // particle as feature body
   int *r_bcon_beg, *r_bcon_cnt;    // rigid body as target: range in bcon_list
   int *bcon_list;                  // contact indices (global)
+  // rigid bodies' J^T v contributions: one run of slots per body, its joints (adjacency
+  // order), then the contacts where it is the feature body, then those where it is the
+  // target (list order); a slot is a force and a torque, two float4, with the target
+  // side's sign applied.  Slots are assigned with the contacts every step.
+  float4 *r_cj;                    // 2 x (2 NJ + 2 NC)
+  int2 *r_slot;                    // NR : (first, end) slot of a body's run
 
   // static adjacency
   const int *p_tadj_ptr, *p_tadj;  // particle -> (tet << 2 | slot)

@@ -856,6 +856,35 @@ __global__ __launch_bounds__(BS) void k_prepare(DevScene S, StepArgs A, int want
     }
   }
 
+  // ---- contribution slots of the rigid bodies: each body's run holds its joints
+  //      (adjacency order), its feature-side contacts, then its target-side contacts,
+  //      in the env's region [2 jnt_off + 2 con_off, + 2 n_jnt + 2 max_con) ----
+  __syncthreads();
+  for (int i = tid; i < nc; i += BS) S.c_slot[E.con_off + i] = make_int2(-1, -1);
+  for (int j = tid; j < E.n_jnt; j += BS) S.j_slot[E.jnt_off + j] = make_int2(-1, -1);
+  if (tid == 0) {
+    int at = 2 * E.jnt_off + 2 * E.con_off;
+    for (int r = 0; r < E.n_rig; ++r) {
+      const int g = E.rig_off + r;
+      const int n = (S.r_jadj_ptr[g + 1] - S.r_jadj_ptr[g]) + (S.r_acon_end[g] - S.r_acon_beg[g]) + S.r_bcon_cnt[g];
+      S.r_slot[g] = make_int2(at, at + n);
+      at += n;
+    }
+  }
+  __syncthreads();
+  for (int r = tid; r < E.n_rig; r += BS) {
+    const int g = E.rig_off + r;
+    int at = S.r_slot[g].x;
+    for (int k = S.r_jadj_ptr[g]; k < S.r_jadj_ptr[g + 1]; ++k, ++at) {
+      const int ent = S.r_jadj[k];
+      if (ent & 1) S.j_slot[ent >> 1].y = at;
+      else S.j_slot[ent >> 1].x = at;
+    }
+    for (int gc = S.r_acon_beg[g]; gc < S.r_acon_end[g]; ++gc, ++at) S.c_slot[gc].x = at;
+    const int b0 = S.r_bcon_beg[g], bn = S.r_bcon_cnt[g];
+    for (int k = 0; k < bn; ++k, ++at) S.c_slot[S.bcon_list[b0 + k]].y = at;
+  }
+
   // ---- warm start by key (previous step) and per-contact features ----
   const int np_prev = S.n_prev[e];
   for (int i = tid; i < nc; i += BS) {
@@ -1320,9 +1349,34 @@ __device__ __forceinline__ void joint_contrib_vals(const Ctx &c, int jl, const f
 #pragma unroll
     for (int q = 0; q < 12; ++q) o[q] += v[r] * gld(J + 12 * r + q);
   }
-  float *dst = c.S.j_cj + (size_t)12 * jg;
-#pragma unroll
-  for (int q = 0; q < 12; ++q) gst(dst + q, o[q]);
+  // side A's six values in its body's slot (none for the world), then side B's
+  const int2 js = gld(c.S.j_slot + jg);
+  if (js.x >= 0) {
+    gst(c.S.r_cj + 2 * (size_t)js.x, make_float4(o[0], o[1], o[2], 0.f));
+    gst(c.S.r_cj + 2 * (size_t)js.x + 1, make_float4(o[3], o[4], o[5], 0.f));
+  }
+  if (js.y >= 0) {
+    gst(c.S.r_cj + 2 * (size_t)js.y, make_float4(o[6], o[7], o[8], 0.f));
+    gst(c.S.r_cj + 2 * (size_t)js.y + 1, make_float4(o[9], o[10], o[11], 0.f));
+  }
+}
+
+// A contact's J^T v, dir applied at its two points: a particle feature body reads the
+// direction (c_cj); a rigid body's slot gets the force and the torque about its
+// centre, with the sign of its side (the target side subtracts)
+__device__ __forceinline__ void contact_store(const DevScene &S, int gc, V3 dir, V3 rA, V3 rB) {
+  const int2 cs = gld(S.c_slot + gc);
+  if (cs.x >= 0) {
+    gst(S.r_cj + 2 * (size_t)cs.x, f4(dir, 0.f));
+    gst(S.r_cj + 2 * (size_t)cs.x + 1, f4(cross(rA, dir), 0.f));
+  } else {
+    gst(S.c_cj + gc, f4(dir, 0.f));
+  }
+  if (cs.y >= 0) {
+    const V3 t = cross(rB, dir);
+    gst(S.r_cj + 2 * (size_t)cs.y, make_float4(-dir.x, -dir.y, -dir.z, 0.f));
+    gst(S.r_cj + 2 * (size_t)cs.y + 1, make_float4(-t.x, -t.y, -t.z, 0.f));
+  }
 }
 
 __device__ __forceinline__ void joint_contrib(const Ctx &c, int jl, const float *src) {
@@ -1359,55 +1413,26 @@ __device__ __forceinline__ void tet_contrib(const Ctx &c, int tl, const float z[
   tet_contrib_core(c, J, z, gld(S.t_dst + tg));
 }
 
-__device__ __forceinline__ void acc_wrench(float out[6], V3 d, V3 arm, float sgn) {
-  const V3 a = cross(arm, d);
-  out[0] += sgn * d.x; out[1] += sgn * d.y; out[2] += sgn * d.z;
-  out[3] += sgn * a.x; out[4] += sgn * a.y; out[5] += sgn * a.z;
-}
-
-// Sums in adjacency order; contact entries four at a time with their loads first
-// (a box low in a stack has tens of contacts: this loop is the body pass's longest).
+// Sums the body's run of contribution slots in order (joints, feature-side contacts,
+// target-side contacts), four slots' loads at a time ahead of their sums.
 __device__ __forceinline__ void gather_rigid(const Ctx &c, int g, float out[6]) {
   const DevScene &S = c.S;
   for (int k = 0; k < 6; ++k) out[k] = 0.f;
-  const int j1 = gld(S.r_jadj_ptr + g + 1);
-  for (int k = gld(S.r_jadj_ptr + g); k < j1; ++k) {
-    const int ent = gld(S.r_jadj + k);
-    const float *o = S.j_cj + (size_t)12 * (ent >> 1) + 6 * (ent & 1);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) out[q] += gld(o + q);
-  }
-  const int a1 = gld(S.r_acon_end + g);
-  int gc = gld(S.r_acon_beg + g);
-  for (; gc + 4 <= a1; gc += 4) {
-    float4 d[4], r[4];
+  const int2 rs = gld(S.r_slot + g);
+  for (int k = rs.x; k < rs.y; k += 4) {
+    float4 f[4], t[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      d[m] = gld(S.c_cj + gc + m);
-      r[m] = gld(S.c_rA + gc + m);
+      if (k + m >= rs.y) continue;
+      f[m] = gld(S.r_cj + 2 * (size_t)(k + m));
+      t[m] = gld(S.r_cj + 2 * (size_t)(k + m) + 1);
     }
-#pragma unroll
-    for (int m = 0; m < 4; ++m) acc_wrench(out, mk(d[m]), mk(r[m]), 1.f);
-  }
-  for (; gc < a1; ++gc) acc_wrench(out, mk(gld(S.c_cj + gc)), mk(gld(S.c_rA + gc)), 1.f);
-  const int b0 = gld(S.r_bcon_beg + g), bn = gld(S.r_bcon_cnt + g);
-  int k = 0;
-  for (; k + 4 <= bn; k += 4) {
-    int id[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) id[m] = gld(S.bcon_list + b0 + k + m);
-    float4 d[4], r[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      d[m] = gld(S.c_cj + id[m]);
-      r[m] = gld(S.c_rB + id[m]);
+      if (k + m >= rs.y) continue;
+      out[0] += f[m].x; out[1] += f[m].y; out[2] += f[m].z;
+      out[3] += t[m].x; out[4] += t[m].y; out[5] += t[m].z;
     }
-#pragma unroll
-    for (int m = 0; m < 4; ++m) acc_wrench(out, mk(d[m]), mk(r[m]), -1.f);
-  }
-  for (; k < bn; ++k) {
-    const int id = gld(S.bcon_list + b0 + k);
-    acc_wrench(out, mk(gld(S.c_cj + id)), mk(gld(S.c_rB + id)), -1.f);
   }
 }
 
@@ -1819,7 +1844,7 @@ __device__ __forceinline__ void contrib_pass(const Ctx &c, const float *src, int
       tet_contrib(c, tl, z, buf);
     } else {
       const int gc = E.con_off + el - E.n_jnt - E.n_tet;
-      gst(c.S.c_cj + gc, f4(contact_dir(c, gc, src, buf), 0.f));
+      contact_store(c.S, gc, contact_dir(c, gc, src, buf), mk(gld(c.S.c_rA + gc)), mk(gld(c.S.c_rB + gc)));
     }
   }
 }
@@ -1956,9 +1981,10 @@ __device__ __forceinline__ void pcr_update_contrib(const Ctx &c, int buf, int ne
       const V3 n = mk(gld(S.c_n + gc));
       const float al = gld(S.c_alpha + (size_t)buf * S.NC + gc);
       const int active = gld(S.c_active + (size_t)buf * S.NC + gc);
+      const V3 rA = mk(gld(S.c_rA + gc)), rB = mk(gld(S.c_rB + gc));
 #pragma unroll
       for (int r = 0; r < 3; ++r) z[r] = act ? pcr_row_apply<INIT>(S, r0 + r, v[r], alpha, beta, upd) : v[r].z;
-      gst(S.c_cj + gc, f4(contact_dir_core(n, al, active, z[0], z[1], z[2]), 0.f));
+      contact_store(S, gc, contact_dir_core(n, al, active, z[0], z[1], z[2]), rA, rB);
     }
   }
 }
@@ -1983,9 +2009,10 @@ __device__ __forceinline__ void resident_contrib(const Ctx &c, int el, int buf, 
   } else {
     const int gc = E.con_off + el - E.n_jnt - E.n_tet;
     const DevScene &S = c.S;
-    gst(S.c_cj + gc, f4(contact_dir_core(mk(gld(S.c_n + gc)), gld(S.c_alpha + (size_t)buf * S.NC + gc),
-                                         gld(S.c_active + (size_t)buf * S.NC + gc), z[0], z[1], z[2]),
-                        0.f));
+    contact_store(S, gc,
+                  contact_dir_core(mk(gld(S.c_n + gc)), gld(S.c_alpha + (size_t)buf * S.NC + gc),
+                                   gld(S.c_active + (size_t)buf * S.NC + gc), z[0], z[1], z[2]),
+                  mk(gld(S.c_rA + gc)), mk(gld(S.c_rB + gc)));
   }
 }
 
@@ -2380,7 +2407,7 @@ __device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int bu
         const float w = jy[r] + C[r] * z[r] + eps * z[r];
         pw[r] = fused_finish<MODE>(S, r0 + r, z[r], w, P[r], q[r], part);
       }
-      gst(S.c_cj + gc, f4(contact_dir_core(n, al, act, pw[0], pw[1], pw[2]), 0.f));
+      contact_store(S, gc, contact_dir_core(n, al, act, pw[0], pw[1], pw[2]), rA, rB);
     }
   }
 }
