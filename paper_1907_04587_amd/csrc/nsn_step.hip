@@ -1414,21 +1414,21 @@ __device__ __forceinline__ void tet_contrib(const Ctx &c, int tl, const float z[
 }
 
 // Sums the body's run of contribution slots in order (joints, feature-side contacts,
-// target-side contacts), four slots' loads at a time ahead of their sums.
+// target-side contacts), eight slots' loads at a time ahead of their sums.
 __device__ __forceinline__ void gather_rigid(const Ctx &c, int g, float out[6]) {
   const DevScene &S = c.S;
   for (int k = 0; k < 6; ++k) out[k] = 0.f;
   const int2 rs = gld(S.r_slot + g);
-  for (int k = rs.x; k < rs.y; k += 4) {
-    float4 f[4], t[4];
+  for (int k = rs.x; k < rs.y; k += 8) {
+    float4 f[8], t[8];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < 8; ++m) {
       if (k + m >= rs.y) continue;
       f[m] = gld(S.r_cj + 2 * (size_t)(k + m));
       t[m] = gld(S.r_cj + 2 * (size_t)(k + m) + 1);
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < 8; ++m) {
       if (k + m >= rs.y) continue;
       out[0] += f[m].x; out[1] += f[m].y; out[2] += f[m].z;
       out[3] += t[m].x; out[4] += t[m].y; out[5] += t[m].z;
