@@ -1338,6 +1338,20 @@ __device__ __forceinline__ V3 contact_dir(const Ctx &c, int gc, const float *src
 // element-parallel), then every body sums the contributions of its elements in a
 // fixed order (deterministic, no atomics) ----
 // v: the joint's six row values
+// a joint's J^T v (o: side A's six values, then side B's) into its bodies' slots (none
+// for the world)
+__device__ __forceinline__ void joint_store_slots(const DevScene &S, int jg, const float o[12]) {
+  const int2 js = gld(S.j_slot + jg);
+  if (js.x >= 0) {
+    gst(S.r_cj + 2 * (size_t)js.x, make_float4(o[0], o[1], o[2], 0.f));
+    gst(S.r_cj + 2 * (size_t)js.x + 1, make_float4(o[3], o[4], o[5], 0.f));
+  }
+  if (js.y >= 0) {
+    gst(S.r_cj + 2 * (size_t)js.y, make_float4(o[6], o[7], o[8], 0.f));
+    gst(S.r_cj + 2 * (size_t)js.y + 1, make_float4(o[9], o[10], o[11], 0.f));
+  }
+}
+
 __device__ __forceinline__ void joint_contrib_vals(const Ctx &c, int jl, const float v[6]) {
   const int jg = c.E.jnt_off + jl;
   const float *J = c.S.j_J + (size_t)72 * jg;
@@ -1349,16 +1363,7 @@ __device__ __forceinline__ void joint_contrib_vals(const Ctx &c, int jl, const f
 #pragma unroll
     for (int q = 0; q < 12; ++q) o[q] += v[r] * gld(J + 12 * r + q);
   }
-  // side A's six values in its body's slot (none for the world), then side B's
-  const int2 js = gld(c.S.j_slot + jg);
-  if (js.x >= 0) {
-    gst(c.S.r_cj + 2 * (size_t)js.x, make_float4(o[0], o[1], o[2], 0.f));
-    gst(c.S.r_cj + 2 * (size_t)js.x + 1, make_float4(o[3], o[4], o[5], 0.f));
-  }
-  if (js.y >= 0) {
-    gst(c.S.r_cj + 2 * (size_t)js.y, make_float4(o[6], o[7], o[8], 0.f));
-    gst(c.S.r_cj + 2 * (size_t)js.y + 1, make_float4(o[9], o[10], o[11], 0.f));
-  }
+  joint_store_slots(c.S, jg, o);
 }
 
 // A contact's J^T v, dir applied at its two points: a particle feature body reads the
@@ -2325,26 +2330,51 @@ __device__ __forceinline__ void fused_visit(const Ctx &c, const float *Y, int bu
                                             float beta, double part[3]) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
-  for (int el = threadIdx.x; el < nel; el += BS) {
-    if (el < E.n_jnt) {
-      const int r0 = row_joint(E, el);
-      float z[6], q[6], P[6], jy[6], pw[6], C[6];
-      RowIn v[6];
+  // Visit slots: eight lanes per joint (one per row, two idle; a group never straddles
+  // a wave), then the tets and contacts.  A joint's rows then cost one memory round
+  // trip, like a tet's, instead of one per row on a single thread.
+  const int nj = E.n_jnt;
+  const int nv = nel + 7 * nj;
+  for (int i = threadIdx.x; i < nv; i += BS) {
+    if (i < 8 * nj) {
+      const int jl = i >> 3, r = i & 7, jg = E.jnt_off + jl;
+      const bool row = r < 6;
+      const int rr = row ? r : 5;  // idle lanes read row 5 and write nothing
+      const int r0 = row_joint(E, jl);
+      const int4 info = gld(S.j_info + jg);
+      RowIn v;
+      fused_row_load<MODE>(S, r0 + rr, v);
+      const float C = gld(S.row_C + r0 + rr);
+      float Jr[12];
 #pragma unroll
-      for (int r = 0; r < 6; ++r) {
-        fused_row_load<MODE>(S, r0 + r, v[r]);
-        C[r] = gld(S.row_C + r0 + r);
+      for (int k = 0; k < 12; ++k) Jr[k] = gld(S.j_J + (size_t)72 * jg + 12 * rr + k);
+      float z = 0.f, q = 0.f, P = 0.f, pw = 0.f;
+      if (row) fused_row<MODE>(S, r0 + r, v, alpha, beta, z, q, P);
+      const int dB = ldof(E, info.z - E.rig_off);
+      const int dA = info.y >= 0 ? ldof(E, info.y - E.rig_off) : -1;
+      float jy = row_dot_rigid(Jr + 6, Y, dB);
+      if (dA >= 0) jy += row_dot_rigid(Jr, Y, dA);
+      if (row) {
+        const float w = jy + C * z + eps * z;
+        pw = fused_finish<MODE>(S, r0 + r, z, w, P, q, part);
       }
+      // J^T (P w) of the joint, summed over its rows in row order as joint_contrib_vals
+      // does, from the row lanes' values; the group's first lane stores it
+      const int lead = (threadIdx.x & 63) & ~7;
+      float o[12];
 #pragma unroll
-      for (int r = 0; r < 6; ++r) fused_row<MODE>(S, r0 + r, v[r], alpha, beta, z[r], q[r], P[r]);
-      joint_JY(c, el, Y, jy);
+      for (int k = 0; k < 12; ++k) o[k] = 0.f;
 #pragma unroll
-      for (int r = 0; r < 6; ++r) {
-        const float w = jy[r] + C[r] * z[r] + eps * z[r];
-        pw[r] = fused_finish<MODE>(S, r0 + r, z[r], w, P[r], q[r], part);
+      for (int rk = 0; rk < 6; ++rk) {
+        const float pk = __shfl(pw, lead + rk, 64);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) o[k] += pk * __shfl(Jr[k], lead + rk, 64);
       }
-      joint_contrib_vals(c, el, pw);
-    } else if (el < E.n_jnt + E.n_tet) {
+      if (r == 0) joint_store_slots(S, jg, o);
+      continue;
+    }
+    const int el = i - 7 * nj;
+    if (el < E.n_jnt + E.n_tet) {
       const int tl = el - E.n_jnt, tg = E.tet_off + tl;
       const int r0 = row_tet(E, tl);
       float z[3], q[3], P[3], jy[3], pw[3];
