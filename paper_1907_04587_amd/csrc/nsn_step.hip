@@ -1441,6 +1441,38 @@ __device__ __forceinline__ void gather_rigid(const Ctx &c, int g, float out[6]) 
   }
 }
 
+// The same sums with the body's slots read by the four lanes sub = 0..3 of an aligned
+// group (slots k + sub and k + 4 + sub of each round of eight): every lane adds the
+// round's slots in slot order from the lanes' registers, so the result is the one
+// gather_rigid gives, in every lane of the group.
+__device__ __forceinline__ void gather_rigid_lanes(const DevScene &S, int g, int sub, float out[6]) {
+  for (int k = 0; k < 6; ++k) out[k] = 0.f;
+  const int2 rs = gld(S.r_slot + g);
+  const int lead = (threadIdx.x & 63) & ~3;
+  for (int k = rs.x; k < rs.y; k += 8) {
+    float4 f[2], t[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int sl = k + sub + 4 * m;
+      f[m] = sl < rs.y ? gld(S.r_cj + 2 * (size_t)sl) : make_float4(0.f, 0.f, 0.f, 0.f);
+      t[m] = sl < rs.y ? gld(S.r_cj + 2 * (size_t)sl + 1) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const int src = lead + l;
+        const float fx = __shfl(f[m].x, src, 64), fy = __shfl(f[m].y, src, 64), fz = __shfl(f[m].z, src, 64);
+        const float tx = __shfl(t[m].x, src, 64), ty = __shfl(t[m].y, src, 64), tz = __shfl(t[m].z, src, 64);
+        if (k + 4 * m + l < rs.y) {
+          out[0] += fx; out[1] += fy; out[2] += fz;
+          out[3] += tx; out[4] += ty; out[5] += tz;
+        }
+      }
+    }
+  }
+}
+
 // The tets wrote their contributions in this particle's adjacency order: a contiguous
 // run, summed in that order with eight loads in flight.
 __device__ __forceinline__ V3 gather_particle(const Ctx &c, int p) {
@@ -2451,10 +2483,12 @@ template <int MODE>
 __device__ __forceinline__ void fused_body(const Ctx &c, float *Y, float alpha, float beta, int tid, int BS) {
   const EnvInfo &E = c.E;
   const DevScene &S = c.S;
-  const int nb = E.n_rig + E.n_par;
-  for (int b = tid; b < nb; b += BS) {
-    if (b < E.n_rig) {
-      const int g = E.rig_off + b;
+  // slots: four lanes per rigid body (they share its gather), then one per particle
+  const int nr4 = 4 * E.n_rig;
+  const int nv = nr4 + E.n_par;
+  for (int i = tid; i < nv; i += BS) {
+    if (i < nr4) {
+      const int b = i >> 2, g = E.rig_off + b;
       float v[6], oq[6], oz[6], Iw[6];
       const int d = E.dof_off + 6 * b;
       // every load before the first store (see fused_row_load), the body's own values
@@ -2466,7 +2500,8 @@ __device__ __forceinline__ void fused_body(const Ctx &c, float *Y, float alpha, 
         Iw[k] = MODE == 3 ? 0.f : gld(S.r_Iwinv + 6 * g + k);
       }
       const float im = MODE == 3 ? 0.f : gld(S.r_inertia + g).w;
-      gather_rigid(c, g, v);
+      gather_rigid_lanes(S, g, i & 3, v);
+      if ((i & 3) != 0) continue;  // the group's first lane finishes the body
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         if (MODE == 4) {
@@ -2484,6 +2519,7 @@ __device__ __forceinline__ void fused_body(const Ctx &c, float *Y, float alpha, 
 #pragma unroll
       for (int k = 0; k < 6; ++k) Y[6 * b + k] = v[k];
     } else {
+      const int b = i - nr4 + E.n_rig;
       const int p = E.par_off + b - E.n_rig;
       float oq[3], oz[3];
       const int d = E.dof_off + 6 * E.n_rig + 3 * (b - E.n_rig);
